@@ -1,0 +1,95 @@
+/*
+ * FP64 CPU oracle of DAMAS on a wavelet-compressed computational grid
+ * (W. Ma, X. Liu, "Improving the Efficiency of DAMAS for Sound Source
+ * Localization via Wavelet Compression Computational Grid").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU path.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no source, header, table or helper with the GPU
+ * library, and it never calls it.
+ *
+ * Every routine is a plain, slow, literal transcription of the paper's
+ * definitions in double precision, with sums in ascending index order and
+ * no blocking or reordering.  Build with -ffp-contract=off so that no
+ * multiply-add is fused behind the reader's back.
+ */
+#ifndef DAMAS_ORACLE_H
+#define DAMAS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Array and scan-grid geometry (section "Beamforming").  Microphones lie in
+ * the plane z = 0 with the origin at the array centre; the scan plane is
+ * z = z0 with N x N equidistant points, n = iy*N + ix, covering
+ * [x0, x1] x [y0, y1] with both end points included. */
+typedef struct {
+    int M;              /* number of microphones                         */
+    const double *mic;  /* M x 3 positions, metres, row-major            */
+    int N;              /* grid points per side, S = N*N                 */
+    double x0, x1;      /* scan-plane extent along x                     */
+    double y0, y1;      /* scan-plane extent along y                     */
+    double z0;          /* distance between array plane and scan plane   */
+    double c;           /* speed of sound, m/s                           */
+} orc_geom;
+
+/* Selection modes for the wavelet-compressed grid. */
+enum {
+    ORC_SEL_KEEP_ALL = 0,   /* no compression: every grid point            */
+    ORC_SEL_EPS_REL = 1,    /* Algorithm 1 with threshold eps * max|b|     */
+    ORC_SEL_KEEP_COUNT = 2  /* the K points of largest |d| (G0 included)   */
+};
+
+/* Coordinates of grid point n. */
+void orc_grid_point(const orc_geom *g, int n, double r[3]);
+
+/* Steering vectors e_nm = exp(-i k |r_n - r_m|), k = 2 pi f / c, for the
+ * n_pts grid points listed in pts.  Output e is n_pts x M complex numbers
+ * stored as interleaved (re, im) pairs. */
+void orc_steering(const orc_geom *g, double freq, int n_pts, const int *pts,
+                  double *e);
+
+/* Delay-and-sum map, Eq. (2): b_n = Re(e_n^H C e_n) / M^2 for every grid
+ * point.  csm is M x M complex, row-major, interleaved (re, im). */
+void orc_das_map(const orc_geom *g, double freq, const double *csm,
+                 double *b);
+
+/* Resolution level of grid point (ix, iy) in the nested dyadic grids G^j of
+ * Algorithm 1, and (for level >= 1) its parent on the next-coarser grid,
+ * whose value predicts it (order-0 interpolation).  Returns the level. */
+int orc_level(int N, int ix, int iy, int *parent_ix, int *parent_iy);
+
+/* Wavelet-compressed grid (Algorithm 1).  Writes the kept grid indices in
+ * ascending order to idx (capacity N*N) and returns their number.  detail
+ * (nullable, N*N) receives |d(p)| (0 on the coarsest grid).  margin
+ * (nullable) receives the relative distance of the closest decision to its
+ * threshold: min |(|d| - tau)| / tau for EPS_REL, the relative gap between
+ * the K'-th and (K'+1)-th largest |d| for KEEP_COUNT, +inf otherwise. */
+int orc_select(int N, const double *b, int mode, double eps, int keep_count,
+               int *idx, double *detail, double *margin);
+
+/* Point-spread matrix over St points, A_ij = |e_i^H e_j|^2 / M^2 (section
+ * "DAMAS", PSF definition), from their steering vectors e (St x M complex,
+ * interleaved).  A is St x St row-major.  Entries with j >= i are computed
+ * and mirrored, so A is exactly symmetric. */
+void orc_psf(int M, int St, const double *e, double *A);
+
+/* DAMAS Gauss-Seidel with the non-negativity clamp: iters full sweeps over
+ * rows 0..St-1 of A x = b, starting from the values in x, updated in place. */
+void orc_gs(int St, const double *A, const double *b, int iters, double *x);
+
+/* The whole path for one frequency bin: DAS map, selection, compressed
+ * system, sweeps.  x_init (nullable) is a full N*N map whose kept entries
+ * start the sweeps (zero otherwise).  Outputs (all nullable except idx):
+ * b_map (N*N), idx (N*N capacity), x_map (N*N, zero off the kept set),
+ * margin.  Returns the number of kept points, or -1 on allocation failure. */
+int orc_solve_bin(const orc_geom *g, double freq, const double *csm,
+                  int mode, double eps, int keep_count, int iters,
+                  const double *x_init, double *b_map, int *idx,
+                  double *x_map, double *margin);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
