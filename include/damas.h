@@ -1,0 +1,242 @@
+/*
+ * damas.h -- C ABI of the MI355X (gfx950) library for DAMAS on a
+ * wavelet-compressed computational grid (W. Ma, X. Liu, "Improving the
+ * Efficiency of DAMAS for Sound Source Localization via Wavelet Compression
+ * Computational Grid").
+ *
+ * The path, per frequency bin f:
+ *   1. delay-and-sum map  b_n = e_n^H C_f e_n / M^2 at every grid point
+ *      (section "Beamforming", Eq. dirty_map_1);
+ *   2. Algorithm 1: wavelet detail of b on nested dyadic grids, threshold,
+ *      kept set G>= (section "Wavelet Compression Computational Grid");
+ *   3. point-spread matrix over the kept points,
+ *      A_ij = |e_i^H e_j|^2 / M^2 (section "DAMAS", PSF and Eq. Axb);
+ *   4. non-negative Gauss-Seidel sweeps on A~ x~ = b~ (section "DAMAS",
+ *      the DAMAS iteration, and Eq. Axb_CG), x = 0 off the kept set.
+ *
+ * Conventions shared by every call.
+ *  - Return value: DAMAS_OK (0) or a negative DAMAS_E* code.  No C++
+ *    exception crosses this boundary.  damas_last_error() describes the most
+ *    recent failure of the calling thread.
+ *  - Arguments are validated on the host before any device work; when
+ *    validation fails nothing is launched and no output is written.  After a
+ *    device error (DAMAS_EDEVICE) outputs are undefined.
+ *  - "device" pointers are HIP device allocations on the current device
+ *    (for example torch tensors' data_ptr()); "host" pointers are ordinary
+ *    memory.  The library never frees memory it did not allocate and keeps
+ *    no pointer to caller memory after a call returns (asynchronous calls:
+ *    after the enqueued work completes).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls that take a stream only enqueue work on it and return.
+ *  - Grid indexing: point n = iy*N + ix, ix along x, both 0-based; the scan
+ *    plane is z = z0 with x = x0 + ix (x1-x0)/(N-1), y likewise, end points
+ *    included (section "Beamforming": S = N x N equidistant points).
+ *  - Complex numbers are interleaved (re, im) pairs of doubles.
+ *  - Steering component of microphone m at point r: exp(-i k |r - r_m|),
+ *    k = 2 pi f / c, unit magnitude, used both for the beamformer and for
+ *    the source model, so A is symmetric with unit diagonal.
+ */
+#ifndef DAMAS_H
+#define DAMAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define DAMAS_OK 0
+#define DAMAS_EINVAL (-1)    /* invalid argument                          */
+#define DAMAS_ENOMEM (-2)    /* device or host allocation failed          */
+#define DAMAS_EDEVICE (-3)   /* HIP runtime or kernel error               */
+#define DAMAS_EADMIT (-4)    /* request can never fit the memory budget   */
+#define DAMAS_EBUSY (-5)     /* queue full                                */
+#define DAMAS_ETIMEDOUT (-6) /* wait timed out                            */
+#define DAMAS_ECAPACITY (-7) /* a device-side capacity bound was exceeded */
+
+/* ---- grid-compression modes (Algorithm 1) --------------------------- */
+#define DAMAS_SEL_KEEP_ALL 0   /* no compression: every grid point        */
+#define DAMAS_SEL_EPS_REL 1    /* keep level-0 points and every point whose
+                                  wavelet detail |d| >= eps * max_n |b_n|   */
+#define DAMAS_SEL_KEEP_COUNT 2 /* keep level-0 points plus the points of
+                                  largest |d| (ties: lower grid index first)
+                                  up to keep_count points in total          */
+
+/* ---- arithmetic of the compressed system ---------------------------- */
+#define DAMAS_PREC_FP64 0 /* A stored in double                          */
+#define DAMAS_PREC_FP32 1 /* A stored in float (half the bytes the sweeps
+                             stream); steering, the PSF products, b, x and
+                             every sweep sum stay double                   */
+
+/* Scan geometry (section "Beamforming").  The struct itself is host memory;
+ * `mic` is a DEVICE pointer to M x 3 doubles (metres, row-major, array in
+ * the plane z = 0 centred on the origin). */
+typedef struct {
+    int32_t M;
+    const double *mic;
+    int32_t N;
+    double x0, x1, y0, y1, z0;
+    double c; /* speed of sound, m/s */
+} damas_geometry;
+
+/* ---- helpers (host only, no device work) ----------------------------- */
+
+/* Message for a status code. */
+const char *damas_strerror(int code);
+
+/* Description of the calling thread's last failure ("" if none). */
+const char *damas_last_error(void);
+
+/* Leading dimension (row stride, in elements) of a compressed system with
+ * s_tilde unknowns: s_tilde rounded up to a multiple of 8.  Rows and the
+ * columns j >= s_tilde of the padding are zero. */
+int64_t damas_ld(int32_t s_tilde);
+
+/* Number of points on the coarsest grid G^0 of Algorithm 1 for an N x N
+ * grid; every compressed grid keeps them, so KEEP_COUNT keeps
+ * clamp(keep_count, |G^0|, N*N) points. */
+int32_t damas_coarse_count(int32_t N);
+
+/* ---- step-level calls (device pointers, enqueue on `stream`) --------- */
+
+/* Step 1, Eq. dirty_map_1: b[f*S + n] = Re(e_n^H C_f e_n) / M^2 for every
+ * bin f < n_bins and grid point n < S = N*N.
+ *   freq  device, n_bins doubles (Hz, > 0)
+ *   csm   device, n_bins x M x M complex (row-major, Hermitian)
+ *   b     device, n_bins x S doubles (output)
+ * Phase k|r - r_m| and all sums in double precision. */
+int damas_das_map(const damas_geometry *g, int32_t n_bins, const double *freq,
+                  const double *csm, double *b, void *stream);
+
+/* Step 2, Algorithm 1 with the order-0 interpolating predictor: per bin,
+ * J = floor(log2 N); grid G^j holds the points whose indices are both
+ * multiples of 2^(J-j); a point first appearing on level j+1 >= 1 has
+ * detail d = b(p) - b(parent), parent = its lower-left neighbour on G^j.
+ * Kept points are written in ascending grid order.
+ *   b           device, n_bins x S doubles
+ *   keep_count  device, n_bins int32 (KEEP_COUNT only; may be NULL otherwise)
+ *   idx         device, n_bins x S int32 (output; entries past s_tilde[f]
+ *               are left untouched)
+ *   s_tilde     device, n_bins int32 (output: kept points per bin)
+ * The decisions are exact functions of b: the same b gives the same idx on
+ * any IEEE machine (no fused operations in the comparisons). */
+int damas_select(int32_t N, int32_t n_bins, const double *b, int32_t mode,
+                 double eps, const int32_t *keep_count, int32_t *idx,
+                 int32_t *s_tilde, void *stream);
+
+/* Packed layout of the per-bin compressed systems: off[f] = sum over g < f
+ * of damas_ld(s_tilde[g])^2, off[n_bins] = total elements.
+ *   s_tilde   device, n_bins int32 (in/out)
+ *   max_kept  host bound on s_tilde[f]
+ *   capacity  elements available in the A arena
+ *   off       device, n_bins + 1 int64 (output)
+ * A bin with s_tilde[f] > max_kept, or whose system would end beyond
+ * `capacity`, is set to s_tilde[f] = 0 (the later steps then skip it and
+ * its map is all zero) and damas_check reports DAMAS_ECAPACITY. */
+int damas_layout(int32_t n_bins, int32_t *s_tilde, int32_t max_kept,
+                 int64_t capacity, int64_t *off, void *stream);
+
+/* Steering rows of the kept points (section "Beamforming", v_m(r) with unit
+ * magnitude), in double: for bin f and i < s_tilde[f], with
+ * n = idx[f*S + i],
+ *   E[f*e_stride + i*2M + m]     = cos(k |r_n - r_m|)
+ *   E[f*e_stride + i*2M + M + m] = -sin(k |r_n - r_m|)
+ * rows s_tilde[f] <= i < damas_ld(s_tilde[f]) are zero.
+ *   idx      device, n_bins x S int32, as written by damas_select
+ *   s_tilde  device, n_bins int32; bins above max_kept are skipped and
+ *            raise the fault that damas_check reports
+ *   E        device, n_bins x e_stride doubles (output)
+ *   e_stride elements per bin, >= damas_ld(max_kept) * 2M when n_bins > 1 */
+int damas_steer(const damas_geometry *g, int32_t n_bins, const double *freq,
+                const int32_t *idx, const int32_t *s_tilde, int32_t max_kept,
+                double *E, int64_t e_stride, void *stream);
+
+/* Step 3 (section "DAMAS", PSF): A_f[i*ld + j] = |sum_m conj(e_im) e_jm|^2 / M^2
+ * over the kept points of bin f, ld = damas_ld(s_tilde[f]), A_f = A + off[f].
+ * Built from the double steering rows E (damas_steer) as two real products
+ * on the f64 matrix cores and rounded once to the storage type (double for
+ * DAMAS_PREC_FP64, float for DAMAS_PREC_FP32).  Every off-diagonal value is
+ * computed once and written to (i,j) and (j,i), so A is bitwise symmetric;
+ * A_ii = 1 exactly (unit-magnitude steering); padding rows and columns
+ * are 0. */
+int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
+              int32_t max_kept, int32_t precision, const double *E,
+              int64_t e_stride, const int64_t *off, void *A, void *stream);
+
+/* Step 4 (section "DAMAS", the DAMAS iteration): for bin f, with
+ * b~_i = b[f*S + idx[f*S + i]], x~ starting at x_init[f*S + idx[..]] (or 0
+ * when x_init is NULL), `iterations` full sweeps over i = 0 .. s_tilde-1:
+ *   r_i = sum_j A_ij x_j - b~_i  (x_j already updated for j < i)
+ *   x_i = max(x_i - r_i / A_ii, 0)
+ * then x_map[f*S + n] = x~_i at n = idx[f*S + i] and 0 at every other n.
+ *   A       device arena of damas_psf's layout (element type by precision)
+ *   b       device, n_bins x S doubles
+ *   x_init  device, n_bins x S (double for FP64, float for FP32), or NULL
+ *   x_map   device, n_bins x S, same type (output)
+ * A must be symmetric (as the PSF matrix is).  The sweep state x~, b~ and
+ * all sums are double at both precisions.  One workgroup owns one bin for
+ * all its sweeps; bins run concurrently. */
+int damas_gs(int32_t N, int32_t n_bins, const int32_t *s_tilde,
+             int32_t max_kept, const int32_t *idx, const int64_t *off,
+             int32_t precision, const void *A, const double *b,
+             int32_t iterations, const void *x_init, void *x_map,
+             void *stream);
+
+/* ---- the whole path -------------------------------------------------- */
+
+typedef struct damas_ctx damas_ctx;
+
+/* A context owns the device workspace (kept points, steering rows, the
+ * packed A arena), grown on demand and reused across calls, for one device.
+ * Not thread-safe. */
+int damas_ctx_create(int32_t device, damas_ctx **out);
+void damas_ctx_destroy(damas_ctx *ctx);
+
+/* Timing of the Gauss-Seidel launches: when enabled, each damas_solve_dev
+ * records HIP events around its sweep launch(es) on the solve's stream;
+ * damas_ctx_gs_time returns the summed milliseconds and launch count of the
+ * recorded launches that have completed (it synchronises on them) and
+ * clears the record. */
+int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled);
+int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches);
+
+/* Parameters of a solve (host struct). */
+typedef struct {
+    int32_t select_mode;       /* DAMAS_SEL_*                               */
+    double eps;                /* EPS_REL threshold (relative to max |b|)   */
+    const int32_t *keep_count; /* HOST, n_bins int32 (KEEP_COUNT), or NULL:
+                                  then keep_count_all applies to every bin  */
+    int32_t keep_count_all;
+    int32_t iterations;        /* Gauss-Seidel sweeps, >= 0                 */
+    int32_t precision;         /* DAMAS_PREC_*                              */
+    int32_t batched;           /* 0: one launch per step per bin ("plain");
+                                  1: one launch per step for all bins       */
+    int32_t max_kept;          /* EPS_REL: host bound on kept points per bin
+                                  (0 = N*N); exceeding it fails with
+                                  DAMAS_ECAPACITY                           */
+} damas_params;
+
+/* Every step for every bin, device-resident, enqueued on `stream`.
+ *   freq, csm   device, as for damas_das_map
+ *   x_init      device map (n_bins x S, the precision's type) or NULL
+ *   x_map       device, n_bins x S, the precision's type (output)
+ *   b_map       device, n_bins x S doubles, or NULL (then kept internally)
+ *   idx         device, n_bins x S int32, or NULL
+ *   s_tilde     device, n_bins int32, or NULL
+ * Device-side capacity failures are reported by damas_check(ctx). */
+int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
+                    const double *freq, const double *csm,
+                    const damas_params *p, const void *x_init, void *x_map,
+                    double *b_map, int32_t *idx, int32_t *s_tilde,
+                    void *stream);
+
+/* Synchronise with the context's last solve and report a device-side
+ * capacity failure (DAMAS_ECAPACITY) or a HIP error. */
+int damas_check(damas_ctx *ctx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DAMAS_H */

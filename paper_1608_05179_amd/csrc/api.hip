@@ -1,0 +1,635 @@
+// C ABI of the library: argument validation, the device workspace of a
+// context, and the order of the launches that make up one solve.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+using namespace damas;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(DAMAS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                                                    \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return hip_fail(e_, what);                                         \
+    } while (0)
+
+// One zero-initialised fault word per device, for kernels that meet a
+// device-side capacity violation.
+std::mutex g_fault_mu;
+std::unordered_map<int, int *> g_fault;
+
+int fault_word(int **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_fault_mu);
+    auto it = g_fault.find(dev);
+    if (it != g_fault.end()) {
+        *out = it->second;
+        return DAMAS_OK;
+    }
+    int *p = nullptr;
+    HIP_TRY(hipMalloc(&p, sizeof(int)), "hipMalloc(fault word)");
+    HIP_TRY(hipMemset(p, 0, sizeof(int)), "hipMemset(fault word)");
+    g_fault[dev] = p;
+    *out = p;
+    return DAMAS_OK;
+}
+
+bool finite(double v) { return isfinite(v) != 0; }
+
+int check_geometry(const damas_geometry *g)
+{
+    if (!g)
+        return fail(DAMAS_EINVAL, "geometry is NULL");
+    if (g->M < 1 || g->M > 128)
+        return fail(DAMAS_EINVAL, "M = %d outside [1, 128]", g->M);
+    if (!g->mic)
+        return fail(DAMAS_EINVAL, "mic positions are NULL");
+    if (g->N < 1 || g->N > 46340)
+        return fail(DAMAS_EINVAL, "N = %d outside [1, 46340]", g->N);
+    if (!finite(g->x0) || !finite(g->x1) || !finite(g->y0) || !finite(g->y1) ||
+        !finite(g->z0))
+        return fail(DAMAS_EINVAL, "scan-plane extent is not finite");
+    if (!(g->c > 0.0) || !finite(g->c))
+        return fail(DAMAS_EINVAL, "speed of sound must be positive and finite");
+    return DAMAS_OK;
+}
+
+int check_precision(int32_t p)
+{
+    if (p != DAMAS_PREC_FP64 && p != DAMAS_PREC_FP32)
+        return fail(DAMAS_EINVAL, "unknown precision %d", p);
+    return DAMAS_OK;
+}
+
+int check_mode(int32_t mode, double eps)
+{
+    if (mode != DAMAS_SEL_KEEP_ALL && mode != DAMAS_SEL_EPS_REL &&
+        mode != DAMAS_SEL_KEEP_COUNT)
+        return fail(DAMAS_EINVAL, "unknown selection mode %d", mode);
+    if (mode == DAMAS_SEL_EPS_REL && (!(eps >= 0.0) || !finite(eps)))
+        return fail(DAMAS_EINVAL, "eps must be finite and >= 0");
+    return DAMAS_OK;
+}
+
+int check_kept(int32_t max_kept, int32_t S, int32_t precision)
+{
+    if (max_kept < 0 || max_kept > S)
+        return fail(DAMAS_EINVAL, "max_kept = %d outside [0, N*N = %d]", max_kept, S);
+    if (max_kept > gs_max_kept(precision))
+        return fail(DAMAS_EINVAL,
+                    "max_kept = %d exceeds the %d unknowns a sweep workgroup "
+                    "holds on chip at this precision",
+                    max_kept, gs_max_kept(precision));
+    return DAMAS_OK;
+}
+
+size_t elem_size(int32_t precision)
+{
+    return precision == DAMAS_PREC_FP64 ? sizeof(double) : sizeof(float);
+}
+
+int coarse_count(int32_t N)
+{
+    int J = 0;
+    while ((2 << J) <= N)
+        ++J;
+    int side = (1 << J) < N ? 2 : 1;
+    return side * side;
+}
+
+} // namespace
+
+hipError_t damas::allow_big_lds(const void *kernel)
+{
+    // Raise the kernel's dynamic-LDS limit to what a workgroup may hold on
+    // this device.  A runtime that needs no opt-in may refuse the call;
+    // the launch itself then reports any real shortfall, so the status is
+    // cleared here rather than left for the next error check.
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+            hipSuccess &&
+        max_lds > 0)
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    (void)hipGetLastError();
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+
+extern "C" const char *damas_strerror(int code)
+{
+    switch (code) {
+    case DAMAS_OK: return "success";
+    case DAMAS_EINVAL: return "invalid argument";
+    case DAMAS_ENOMEM: return "out of memory";
+    case DAMAS_EDEVICE: return "device error";
+    case DAMAS_EADMIT: return "request exceeds the memory budget";
+    case DAMAS_EBUSY: return "queue full";
+    case DAMAS_ETIMEDOUT: return "timed out";
+    case DAMAS_ECAPACITY: return "device-side capacity exceeded";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *damas_last_error(void) { return g_err.c_str(); }
+
+extern "C" int64_t damas_ld(int32_t s_tilde) { return s_tilde < 0 ? 0 : ld_of(s_tilde); }
+
+extern "C" int32_t damas_coarse_count(int32_t N) { return N < 1 ? 0 : coarse_count(N); }
+
+// ---------------------------------------------------------------------------
+// step-level calls
+
+extern "C" int damas_das_map(const damas_geometry *g, int32_t n_bins,
+                             const double *freq, const double *csm, double *b,
+                             void *stream)
+{
+    int rc = check_geometry(g);
+    if (rc)
+        return rc;
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    if (n_bins > 0 && (!freq || !csm || !b))
+        return fail(DAMAS_EINVAL, "freq, csm and b must be non-NULL");
+    HIP_TRY(launch_das(make_geom(*g), n_bins, freq, csm, b, (hipStream_t)stream),
+            "das launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_select(int32_t N, int32_t n_bins, const double *b,
+                            int32_t mode, double eps,
+                            const int32_t *keep_count, int32_t *idx,
+                            int32_t *s_tilde, void *stream)
+{
+    if (N < 1 || N > 46340)
+        return fail(DAMAS_EINVAL, "N = %d outside [1, 46340]", N);
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    int rc = check_mode(mode, eps);
+    if (rc)
+        return rc;
+    if (n_bins > 0 && (!b || !idx || !s_tilde))
+        return fail(DAMAS_EINVAL, "b, idx and s_tilde must be non-NULL");
+    if (n_bins > 0 && mode == DAMAS_SEL_KEEP_COUNT && !keep_count)
+        return fail(DAMAS_EINVAL, "KEEP_COUNT needs keep_count");
+    HIP_TRY(launch_select(N, n_bins, b, mode, eps, keep_count, idx, s_tilde,
+                          (hipStream_t)stream),
+            "select launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_layout(int32_t n_bins, int32_t *s_tilde, int32_t max_kept,
+                            int64_t capacity, int64_t *off, void *stream)
+{
+    if (n_bins < 0 || max_kept < 0 || capacity < 0)
+        return fail(DAMAS_EINVAL, "n_bins, max_kept and capacity must be >= 0");
+    if (!off || (n_bins > 0 && !s_tilde))
+        return fail(DAMAS_EINVAL, "s_tilde and off must be non-NULL");
+    int *fault;
+    int rc = fault_word(&fault);
+    if (rc)
+        return rc;
+    HIP_TRY(launch_layout(n_bins, s_tilde, max_kept, capacity, off, fault,
+                          (hipStream_t)stream),
+            "layout launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_steer(const damas_geometry *g, int32_t n_bins,
+                           const double *freq, const int32_t *idx,
+                           const int32_t *s_tilde, int32_t max_kept, double *E,
+                           int64_t e_stride, void *stream)
+{
+    int rc = check_geometry(g);
+    if (rc)
+        return rc;
+    const int32_t S = g->N * g->N;
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    if (max_kept < 0 || max_kept > S)
+        return fail(DAMAS_EINVAL, "max_kept = %d outside [0, N*N]", max_kept);
+    if (n_bins > 0 && (!freq || !idx || !s_tilde || !E))
+        return fail(DAMAS_EINVAL, "freq, idx, s_tilde and E must be non-NULL");
+    if (n_bins > 1 && e_stride < ld_of(max_kept) * 2 * g->M)
+        return fail(DAMAS_EINVAL, "e_stride < damas_ld(max_kept) * 2M");
+    int *fault;
+    if ((rc = fault_word(&fault)))
+        return rc;
+    HIP_TRY(launch_steer(make_geom(*g), n_bins, freq, idx, s_tilde, max_kept, E,
+                         e_stride, fault, (hipStream_t)stream),
+            "steer launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
+                         int32_t max_kept, int32_t precision, const double *E,
+                         int64_t e_stride, const int64_t *off, void *A,
+                         void *stream)
+{
+    int rc = check_precision(precision);
+    if (rc)
+        return rc;
+    if (M < 1 || M > 128)
+        return fail(DAMAS_EINVAL, "M = %d outside [1, 128]", M);
+    if (n_bins < 0 || max_kept < 0)
+        return fail(DAMAS_EINVAL, "n_bins and max_kept must be >= 0");
+    if (n_bins > 0 && (!s_tilde || !E || !off || !A))
+        return fail(DAMAS_EINVAL, "s_tilde, E, off and A must be non-NULL");
+    if (n_bins > 1 && e_stride < ld_of(max_kept) * 2 * M)
+        return fail(DAMAS_EINVAL, "e_stride < damas_ld(max_kept) * 2M");
+    int *fault;
+    if ((rc = fault_word(&fault)))
+        return rc;
+    HIP_TRY(launch_psf(M, n_bins, s_tilde, max_kept, precision, E, e_stride, off,
+                       A, fault, (hipStream_t)stream),
+            "psf launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_gs(int32_t N, int32_t n_bins, const int32_t *s_tilde,
+                        int32_t max_kept, const int32_t *idx,
+                        const int64_t *off, int32_t precision, const void *A,
+                        const double *b, int32_t iterations,
+                        const void *x_init, void *x_map, void *stream)
+{
+    int rc = check_precision(precision);
+    if (rc)
+        return rc;
+    if (N < 1 || N > 46340)
+        return fail(DAMAS_EINVAL, "N = %d outside [1, 46340]", N);
+    if (n_bins < 0 || iterations < 0)
+        return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
+    if ((rc = check_kept(max_kept, N * N, precision)))
+        return rc;
+    if (n_bins > 0 && (!s_tilde || !idx || !off || !A || !b || !x_map))
+        return fail(DAMAS_EINVAL, "s_tilde, idx, off, A, b and x_map must be non-NULL");
+    int *fault;
+    if ((rc = fault_word(&fault)))
+        return rc;
+    HIP_TRY(launch_gs(N, n_bins, s_tilde, max_kept, idx, off, precision, A, b,
+                      iterations, x_init, x_map, fault, (hipStream_t)stream),
+            "gs launch");
+    return DAMAS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+
+namespace {
+
+struct Buffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+} // namespace
+
+struct damas_ctx {
+    int device = 0;
+    Buffer b, idx, st, kc, off, E, A;
+    // keep counts last uploaded to kc (skip identical re-uploads)
+    std::vector<int32_t> kc_host;
+    int32_t *kc_pinned = nullptr;
+    size_t kc_pinned_n = 0;
+    hipEvent_t kc_done = nullptr;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> gs_events, event_pool;
+};
+
+namespace {
+
+int ensure(damas_ctx *ctx, Buffer &buf, size_t bytes, hipStream_t s, const char *what)
+{
+    if (buf.bytes >= bytes)
+        return DAMAS_OK;
+    if (buf.p) {
+        // Work already enqueued may still read the old buffer.
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        HIP_TRY(hipFree(buf.p), "hipFree");
+        buf.p = nullptr;
+        buf.bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)256);
+    if (hipMalloc(&buf.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        buf.p = nullptr;
+        return fail(DAMAS_ENOMEM, "cannot allocate %zu bytes for %s", want, what);
+    }
+    buf.bytes = want;
+    (void)ctx;
+    return DAMAS_OK;
+}
+
+int pop_events(damas_ctx *ctx, std::pair<hipEvent_t, hipEvent_t> *ev)
+{
+    if (!ctx->event_pool.empty()) {
+        *ev = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return DAMAS_OK;
+    }
+    HIP_TRY(hipEventCreate(&ev->first), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&ev->second), "hipEventCreate");
+    return DAMAS_OK;
+}
+
+} // namespace
+
+extern "C" int damas_ctx_create(int32_t device, damas_ctx **out)
+{
+    if (!out)
+        return fail(DAMAS_EINVAL, "out is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    if (device < 0 || device >= n)
+        return fail(DAMAS_EINVAL, "device %d outside [0, %d)", device, n);
+    HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    damas_ctx *c = new (std::nothrow) damas_ctx();
+    if (!c)
+        return fail(DAMAS_ENOMEM, "context allocation");
+    c->device = device;
+    if (hipEventCreateWithFlags(&c->kc_done, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return fail(DAMAS_EDEVICE, "hipEventCreate");
+    }
+    *out = c;
+    return DAMAS_OK;
+}
+
+extern "C" void damas_ctx_destroy(damas_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A})
+        if (b->p)
+            (void)hipFree(b->p);
+    if (ctx->kc_pinned)
+        (void)hipHostFree(ctx->kc_pinned);
+    if (ctx->kc_done)
+        (void)hipEventDestroy(ctx->kc_done);
+    for (auto *v : {&ctx->gs_events, &ctx->event_pool})
+        for (auto &e : *v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    delete ctx;
+}
+
+extern "C" int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled)
+{
+    if (!ctx)
+        return fail(DAMAS_EINVAL, "ctx is NULL");
+    ctx->timing = enabled != 0;
+    return DAMAS_OK;
+}
+
+extern "C" int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches)
+{
+    if (!ctx || !ms || !launches)
+        return fail(DAMAS_EINVAL, "NULL argument");
+    double total = 0.0;
+    int64_t n = 0;
+    for (auto &e : ctx->gs_events) {
+        HIP_TRY(hipEventSynchronize(e.second), "hipEventSynchronize");
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e.first, e.second), "hipEventElapsedTime");
+        total += t;
+        ++n;
+        ctx->event_pool.push_back(e);
+    }
+    ctx->gs_events.clear();
+    *ms = total;
+    *launches = n;
+    return DAMAS_OK;
+}
+
+extern "C" int damas_check(damas_ctx *ctx, void *stream)
+{
+    if (ctx)
+        HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    int *fault;
+    int rc = fault_word(&fault);
+    if (rc)
+        return rc;
+    int v = 0;
+    HIP_TRY(hipMemcpy(&v, fault, sizeof v, hipMemcpyDeviceToHost), "read fault word");
+    if (v) {
+        HIP_TRY(hipMemset(fault, 0, sizeof(int)), "clear fault word");
+        return fail(DAMAS_ECAPACITY,
+                    "a bin kept more points than max_kept (fault bits 0x%x)", v);
+    }
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
+                               int32_t n_bins, const double *freq,
+                               const double *csm, const damas_params *p,
+                               const void *x_init, void *x_map, double *b_map,
+                               int32_t *idx, int32_t *s_tilde, void *stream)
+{
+    if (!ctx)
+        return fail(DAMAS_EINVAL, "ctx is NULL");
+    int rc = check_geometry(g);
+    if (rc)
+        return rc;
+    if (!p)
+        return fail(DAMAS_EINVAL, "params are NULL");
+    if ((rc = check_mode(p->select_mode, p->eps)) || (rc = check_precision(p->precision)))
+        return rc;
+    if (n_bins < 0 || p->iterations < 0)
+        return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
+    if (n_bins == 0)
+        return DAMAS_OK;
+    if (!freq || !csm || !x_map)
+        return fail(DAMAS_EINVAL, "freq, csm and x_map must be non-NULL");
+    const int32_t N = g->N, M = g->M;
+    const int32_t S = N * N;
+    const int n0 = coarse_count(N);
+
+    // Kept points per bin, where the host can know them.
+    std::vector<int32_t> st_host;
+    int32_t max_kept = 0;
+    if (p->select_mode == DAMAS_SEL_KEEP_ALL) {
+        max_kept = S;
+        st_host.assign(n_bins, S);
+    } else if (p->select_mode == DAMAS_SEL_KEEP_COUNT) {
+        st_host.resize(n_bins);
+        for (int f = 0; f < n_bins; ++f) {
+            int32_t K = p->keep_count ? p->keep_count[f] : p->keep_count_all;
+            if (K < 0)
+                return fail(DAMAS_EINVAL, "keep_count[%d] = %d < 0", f, K);
+            st_host[f] = std::min(std::max(K, (int32_t)n0), S);
+            max_kept = std::max(max_kept, st_host[f]);
+        }
+    } else {
+        max_kept = p->max_kept > 0 ? std::min(p->max_kept, S) : S;
+    }
+    if ((rc = check_kept(max_kept, S, p->precision)))
+        return rc;
+
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = elem_size(p->precision);
+    const bool batched = p->batched != 0;
+    const int64_t ldm = ld_of(max_kept);
+    const int64_t e_stride = ldm * 2 * M;
+    int64_t a_elems = 0;
+    if (!batched) {
+        a_elems = ldm * ldm;
+    } else if (!st_host.empty()) {
+        for (int32_t v : st_host)
+            a_elems += ld_of(v) * ld_of(v);
+    } else {
+        a_elems = (int64_t)n_bins * ldm * ldm;
+    }
+    const int nb_ws = batched ? n_bins : 1;
+
+    if (!b_map && (rc = ensure(ctx, ctx->b, sizeof(double) * (size_t)n_bins * S, s, "b")))
+        return rc;
+    if (!idx && (rc = ensure(ctx, ctx->idx, sizeof(int32_t) * (size_t)n_bins * S, s, "idx")))
+        return rc;
+    if (!s_tilde && (rc = ensure(ctx, ctx->st, sizeof(int32_t) * (size_t)n_bins, s, "s_tilde")))
+        return rc;
+    if ((rc = ensure(ctx, ctx->off, sizeof(int64_t) * (size_t)(nb_ws + 1), s, "offsets")) ||
+        (rc = ensure(ctx, ctx->E, sizeof(double) * (size_t)e_stride * nb_ws, s,
+                     "steering rows")) ||
+        (rc = ensure(ctx, ctx->A, es * (size_t)a_elems, s, "A arena")))
+        return rc;
+    double *bm = b_map ? b_map : (double *)ctx->b.p;
+    int32_t *ix = idx ? idx : (int32_t *)ctx->idx.p;
+    int32_t *st = s_tilde ? s_tilde : (int32_t *)ctx->st.p;
+    int64_t *off = (int64_t *)ctx->off.p;
+
+    const int32_t *kc = nullptr;
+    if (p->select_mode == DAMAS_SEL_KEEP_COUNT) {
+        std::vector<int32_t> want(n_bins);
+        for (int f = 0; f < n_bins; ++f)
+            want[f] = p->keep_count ? p->keep_count[f] : p->keep_count_all;
+        if (want != ctx->kc_host) {
+            if ((rc = ensure(ctx, ctx->kc, sizeof(int32_t) * (size_t)n_bins, s, "keep counts")))
+                return rc;
+            // The staging buffer may still feed the previous upload.
+            HIP_TRY(hipEventSynchronize(ctx->kc_done), "hipEventSynchronize");
+            if (ctx->kc_pinned_n < (size_t)n_bins) {
+                if (ctx->kc_pinned)
+                    HIP_TRY(hipHostFree(ctx->kc_pinned), "hipHostFree");
+                ctx->kc_pinned = nullptr;
+                ctx->kc_pinned_n = 0;
+                HIP_TRY(hipHostMalloc((void **)&ctx->kc_pinned, sizeof(int32_t) * n_bins),
+                        "hipHostMalloc");
+                ctx->kc_pinned_n = n_bins;
+            }
+            memcpy(ctx->kc_pinned, want.data(), sizeof(int32_t) * n_bins);
+            HIP_TRY(hipMemcpyAsync(ctx->kc.p, ctx->kc_pinned, sizeof(int32_t) * n_bins,
+                                   hipMemcpyHostToDevice, s),
+                    "upload keep counts");
+            HIP_TRY(hipEventRecord(ctx->kc_done, s), "hipEventRecord");
+            ctx->kc_host = want;
+        }
+        kc = (const int32_t *)ctx->kc.p;
+    }
+
+    int *fault;
+    if ((rc = fault_word(&fault)))
+        return rc;
+    const Geom kg = make_geom(*g);
+
+    if (batched) {
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (ctx->timing && (rc = pop_events(ctx, &ev)))
+            return rc;
+        HIP_TRY(launch_das(kg, n_bins, freq, csm, bm, s), "das launch");
+        HIP_TRY(launch_select(N, n_bins, bm, p->select_mode, p->eps, kc, ix, st, s),
+                "select launch");
+        HIP_TRY(launch_layout(n_bins, st, max_kept, a_elems, off, fault, s),
+                "layout launch");
+        HIP_TRY(launch_steer(kg, n_bins, freq, ix, st, max_kept, (double *)ctx->E.p,
+                             e_stride, fault, s),
+                "steer launch");
+        HIP_TRY(launch_psf(M, n_bins, st, max_kept, p->precision, (const double *)ctx->E.p,
+                           e_stride, off, ctx->A.p, fault, s),
+                "psf launch");
+        if (ctx->timing)
+            HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
+        HIP_TRY(launch_gs(N, n_bins, st, max_kept, ix, off, p->precision, ctx->A.p,
+                          bm, p->iterations, x_init, x_map, fault, s),
+                "gs launch");
+        if (ctx->timing) {
+            HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
+            ctx->gs_events.push_back(ev);
+        }
+        return DAMAS_OK;
+    }
+
+    // Plain: each bin on its own, one launch per step; A, E and the layout
+    // are reused from bin to bin.
+    for (int f = 0; f < n_bins; ++f) {
+        const int32_t mk = st_host.empty() ? max_kept : st_host[f];
+        const size_t fS = (size_t)f * S;
+        const char *xi = x_init ? (const char *)x_init + es * fS : nullptr;
+        char *xm = (char *)x_map + es * fS;
+        HIP_TRY(launch_das(kg, 1, freq + f, csm + (size_t)f * M * M * 2, bm + fS, s),
+                "das launch");
+        HIP_TRY(launch_select(N, 1, bm + fS, p->select_mode, p->eps, kc ? kc + f : nullptr,
+                              ix + fS, st + f, s),
+                "select launch");
+        HIP_TRY(launch_layout(1, st + f, mk, a_elems, off, fault, s), "layout launch");
+        HIP_TRY(launch_steer(kg, 1, freq + f, ix + fS, st + f, mk, (double *)ctx->E.p,
+                             e_stride, fault, s),
+                "steer launch");
+        HIP_TRY(launch_psf(M, 1, st + f, mk, p->precision, (const double *)ctx->E.p,
+                           e_stride, off, ctx->A.p, fault, s),
+                "psf launch");
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (ctx->timing) {
+            if ((rc = pop_events(ctx, &ev)))
+                return rc;
+            HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
+        }
+        HIP_TRY(launch_gs(N, 1, st + f, mk, ix + fS, off, p->precision, ctx->A.p,
+                          bm + fS, p->iterations, xi, xm, fault, s),
+                "gs launch");
+        if (ctx->timing) {
+            HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
+            ctx->gs_events.push_back(ev);
+        }
+    }
+    return DAMAS_OK;
+}

@@ -1,0 +1,103 @@
+// Shared declarations of the HIP library: kernel-side geometry, small
+// device helpers and the host launchers of every kernel.  gfx950 only
+// (wave64, MFMA, 160 KB LDS per CU).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "damas.h"
+
+namespace damas {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Geometry passed by value to kernels (section "Beamforming").
+struct Geom {
+    int M;
+    const double *mic; // device, M x 3
+    int N;
+    double x0, dx, y0, dy, z0;
+    double c;
+};
+
+inline Geom make_geom(const damas_geometry &g)
+{
+    Geom k;
+    k.M = g.M;
+    k.mic = g.mic;
+    k.N = g.N;
+    k.x0 = g.x0;
+    k.y0 = g.y0;
+    k.dx = g.N > 1 ? (g.x1 - g.x0) / (double)(g.N - 1) : 0.0;
+    k.dy = g.N > 1 ? (g.y1 - g.y0) / (double)(g.N - 1) : 0.0;
+    k.z0 = g.z0;
+    k.c = g.c;
+    return k;
+}
+
+// Row stride of a compressed system: s_tilde rounded up to 8 elements.
+__host__ __device__ inline int64_t ld_of(int32_t st) { return ((int64_t)st + 7) & ~(int64_t)7; }
+
+// Distance from grid point n to microphone m, in double.
+__device__ inline double point_mic_dist(const Geom &g, int n, int m)
+{
+    int ix = n % g.N, iy = n / g.N;
+    double px = g.x0 + (double)ix * g.dx;
+    double py = g.y0 + (double)iy * g.dy;
+    double ddx = px - g.mic[3 * m + 0];
+    double ddy = py - g.mic[3 * m + 1];
+    double ddz = g.z0 - g.mic[3 * m + 2];
+    return sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+}
+
+// Lane-uniform broadcast of lane `src` (wave64); src must be uniform.
+__device__ inline float lane_bcast(float v, int src)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ inline double lane_bcast(double v, int src)
+{
+    long long u = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
+    int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---- launchers (each returns the launch status) ------------------------
+// fault: device word set non-zero by a kernel that met a capacity violation.
+
+hipError_t launch_das(const Geom &g, int n_bins, const double *freq,
+                      const double *csm, double *b, hipStream_t s);
+
+hipError_t launch_select(int N, int n_bins, const double *b, int mode,
+                         double eps, const int32_t *keep_count, int32_t *idx,
+                         int32_t *s_tilde, hipStream_t s);
+
+hipError_t launch_layout(int n_bins, int32_t *s_tilde, int max_kept,
+                         int64_t capacity, int64_t *off, int *fault,
+                         hipStream_t s);
+
+// Lift the dynamic-LDS limit of a kernel to the whole 160 KB of a CU
+// (once per kernel).
+hipError_t allow_big_lds(const void *kernel);
+
+hipError_t launch_steer(const Geom &g, int n_bins, const double *freq,
+                        const int32_t *idx, const int32_t *s_tilde,
+                        int max_kept, double *E, int64_t e_stride, int *fault,
+                        hipStream_t s);
+
+hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
+                      int precision, const double *E, int64_t e_stride,
+                      const int64_t *off, void *A, int *fault, hipStream_t s);
+
+hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
+                     const int32_t *idx, const int64_t *off, int precision,
+                     const void *A, const double *b, int iterations,
+                     const void *x_init, void *x_map, int *fault,
+                     hipStream_t s);
+
+// Largest s_tilde the sweep kernel holds on chip for a precision.
+int gs_max_kept(int precision);
+
+} // namespace damas

@@ -1,0 +1,96 @@
+// Delay-and-sum beamforming map (section "Beamforming", Eq. dirty_map_1):
+// b_n = Re(e_n^H C e_n) / M^2 at every grid point of every bin, in double.
+//
+// One workgroup = one bin x 64 grid points; lane = grid point.  The 64
+// steering vectors of the tile are built once into LDS (M x 64 complex
+// doubles, mic-major so a wave reads 64 consecutive points).  Wave w takes
+// CSM rows m = w, w+4, ...; a CSM row is wave-uniform, so its entries come
+// through the scalar cache while LDS feeds the per-lane steering values.
+#include "common.h"
+
+namespace damas {
+
+constexpr int kDasPts = 64;
+constexpr int kDasThreads = 256;
+
+__global__ __launch_bounds__(kDasThreads) void das_kernel(
+    Geom g, int S, const double *__restrict__ freq,
+    const double *__restrict__ csm, double *__restrict__ b)
+{
+    extern __shared__ double2 sh_e[]; // [M][64]: (cos, -sin) of k d
+    __shared__ double part[kDasThreads / 64][kDasPts];
+
+    const int f = blockIdx.y;
+    const int p0 = blockIdx.x * kDasPts;
+    const int M = g.M;
+    const double k = kTwoPi * freq[f] / g.c;
+
+    for (int t = threadIdx.x; t < M * kDasPts; t += kDasThreads) {
+        int m = t / kDasPts, p = t % kDasPts;
+        int n = p0 + p;
+        double2 e = make_double2(0.0, 0.0);
+        if (n < S) {
+            double s, c;
+            sincos(k * point_mic_dist(g, n, m), &s, &c);
+            e = make_double2(c, -s);
+        }
+        sh_e[m * kDasPts + p] = e;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const double *C = csm + (size_t)f * M * M * 2;
+    double acc = 0.0;
+    // Two CSM rows per pass so each steering value read from LDS feeds
+    // eight multiply-adds.
+    for (int m = w; m < M; m += 8) {
+        const bool two = m + 4 < M;
+        const double *c0 = C + (size_t)m * M * 2;
+        const double *c1 = C + (size_t)(two ? m + 4 : m) * M * 2;
+        double y0r = 0.0, y0i = 0.0, y1r = 0.0, y1i = 0.0;
+        for (int mp = 0; mp < M; ++mp) {
+            double2 e = sh_e[mp * kDasPts + lane];
+            double ar = c0[2 * mp], ai = c0[2 * mp + 1];
+            double br = c1[2 * mp], bi = c1[2 * mp + 1];
+            y0r += ar * e.x - ai * e.y;
+            y0i += ar * e.y + ai * e.x;
+            y1r += br * e.x - bi * e.y;
+            y1i += br * e.y + bi * e.x;
+        }
+        // Re(conj(e_m) y_m) = er*yr + ei*yi
+        double2 e0 = sh_e[m * kDasPts + lane];
+        acc += e0.x * y0r + e0.y * y0i;
+        if (two) {
+            double2 e1 = sh_e[(m + 4) * kDasPts + lane];
+            acc += e1.x * y1r + e1.y * y1i;
+        }
+    }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < kDasPts) {
+        int n = p0 + lane;
+        if (n < S) {
+            double s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+            b[(size_t)f * S + n] = s / ((double)M * (double)M);
+        }
+    }
+}
+
+hipError_t launch_das(const Geom &g, int n_bins, const double *freq,
+                      const double *csm, double *b, hipStream_t s)
+{
+    const int S = g.N * g.N;
+    if (n_bins == 0 || S == 0)
+        return hipSuccess;
+    dim3 grid((S + kDasPts - 1) / kDasPts, n_bins);
+    size_t lds = sizeof(double2) * (size_t)g.M * kDasPts;
+    static const hipError_t attr = allow_big_lds((const void *)das_kernel);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL(das_kernel, grid, dim3(kDasThreads), lds, s, g, S, freq,
+                       csm, b);
+    return hipGetLastError();
+}
+
+} // namespace damas

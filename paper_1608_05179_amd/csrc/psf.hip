@@ -1,0 +1,233 @@
+// Steering rows of the kept points and the point-spread matrix over them
+// (section "DAMAS": PSF(r|r_s) = |v(r)^H g_{r_s}|^2 / M^2 arranged as A of
+// Eq. Axb, restricted to the compressed grid as in Eq. Axb_CG).
+//
+// With unit-magnitude steering e_m = er_m + i ei_m the complex Gram entry
+// G_ij = sum_m conj(e_im) e_jm splits into two real products over the mics:
+//   Re G = Er_I Er_J^T + Ei_I Ei_J^T,   Im G = Er_I Ei_J^T - Ei_I Er_J^T,
+// and A_ij = ((Re G)^2 + (Im G)^2) / M^2.  Both products run on the matrix
+// cores (16x16x4 f64 MFMA); A is formed in double and rounded once to its
+// storage type.  A is symmetric, so only tiles I <= J are computed and each
+// value is written to (i,j) and (j,i).
+#include "common.h"
+
+namespace damas {
+
+// ---------------------------------------------------------------------------
+// Steering rows (double): E[f][i] = [cos(k d_0..M-1), -sin(k d_0..M-1)] for
+// the kept points i < s_tilde, zero for the padding rows up to ld.
+
+__global__ __launch_bounds__(256) void steer_kernel(
+    Geom g, const double *__restrict__ freq, const int32_t *__restrict__ idx,
+    const int32_t *__restrict__ s_tilde, int max_kept, double *__restrict__ E,
+    int64_t e_stride, int *fault)
+{
+    const int f = blockIdx.y;
+    int St = s_tilde[f];
+    if (St > max_kept) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(fault, 1);
+        St = 0;
+    }
+    const int64_t ld = ld_of(St);
+    const int M = g.M;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / M;
+    const int m = (int)(t % M);
+    if (i >= ld)
+        return;
+    double *row = E + (int64_t)f * e_stride + i * 2 * M;
+    if (i < St) {
+        const int S = g.N * g.N;
+        const int n = idx[(int64_t)f * S + i];
+        const double k = kTwoPi * freq[f] / g.c;
+        double s, c;
+        sincos(k * point_mic_dist(g, n, m), &s, &c);
+        row[m] = c;
+        row[M + m] = -s;
+    } else {
+        row[m] = 0.0;
+        row[M + m] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA tile of A: f64 16x16x4 products (steering in double), stored as TS.
+//
+// Operand layout of v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][k] and
+// B[k][l % 16] with k = l / 16; accumulator element v of lane l holds
+// D[l / 16 + 4 v][l % 16].  The k index may be any permutation of the mics
+// as long as both operands use the same one: each lane reads two
+// consecutive mics (16 bytes) and feeds them to two successive MFMAs.
+
+typedef double dacc4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPsfTile = 64;
+constexpr int kPsfThreads = 256;
+constexpr int kPsfChunk = 32;                // mics staged in LDS at a time
+constexpr int kPsfPitch = kPsfChunk + 2;     // doubles per LDS row
+
+__device__ inline dacc4 mma64(double a, double b, dacc4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename TS>
+__global__ __launch_bounds__(kPsfThreads) void psf_kernel(
+    int M, const int32_t *__restrict__ s_tilde, int max_kept,
+    const double *__restrict__ E, int64_t e_stride,
+    const int64_t *__restrict__ off, TS *__restrict__ A, int *fault)
+{
+    __shared__ double erI[kPsfTile * kPsfPitch];
+    __shared__ double eiI[kPsfTile * kPsfPitch];
+    __shared__ double erJ[kPsfTile * kPsfPitch];
+    __shared__ double eiJ[kPsfTile * kPsfPitch];
+
+    const int f = blockIdx.y;
+    const int St = s_tilde[f];
+    if (St > max_kept) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(fault, 2);
+        return;
+    }
+    const int64_t ld = ld_of(St);
+    const int nt = (int)((ld + kPsfTile - 1) / kPsfTile);
+    const int t = blockIdx.x;
+    if (t >= nt * (nt + 1) / 2)
+        return;
+    // Upper-triangle tile (I <= J), J-major numbering t = J(J+1)/2 + I.
+    int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (J * (J + 1) / 2 > t)
+        --J;
+    while ((J + 1) * (J + 2) / 2 <= t)
+        ++J;
+    const int I = t - J * (J + 1) / 2;
+    const int64_t I0 = (int64_t)I * kPsfTile, J0 = (int64_t)J * kPsfTile;
+
+    const double *Ef = E + (int64_t)f * e_stride;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int wr = w >> 1, wc = w & 1; // 32 x 32 quadrant of the tile
+    const int lr = lane & 15, lg = lane >> 4;
+
+    dacc4 re[2][2], im[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c) {
+            re[a][c] = dacc4{0, 0, 0, 0};
+            im[a][c] = dacc4{0, 0, 0, 0};
+        }
+
+    for (int mc = 0; mc < M; mc += kPsfChunk) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kPsfTile * kPsfChunk; e += kPsfThreads) {
+            const int r = e / kPsfChunk, mm = e % kPsfChunk, m = mc + mm;
+            double vrI = 0, viI = 0, vrJ = 0, viJ = 0;
+            if (m < M) {
+                if (I0 + r < ld) {
+                    const double *row = Ef + (I0 + r) * 2 * M;
+                    vrI = row[m];
+                    viI = row[M + m];
+                }
+                if (J0 + r < ld) {
+                    const double *row = Ef + (J0 + r) * 2 * M;
+                    vrJ = row[m];
+                    viJ = row[M + m];
+                }
+            }
+            erI[r * kPsfPitch + mm] = vrI;
+            eiI[r * kPsfPitch + mm] = viI;
+            erJ[r * kPsfPitch + mm] = vrJ;
+            eiJ[r * kPsfPitch + mm] = viJ;
+        }
+        __syncthreads();
+        const int mlen = min(kPsfChunk, M - mc);
+        // Groups of 8 mics: lane group lg reads mics [m8 + 2 lg, m8 + 2 lg + 2).
+        for (int m8 = 0; m8 < mlen; m8 += 8) {
+            double2 ar[2], ai[2], br[2], bi[2];
+            const int col = m8 + 2 * lg;
+            for (int a = 0; a < 2; ++a) {
+                const int r = wr * 32 + a * 16 + lr;
+                ar[a] = *reinterpret_cast<const double2 *>(&erI[r * kPsfPitch + col]);
+                ai[a] = *reinterpret_cast<const double2 *>(&eiI[r * kPsfPitch + col]);
+            }
+            for (int c = 0; c < 2; ++c) {
+                const int r = wc * 32 + c * 16 + lr;
+                br[c] = *reinterpret_cast<const double2 *>(&erJ[r * kPsfPitch + col]);
+                bi[c] = *reinterpret_cast<const double2 *>(&eiJ[r * kPsfPitch + col]);
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const double xr = s ? ar[a].y : ar[a].x;
+                    const double xi = s ? ai[a].y : ai[a].x;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const double yr = s ? br[c].y : br[c].x;
+                        const double yi = s ? bi[c].y : bi[c].x;
+                        re[a][c] = mma64(xr, yr, re[a][c]);
+                        re[a][c] = mma64(xi, yi, re[a][c]);
+                        im[a][c] = mma64(xr, yi, im[a][c]);
+                        im[a][c] = mma64(-xi, yr, im[a][c]);
+                    }
+                }
+            }
+        }
+    }
+
+    // Epilogue: A = (Re^2 + Im^2) / M^2 in double, rounded once to TS,
+    // mirrored; unit diagonal.
+    TS *Af = A + off[f];
+    const double inv = 1.0 / ((double)M * (double)M);
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c)
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = I0 + wr * 32 + a * 16 + lg + 4 * v;
+                const int64_t colj = J0 + wc * 32 + c * 16 + lr;
+                if (row >= ld || colj >= ld)
+                    continue;
+                const double x = re[a][c][v], y = im[a][c][v];
+                const TS val = (TS)((x * x + y * y) * inv);
+                // Tiles with I < J have every column beyond every row; on
+                // diagonal tiles the lower half is the mirror of the upper.
+                if (colj > row) {
+                    Af[row * ld + colj] = val;
+                    Af[colj * ld + row] = val;
+                } else if (colj == row) {
+                    Af[row * ld + row] = row < St ? (TS)1 : (TS)0;
+                }
+            }
+}
+
+hipError_t launch_steer(const Geom &g, int n_bins, const double *freq,
+                        const int32_t *idx, const int32_t *s_tilde,
+                        int max_kept, double *E, int64_t e_stride, int *fault,
+                        hipStream_t s)
+{
+    if (n_bins == 0 || max_kept == 0)
+        return hipSuccess;
+    const int64_t work = ld_of(max_kept) * g.M;
+    dim3 grid((unsigned)((work + 255) / 256), n_bins);
+    hipLaunchKernelGGL(steer_kernel, grid, dim3(256), 0, s, g, freq, idx, s_tilde,
+                       max_kept, E, e_stride, fault);
+    return hipGetLastError();
+}
+
+hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
+                      int precision, const double *E, int64_t e_stride,
+                      const int64_t *off, void *A, int *fault, hipStream_t s)
+{
+    if (n_bins == 0 || max_kept == 0)
+        return hipSuccess;
+    const int64_t nt = (ld_of(max_kept) + kPsfTile - 1) / kPsfTile;
+    dim3 grid((unsigned)(nt * (nt + 1) / 2), n_bins);
+    if (precision == DAMAS_PREC_FP64)
+        hipLaunchKernelGGL(psf_kernel<double>, grid, dim3(kPsfThreads), 0, s, M,
+                           s_tilde, max_kept, E, e_stride, off, (double *)A, fault);
+    else
+        hipLaunchKernelGGL(psf_kernel<float>, grid, dim3(kPsfThreads), 0, s, M,
+                           s_tilde, max_kept, E, e_stride, off, (float *)A, fault);
+    return hipGetLastError();
+}
+
+} // namespace damas

@@ -1,0 +1,305 @@
+"""Thin ctypes binding of ``libdamas_hip.so`` (C ABI in ``include/damas.h``).
+
+Argument marshalling only: torch tensors supply device memory and torch's
+current HIP stream; every step of the path runs in the library's kernels.
+There is no fallback: if the library is missing, importing this module
+fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdamas_hip.so")
+
+OK = 0
+EINVAL = -1
+ENOMEM = -2
+EDEVICE = -3
+EADMIT = -4
+EBUSY = -5
+ETIMEDOUT = -6
+ECAPACITY = -7
+
+SEL_KEEP_ALL = 0
+SEL_EPS_REL = 1
+SEL_KEEP_COUNT = 2
+
+PREC_FP64 = 0
+PREC_FP32 = 1
+
+_DTYPE = {PREC_FP64: torch.float64, PREC_FP32: torch.float32}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+        " (or python paper_1608_05179_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class Geometry(ctypes.Structure):
+    """damas_geometry: M mics (device M x 3 doubles), N x N scan grid on the
+    plane z = z0 spanning [x0, x1] x [y0, y1], speed of sound c."""
+    _fields_ = [("M", c_i32), ("mic", c_vp), ("N", c_i32), ("x0", c_dbl),
+                ("x1", c_dbl), ("y0", c_dbl), ("y1", c_dbl), ("z0", c_dbl),
+                ("c", c_dbl)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("select_mode", c_i32), ("eps", c_dbl),
+                ("keep_count", ctypes.POINTER(c_i32)), ("keep_count_all", c_i32),
+                ("iterations", c_i32), ("precision", c_i32), ("batched", c_i32),
+                ("max_kept", c_i32)]
+
+
+def _sig(name, res, *args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = list(args)
+    return fn
+
+
+_sig("damas_strerror", ctypes.c_char_p, ctypes.c_int)
+_sig("damas_last_error", ctypes.c_char_p)
+_sig("damas_ld", c_i64, c_i32)
+_sig("damas_coarse_count", c_i32, c_i32)
+_G = ctypes.POINTER(Geometry)
+_sig("damas_das_map", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_vp)
+_sig("damas_select", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp, c_vp)
+_sig("damas_layout", ctypes.c_int, c_i32, c_vp, c_i32, c_i64, c_vp, c_vp)
+_sig("damas_steer", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i64, c_vp)
+_sig("damas_psf", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp)
+_sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp,
+     c_i32, c_vp, c_vp, c_vp)
+_sig("damas_ctx_create", ctypes.c_int, c_i32, ctypes.POINTER(c_vp))
+_sig("damas_ctx_destroy", None, c_vp)
+_sig("damas_ctx_set_timing", ctypes.c_int, c_vp, c_i32)
+_sig("damas_ctx_gs_time", ctypes.c_int, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64))
+_sig("damas_solve_dev", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
+     c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
+_sig("damas_check", ctypes.c_int, c_vp, c_vp)
+
+
+class DamasError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.damas_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise DamasError(rc, _lib.damas_last_error().decode())
+
+
+def strerror(code: int) -> str:
+    return _lib.damas_strerror(code).decode()
+
+
+def last_error() -> str:
+    return _lib.damas_last_error().decode()
+
+
+def ld(s_tilde: int) -> int:
+    """Row stride of a compressed system with s_tilde unknowns."""
+    return int(_lib.damas_ld(int(s_tilde)))
+
+
+def coarse_count(N: int) -> int:
+    """Points of the coarsest grid G^0, always kept."""
+    return int(_lib.damas_coarse_count(int(N)))
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def geometry(mic: torch.Tensor, N: int, x0: float, x1: float, y0: float,
+             y1: float, z0: float, c: float = 343.0) -> Geometry:
+    """Build a damas_geometry; ``mic`` is a device tensor (M, 3) float64 that
+    the caller keeps alive while the geometry is in use."""
+    if mic.dim() != 2 or mic.shape[1] != 3:
+        raise ValueError("mic must have shape (M, 3)")
+    return Geometry(mic.shape[0], _ptr(mic, torch.float64, "mic"), int(N), float(x0),
+                    float(x1), float(y0), float(y1), float(z0), float(c))
+
+
+# ---- step-level calls ------------------------------------------------------
+
+def das_map(g: Geometry, freq, csm, b=None, stream=None):
+    """b[f, n] = Re(e_n^H C_f e_n) / M^2 (float64, n_bins x N*N).
+    csm: complex128 (n_bins, M, M) or float64 (n_bins, M, M, 2)."""
+    csm = _as_interleaved(csm)
+    nb = freq.numel()
+    if b is None:
+        b = torch.empty(nb, g.N * g.N, dtype=torch.float64, device=freq.device)
+    _check(_lib.damas_das_map(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
+                              _ptr(csm, torch.float64, "csm"),
+                              _ptr(b, torch.float64, "b"), _stream(stream)))
+    return b
+
+
+def select(N: int, b, mode: int, eps: float = 0.0, keep_count=None, stream=None):
+    """Algorithm 1: returns (idx int32 (n_bins, N*N), s_tilde int32 (n_bins))."""
+    nb = b.shape[0]
+    idx = torch.zeros(nb, N * N, dtype=torch.int32, device=b.device)
+    st = torch.zeros(nb, dtype=torch.int32, device=b.device)
+    _check(_lib.damas_select(int(N), nb, _ptr(b, torch.float64, "b"), int(mode), float(eps),
+                             _ptr(keep_count, torch.int32, "keep_count"),
+                             _ptr(idx, torch.int32, "idx"), _ptr(st, torch.int32, "s_tilde"),
+                             _stream(stream)))
+    return idx, st
+
+
+def layout(s_tilde, max_kept: int, capacity: int = 2 ** 62, stream=None):
+    """Offsets (int64, n_bins + 1) of the packed per-bin systems; bins over
+    max_kept or past `capacity` elements get s_tilde = 0 (in place)."""
+    nb = s_tilde.numel()
+    off = torch.zeros(nb + 1, dtype=torch.int64, device=s_tilde.device)
+    _check(_lib.damas_layout(nb, _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
+                             int(capacity), _ptr(off, torch.int64, "off"), _stream(stream)))
+    return off
+
+
+def steer(g: Geometry, freq, idx, s_tilde, max_kept: int, stream=None):
+    """Steering rows of the kept points, double: (n_bins, ld(max_kept), 2M)."""
+    nb = freq.numel()
+    L = ld(max_kept)
+    E = torch.zeros(nb, L, 2 * g.M, dtype=torch.float64, device=freq.device)
+    _check(_lib.damas_steer(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
+                            _ptr(idx, torch.int32, "idx"), _ptr(s_tilde, torch.int32, "s_tilde"),
+                            int(max_kept), _ptr(E, torch.float64, "E"), L * 2 * g.M,
+                            _stream(stream)))
+    return E
+
+
+def psf(M: int, s_tilde, max_kept: int, precision: int, E, off, A=None, stream=None):
+    """Packed A arena of all bins (flat tensor, off[-1] elements)."""
+    nb = s_tilde.numel()
+    if A is None:
+        total = int(off[-1].item())
+        A = torch.full((max(total, 1),), float("nan"), dtype=_DTYPE[precision],
+                       device=off.device)
+    _check(_lib.damas_psf(int(M), nb, _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
+                          int(precision), _ptr(E, torch.float64, "E"),
+                          E.shape[1] * E.shape[2], _ptr(off, torch.int64, "off"),
+                          _ptr(A, _DTYPE[precision], "A"), _stream(stream)))
+    return A
+
+
+def gs(N: int, s_tilde, max_kept: int, idx, off, precision: int, A, b, iterations: int,
+       x_init=None, x_map=None, stream=None):
+    """Non-negative Gauss-Seidel sweeps; returns x_map (n_bins, N*N)."""
+    nb = s_tilde.numel()
+    dt = _DTYPE[precision]
+    if x_map is None:
+        x_map = torch.empty(nb, N * N, dtype=dt, device=b.device)
+    _check(_lib.damas_gs(int(N), nb, _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
+                         _ptr(idx, torch.int32, "idx"), _ptr(off, torch.int64, "off"),
+                         int(precision), _ptr(A, dt, "A"), _ptr(b, torch.float64, "b"),
+                         int(iterations), _ptr(x_init, dt, "x_init"),
+                         _ptr(x_map, dt, "x_map"), _stream(stream)))
+    return x_map
+
+
+def check(ctx=None, stream=None):
+    """Synchronise and report device-side capacity failures."""
+    _check(_lib.damas_check(ctx._h if ctx is not None else None, _stream(stream)))
+
+
+# ---- the whole path ----------------------------------------------------------
+
+class Context:
+    """damas_ctx: the device workspace of whole-path solves."""
+
+    def __init__(self, device: int = 0):
+        h = c_vp()
+        _check(_lib.damas_ctx_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.damas_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, enabled: bool):
+        _check(_lib.damas_ctx_set_timing(self._h, 1 if enabled else 0))
+
+    def gs_time(self):
+        """(milliseconds, launches) of the timed sweep launches since the
+        last call."""
+        ms, n = c_dbl(), c_i64()
+        _check(_lib.damas_ctx_gs_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def solve(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
+              keep_count=None, iterations=1000, precision=PREC_FP32, batched=True,
+              max_kept=0, x_init=None, x_map=None, b_map=None, idx=None, s_tilde=None,
+              stream=None):
+        """Every step for every bin on the device; returns x_map.
+
+        keep_count: an int, or a sequence of per-bin ints (host values)."""
+        csm = _as_interleaved(csm)
+        nb = freq.numel()
+        S = g.N * g.N
+        if x_map is None:
+            x_map = torch.empty(nb, S, dtype=_DTYPE[precision], device=freq.device)
+        kc_arr = None
+        kc_all = 0
+        if keep_count is not None:
+            if isinstance(keep_count, int):
+                kc_all = keep_count
+            else:
+                vals = [int(v) for v in keep_count]
+                if len(vals) != nb:
+                    raise ValueError("keep_count needs one value per bin")
+                kc_arr = (c_i32 * nb)(*vals)
+        p = Params(int(select_mode), float(eps),
+                   ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
+                   int(kc_all), int(iterations), int(precision), 1 if batched else 0,
+                   int(max_kept))
+        dt = _DTYPE[precision]
+        _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
+                                    _ptr(freq, torch.float64, "freq"),
+                                    _ptr(csm, torch.float64, "csm"), ctypes.byref(p),
+                                    _ptr(x_init, dt, "x_init"), _ptr(x_map, dt, "x_map"),
+                                    _ptr(b_map, torch.float64, "b_map"),
+                                    _ptr(idx, torch.int32, "idx"),
+                                    _ptr(s_tilde, torch.int32, "s_tilde"), _stream(stream)))
+        return x_map
+
+    def check(self, stream=None):
+        check(self, stream)
+
+
+def _as_interleaved(csm):
+    if csm.dtype == torch.complex128:
+        return torch.view_as_real(csm.contiguous()).contiguous()
+    return csm

@@ -17,3 +17,19 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def dm():
+    """The HIP library's binding, on a machine with a GPU."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_1608_05179_amd import damas
+    return damas
+
+
+@pytest.fixture(scope="session")
+def dev(dm):
+    import torch
+    return torch.device("cuda:0")

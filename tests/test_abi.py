@@ -1,0 +1,95 @@
+"""The C ABI library on a machine without a GPU: it loads, exports every
+function include/damas.h declares, and rejects invalid arguments on the host
+(before any device work) with the documented codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "damas.h")
+LIB = os.path.join(ROOT, "paper_1608_05179_amd", "libdamas_hip.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(damas_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1608_05179_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    lib.damas_strerror.restype = ctypes.c_char_p
+    assert lib.damas_strerror(0) == b"success"
+    assert lib.damas_strerror(-1) == b"invalid argument"
+    assert lib.damas_strerror(-7) == b"device-side capacity exceeded"
+    assert lib.damas_strerror(-99) == b"unknown status"
+
+
+def test_layout_helpers(lib):
+    lib.damas_ld.restype = ctypes.c_int64
+    assert [lib.damas_ld(v) for v in (0, 1, 8, 9, 337)] == [0, 8, 8, 16, 344]
+    # |G^0| = 4 unless N is a power of two (then only index 0 of each axis)
+    assert [lib.damas_coarse_count(n) for n in (1, 2, 3, 4, 5, 16, 17, 21, 41, 101)] == \
+        [1, 1, 4, 1, 4, 1, 4, 4, 4, 4]
+
+
+def test_coarse_count_matches_oracle(lib, orc):
+    for N in (1, 2, 3, 7, 8, 9, 33, 50, 64, 101):
+        n0 = sum(orc.level(N, ix, iy)[0] == 0 for ix in range(N) for iy in range(N))
+        assert lib.damas_coarse_count(N) == n0
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    from paper_1608_05179_amd import damas as dm
+    lib.damas_last_error.restype = ctypes.c_char_p
+    G = dm.Geometry
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    # NULL geometry / bad M / bad N / non-positive c
+    assert dm._lib.damas_das_map(None, 1, fake, fake, fake, None) == dm.EINVAL
+    g = G(0, 0x1000, 21, -1, 1, -1, 1, 1.5, 343.0)
+    assert dm._lib.damas_das_map(ctypes.byref(g), 1, fake, fake, fake, None) == dm.EINVAL
+    assert b"M = 0" in lib.damas_last_error()
+    g = G(16, 0x1000, 0, -1, 1, -1, 1, 1.5, 343.0)
+    assert dm._lib.damas_das_map(ctypes.byref(g), 1, fake, fake, fake, None) == dm.EINVAL
+    g = G(16, 0x1000, 21, -1, 1, -1, 1, 1.5, -1.0)
+    assert dm._lib.damas_das_map(ctypes.byref(g), 1, fake, fake, fake, None) == dm.EINVAL
+    g = G(16, 0x1000, 21, -1, 1, -1, float("nan"), 1.5, 343.0)
+    assert dm._lib.damas_das_map(ctypes.byref(g), 1, fake, fake, fake, None) == dm.EINVAL
+    # selection: unknown mode, negative eps, KEEP_COUNT without counts
+    assert dm._lib.damas_select(21, 1, fake, 7, 0.0, None, fake, fake, None) == dm.EINVAL
+    assert dm._lib.damas_select(21, 1, fake, dm.SEL_EPS_REL, -0.1, None, fake, fake, None) == dm.EINVAL
+    assert dm._lib.damas_select(21, 1, fake, dm.SEL_KEEP_COUNT, 0.0, None, fake, fake, None) == dm.EINVAL
+    # sweeps: max_kept beyond the grid, beyond on-chip capacity, bad precision
+    assert dm._lib.damas_gs(21, 1, fake, 442, fake, fake, dm.PREC_FP32, fake, fake, 10,
+                            None, fake, None) == dm.EINVAL
+    assert dm._lib.damas_gs(301, 1, fake, 60000, fake, fake, dm.PREC_FP32, fake, fake, 10,
+                            None, fake, None) == dm.EINVAL
+    assert b"on chip" in lib.damas_last_error()
+    assert dm._lib.damas_gs(21, 1, fake, 100, fake, fake, 9, fake, fake, 10,
+                            None, fake, None) == dm.EINVAL
+    assert dm._lib.damas_gs(21, 1, fake, 100, fake, fake, dm.PREC_FP32, fake, fake, -1,
+                            None, fake, None) == dm.EINVAL
+    # layout and PSF argument checks
+    assert dm._lib.damas_layout(1, None, 10, 100, fake, None) == dm.EINVAL
+    assert dm._lib.damas_psf(0, 1, fake, 10, dm.PREC_FP32, fake, 1000, fake, fake, None) == dm.EINVAL
+    assert dm._lib.damas_psf(16, 2, fake, 10, dm.PREC_FP32, fake, 10, fake, fake, None) == dm.EINVAL
+    # whole-path: NULL context / NULL params
+    assert dm._lib.damas_solve_dev(None, ctypes.byref(G(16, 0x1000, 21, -1, 1, -1, 1, 1, 343.0)),
+                                   1, fake, fake, None, None, fake, None, None, None,
+                                   None) == dm.EINVAL

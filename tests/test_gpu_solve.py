@@ -1,0 +1,126 @@
+"""End-to-end parity of the whole path (damas_solve_dev) with the oracle.
+
+Per bin: the kept indices equal the oracle's whenever the oracle's decision
+margin exceeds 1e-12 (both sides compute b in double but sum in different
+orders), and x agrees within 1e-4 relative L2 (float path) or 1e-9 (double
+path).  The batched launch and the plain per-bin launches give bitwise
+identical maps.
+"""
+import numpy as np
+import pytest
+
+from paper_1608_05179_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dtype)
+
+
+def _run(dm, dev, w, mode, K=0, eps=0.0, prec=None, batched=True, bins=None, max_kept=0):
+    import torch
+    mic = _t(w.mic, torch.float64, dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    freq = _t(w.freqs, torch.float64, dev)
+    csm = _t(w.csm, torch.complex128, dev)
+    nb = w.n_bins
+    st = torch.zeros(nb, dtype=torch.int32, device=dev)
+    idx = torch.zeros(nb, w.S, dtype=torch.int32, device=dev)
+    b = torch.zeros(nb, w.S, dtype=torch.float64, device=dev)
+    prec = dm.PREC_FP32 if prec is None else prec
+    ctx = dm.Context(0)
+    x = ctx.solve(g, freq, csm, select_mode=mode, eps=eps, keep_count=K,
+                  iterations=w.iterations, precision=prec, batched=batched,
+                  b_map=b, idx=idx, s_tilde=st, max_kept=max_kept)
+    ctx.check()
+    out = dict(x=x.double().cpu().numpy(), st=st.cpu().numpy(), idx=idx.cpu().numpy(),
+               b=b.cpu().numpy())
+    ctx.close()
+    return out
+
+
+def _compare(orc, w, r, mode, K=0, eps=0.0, tol=1e-4, bins=None):
+    og = orc.Geometry(w.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    bins = range(w.n_bins) if bins is None else bins
+    worst = 0.0
+    for f in bins:
+        kf = K if isinstance(K, int) else int(K[f])
+        ref = orc.solve_bin(og, w.freqs[f], w.csm[f], mode, eps=eps, keep_count=kf,
+                            iters=w.iterations)
+        assert np.abs(r["b"][f] - ref["b"]).max() <= 1e-12 * np.abs(ref["b"]).max()
+        st = r["st"][f]
+        if ref["margin"] > 1e-12:
+            assert st == len(ref["idx"]), f
+            assert np.array_equal(r["idx"][f, :st], ref["idx"]), f
+        else:
+            pytest.skip(f"bin {f}: oracle decision margin {ref['margin']:.1e} is in the tie zone")
+        nrm = np.linalg.norm(ref["x"])
+        err = np.linalg.norm(r["x"][f] - ref["x"]) / nrm if nrm > 0 else np.abs(r["x"][f]).max()
+        worst = max(worst, err)
+        assert err <= tol, (f, err)
+    return worst
+
+
+def test_plain_fp64_config(orc, dm, dev):
+    # 16-mic disc, 21 x 21 grid, one bin at 4 kHz, exact CSM, 500 sweeps.
+    w = synth.plain_fp64()
+    r = _run(dm, dev, w, dm.SEL_KEEP_ALL, prec=dm.PREC_FP64, batched=False)
+    _compare(orc, w, r, orc.SEL_KEEP_ALL, tol=1e-9)
+    r32 = _run(dm, dev, w, dm.SEL_KEEP_ALL, prec=dm.PREC_FP32)
+    _compare(orc, w, r32, orc.SEL_KEEP_ALL, tol=1e-4)
+
+
+@pytest.mark.parametrize("frac", [0.1, 0.2, 0.3])
+def test_compressed_fp32_bins(orc, dm, dev, frac):
+    # 64-mic spiral, 41 x 41 grid, 1000 sweeps; 6 of the 64 bins (spread over
+    # the band) keep the top fraction of points by wavelet detail.
+    full = synth.compressed_fp32(keep_frac=frac)
+    pick = [0, 13, 27, 40, 52, 63]
+    w = synth.compressed_fp32(keep_frac=frac)
+    w.freqs = full.freqs[pick]
+    w.csm = full.csm[pick]
+    r = _run(dm, dev, w, dm.SEL_KEEP_COUNT, K=w.keep_count)
+    _compare(orc, w, r, orc.SEL_KEEP_COUNT, K=w.keep_count)
+
+
+def test_batched_equals_plain(dm, dev):
+    w = synth.compressed_fp32(n_bins=5, N=33, iterations=60)
+    a = _run(dm, dev, w, dm.SEL_KEEP_COUNT, K=w.keep_count, batched=True)
+    b = _run(dm, dev, w, dm.SEL_KEEP_COUNT, K=w.keep_count, batched=False)
+    assert np.array_equal(a["x"], b["x"])
+    assert np.array_equal(a["idx"], b["idx"])
+
+
+def test_eps_rel_and_uneven_counts(orc, dm, dev):
+    w = synth.compressed_fp32(n_bins=4, N=41, iterations=300)
+    r = _run(dm, dev, w, dm.SEL_EPS_REL, eps=0.02)
+    _compare(orc, w, r, orc.SEL_EPS_REL, eps=0.02)
+    Ks = [4, 50, 401, 900]
+    r = _run(dm, dev, w, dm.SEL_KEEP_COUNT, K=Ks)
+    _compare(orc, w, r, orc.SEL_KEEP_COUNT, K=Ks)
+
+
+def test_eps_rel_capacity_is_reported(dm, dev):
+    import torch
+    w = synth.compressed_fp32(n_bins=2, N=21, iterations=5)
+    mic = _t(w.mic, torch.float64, dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    ctx = dm.Context(0)
+    ctx.solve(g, _t(w.freqs, torch.float64, dev), _t(w.csm, torch.complex128, dev),
+              select_mode=dm.SEL_EPS_REL, eps=0.0, iterations=5, max_kept=10)
+    with pytest.raises(dm.DamasError) as ei:
+        ctx.check()
+    assert ei.value.code == dm.ECAPACITY
+    ctx.check()  # the fault word was cleared
+    ctx.close()
+
+
+def test_bench_workload_sampled(orc, dm, dev):
+    # The benchmarked launch: all 64 bins of the compressed FP32 workload in
+    # one batched solve; four bins checked against the oracle.
+    w = synth.compressed_fp32(keep_frac=0.2)
+    r = _run(dm, dev, w, dm.SEL_KEEP_COUNT, K=w.keep_count)
+    assert (r["st"] == w.keep_count).all()
+    _compare(orc, w, r, orc.SEL_KEEP_COUNT, K=w.keep_count, bins=[0, 21, 42, 63])
