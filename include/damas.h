@@ -175,14 +175,17 @@ int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
  *   b       device, n_bins x S doubles
  *   x_init  device, n_bins x S (double for FP64, float for FP32), or NULL
  *   x_map   device, n_bins x S, same type (output)
+ *   unit_diagonal  non-zero promises A_ii = 1 for every kept row (true of
+ *                  damas_psf's output); the sweeps then skip the scaling by
+ *                  1 / A_ii.  Zero accepts any positive diagonal.
  * A must be symmetric (as the PSF matrix is).  The sweep state x~, b~ and
  * all sums are double at both precisions.  One workgroup owns one bin for
  * all its sweeps; bins run concurrently. */
 int damas_gs(int32_t N, int32_t n_bins, const int32_t *s_tilde,
              int32_t max_kept, const int32_t *idx, const int64_t *off,
-             int32_t precision, const void *A, const double *b,
-             int32_t iterations, const void *x_init, void *x_map,
-             void *stream);
+             int32_t precision, int32_t unit_diagonal, const void *A,
+             const double *b, int32_t iterations, const void *x_init,
+             void *x_map, void *stream);
 
 /* ---- the whole path -------------------------------------------------- */
 

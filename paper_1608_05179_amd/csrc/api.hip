@@ -281,8 +281,8 @@ extern "C" int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
 
 extern "C" int damas_gs(int32_t N, int32_t n_bins, const int32_t *s_tilde,
                         int32_t max_kept, const int32_t *idx,
-                        const int64_t *off, int32_t precision, const void *A,
-                        const double *b, int32_t iterations,
+                        const int64_t *off, int32_t precision, int32_t unit_diagonal,
+                        const void *A, const double *b, int32_t iterations,
                         const void *x_init, void *x_map, void *stream)
 {
     int rc = check_precision(precision);
@@ -299,8 +299,8 @@ extern "C" int damas_gs(int32_t N, int32_t n_bins, const int32_t *s_tilde,
     int *fault;
     if ((rc = fault_word(&fault)))
         return rc;
-    HIP_TRY(launch_gs(N, n_bins, s_tilde, max_kept, idx, off, precision, A, b,
-                      iterations, x_init, x_map, fault, (hipStream_t)stream),
+    HIP_TRY(launch_gs(N, n_bins, s_tilde, max_kept, idx, off, precision, unit_diagonal != 0,
+                      A, b, iterations, x_init, x_map, fault, (hipStream_t)stream),
             "gs launch");
     return DAMAS_OK;
 }
@@ -588,7 +588,7 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
                 "psf launch");
         if (ctx->timing)
             HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
-        HIP_TRY(launch_gs(N, n_bins, st, max_kept, ix, off, p->precision, ctx->A.p,
+        HIP_TRY(launch_gs(N, n_bins, st, max_kept, ix, off, p->precision, 1, ctx->A.p,
                           bm, p->iterations, x_init, x_map, fault, s),
                 "gs launch");
         if (ctx->timing) {
@@ -623,7 +623,7 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
                 return rc;
             HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
         }
-        HIP_TRY(launch_gs(N, 1, st + f, mk, ix + fS, off, p->precision, ctx->A.p,
+        HIP_TRY(launch_gs(N, 1, st + f, mk, ix + fS, off, p->precision, 1, ctx->A.p,
                           bm + fS, p->iterations, xi, xm, fault, s),
                 "gs launch");
         if (ctx->timing) {

@@ -93,9 +93,8 @@ hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
 
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                      const int32_t *idx, const int64_t *off, int precision,
-                     const void *A, const double *b, int iterations,
-                     const void *x_init, void *x_map, int *fault,
-                     hipStream_t s);
+                     int unit_diagonal, const void *A, const double *b, int iterations,
+                     const void *x_init, void *x_map, int *fault, hipStream_t s);
 
 // Largest s_tilde the sweep kernel holds on chip for a precision.
 int gs_max_kept(int precision);

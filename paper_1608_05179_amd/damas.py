@@ -75,8 +75,8 @@ _sig("damas_select", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp,
 _sig("damas_layout", ctypes.c_int, c_i32, c_vp, c_i32, c_i64, c_vp, c_vp)
 _sig("damas_steer", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i64, c_vp)
 _sig("damas_psf", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp)
-_sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp,
-     c_i32, c_vp, c_vp, c_vp)
+_sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp,
+     c_vp, c_i32, c_vp, c_vp, c_vp)
 _sig("damas_ctx_create", ctypes.c_int, c_i32, ctypes.POINTER(c_vp))
 _sig("damas_ctx_destroy", None, c_vp)
 _sig("damas_ctx_set_timing", ctypes.c_int, c_vp, c_i32)
@@ -208,15 +208,17 @@ def psf(M: int, s_tilde, max_kept: int, precision: int, E, off, A=None, stream=N
 
 
 def gs(N: int, s_tilde, max_kept: int, idx, off, precision: int, A, b, iterations: int,
-       x_init=None, x_map=None, stream=None):
-    """Non-negative Gauss-Seidel sweeps; returns x_map (n_bins, N*N)."""
+       x_init=None, x_map=None, unit_diagonal=False, stream=None):
+    """Non-negative Gauss-Seidel sweeps; returns x_map (n_bins, N*N).
+    unit_diagonal: A_ii = 1 for every row (true of psf()'s output)."""
     nb = s_tilde.numel()
     dt = _DTYPE[precision]
     if x_map is None:
         x_map = torch.empty(nb, N * N, dtype=dt, device=b.device)
     _check(_lib.damas_gs(int(N), nb, _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
                          _ptr(idx, torch.int32, "idx"), _ptr(off, torch.int64, "off"),
-                         int(precision), _ptr(A, dt, "A"), _ptr(b, torch.float64, "b"),
+                         int(precision), 1 if unit_diagonal else 0, _ptr(A, dt, "A"),
+                         _ptr(b, torch.float64, "b"),
                          int(iterations), _ptr(x_init, dt, "x_init"),
                          _ptr(x_map, dt, "x_map"), _stream(stream)))
     return x_map

@@ -76,14 +76,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert dm._lib.damas_select(21, 1, fake, dm.SEL_EPS_REL, -0.1, None, fake, fake, None) == dm.EINVAL
     assert dm._lib.damas_select(21, 1, fake, dm.SEL_KEEP_COUNT, 0.0, None, fake, fake, None) == dm.EINVAL
     # sweeps: max_kept beyond the grid, beyond on-chip capacity, bad precision
-    assert dm._lib.damas_gs(21, 1, fake, 442, fake, fake, dm.PREC_FP32, fake, fake, 10,
+    assert dm._lib.damas_gs(21, 1, fake, 442, fake, fake, dm.PREC_FP32, 1, fake, fake, 10,
                             None, fake, None) == dm.EINVAL
-    assert dm._lib.damas_gs(301, 1, fake, 60000, fake, fake, dm.PREC_FP32, fake, fake, 10,
+    assert dm._lib.damas_gs(301, 1, fake, 60000, fake, fake, dm.PREC_FP32, 1, fake, fake, 10,
                             None, fake, None) == dm.EINVAL
     assert b"on chip" in lib.damas_last_error()
-    assert dm._lib.damas_gs(21, 1, fake, 100, fake, fake, 9, fake, fake, 10,
+    assert dm._lib.damas_gs(21, 1, fake, 100, fake, fake, 9, 1, fake, fake, 10,
                             None, fake, None) == dm.EINVAL
-    assert dm._lib.damas_gs(21, 1, fake, 100, fake, fake, dm.PREC_FP32, fake, fake, -1,
+    assert dm._lib.damas_gs(21, 1, fake, 100, fake, fake, dm.PREC_FP32, 1, fake, fake, -1,
                             None, fake, None) == dm.EINVAL
     # layout and PSF argument checks
     assert dm._lib.damas_layout(1, None, 10, 100, fake, None) == dm.EINVAL

@@ -191,7 +191,7 @@ def _pack_system(dm, A, bt, N=None):
     return N, Ap.ravel(), b[None], idx[None], np.array([n], np.int32), np.array([0, L * L])
 
 
-def _gpu_gs(dm, dev, A, bt, iters, prec, x0=None):
+def _gpu_gs(dm, dev, A, bt, iters, prec, x0=None, unit=False):
     import torch
     N, Ap, b, idx, st, off = _pack_system(dm, A, bt)
     dt = torch.float64 if prec == dm.PREC_FP64 else torch.float32
@@ -202,7 +202,7 @@ def _gpu_gs(dm, dev, A, bt, iters, prec, x0=None):
         xi = _t(xm[None], dt, dev)
     x = dm.gs(N, _t(st, torch.int32, dev), int(st[0]), _t(idx, torch.int32, dev),
               _t(off, torch.int64, dev), prec, _t(Ap, dt, dev), _t(b, torch.float64, dev),
-              iters, x_init=xi)
+              iters, x_init=xi, unit_diagonal=unit)
     x = x.double().cpu().numpy()[0]
     assert (x[len(bt):] == 0).all()
     return x[:len(bt)]
@@ -226,16 +226,31 @@ def test_gs_matches_oracle(orc, dm, dev, n):
     bt = np.abs(rng.standard_normal(n)) * 0.5
     for it in (0, 1, 3, 40):
         ref = orc.gs(A, bt, it)
-        x64 = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP64)
         scale = max(np.linalg.norm(ref), 1e-300)
-        assert np.linalg.norm(x64 - ref) / scale < 1e-10, (n, it)
-        x32 = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP32)
-        if it:
-            assert np.linalg.norm(x32 - ref) / scale < 1e-4, (n, it)
+        for unit in (False, True):  # A_ii = 1 here, so both variants apply
+            x64 = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP64, unit=unit)
+            assert np.linalg.norm(x64 - ref) / scale < 1e-10, (n, it, unit)
+            x32 = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP32, unit=unit)
+            if it:
+                assert np.linalg.norm(x32 - ref) / scale < 1e-4, (n, it, unit)
     # warm start equals a longer run
     x1 = orc.gs(A, bt, 5)
     x2 = _gpu_gs(dm, dev, A, bt, 7, dm.PREC_FP64, x0=x1)
     assert np.linalg.norm(x2 - orc.gs(A, bt, 12)) <= 1e-10 * np.linalg.norm(x2)
+
+
+@pytest.mark.parametrize("n", [3, 64, 65, 200])
+def test_gs_general_diagonal(orc, dm, dev, n):
+    # Symmetric positive definite A with a non-unit diagonal: the sweeps
+    # divide by A_ii (scaling variant).
+    rng = np.random.default_rng(300 + n)
+    Bm = rng.standard_normal((n, n)) / np.sqrt(n)
+    A = Bm @ Bm.T + np.diag(rng.uniform(0.5, 3.0, n))
+    bt = rng.standard_normal(n)
+    for it in (1, 2, 25):
+        ref = orc.gs(A, bt, it)
+        x = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP64)
+        assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref), (n, it)
 
 
 def test_gs_identity_one_sweep(dm, dev):
