@@ -36,6 +36,15 @@ inline Geom make_geom(const damas_geometry &g)
     return k;
 }
 
+// bfloat16 storage word (the upper half of an IEEE single).
+struct bf16s {
+    uint16_t u;
+};
+__host__ __device__ inline float bf16_to_float(bf16s v)
+{
+    return __builtin_bit_cast(float, (uint32_t)v.u << 16);
+}
+
 // Row stride of a compressed system: s_tilde rounded up to 8 elements.
 __host__ __device__ inline int64_t ld_of(int32_t st) { return ((int64_t)st + 7) & ~(int64_t)7; }
 

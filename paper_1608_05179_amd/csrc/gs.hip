@@ -4,12 +4,12 @@
 // followed by the scatter of x~ back onto the full grid (zero elsewhere).
 //
 // One workgroup owns one bin for all its sweeps; x~ lives in LDS in double,
-// whatever A's storage type: the sweep state, b~ and every sum are double,
-// and float storage of A only rounds its entries once.
+// whatever A's storage type (double, float or bf16): the sweep state, b~ and
+// every sum are double, and a narrow A only rounds its entries once.
 //
 // Rows go in tiles of 64, and the tiles of all sweeps form one stream
 // q = 0, 1, ... (tile q mod T of sweep q div T).  Two roles run side by side:
-//   wave 0 (serial): updates the 64 rows of tile q in order.  Lane l holds
+//   wave 0 (serial): updates the rows of tile q in order.  Lane l holds
 //     the residual of row l; after row i moves by d_i every later row l
 //     adds A_li d_i, so row l sees the new value of each earlier row of the
 //     tile.  The same broadcast d_i also accumulates, for the next tile's
@@ -18,189 +18,306 @@
 //     every column, taking tile q's columns at their values before this
 //     tile's update (a snapshot, so the serial wave may overwrite them), and
 //     by symmetry reading row r's sum down column r: each j is a contiguous
-//     64-column strip, 16 bytes per lane.  The same reads hand wave 0, through
-//     double-buffered LDS, the next tile's diagonal block and its coupling
-//     to the tile after it, so the serial wave never waits on A.
+//     64-column strip, 16 bytes per lane.  While summing they hand wave 0,
+//     through double-buffered LDS, the next tile's diagonal block and its
+//     coupling to the tile after it (both are rows of the same strip).
+// A is constant, so each stream wave issues the loads of the first part of
+// its next strip a whole tile ahead (the "head", held in registers); only
+// the rest of a long strip (the "tail") is fetched within the tile, two
+// batches in flight.
+//
 // The residual of tile q+1 is then exactly the sum over the new values of
 // every row before it and the previous sweep's values of itself and the rows
 // after it: the same iteration as the row-by-row scheme; only the order in
 // which each r_i's terms are summed (and, for a diagonal other than 1, the
 // scaling by 1 / A_ii) differ.
+//
+// Rows and columns at or beyond S~ contribute exact zeros: the stream masks
+// them out of the partial sums and of the hand-over blocks, and the serial
+// wave starts such rows at a zero residual, so their change is always 0.
 #include "common.h"
 
 namespace damas {
 
 constexpr int kGsTile = 64;
-constexpr int kGsStreamWaves = 4;
-constexpr int kGsThreads = 64 * (1 + kGsStreamWaves);
+constexpr int kGsMaxStreamWaves = 7;    // stream waves per workgroup, at most
 constexpr int kGsCtPitch = kGsTile + 1; // rows of the coupling block
-constexpr int kGsBatch = 8;             // loads in flight per stream lane
+constexpr int kGsBatch = 8;             // tail loads per batch (two batches in flight)
+constexpr int kGsPre = 8;               // serial wave: LDS reads issued this many steps ahead
 
-// 16 bytes of A per lane: CPL = 4 floats or 2 doubles.
+// 16 bytes of A per lane: CPL = 2 doubles, 4 floats or 8 bf16.
 template <typename TA> struct Vec16;
-template <> struct Vec16<float> {
-    typedef float4 type;
-    static constexpr int n = 4;
-    __device__ static float at(const float4 &v, int s)
-    {
-        return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
-    }
-    __device__ static float4 make(const float *a) { return make_float4(a[0], a[1], a[2], a[3]); }
-};
 template <> struct Vec16<double> {
     typedef double2 type;
     static constexpr int n = 2;
-    __device__ static double at(const double2 &v, int s) { return s == 0 ? v.x : v.y; }
-    __device__ static double2 make(const double *a) { return make_double2(a[0], a[1]); }
+    __device__ static double raw(const double2 &v, int s) { return s == 0 ? v.x : v.y; }
+    __device__ static double wide(double r) { return r; }
+    __device__ static double2 pack(const double (&r)[2]) { return make_double2(r[0], r[1]); }
 };
+template <> struct Vec16<float> {
+    typedef float4 type;
+    static constexpr int n = 4;
+    __device__ static float raw(const float4 &v, int s)
+    {
+        return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+    }
+    __device__ static double wide(float r) { return (double)r; }
+    __device__ static float4 pack(const float (&r)[4]) { return make_float4(r[0], r[1], r[2], r[3]); }
+};
+template <> struct Vec16<bf16s> {
+    typedef uint4 type;
+    static constexpr int n = 8;
+    __device__ static bf16s raw(const uint4 &v, int s)
+    {
+        const uint32_t w = s < 2 ? v.x : s < 4 ? v.y : s < 6 ? v.z : v.w;
+        bf16s r;
+        r.u = (uint16_t)((s & 1) ? (w >> 16) : (w & 0xffffu));
+        return r;
+    }
+    __device__ static double wide(bf16s r) { return (double)bf16_to_float(r); }
+    __device__ static uint4 pack(const bf16s (&r)[8])
+    {
+        return make_uint4(r[0].u | ((uint32_t)r[1].u << 16), r[2].u | ((uint32_t)r[3].u << 16),
+                          r[4].u | ((uint32_t)r[5].u << 16), r[6].u | ((uint32_t)r[7].u << 16));
+    }
+};
+
+__device__ inline double widen(double v) { return v; }
+__device__ inline double widen(float v) { return (double)v; }
+__device__ inline double widen(bf16s v) { return (double)bf16_to_float(v); }
+template <typename TA> __device__ inline TA zero_of();
+template <> __device__ inline double zero_of<double>() { return 0.0; }
+template <> __device__ inline float zero_of<float>() { return 0.0f; }
+template <> __device__ inline bf16s zero_of<bf16s>()
+{
+    bf16s z;
+    z.u = 0;
+    return z;
+}
 
 // LDS blocks handed from the stream waves to the serial wave for tile t
 // (tn = the tile after it):
-//   U[i][l]       = A_{t0+i, t0+l} for l > i, 0 for l <= i (strict upper)
-//   dg[l]         = A_{t0+l, t0+l}
-//   Ct[l][i]      = A_{tn0+l, t0+i} (pitch 65: lane l reads row l)
-template <typename TA> struct TileBlocks {
-    TA U[kGsTile * kGsTile];
-    TA Ct[kGsTile * kGsCtPitch];
+//   U[i][l]   = A_{t0+i, t0+l} for l > i, 0 for l <= i (strict upper)
+//   dg[l]     = A_{t0+l, t0+l}
+//   Ct[l][i]  = A_{tn0+l, t0+i} (pitch 65: lane l reads row l)
+// Entries outside S~ are 0.  The serial wave reads kGsPre rows / columns
+// past the last step it runs, hence the padding.
+template <typename TA> struct alignas(16) TileBlocks {
+    TA U[(kGsTile + kGsPre) * kGsTile];
+    TA Ct[kGsTile * kGsCtPitch + kGsPre];
     TA dg[kGsTile];
 };
 
-// Stream role, one of kGsStreamWaves waves (sw = 0..): partial residual
-// sums of the 64 rows of tile T (columns T0..T0+63 of every row j of A, A
-// being symmetric) over the row groups this wave owns.  Rows j of the tile
-// being updated, [X0, X0 + 64), take x from the snapshot xold.  Rows j in
-// [T0, T0 + 64) also fill U and dg, rows j in [TN0, TN0 + 64) fill Ct.
-// part[sw][r] receives the partial sum of row T0 + r.
+// ---------------------------------------------------------------------------
+// Stream role: one of NW waves (sw = 0..).  A period computes
+// the partial residual sums of the 64 rows of tile T (columns T0..T0+63 of
+// every row j of A, A being symmetric) over the row groups this wave owns:
+// group g = sw + NW k holds rows [g CPL, g CPL + CPL), row jp = lane / LPJ
+// of the group, columns cl .. cl+CPL-1 with cl = (lane % LPJ) CPL.
 //
-// The sum runs branch-free over batches of kGsBatch loads, two batches in
-// flight (rows past the wave's last group are read clamped and weighted 0),
-// so the loads of one batch overlap the arithmetic of the other.
-template <typename TA>
-__device__ __forceinline__ void stream_strip(const TA *__restrict__ A, int64_t ld,
-                                             const double *xs, const double *xold,
-                                             const double *zero, int St, int T0, int X0,
-                                             int TN0, double *part, TileBlocks<TA> *blk,
-                                             int sw, int lane)
-{
+// A is read through a buffer resource whose range is the bin's system, so a
+// load past its end returns 0: the sums run branch-free over whole batches
+// and groups past S~ add exact zeros (rows S~ .. ld-1 are zero padding).
+// Columns at or past S~ are masked out of every result.
+//
+// NH: groups per wave loaded a whole tile ahead (the head), together with
+// the rows of the two hand-over blocks; NB: groups per tail batch, two
+// batches in flight.
+template <typename TA, int NW, int NH, int NB> struct StreamWave {
     typedef Vec16<TA> VA;
     typedef typename VA::type VT;
-    constexpr int CPL = VA::n;         // columns per lane
-    constexpr int LPJ = kGsTile / CPL; // lanes per row j
-    constexpr int NW = kGsStreamWaves;
-    const int jp = lane / LPJ;         // which of the CPL rows of a group
-    const int cl = (lane % LPJ) * CPL; // first tile column of this lane
-    const int64_t csrc = min((int64_t)(T0 + cl), ld - CPL);
-    const TA *Ac = A + csrc;
-    // Row groups of CPL consecutive j; this wave owns g = sw + NW k.
-    const int ngroup = (St + CPL - 1) / CPL;
-    const int nk = ngroup > sw ? (ngroup - sw + NW - 1) / NW : 0;
-    const int gmax = ngroup - 1;
+    static constexpr int CPL = VA::n;
+    static constexpr int LPJ = kGsTile / CPL;
+    static constexpr int GT = kGsTile / CPL;         // row groups per tile
+    static constexpr int NU = (GT + NW - 1) / NW;    // of them per wave, at most
 
-    double acc[CPL];
-#pragma unroll
-    for (int s = 0; s < CPL; ++s)
-        acc[s] = 0.0;
+    __amdgpu_buffer_rsrc_t rsrc;
+    int64_t ld;
+    int St, sw, lane, jp, cl;
+    int nk;           // groups of this wave per strip
+    int xcap;         // last row group start with x on chip (ld - CPL)
+    uint32_t gstride; // bytes per group
+    VT head[NH], hu[NU], hc[NU];
 
-    // Addresses split into a wave-uniform part (the group, scalar registers)
-    // and a fixed per-lane byte offset (row jp of the group, column cl), so a
-    // load costs no vector address arithmetic.
-    const char *Ab = reinterpret_cast<const char *>(A);
-    const uint32_t voff = (uint32_t)(((int64_t)jp * ld + csrc) * sizeof(TA));
-    const int64_t gstride = (int64_t)CPL * ld * sizeof(TA); // bytes per group
-    auto load = [&](VT *dst, int k0) {
+    __device__ __forceinline__ void init(const TA *A, int64_t ld_, int St_, int sw_, int lane_)
+    {
+        ld = ld_;
+        St = St_;
+        sw = sw_;
+        lane = lane_;
+        jp = lane / LPJ;
+        cl = (lane % LPJ) * CPL;
+        const int ngroup = (St + CPL - 1) / CPL;
+        nk = ngroup > sw ? (ngroup - sw + NW - 1) / NW : 0;
+        xcap = (int)max(ld - CPL, (int64_t)0);
+        gstride = (uint32_t)(CPL * ld * (int64_t)sizeof(TA));
+        rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<TA *>(A), (short)0,
+                                                 (int)(ld * ld * (int64_t)sizeof(TA)),
+                                                 0x00020000);
+    }
+
+    // Per-lane byte offset of row jp, columns from T0 + cl.
+    __device__ __forceinline__ uint32_t voff(int T0) const
+    {
+        return (uint32_t)(((int64_t)jp * ld + T0 + cl) * (int64_t)sizeof(TA));
+    }
+
+    // Group g (wave-uniform) of the strip at per-lane offset vo.
+    __device__ __forceinline__ VT load(int g, uint32_t vo) const
+    {
+        return __builtin_bit_cast(
+            VT, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)vo, (int)(g * gstride), 0));
+    }
+
+    // The head of strip T0 and the rows of its hand-over blocks (tile T0
+    // and tile TN0).
+    __device__ __forceinline__ void prefetch(int T0, int TN0)
+    {
+        const uint32_t vo = voff(T0);
 #pragma unroll
-        for (int n = 0; n < kGsBatch; ++n) {
-            const int g = min(sw + NW * (k0 + n), gmax); // wave-uniform
-            dst[n] = *reinterpret_cast<const VT *>(Ab + g * gstride + voff);
-        }
-    };
-    auto accumulate = [&](const VT *src, int k0) {
+        for (int n = 0; n < NH; ++n)
+            head[n] = load(sw + NW * n, vo);
 #pragma unroll
-        for (int n = 0; n < kGsBatch; ++n) {
-            const int jb = (sw + NW * (k0 + n)) * CPL; // wave-uniform
-            // x of row jb + jp: the snapshot inside the tile being updated,
-            // the zero word past the wave's last group.
-            const double *xb = k0 + n >= nk                 ? zero - jp
-                               : jb >= X0 && jb < X0 + kGsTile ? xold + (jb - X0)
-                                                               : xs + jb;
-            const double xj = xb[jp];
-#pragma unroll
-            for (int s = 0; s < CPL; ++s)
-                acc[s] += (double)VA::at(src[n], s) * xj;
-        }
-    };
-    // sched_barrier keeps each batch's loads issued ahead of the arithmetic
-    // on the other batch (the scheduler would otherwise sink them to their
-    // uses and leave one or two loads in flight).
-    if (nk > 0) {
-        VT b0[kGsBatch], b1[kGsBatch];
-        load(b0, 0);
-        for (int k0 = 0; k0 < nk; k0 += 2 * kGsBatch) {
-            load(b1, k0 + kGsBatch);
-            __builtin_amdgcn_sched_barrier(0);
-            accumulate(b0, k0);
-            __builtin_amdgcn_sched_barrier(0);
-            load(b0, k0 + 2 * kGsBatch);
-            __builtin_amdgcn_sched_barrier(0);
-            accumulate(b1, k0 + kGsBatch);
-            __builtin_amdgcn_sched_barrier(0);
+        for (int m = 0; m < NU; ++m) {
+            hu[m] = load(T0 / CPL + sw + NW * m, vo);
+            hc[m] = load(TN0 / CPL + sw + NW * m, vo);
         }
     }
 
-    // Hand-over blocks: the rows j of tiles T and TN that this wave owns
-    // (re-read; they were just fetched).
+    // LDS address of x for the rows of group g: the snapshot inside the
+    // tile being updated, the live values elsewhere (clamped to the rows on
+    // chip; rows past S~ carry zero A).
+    __device__ __forceinline__ const double *xrow(int g, const double *xs, const double *xold,
+                                                  int X0) const
     {
-        const int n = kGsTile / CPL / NW + 1; // groups per wave in a tile, at most
-        VT u[n], c[n];
+        const int jb = g * CPL; // wave-uniform
+        return jb >= X0 && jb < X0 + kGsTile ? xold + (jb - X0) : xs + min(jb, xcap);
+    }
+
+    // acc += the groups in v[0..n) (groups g0, g0 + NW, ...), in chunks of
+    // eight: the x reads of a chunk are issued together, and sched_barrier
+    // keeps the scheduler from widening every group of a long head at once.
+    template <int n>
+    __device__ __forceinline__ void sum(const VT (&v)[n], int g0, double (&acc)[CPL],
+                                        const double *xs, const double *xold, int X0) const
+    {
+        constexpr int C = 8;
 #pragma unroll
-        for (int m = 0; m < n; ++m) {
-            const int gu = T0 / CPL + sw + NW * m, gc = TN0 / CPL + sw + NW * m;
-            const int64_t ju = min((int64_t)gu * CPL + jp, ld - 1);
-            const int64_t jc = min((int64_t)gc * CPL + jp, ld - 1);
-            u[m] = *reinterpret_cast<const VT *>(&Ac[ju * ld]);
-            c[m] = *reinterpret_cast<const VT *>(&Ac[jc * ld]);
-        }
+        for (int k0 = 0; k0 < n; k0 += C) {
+            double xj[C];
 #pragma unroll
-        for (int m = 0; m < n; ++m) {
-            const int g = sw + NW * m; // group within the tile
-            if (g * CPL < kGsTile) {
-                const int i = g * CPL + jp;
-                TA uu[CPL];
+            for (int k = k0; k < k0 + C && k < n; ++k)
+                xj[k - k0] = xrow(g0 + NW * k, xs, xold, X0)[jp];
 #pragma unroll
-                for (int s = 0; s < CPL; ++s) {
-                    const TA v = VA::at(u[m], s);
-                    uu[s] = cl + s > i ? v : (TA)0;
-                    if (cl + s == i)
-                        blk->dg[i] = v;
-                }
-                *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::make(uu);
+            for (int k = k0; k < k0 + C && k < n; ++k)
 #pragma unroll
                 for (int s = 0; s < CPL; ++s)
-                    blk->Ct[i * kGsCtPitch + cl + s] = VA::at(c[m], s);
-            }
+                    acc[s] += VA::wide(VA::raw(v[k], s)) * xj[k - k0];
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
-    // Sum the CPL row groups (lanes l, l + LPJ, ...), then lanes 0..LPJ-1
-    // hold the partial sums of the tile's 64 rows.
+    // Blocks of tile T for the serial wave, from hu / hc (zero outside S~).
+    __device__ __forceinline__ void handover(int T0, int TN0, const bool (&colok)[CPL],
+                                             TileBlocks<TA> *blk) const
+    {
 #pragma unroll
-    for (int m = LPJ; m < 64; m <<= 1)
+        for (int m = 0; m < NU; ++m) {
+            if (sw + NW * m >= GT) // wave-uniform: this wave has one group fewer
+                break;
+            const int i = (sw + NW * m) * CPL + jp; // row within the tile
+            const bool rowu = T0 + i < St, rowc = TN0 + i < St;
+            TA u[CPL];
 #pragma unroll
-        for (int s = 0; s < CPL; ++s)
-            acc[s] += __shfl_xor(acc[s], m);
-    if (lane < LPJ)
-#pragma unroll
-        for (int s = 0; s < CPL; ++s)
-            part[sw * kGsTile + cl + s] = acc[s];
-}
+            for (int s = 0; s < CPL; ++s) {
+                const int c = cl + s;
+                const TA v = VA::raw(hu[m], s);
+                u[s] = rowu && colok[s] && c > i ? v : zero_of<TA>();
+                if (c == i)
+                    blk->dg[i] = v;
+                blk->Ct[i * kGsCtPitch + c] = rowc && colok[s] ? VA::raw(hc[m], s) : zero_of<TA>();
+            }
+            *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
+        }
+    }
 
+    // The period that sums strip T while tile X0 (-2 tiles: none) is being
+    // updated and hands over the blocks of T and of the tile TN after it;
+    // when `next`, it also issues the head of strip NT0 (with hand-over
+    // tile NTN0) for the following period.
+    __device__ __forceinline__ void period(const double *xs, const double *xold, int T0, int X0,
+                                           int TN0, bool next, int NT0, int NTN0, double *part,
+                                           TileBlocks<TA> *blk)
+    {
+        double acc[CPL];
+        bool colok[CPL];
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) {
+            acc[s] = 0.0;
+            colok[s] = T0 + cl + s < St;
+        }
+        // Per-period copies of the loop-invariant strides keep the compiler
+        // from hoisting every group's offset into a scalar register of its
+        // own for the whole loop.
+        asm volatile("" : "+s"(gstride), "+s"(xcap));
+        sum(head, sw, acc, xs, xold, X0);
+        handover(T0, TN0, colok, blk);
+        __builtin_amdgcn_sched_barrier(0);
+        if (next)
+            prefetch(NT0, NTN0);
+        __builtin_amdgcn_sched_barrier(0);
+
+        // Tail: groups NH .. nk-1 in batches of NB, two batches in flight.
+        // sched_barrier keeps each batch's loads issued ahead of the
+        // arithmetic on the other batch (the scheduler would otherwise sink
+        // them to their uses and leave one or two loads in flight).
+        if (nk > NH) {
+            const uint32_t vo = voff(T0);
+            VT b0[NB], b1[NB];
+            auto fill = [&](VT(&dst)[NB], int k0) {
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+                    dst[n] = load(sw + NW * (k0 + n), vo);
+            };
+            fill(b0, NH);
+            for (int k0 = NH; k0 < nk; k0 += 2 * NB) {
+                fill(b1, k0 + NB);
+                __builtin_amdgcn_sched_barrier(0);
+                sum(b0, sw + NW * k0, acc, xs, xold, X0);
+                __builtin_amdgcn_sched_barrier(0);
+                fill(b0, k0 + 2 * NB);
+                __builtin_amdgcn_sched_barrier(0);
+                sum(b1, sw + NW * (k0 + NB), acc, xs, xold, X0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+
+        // Sum the CPL row groups (lanes l, l + LPJ, ...), then lanes
+        // 0..LPJ-1 hold the partial sums of the tile's 64 columns.
+#pragma unroll
+        for (int m = LPJ; m < 64; m <<= 1)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+                acc[s] += __shfl_xor(acc[s], m);
+        if (lane < LPJ)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+                part[sw * kGsTile + cl + s] = colok[s] ? acc[s] : 0.0;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Serial role (one wave): the rows of each tile in order.  With the scaled
 // residual rho_l = r_l / A_ll, row i's change is d_i = max(-rho_i, -x_i)
 // (x_i + d_i = max(x_i - r_i / A_ii, 0)), and every later row l of the
 // tile takes rho_l += (A_li / A_ll) d_i.  U is zero on and below the
 // diagonal, so lane l's rho stops changing once its own row is done and its
 // new value is formed once after the loop.  UNIT: A_ii = 1, no scaling.
-template <typename TA, bool UNIT>
+// Only the tile's rows, rounded up to 8, are stepped through; rows past S~
+// start at rho = 0, x = 0 and so never move.  The b~ of each tile is
+// gathered two tiles ahead (grid index one period, value the next), with
+// the loads issued at the end of a period, off the step chain.
+template <typename TA, int NW, bool UNIT>
 __device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xold,
                                             const TileBlocks<TA> *blks,
                                             const int32_t *__restrict__ id,
@@ -208,73 +325,84 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                                             long long total, int lane)
 {
     __builtin_amdgcn_s_setprio(3);
+    auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
     int t = 0;
-    double bt = lane < St ? bf[id[lane]] : 0.0;
+    const int t1 = nxt(0), t2 = nxt(t1);
+    double bt = lane < St ? bf[id[lane]] : 0.0;               // tile t
+    double bq1 = t1 * kGsTile + lane < St ? bf[id[t1 * kGsTile + lane]] : 0.0; // tile t+1
+    int iq2 = t2 * kGsTile + lane < St ? id[t2 * kGsTile + lane] : 0;         // tile t+2
     double rn = 0.0; // change of the next tile's residuals from this tile
     for (long long q = 0; q < total; ++q) {
         const int t0 = t * kGsTile;
-        const int tn = t + 1 == ntile ? 0 : t + 1;
+        const int tn = nxt(t);
         const int tn0 = tn * kGsTile;
         const int rows = min(kGsTile, St - t0);
+        const int steps = (rows + 7) & ~7;
         const bool mine = lane < rows;
         const TileBlocks<TA> &bk = blks[q & 1];
-        const double *pt = parts + (q & 1) * kGsStreamWaves * kGsTile;
-        // b~ of the next tile's rows, needed one tile from now.
-        const double bt_next = tn0 + lane < St ? bf[id[tn0 + lane]] : 0.0;
+        const double *pt = parts + (q & 1) * NW * kGsTile;
         double r = -bt + rn;
 #pragma unroll
-        for (int k = 0; k < kGsStreamWaves; ++k)
+        for (int k = 0; k < NW; ++k)
             r += pt[k * kGsTile + lane];
         double il = 1.0;
         if (!UNIT)
-            il = mine ? 1.0 / (double)bk.dg[lane] : 0.0;
-        const double xl = mine ? xs[min(t0 + lane, St - 1)] : 0.0;
-        double rho = UNIT ? r : r * il;
-        // Software pipeline: the block entries of step i + kPre are read
+            il = mine ? 1.0 / widen(bk.dg[lane]) : 0.0;
+        const double xl = mine ? xs[t0 + lane] : 0.0;
+        double rho = mine ? (UNIT ? r : r * il) : 0.0;
+        // Software pipeline: the block entries of step i + kGsPre are read
         // from LDS during step i (raw storage type), and those of step i + 1
         // are widened to double at the end of step i, off the serial chain
-        //   max -> readlane -> fma;
+        //   min -> readlane -> fma;
         // sched_barrier keeps each step's instructions together, and the
         // four independent coupling sums fill the chain's latency.
-        constexpr int kPre = 8;
-        TA ur[kPre], cr[kPre];
+        TA ur[kGsPre], cr[kGsPre];
 #pragma unroll
-        for (int i = 0; i < kPre; ++i) {
+        for (int i = 0; i < kGsPre; ++i) {
             ur[i] = bk.U[i * kGsTile + lane];
             cr[i] = bk.Ct[lane * kGsCtPitch + i];
         }
-        double ud = UNIT ? (double)ur[0] : (double)ur[0] * il, cd = (double)cr[0];
+        double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il, cd = widen(cr[0]);
         double rn4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i0 = 0; i0 < steps; i0 += kGsPre) {
 #pragma unroll
-        for (int i = 0; i < kGsTile; ++i) {
-            const double d = lane_bcast(fmax(-rho, -xl), i);
-            rho += ud * d;
-            // Pin the chain update first in the step, then the coupling sum
-            // (otherwise it is sunk past the loop and all 64 broadcasts stay
-            // live in scalar registers).
-            asm volatile("" : "+v"(rho));
-            rn4[i & 3] += cd * d;
-            asm volatile("" : "+v"(rn4[i & 3]));
-            if (i + kPre < kGsTile) {
-                ur[i % kPre] = bk.U[(i + kPre) * kGsTile + lane];
-                cr[i % kPre] = bk.Ct[lane * kGsCtPitch + i + kPre];
-            }
-            if (i + 1 < kGsTile) {
-                ud = (double)ur[(i + 1) % kPre];
+            for (int u = 0; u < kGsPre; ++u) {
+                const int i = i0 + u; // wave-uniform
+                // d = max(-rho, -x) = -min(rho, x): the broadcast carries
+                // min(rho, x) and the updates subtract.
+                const double m = lane_bcast(fmin(rho, xl), i);
+                rho -= ud * m;
+                // The coupling sum takes the broadcast through an empty asm
+                // that depends on the new rho, so the chain's fma issues
+                // first; its own pin keeps it in this step (otherwise it is
+                // sunk past the loop and the broadcasts stay live in scalar
+                // registers).  rho itself is never passed through asm: the
+                // min would then canonicalise it first.
+                double mc = m;
+                asm volatile("" : "+s"(mc) : "v"(rho));
+                rn4[u & 3] -= cd * mc;
+                asm volatile("" : "+v"(rn4[u & 3]));
+                ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
+                cr[u] = bk.Ct[lane * kGsCtPitch + i + kGsPre];
+                ud = widen(ur[(u + 1) % kGsPre]);
                 if (!UNIT)
                     ud *= il;
-                cd = (double)cr[(i + 1) % kPre];
+                cd = widen(cr[(u + 1) % kGsPre]);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
         rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         if (mine)
-            xs[t0 + lane] = xl + fmax(-rho, -xl);
+            xs[t0 + lane] = xl - fmin(rho, xl);
         // Snapshot of the next tile's values for the stream waves, which
         // read it while this wave overwrites that tile.
-        xold[((q + 1) & 1) * kGsTile + lane] =
-            tn0 + lane < St ? xs[min(tn0 + lane, St - 1)] : 0.0;
-        bt = bt_next;
+        xold[((q + 1) & 1) * kGsTile + lane] = tn0 + lane < St ? xs[tn0 + lane] : 0.0;
+        // b~ two tiles ahead: value of tile t+2 (its grid index arrived a
+        // period ago), grid index of tile t+3 (tn = t+1).
+        const int ta = nxt(tn), tb = nxt(ta);
+        bt = bq1;
+        bq1 = ta * kGsTile + lane < St ? bf[iq2] : 0.0;
+        iq2 = tb * kGsTile + lane < St ? id[tb * kGsTile + lane] : 0;
         t = tn;
         __syncthreads();
     }
@@ -282,25 +410,25 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
 
 template <typename TA> constexpr size_t gs_lds_fixed()
 {
-    return sizeof(double) * (2 * kGsStreamWaves * kGsTile + 2 * kGsTile + 8) +
+    return sizeof(double) * (2 * kGsMaxStreamWaves * kGsTile + 2 * kGsTile) +
            2 * sizeof(TileBlocks<TA>);
 }
 
-template <typename TA, typename TX, bool UNIT>
-__global__ __launch_bounds__(kGsThreads) void gs_kernel(
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
+__global__ __launch_bounds__(64 * (1 + NW)) void gs_kernel(
     int N, const int32_t *__restrict__ s_tilde, int max_kept,
     const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
     const TA *__restrict__ A_all, const double *__restrict__ b, int iters,
     const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault)
 {
-    // LDS: x~ [ld_cap] | partial sums [2][NW][64] | snapshots [2][64] |
-    //      zero words [8] | tile blocks [2]
+    // LDS: x~ [ld_cap] | partial sums [2][NW][64] (room for the widest
+    //      shape) | snapshots [2][64] |
+    //      tile blocks [2]
     extern __shared__ double xs[];
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
-    double *xold = parts + 2 * kGsStreamWaves * kGsTile;
-    double *zero = xold + 2 * kGsTile;
-    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(zero + 8);
+    double *xold = parts + 2 * kGsMaxStreamWaves * kGsTile;
+    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xold + 2 * kGsTile);
 
     const int f = blockIdx.x;
     const int S = N * N;
@@ -318,43 +446,44 @@ __global__ __launch_bounds__(kGsThreads) void gs_kernel(
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    for (int64_t i = tid; i < ld; i += kGsThreads)
+    constexpr int nthr = 64 * (1 + NW);
+    for (int64_t i = tid; i < ld; i += nthr)
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
-    if (tid < 8)
-        zero[tid] = 0.0;
     {
         TA *z = reinterpret_cast<TA *>(blks);
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / sizeof(TA)); i += kGsThreads)
-            z[i] = (TA)0;
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / sizeof(TA)); i += nthr)
+            z[i] = zero_of<TA>();
     }
     __syncthreads();
 
     const int ntile = (St + kGsTile - 1) / kGsTile;
     const long long total = (long long)iters * ntile;
     if (total > 0) {
-        // Prologue: residuals and blocks of tile 0; snapshot of tile 0.
-        const int t1 = ntile > 1 ? kGsTile : 0;
-        if (w > 0)
-            stream_strip<TA>(A, ld, xs, xold, zero, St, 0, -2 * kGsTile, t1, parts,
-                             &blks[0], w - 1, lane);
-        else
-            xold[lane] = lane < St ? xs[min(lane, St - 1)] : 0.0;
-        __syncthreads();
         // The two roles run separate loops (w is wave-uniform) so that each
         // allocates only its own registers; both pass exactly one barrier
-        // per tile.
+        // per period.  Period -1 (prologue): the stream waves sum strip 0
+        // and hand over its blocks; wave 0 takes the snapshot of tile 0.
+        auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
         if (w == 0) {
-            serial_role<TA, UNIT>(xs, parts, xold, blks, id, bf, St, ntile, total, lane);
+            xold[lane] = lane < St ? xs[lane] : 0.0;
+            __syncthreads();
+            serial_role<TA, NW, UNIT>(xs, parts, xold, blks, id, bf, St, ntile, total, lane);
         } else {
+            StreamWave<TA, NW, NH, NB> sw;
+            sw.init(A, ld, St, w - 1, lane);
+            const int t1 = nxt(0), t2 = nxt(t1);
+            sw.prefetch(0, t1 * kGsTile);
+            sw.period(xs, xold, 0, -2 * kGsTile, t1 * kGsTile, total > 1, t1 * kGsTile,
+                      t2 * kGsTile, parts, &blks[0]);
+            __syncthreads();
             int t = 0;
             for (long long q = 0; q < total; ++q) {
-                const int tn = t + 1 == ntile ? 0 : t + 1;
-                const int tnn = tn + 1 == ntile ? 0 : tn + 1;
+                const int tn = nxt(t), tnn = nxt(tn), tn3 = nxt(tnn);
                 if (q + 1 < total)
-                    stream_strip<TA>(A, ld, xs, xold + (q & 1) * kGsTile, zero, St,
-                                     tn * kGsTile, t * kGsTile, tnn * kGsTile,
-                                     parts + ((q + 1) & 1) * kGsStreamWaves * kGsTile,
-                                     &blks[(q + 1) & 1], w - 1, lane);
+                    sw.period(xs, xold + (q & 1) * kGsTile, tn * kGsTile, t * kGsTile,
+                              tnn * kGsTile, q + 2 < total, tnn * kGsTile, tn3 * kGsTile,
+                              parts + ((q + 1) & 1) * NW * kGsTile,
+                              &blks[(q + 1) & 1]);
                 t = tn;
                 __syncthreads();
             }
@@ -365,11 +494,11 @@ __global__ __launch_bounds__(kGsThreads) void gs_kernel(
     // points, so every grid point is written exactly once.
     TX *xo = x_map + (int64_t)f * S;
     if (St == 0) {
-        for (int n = tid; n < S; n += kGsThreads)
+        for (int n = tid; n < S; n += nthr)
             xo[n] = (TX)0;
         return;
     }
-    for (int i = tid; i < St; i += kGsThreads) {
+    for (int i = tid; i < St; i += nthr) {
         const int n = id[i];
         const int prev = i == 0 ? -1 : id[i - 1];
         for (int q = prev + 1; q < n; ++q)
@@ -381,11 +510,18 @@ __global__ __launch_bounds__(kGsThreads) void gs_kernel(
     }
 }
 
+template <typename TA> static size_t gs_lds_bytes_t(int max_kept)
+{
+    return gs_lds_fixed<TA>() + sizeof(double) * (size_t)ld_of(max_kept);
+}
+
 static size_t gs_lds_bytes(int precision, int max_kept)
 {
-    const size_t fixed = precision == DAMAS_PREC_FP64 ? gs_lds_fixed<double>()
-                                                      : gs_lds_fixed<float>();
-    return fixed + sizeof(double) * (size_t)ld_of(max_kept);
+    switch (precision) {
+    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float>(max_kept);
+    default: return gs_lds_bytes_t<bf16s>(max_kept);
+    }
 }
 
 int gs_max_kept(int precision)
@@ -396,20 +532,56 @@ int gs_max_kept(int precision)
     return (int)(((lds - fixed) / sizeof(double)) & ~(size_t)7);
 }
 
-template <typename TA, typename TX, bool UNIT>
+// Launch shapes (stream waves NW, head groups NH, tail batch NB): short
+// strips keep a whole strip in the head; long strips keep a short head and
+// a deep tail.
+template <typename TA> struct GsShapes;
+template <> struct GsShapes<float> {
+    static constexpr int nw = 7, short_nh = 14, short_nb = 4, long_nh = 6, long_nb = 8;
+};
+template <> struct GsShapes<double> {
+    static constexpr int nw = 7, short_nh = 12, short_nb = 4, long_nh = 6, long_nb = 6;
+};
+template <> struct GsShapes<bf16s> {
+    static constexpr int nw = 7, short_nh = 14, short_nb = 4, long_nh = 6, long_nb = 8;
+};
+
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
 static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                               const int32_t *idx, const int64_t *off, const void *A,
                               const double *b, int iterations, const void *x_init,
                               void *x_map, int *fault, hipStream_t s)
 {
-    static const hipError_t attr = allow_big_lds((const void *)gs_kernel<TA, TX, UNIT>);
+    static_assert(NW <= kGsMaxStreamWaves, "LDS holds the partial sums of at most kGsMaxStreamWaves waves");
+    static const hipError_t attr =
+        allow_big_lds((const void *)gs_kernel<TA, TX, UNIT, NW, NH, NB>);
     if (attr != hipSuccess)
         return attr;
-    const size_t lds = gs_lds_fixed<TA>() + sizeof(double) * (size_t)ld_of(max_kept);
-    hipLaunchKernelGGL((gs_kernel<TA, TX, UNIT>), dim3(n_bins), dim3(kGsThreads), lds, s, N,
-                       s_tilde, max_kept, idx, off, (const TA *)A, b, iterations,
-                       (const TX *)x_init, (TX *)x_map, fault);
+    hipLaunchKernelGGL((gs_kernel<TA, TX, UNIT, NW, NH, NB>), dim3(n_bins), dim3(64 * (1 + NW)),
+                       gs_lds_bytes_t<TA>(max_kept), s, N, s_tilde, max_kept, idx, off,
+                       (const TA *)A, b, iterations, (const TX *)x_init, (TX *)x_map, fault);
     return hipGetLastError();
+}
+
+template <typename TA, typename TX>
+static hipError_t launch_gs_u(int N, int n_bins, const int32_t *s_tilde, int max_kept,
+                              const int32_t *idx, const int64_t *off, int unit_diagonal,
+                              const void *A, const double *b, int iterations,
+                              const void *x_init, void *x_map, int *fault, hipStream_t s)
+{
+    typedef GsShapes<TA> SH;
+    // A strip fits the short shape's head when every wave's groups do.
+    const bool shrt =
+        ld_of(max_kept) <= (int64_t)SH::short_nh * SH::nw * Vec16<TA>::n;
+#define DAMAS_GS_LAUNCH(U, NH, NB)                                                               \
+    launch_gs_t<TA, TX, U, SH::nw, NH, NB>(N, n_bins, s_tilde, max_kept, idx, off, A, b,       \
+                                           iterations, x_init, x_map, fault, s)
+    if (unit_diagonal)
+        return shrt ? DAMAS_GS_LAUNCH(true, SH::short_nh, SH::short_nb)
+                    : DAMAS_GS_LAUNCH(true, SH::long_nh, SH::long_nb);
+    return shrt ? DAMAS_GS_LAUNCH(false, SH::short_nh, SH::short_nb)
+                : DAMAS_GS_LAUNCH(false, SH::long_nh, SH::long_nb);
+#undef DAMAS_GS_LAUNCH
 }
 
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
@@ -420,16 +592,11 @@ hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
     if (n_bins == 0)
         return hipSuccess;
     if (precision == DAMAS_PREC_FP64)
-        return unit_diagonal
-                   ? launch_gs_t<double, double, true>(N, n_bins, s_tilde, max_kept, idx, off,
-                                                       A, b, iterations, x_init, x_map, fault, s)
-                   : launch_gs_t<double, double, false>(N, n_bins, s_tilde, max_kept, idx, off,
-                                                        A, b, iterations, x_init, x_map, fault, s);
-    return unit_diagonal
-               ? launch_gs_t<float, float, true>(N, n_bins, s_tilde, max_kept, idx, off, A, b,
-                                                 iterations, x_init, x_map, fault, s)
-               : launch_gs_t<float, float, false>(N, n_bins, s_tilde, max_kept, idx, off, A, b,
-                                                  iterations, x_init, x_map, fault, s);
+        return launch_gs_u<double, double>(N, n_bins, s_tilde, max_kept, idx, off,
+                                           unit_diagonal, A, b, iterations, x_init, x_map,
+                                           fault, s);
+    return launch_gs_u<float, float>(N, n_bins, s_tilde, max_kept, idx, off, unit_diagonal,
+                                     A, b, iterations, x_init, x_map, fault, s);
 }
 
 } // namespace damas

@@ -217,7 +217,10 @@ def test_gs_hand_cases(dm, dev):
         assert x.tolist() == case["x"], case
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130, 337, 441, 1000])
+# Sizes span one and several 64-row tiles, S~ a multiple of 8 with a partial
+# last tile (72, 136), and strips longer than the part of a strip the stream
+# waves prefetch a tile ahead (256 rows for double A, 384 for float A).
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 72, 130, 136, 257, 337, 385, 441, 1000])
 def test_gs_matches_oracle(orc, dm, dev, n):
     rng = np.random.default_rng(n)
     M = 24
@@ -239,7 +242,7 @@ def test_gs_matches_oracle(orc, dm, dev, n):
     assert np.linalg.norm(x2 - orc.gs(A, bt, 12)) <= 1e-10 * np.linalg.norm(x2)
 
 
-@pytest.mark.parametrize("n", [3, 64, 65, 200])
+@pytest.mark.parametrize("n", [3, 64, 65, 72, 200, 264, 392])
 def test_gs_general_diagonal(orc, dm, dev, n):
     # Symmetric positive definite A with a non-unit diagonal: the sweeps
     # divide by A_ii (scaling variant).
@@ -251,6 +254,8 @@ def test_gs_general_diagonal(orc, dm, dev, n):
         ref = orc.gs(A, bt, it)
         x = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP64)
         assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref), (n, it)
+        x32 = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP32)
+        assert np.linalg.norm(x32 - ref) <= 1e-5 * np.linalg.norm(ref), (n, it)
 
 
 def test_gs_identity_one_sweep(dm, dev):
