@@ -69,6 +69,12 @@ extern "C" {
 #define DAMAS_PREC_FP32 1 /* A stored in float (half the bytes the sweeps
                              stream); steering, the PSF products, b, x and
                              every sweep sum stay double                   */
+#define DAMAS_PREC_BF16 2 /* bulk sweeps on A stored in bf16 (a quarter of
+                             the bytes of double), built on the bf16 matrix
+                             cores with FP32 accumulation; then the last
+                             refine_sweeps sweeps on an FP32 copy of A built
+                             as for DAMAS_PREC_FP32.  x maps are float;
+                             the sweep state and sums stay double          */
 
 /* Scan geometry (section "Beamforming").  The struct itself is host memory;
  * `mic` is a DEVICE pointer to M x 3 doubles (metres, row-major, array in
@@ -153,6 +159,33 @@ int damas_steer(const damas_geometry *g, int32_t n_bins, const double *freq,
                 const int32_t *idx, const int32_t *s_tilde, int32_t max_kept,
                 double *E, int64_t e_stride, void *stream);
 
+/* Half-width of a bf16 steering row: M rounded up to 16. */
+int32_t damas_mp(int32_t M);
+
+/* Steering rows of the kept points in bf16 (round to nearest even of the
+ * double values), for damas_psf_bf16: for bin f and i < s_tilde[f],
+ *   E16[f*e16_stride + i*2MP + m]      = bf16(cos(k |r_n - r_m|))
+ *   E16[f*e16_stride + i*2MP + MP + m] = bf16(-sin(k |r_n - r_m|))
+ * with MP = damas_mp(M); entries m >= M and rows s_tilde[f] <= i <
+ * damas_ld(s_tilde[f]) are zero.  Phases in double as for damas_steer.
+ *   E16       device, n_bins x e16_stride uint16 (bf16 bit patterns)
+ *   e16_stride elements per bin, >= damas_ld(max_kept) * 2MP when n_bins > 1 */
+int damas_steer_bf16(const damas_geometry *g, int32_t n_bins, const double *freq,
+                     const int32_t *idx, const int32_t *s_tilde, int32_t max_kept,
+                     uint16_t *E16, int64_t e16_stride, void *stream);
+
+/* Step 3 on the bf16 matrix cores (section "DAMAS", PSF):
+ *   A16_f[i*ld + j] = bf16(((Re G_ij)^2 + (Im G_ij)^2) / M^2),
+ *   G_ij = sum_m conj(e_im) e_jm over the bf16 steering rows E16
+ * (damas_steer_bf16), both real products with FP32 accumulation, the value
+ * rounded once to bf16 (nearest even).  Same packed layout as damas_psf
+ * (A16_f = A16 + off[f], ld = damas_ld(s_tilde[f])); A16 is bitwise
+ * symmetric, A_ii = 1 exactly, padding rows and columns are 0.
+ *   A16  device, bf16 bit patterns (output) */
+int damas_psf_bf16(int32_t M, int32_t n_bins, const int32_t *s_tilde,
+                   int32_t max_kept, const uint16_t *E16, int64_t e16_stride,
+                   const int64_t *off, uint16_t *A16, void *stream);
+
 /* Step 3 (section "DAMAS", PSF): A_f[i*ld + j] = |sum_m conj(e_im) e_jm|^2 / M^2
  * over the kept points of bin f, ld = damas_ld(s_tilde[f]), A_f = A + off[f].
  * Built from the double steering rows E (damas_steer) as two real products
@@ -171,9 +204,12 @@ int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
  *   r_i = sum_j A_ij x_j - b~_i  (x_j already updated for j < i)
  *   x_i = max(x_i - r_i / A_ii, 0)
  * then x_map[f*S + n] = x~_i at n = idx[f*S + i] and 0 at every other n.
- *   A       device arena of damas_psf's layout (element type by precision)
+ *   A       device arena of damas_psf's layout (element type by precision:
+ *           double, float, or bf16 bit patterns for DAMAS_PREC_BF16)
  *   b       device, n_bins x S doubles
- *   x_init  device, n_bins x S (double for FP64, float for FP32), or NULL
+ *   x_init  device, n_bins x S (double for FP64, float otherwise), or NULL;
+ *           it may be the same buffer as x_map (each bin reads its x_init
+ *           before it writes its x_map)
  *   x_map   device, n_bins x S, same type (output)
  *   unit_diagonal  non-zero promises A_ii = 1 for every kept row (true of
  *                  damas_psf's output); the sweeps then skip the scaling by
@@ -219,6 +255,10 @@ typedef struct {
     int32_t max_kept;          /* EPS_REL: host bound on kept points per bin
                                   (0 = N*N); exceeding it fails with
                                   DAMAS_ECAPACITY                           */
+    int32_t refine_sweeps;     /* DAMAS_PREC_BF16: how many of the
+                                  `iterations` sweeps run last, on the FP32
+                                  copy of A (0 .. iterations); ignored
+                                  otherwise                                 */
 } damas_params;
 
 /* Every step for every bin, device-resident, enqueued on `stream`.

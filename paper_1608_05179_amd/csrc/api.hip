@@ -87,8 +87,17 @@ int check_geometry(const damas_geometry *g)
 
 int check_precision(int32_t p)
 {
-    if (p != DAMAS_PREC_FP64 && p != DAMAS_PREC_FP32)
+    if (p != DAMAS_PREC_FP64 && p != DAMAS_PREC_FP32 && p != DAMAS_PREC_BF16)
         return fail(DAMAS_EINVAL, "unknown precision %d", p);
+    return DAMAS_OK;
+}
+
+// Storage precisions of damas_psf (double steering rows in).
+int check_psf_precision(int32_t p)
+{
+    if (p != DAMAS_PREC_FP64 && p != DAMAS_PREC_FP32)
+        return fail(DAMAS_EINVAL, "damas_psf stores FP64 or FP32 (precision %d); "
+                                  "bf16 systems come from damas_psf_bf16", p);
     return DAMAS_OK;
 }
 
@@ -106,6 +115,12 @@ int check_kept(int32_t max_kept, int32_t S, int32_t precision)
 {
     if (max_kept < 0 || max_kept > S)
         return fail(DAMAS_EINVAL, "max_kept = %d outside [0, N*N = %d]", max_kept, S);
+    // The bf16 path ends with FP32 sweeps: both must fit.
+    if (precision == DAMAS_PREC_BF16 && max_kept > gs_max_kept(DAMAS_PREC_FP32))
+        return fail(DAMAS_EINVAL,
+                    "max_kept = %d exceeds the %d unknowns a sweep workgroup "
+                    "holds on chip for the FP32 refinement sweeps",
+                    max_kept, gs_max_kept(DAMAS_PREC_FP32));
     if (max_kept > gs_max_kept(precision))
         return fail(DAMAS_EINVAL,
                     "max_kept = %d exceeds the %d unknowns a sweep workgroup "
@@ -115,6 +130,14 @@ int check_kept(int32_t max_kept, int32_t S, int32_t precision)
 }
 
 size_t elem_size(int32_t precision)
+{
+    return precision == DAMAS_PREC_FP64   ? sizeof(double)
+           : precision == DAMAS_PREC_FP32 ? sizeof(float)
+                                          : sizeof(uint16_t);
+}
+
+// Element size of the x maps.
+size_t x_size(int32_t precision)
 {
     return precision == DAMAS_PREC_FP64 ? sizeof(double) : sizeof(float);
 }
@@ -169,6 +192,8 @@ extern "C" const char *damas_last_error(void) { return g_err.c_str(); }
 extern "C" int64_t damas_ld(int32_t s_tilde) { return s_tilde < 0 ? 0 : ld_of(s_tilde); }
 
 extern "C" int32_t damas_coarse_count(int32_t N) { return N < 1 ? 0 : coarse_count(N); }
+
+extern "C" int32_t damas_mp(int32_t M) { return M < 1 ? 0 : mp_of(M); }
 
 // ---------------------------------------------------------------------------
 // step-level calls
@@ -259,7 +284,7 @@ extern "C" int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
                          int64_t e_stride, const int64_t *off, void *A,
                          void *stream)
 {
-    int rc = check_precision(precision);
+    int rc = check_psf_precision(precision);
     if (rc)
         return rc;
     if (M < 1 || M > 128)
@@ -276,6 +301,54 @@ extern "C" int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
     HIP_TRY(launch_psf(M, n_bins, s_tilde, max_kept, precision, E, e_stride, off,
                        A, fault, (hipStream_t)stream),
             "psf launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_steer_bf16(const damas_geometry *g, int32_t n_bins,
+                                const double *freq, const int32_t *idx,
+                                const int32_t *s_tilde, int32_t max_kept, uint16_t *E16,
+                                int64_t e16_stride, void *stream)
+{
+    int rc = check_geometry(g);
+    if (rc)
+        return rc;
+    const int32_t S = g->N * g->N;
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    if (max_kept < 0 || max_kept > S)
+        return fail(DAMAS_EINVAL, "max_kept = %d outside [0, N*N]", max_kept);
+    if (n_bins > 0 && (!freq || !idx || !s_tilde || !E16))
+        return fail(DAMAS_EINVAL, "freq, idx, s_tilde and E16 must be non-NULL");
+    if (n_bins > 1 && e16_stride < ld_of(max_kept) * 2 * mp_of(g->M))
+        return fail(DAMAS_EINVAL, "e16_stride < damas_ld(max_kept) * 2 * damas_mp(M)");
+    int *fault;
+    if ((rc = fault_word(&fault)))
+        return rc;
+    HIP_TRY(launch_steer16(make_geom(*g), n_bins, freq, idx, s_tilde, max_kept, E16,
+                           e16_stride, fault, (hipStream_t)stream),
+            "steer16 launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_psf_bf16(int32_t M, int32_t n_bins, const int32_t *s_tilde,
+                              int32_t max_kept, const uint16_t *E16, int64_t e16_stride,
+                              const int64_t *off, uint16_t *A16, void *stream)
+{
+    if (M < 1 || M > 128)
+        return fail(DAMAS_EINVAL, "M = %d outside [1, 128]", M);
+    if (n_bins < 0 || max_kept < 0)
+        return fail(DAMAS_EINVAL, "n_bins and max_kept must be >= 0");
+    if (n_bins > 0 && (!s_tilde || !E16 || !off || !A16))
+        return fail(DAMAS_EINVAL, "s_tilde, E16, off and A16 must be non-NULL");
+    if (n_bins > 1 && e16_stride < ld_of(max_kept) * 2 * mp_of(M))
+        return fail(DAMAS_EINVAL, "e16_stride < damas_ld(max_kept) * 2 * damas_mp(M)");
+    int *fault;
+    int rc = fault_word(&fault);
+    if (rc)
+        return rc;
+    HIP_TRY(launch_psf16(M, n_bins, s_tilde, max_kept, E16, e16_stride, off, A16, fault,
+                         (hipStream_t)stream),
+            "psf16 launch");
     return DAMAS_OK;
 }
 
@@ -319,7 +392,7 @@ struct Buffer {
 
 struct damas_ctx {
     int device = 0;
-    Buffer b, idx, st, kc, off, E, A;
+    Buffer b, idx, st, kc, off, E, A, E16, A32;
     // keep counts last uploaded to kc (skip identical re-uploads)
     std::vector<int32_t> kc_host;
     int32_t *kc_pinned = nullptr;
@@ -395,7 +468,8 @@ extern "C" void damas_ctx_destroy(damas_ctx *ctx)
         return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A})
+    for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
+                      &ctx->E16, &ctx->A32})
         if (b->p)
             (void)hipFree(b->p);
     if (ctx->kc_pinned)
@@ -458,6 +532,86 @@ extern "C" int damas_check(damas_ctx *ctx, void *stream)
     return DAMAS_OK;
 }
 
+namespace {
+
+// Device buffers and launch parameters of one solve.
+struct SolvePlan {
+    Geom kg;
+    int32_t N, M, S;
+    const damas_params *p;
+    int32_t bulk, refine;       // sweeps on the storage precision / FP32 copy
+    int64_t e_stride, e16_stride;
+    int64_t a_elems;
+    double *bm;
+    int32_t *ix, *st;
+    int64_t *off;
+    const int32_t *kc;
+    int *fault;
+};
+
+// Everything after the DAS map and the selection for bins [f0, f0 + nb)
+// (arrays offset by the caller): layout, steering, PSF(s) and sweeps.
+int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
+                              int32_t max_kept, const double *freq, double *bm,
+                              int32_t *ix, int32_t *st, const void *x_init, void *x_map,
+                              hipStream_t s)
+{
+    const damas_params *p = P.p;
+    HIP_TRY(launch_layout(nb, st, max_kept, P.a_elems, P.off, P.fault, s), "layout launch");
+    const bool bf16 = p->precision == DAMAS_PREC_BF16;
+    // Storage-precision system (bulk sweeps) and, for BF16, the FP32 copy.
+    if (!bf16 || P.refine > 0) {
+        HIP_TRY(launch_steer(P.kg, nb, freq, ix, st, max_kept, (double *)ctx->E.p, P.e_stride,
+                             P.fault, s),
+                "steer launch");
+        HIP_TRY(launch_psf(P.M, nb, st, max_kept, bf16 ? DAMAS_PREC_FP32 : p->precision,
+                           (const double *)ctx->E.p, P.e_stride, P.off,
+                           bf16 ? ctx->A32.p : ctx->A.p, P.fault, s),
+                "psf launch");
+    }
+    if (bf16 && P.bulk > 0) {
+        HIP_TRY(launch_steer16(P.kg, nb, freq, ix, st, max_kept, (uint16_t *)ctx->E16.p,
+                               P.e16_stride, P.fault, s),
+                "steer16 launch");
+        HIP_TRY(launch_psf16(P.M, nb, st, max_kept, (const uint16_t *)ctx->E16.p,
+                             P.e16_stride, P.off, (uint16_t *)ctx->A.p, P.fault, s),
+                "psf16 launch");
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    int rc;
+    if (ctx->timing) {
+        if ((rc = pop_events(ctx, &ev)))
+            return rc;
+        HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
+    }
+    if (!bf16) {
+        HIP_TRY(launch_gs(P.N, nb, st, max_kept, ix, P.off, p->precision, 1, ctx->A.p, bm,
+                          p->iterations, x_init, x_map, P.fault, s),
+                "gs launch");
+    } else {
+        // Bulk sweeps on bf16 A, then the refinement sweeps on the FP32
+        // copy, warm-started from the bulk result in place.
+        const void *xi = x_init;
+        if (P.bulk > 0 || P.refine == 0) {
+            HIP_TRY(launch_gs(P.N, nb, st, max_kept, ix, P.off, DAMAS_PREC_BF16, 1, ctx->A.p,
+                              bm, P.bulk, xi, x_map, P.fault, s),
+                    "gs launch (bf16)");
+            xi = x_map;
+        }
+        if (P.refine > 0)
+            HIP_TRY(launch_gs(P.N, nb, st, max_kept, ix, P.off, DAMAS_PREC_FP32, 1,
+                              ctx->A32.p, bm, P.refine, xi, x_map, P.fault, s),
+                    "gs launch (fp32 refinement)");
+    }
+    if (ctx->timing) {
+        HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
+        ctx->gs_events.push_back(ev);
+    }
+    return DAMAS_OK;
+}
+
+} // namespace
+
 extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
                                int32_t n_bins, const double *freq,
                                const double *csm, const damas_params *p,
@@ -475,6 +629,10 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
         return rc;
     if (n_bins < 0 || p->iterations < 0)
         return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
+    const bool bf16 = p->precision == DAMAS_PREC_BF16;
+    if (bf16 && (p->refine_sweeps < 0 || p->refine_sweeps > p->iterations))
+        return fail(DAMAS_EINVAL, "refine_sweeps = %d outside [0, iterations = %d]",
+                    p->refine_sweeps, p->iterations);
     if (n_bins == 0)
         return DAMAS_OK;
     if (!freq || !csm || !x_map)
@@ -506,20 +664,30 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
 
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    const size_t es = elem_size(p->precision);
+    const size_t es = elem_size(p->precision), xs = x_size(p->precision);
     const bool batched = p->batched != 0;
     const int64_t ldm = ld_of(max_kept);
-    const int64_t e_stride = ldm * 2 * M;
-    int64_t a_elems = 0;
+    SolvePlan P;
+    P.kg = make_geom(*g);
+    P.N = N;
+    P.M = M;
+    P.S = S;
+    P.p = p;
+    P.refine = bf16 ? p->refine_sweeps : 0;
+    P.bulk = p->iterations - P.refine;
+    P.e_stride = ldm * 2 * M;
+    P.e16_stride = ldm * 2 * mp_of(M);
     if (!batched) {
-        a_elems = ldm * ldm;
+        P.a_elems = ldm * ldm;
     } else if (!st_host.empty()) {
+        P.a_elems = 0;
         for (int32_t v : st_host)
-            a_elems += ld_of(v) * ld_of(v);
+            P.a_elems += ld_of(v) * ld_of(v);
     } else {
-        a_elems = (int64_t)n_bins * ldm * ldm;
+        P.a_elems = (int64_t)n_bins * ldm * ldm;
     }
     const int nb_ws = batched ? n_bins : 1;
+    const bool need64 = !bf16 || P.refine > 0, need16 = bf16 && P.bulk > 0;
 
     if (!b_map && (rc = ensure(ctx, ctx->b, sizeof(double) * (size_t)n_bins * S, s, "b")))
         return rc;
@@ -527,17 +695,26 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
         return rc;
     if (!s_tilde && (rc = ensure(ctx, ctx->st, sizeof(int32_t) * (size_t)n_bins, s, "s_tilde")))
         return rc;
-    if ((rc = ensure(ctx, ctx->off, sizeof(int64_t) * (size_t)(nb_ws + 1), s, "offsets")) ||
-        (rc = ensure(ctx, ctx->E, sizeof(double) * (size_t)e_stride * nb_ws, s,
-                     "steering rows")) ||
-        (rc = ensure(ctx, ctx->A, es * (size_t)a_elems, s, "A arena")))
+    if ((rc = ensure(ctx, ctx->off, sizeof(int64_t) * (size_t)(nb_ws + 1), s, "offsets")))
         return rc;
-    double *bm = b_map ? b_map : (double *)ctx->b.p;
-    int32_t *ix = idx ? idx : (int32_t *)ctx->idx.p;
-    int32_t *st = s_tilde ? s_tilde : (int32_t *)ctx->st.p;
-    int64_t *off = (int64_t *)ctx->off.p;
+    if (need64 && (rc = ensure(ctx, ctx->E, sizeof(double) * (size_t)P.e_stride * nb_ws, s,
+                               "steering rows")))
+        return rc;
+    if (need16 && (rc = ensure(ctx, ctx->E16, sizeof(uint16_t) * (size_t)P.e16_stride * nb_ws,
+                               s, "bf16 steering rows")))
+        return rc;
+    if ((need16 || !bf16) &&
+        (rc = ensure(ctx, ctx->A, es * (size_t)P.a_elems, s, "A arena")))
+        return rc;
+    if (bf16 && P.refine > 0 &&
+        (rc = ensure(ctx, ctx->A32, sizeof(float) * (size_t)P.a_elems, s, "FP32 A arena")))
+        return rc;
+    P.bm = b_map ? b_map : (double *)ctx->b.p;
+    P.ix = idx ? idx : (int32_t *)ctx->idx.p;
+    P.st = s_tilde ? s_tilde : (int32_t *)ctx->st.p;
+    P.off = (int64_t *)ctx->off.p;
 
-    const int32_t *kc = nullptr;
+    P.kc = nullptr;
     if (p->select_mode == DAMAS_SEL_KEEP_COUNT) {
         std::vector<int32_t> want(n_bins);
         for (int f = 0; f < n_bins; ++f)
@@ -563,39 +740,17 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
             HIP_TRY(hipEventRecord(ctx->kc_done, s), "hipEventRecord");
             ctx->kc_host = want;
         }
-        kc = (const int32_t *)ctx->kc.p;
+        P.kc = (const int32_t *)ctx->kc.p;
     }
-
-    int *fault;
-    if ((rc = fault_word(&fault)))
+    if ((rc = fault_word(&P.fault)))
         return rc;
-    const Geom kg = make_geom(*g);
 
     if (batched) {
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (ctx->timing && (rc = pop_events(ctx, &ev)))
-            return rc;
-        HIP_TRY(launch_das(kg, n_bins, freq, csm, bm, s), "das launch");
-        HIP_TRY(launch_select(N, n_bins, bm, p->select_mode, p->eps, kc, ix, st, s),
+        HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s), "das launch");
+        HIP_TRY(launch_select(N, n_bins, P.bm, p->select_mode, p->eps, P.kc, P.ix, P.st, s),
                 "select launch");
-        HIP_TRY(launch_layout(n_bins, st, max_kept, a_elems, off, fault, s),
-                "layout launch");
-        HIP_TRY(launch_steer(kg, n_bins, freq, ix, st, max_kept, (double *)ctx->E.p,
-                             e_stride, fault, s),
-                "steer launch");
-        HIP_TRY(launch_psf(M, n_bins, st, max_kept, p->precision, (const double *)ctx->E.p,
-                           e_stride, off, ctx->A.p, fault, s),
-                "psf launch");
-        if (ctx->timing)
-            HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
-        HIP_TRY(launch_gs(N, n_bins, st, max_kept, ix, off, p->precision, 1, ctx->A.p,
-                          bm, p->iterations, x_init, x_map, fault, s),
-                "gs launch");
-        if (ctx->timing) {
-            HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
-            ctx->gs_events.push_back(ev);
-        }
-        return DAMAS_OK;
+        return enqueue_system_and_sweeps(ctx, P, n_bins, max_kept, freq, P.bm, P.ix, P.st,
+                                         x_init, x_map, s);
     }
 
     // Plain: each bin on its own, one launch per step; A, E and the layout
@@ -603,33 +758,16 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
     for (int f = 0; f < n_bins; ++f) {
         const int32_t mk = st_host.empty() ? max_kept : st_host[f];
         const size_t fS = (size_t)f * S;
-        const char *xi = x_init ? (const char *)x_init + es * fS : nullptr;
-        char *xm = (char *)x_map + es * fS;
-        HIP_TRY(launch_das(kg, 1, freq + f, csm + (size_t)f * M * M * 2, bm + fS, s),
+        const char *xi = x_init ? (const char *)x_init + xs * fS : nullptr;
+        char *xm = (char *)x_map + xs * fS;
+        HIP_TRY(launch_das(P.kg, 1, freq + f, csm + (size_t)f * M * M * 2, P.bm + fS, s),
                 "das launch");
-        HIP_TRY(launch_select(N, 1, bm + fS, p->select_mode, p->eps, kc ? kc + f : nullptr,
-                              ix + fS, st + f, s),
+        HIP_TRY(launch_select(N, 1, P.bm + fS, p->select_mode, p->eps, P.kc ? P.kc + f : nullptr,
+                              P.ix + fS, P.st + f, s),
                 "select launch");
-        HIP_TRY(launch_layout(1, st + f, mk, a_elems, off, fault, s), "layout launch");
-        HIP_TRY(launch_steer(kg, 1, freq + f, ix + fS, st + f, mk, (double *)ctx->E.p,
-                             e_stride, fault, s),
-                "steer launch");
-        HIP_TRY(launch_psf(M, 1, st + f, mk, p->precision, (const double *)ctx->E.p,
-                           e_stride, off, ctx->A.p, fault, s),
-                "psf launch");
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (ctx->timing) {
-            if ((rc = pop_events(ctx, &ev)))
-                return rc;
-            HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
-        }
-        HIP_TRY(launch_gs(N, 1, st + f, mk, ix + fS, off, p->precision, 1, ctx->A.p,
-                          bm + fS, p->iterations, xi, xm, fault, s),
-                "gs launch");
-        if (ctx->timing) {
-            HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
-            ctx->gs_events.push_back(ev);
-        }
+        if ((rc = enqueue_system_and_sweeps(ctx, P, 1, mk, freq + f, P.bm + fS, P.ix + fS,
+                                            P.st + f, xi, xm, s)))
+            return rc;
     }
     return DAMAS_OK;
 }

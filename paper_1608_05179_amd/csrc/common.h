@@ -100,6 +100,16 @@ hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                       int precision, const double *E, int64_t e_stride,
                       const int64_t *off, void *A, int *fault, hipStream_t s);
 
+// bf16 steering rows (half-width MP = M rounded up to 16) and the PSF on the
+// bf16 matrix cores.
+int mp_of(int M);
+hipError_t launch_steer16(const Geom &g, int n_bins, const double *freq, const int32_t *idx,
+                          const int32_t *s_tilde, int max_kept, uint16_t *E, int64_t e_stride,
+                          int *fault, hipStream_t s);
+hipError_t launch_psf16(int M, int n_bins, const int32_t *s_tilde, int max_kept,
+                        const uint16_t *E, int64_t e_stride, const int64_t *off, uint16_t *A,
+                        int *fault, hipStream_t s);
+
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                      const int32_t *idx, const int64_t *off, int precision,
                      int unit_diagonal, const void *A, const double *b, int iterations,

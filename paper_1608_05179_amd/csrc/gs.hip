@@ -595,6 +595,9 @@ hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
         return launch_gs_u<double, double>(N, n_bins, s_tilde, max_kept, idx, off,
                                            unit_diagonal, A, b, iterations, x_init, x_map,
                                            fault, s);
+    if (precision == DAMAS_PREC_BF16)
+        return launch_gs_u<bf16s, float>(N, n_bins, s_tilde, max_kept, idx, off, unit_diagonal,
+                                         A, b, iterations, x_init, x_map, fault, s);
     return launch_gs_u<float, float>(N, n_bins, s_tilde, max_kept, idx, off, unit_diagonal,
                                      A, b, iterations, x_init, x_map, fault, s);
 }

@@ -199,6 +199,217 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
             }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 path: steering rows in bf16 and the PSF on the bf16 matrix cores.
+//
+// Row i of E16 (per bin, stride e16_stride elements) is
+//   [er_0 .. er_{MP-1} | ei_0 .. ei_{MP-1}],  er = cos(k d), ei = -sin(k d),
+// MP = M rounded up to 16 (padding zero), K = 2 MP a multiple of 32.  With
+// P_i = row i and Q_j = [ei_j | -er_j]:
+//   Re G_ij = P_i . P_j,   Im G_ij = P_i . Q_j,
+// so both are real products over K on v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation).  Q_j is P_j read half a row further on, the sign flipped on
+// its second half.
+
+__device__ inline uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7fffu + ((u >> 16) & 1u); // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+int mp_of(int M) { return (M + 15) & ~15; }
+
+__global__ __launch_bounds__(256) void steer16_kernel(
+    Geom g, const double *__restrict__ freq, const int32_t *__restrict__ idx,
+    const int32_t *__restrict__ s_tilde, int max_kept, uint16_t *__restrict__ E,
+    int64_t e_stride, int *fault)
+{
+    const int f = blockIdx.y;
+    int St = s_tilde[f];
+    if (St > max_kept) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(fault, 1);
+        St = 0;
+    }
+    const int64_t ld = ld_of(St);
+    const int M = g.M, MP = (M + 15) & ~15;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / MP;
+    const int m = (int)(t % MP);
+    if (i >= ld)
+        return;
+    uint16_t *row = E + (int64_t)f * e_stride + i * 2 * MP;
+    uint16_t c16 = 0, s16 = 0;
+    if (i < St && m < M) {
+        const int S = g.N * g.N;
+        const int n = idx[(int64_t)f * S + i];
+        const double k = kTwoPi * freq[f] / g.c;
+        double s, c;
+        sincos(k * point_mic_dist(g, n, m), &s, &c);
+        c16 = f32_to_bf16_rne((float)c);
+        s16 = f32_to_bf16_rne((float)(-s));
+    }
+    row[m] = c16;
+    row[MP + m] = s16;
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPsf16Pitch = kPsfTile + 8; // bf16 per LDS row of the staged tile
+
+// One 64 x 64 tile (I <= J) of the bf16 A per 256-thread workgroup; wave w
+// computes the 32 x 32 quadrant (w >> 1, w & 1) as 2 x 2 blocks of 16 x 16.
+// MFMA operand layout: lane l holds row l % 16 of its block, k = 8 (l / 16)
+// .. +7 of the current 32-wide k step (16 contiguous bytes of a row); the
+// accumulator element v of lane l is D[4 (l / 16) + v][l % 16].
+__global__ __launch_bounds__(kPsfThreads) void psf16_kernel(
+    int M, const int32_t *__restrict__ s_tilde, int max_kept,
+    const uint16_t *__restrict__ E, int64_t e_stride, const int64_t *__restrict__ off,
+    uint16_t *__restrict__ A, int *fault)
+{
+    __shared__ uint16_t T[kPsfTile * kPsf16Pitch];
+
+    const int f = blockIdx.y;
+    const int St = s_tilde[f];
+    if (St > max_kept) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(fault, 2);
+        return;
+    }
+    const int64_t ld = ld_of(St);
+    const int nt = (int)((ld + kPsfTile - 1) / kPsfTile);
+    const int t = blockIdx.x;
+    if (t >= nt * (nt + 1) / 2)
+        return;
+    int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (J * (J + 1) / 2 > t)
+        --J;
+    while ((J + 1) * (J + 2) / 2 <= t)
+        ++J;
+    const int I = t - J * (J + 1) / 2;
+    const int64_t I0 = (int64_t)I * kPsfTile, J0 = (int64_t)J * kPsfTile;
+
+    const int MP = (M + 15) & ~15, K = 2 * MP;
+    const uint16_t *Ef = E + (int64_t)f * e_stride;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    // Rows past ld read row 0 (their results are never stored).
+    const uint16_t *pa[2], *pb[2];
+    for (int a = 0; a < 2; ++a) {
+        const int64_t r = I0 + wr * 32 + a * 16 + lr;
+        pa[a] = Ef + (r < ld ? r : 0) * K;
+    }
+    for (int c = 0; c < 2; ++c) {
+        const int64_t r = J0 + wc * 32 + c * 16 + lr;
+        pb[c] = Ef + (r < ld ? r : 0) * K;
+    }
+
+    f32x4 re[2][2], im[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c) {
+            re[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            im[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    for (int kk = 0; kk < K; kk += 32) {
+        const int k0 = kk + 8 * lg;                 // this lane's 8 k values
+        const int kq = k0 < MP ? k0 + MP : k0 - MP; // Q_j = P_j shifted by MP
+        const uint32_t qsign = k0 < MP ? 0u : 0x80008000u;
+        bf16x8 xa[2], xb[2], xq[2];
+        for (int a = 0; a < 2; ++a)
+            xa[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pa[a] + k0));
+        for (int c = 0; c < 2; ++c) {
+            xb[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pb[c] + k0));
+            uint4 q = *reinterpret_cast<const uint4 *>(pb[c] + kq);
+            q.x ^= qsign;
+            q.y ^= qsign;
+            q.z ^= qsign;
+            q.w ^= qsign;
+            xq[c] = __builtin_bit_cast(bf16x8, q);
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 2; ++c) {
+                re[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[a], xb[c], re[a][c], 0, 0, 0);
+                im[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[a], xq[c], im[a][c], 0, 0, 0);
+            }
+    }
+
+    // A = (Re^2 + Im^2) / M^2 in FP32, rounded once to bf16, staged in LDS.
+    const float inv = 1.0f / ((float)M * (float)M);
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c)
+            for (int v = 0; v < 4; ++v) {
+                const int r = wr * 32 + a * 16 + 4 * lg + v, col = wc * 32 + c * 16 + lr;
+                const float x = re[a][c][v], y = im[a][c][v];
+                T[r * kPsf16Pitch + col] = f32_to_bf16_rne((x * x + y * y) * inv);
+            }
+    __syncthreads();
+
+    // Coalesced stores of 8 bf16 per thread: the tile at (I, J) and, for
+    // I < J, its transpose at (J, I).  A diagonal tile mirrors its upper
+    // half, so A is bitwise symmetric; A_ii = 1 on kept rows, 0 on padding.
+    uint16_t *Af = A + off[f];
+    const bool diag = I == J;
+    for (int e = threadIdx.x; e < kPsfTile * kPsfTile / 8; e += kPsfThreads) {
+        const int r = e / (kPsfTile / 8), c0 = (e % (kPsfTile / 8)) * 8;
+        uint16_t v8[8];
+        uint16_t w8[8];
+        for (int s = 0; s < 8; ++s) {
+            const int c = c0 + s;
+            uint16_t v;
+            if (!diag || c > r)
+                v = T[r * kPsf16Pitch + c];
+            else if (c < r)
+                v = T[c * kPsf16Pitch + r];
+            else
+                v = I0 + r < St ? (uint16_t)0x3f80 : (uint16_t)0; // 1.0 or 0
+            v8[s] = v;
+            w8[s] = T[c * kPsf16Pitch + r]; // transpose: row c0.. of (J, I)
+        }
+        // e indexes (row r, cols c0..c0+7) of the tile; the transposed store
+        // writes row c of (J, I) -- here the roles of r and c swap, so the
+        // transpose is written as (row r of (J,I)) = column r of T.
+        if (I0 + r < ld && J0 + c0 < ld)
+            *reinterpret_cast<uint4 *>(&Af[(I0 + r) * ld + J0 + c0]) =
+                make_uint4(v8[0] | ((uint32_t)v8[1] << 16), v8[2] | ((uint32_t)v8[3] << 16),
+                           v8[4] | ((uint32_t)v8[5] << 16), v8[6] | ((uint32_t)v8[7] << 16));
+        if (!diag && J0 + r < ld && I0 + c0 < ld)
+            *reinterpret_cast<uint4 *>(&Af[(J0 + r) * ld + I0 + c0]) =
+                make_uint4(w8[0] | ((uint32_t)w8[1] << 16), w8[2] | ((uint32_t)w8[3] << 16),
+                           w8[4] | ((uint32_t)w8[5] << 16), w8[6] | ((uint32_t)w8[7] << 16));
+    }
+}
+
+hipError_t launch_steer16(const Geom &g, int n_bins, const double *freq, const int32_t *idx,
+                          const int32_t *s_tilde, int max_kept, uint16_t *E, int64_t e_stride,
+                          int *fault, hipStream_t s)
+{
+    if (n_bins == 0 || max_kept == 0)
+        return hipSuccess;
+    const int64_t work = ld_of(max_kept) * mp_of(g.M);
+    dim3 grid((unsigned)((work + 255) / 256), n_bins);
+    hipLaunchKernelGGL(steer16_kernel, grid, dim3(256), 0, s, g, freq, idx, s_tilde, max_kept,
+                       E, e_stride, fault);
+    return hipGetLastError();
+}
+
+hipError_t launch_psf16(int M, int n_bins, const int32_t *s_tilde, int max_kept,
+                        const uint16_t *E, int64_t e_stride, const int64_t *off, uint16_t *A,
+                        int *fault, hipStream_t s)
+{
+    if (n_bins == 0 || max_kept == 0)
+        return hipSuccess;
+    const int64_t nt = (ld_of(max_kept) + kPsfTile - 1) / kPsfTile;
+    dim3 grid((unsigned)(nt * (nt + 1) / 2), n_bins);
+    hipLaunchKernelGGL(psf16_kernel, grid, dim3(kPsfThreads), 0, s, M, s_tilde, max_kept, E,
+                       e_stride, off, A, fault);
+    return hipGetLastError();
+}
+
 hipError_t launch_steer(const Geom &g, int n_bins, const double *freq,
                         const int32_t *idx, const int32_t *s_tilde,
                         int max_kept, double *E, int64_t e_stride, int *fault,

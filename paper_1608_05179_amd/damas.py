@@ -30,8 +30,11 @@ SEL_KEEP_COUNT = 2
 
 PREC_FP64 = 0
 PREC_FP32 = 1
+PREC_BF16 = 2
 
-_DTYPE = {PREC_FP64: torch.float64, PREC_FP32: torch.float32}
+# Element type of A by precision, and of the x maps.
+_DTYPE = {PREC_FP64: torch.float64, PREC_FP32: torch.float32, PREC_BF16: torch.bfloat16}
+_XTYPE = {PREC_FP64: torch.float64, PREC_FP32: torch.float32, PREC_BF16: torch.float32}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -55,7 +58,7 @@ class Params(ctypes.Structure):
     _fields_ = [("select_mode", c_i32), ("eps", c_dbl),
                 ("keep_count", ctypes.POINTER(c_i32)), ("keep_count_all", c_i32),
                 ("iterations", c_i32), ("precision", c_i32), ("batched", c_i32),
-                ("max_kept", c_i32)]
+                ("max_kept", c_i32), ("refine_sweeps", c_i32)]
 
 
 def _sig(name, res, *args):
@@ -69,12 +72,15 @@ _sig("damas_strerror", ctypes.c_char_p, ctypes.c_int)
 _sig("damas_last_error", ctypes.c_char_p)
 _sig("damas_ld", c_i64, c_i32)
 _sig("damas_coarse_count", c_i32, c_i32)
+_sig("damas_mp", c_i32, c_i32)
 _G = ctypes.POINTER(Geometry)
 _sig("damas_das_map", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_select", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_layout", ctypes.c_int, c_i32, c_vp, c_i32, c_i64, c_vp, c_vp)
 _sig("damas_steer", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i64, c_vp)
 _sig("damas_psf", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp)
+_sig("damas_steer_bf16", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i64, c_vp)
+_sig("damas_psf_bf16", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp)
 _sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp,
      c_vp, c_i32, c_vp, c_vp, c_vp)
 _sig("damas_ctx_create", ctypes.c_int, c_i32, ctypes.POINTER(c_vp))
@@ -113,6 +119,11 @@ def ld(s_tilde: int) -> int:
 def coarse_count(N: int) -> int:
     """Points of the coarsest grid G^0, always kept."""
     return int(_lib.damas_coarse_count(int(N)))
+
+
+def mp(M: int) -> int:
+    """Half-width of a bf16 steering row (M rounded up to 16)."""
+    return int(_lib.damas_mp(int(M)))
 
 
 def _ptr(t, dtype=None, name="tensor"):
@@ -207,20 +218,48 @@ def psf(M: int, s_tilde, max_kept: int, precision: int, E, off, A=None, stream=N
     return A
 
 
+def steer_bf16(g: Geometry, freq, idx, s_tilde, max_kept: int, stream=None):
+    """bf16 steering rows of the kept points: (n_bins, ld(max_kept), 2 mp(M))
+    torch.bfloat16, [cos | -sin] each padded to mp(M) mics."""
+    nb = freq.numel()
+    L = ld(max_kept)
+    K = 2 * mp(g.M)
+    E = torch.zeros(nb, L, K, dtype=torch.bfloat16, device=freq.device)
+    _check(_lib.damas_steer_bf16(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
+                                 _ptr(idx, torch.int32, "idx"),
+                                 _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
+                                 _ptr(E, torch.bfloat16, "E16"), L * K, _stream(stream)))
+    return E
+
+
+def psf_bf16(M: int, s_tilde, max_kept: int, E16, off, A=None, stream=None):
+    """Packed bf16 A arena of all bins (flat torch.bfloat16, off[-1] elements),
+    built on the bf16 matrix cores."""
+    nb = s_tilde.numel()
+    if A is None:
+        total = int(off[-1].item())
+        A = torch.full((max(total, 1),), float("nan"), dtype=torch.bfloat16, device=off.device)
+    _check(_lib.damas_psf_bf16(int(M), nb, _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
+                               _ptr(E16, torch.bfloat16, "E16"), E16.shape[1] * E16.shape[2],
+                               _ptr(off, torch.int64, "off"), _ptr(A, torch.bfloat16, "A16"),
+                               _stream(stream)))
+    return A
+
+
 def gs(N: int, s_tilde, max_kept: int, idx, off, precision: int, A, b, iterations: int,
        x_init=None, x_map=None, unit_diagonal=False, stream=None):
     """Non-negative Gauss-Seidel sweeps; returns x_map (n_bins, N*N).
     unit_diagonal: A_ii = 1 for every row (true of psf()'s output)."""
     nb = s_tilde.numel()
-    dt = _DTYPE[precision]
+    dt, xt = _DTYPE[precision], _XTYPE[precision]
     if x_map is None:
-        x_map = torch.empty(nb, N * N, dtype=dt, device=b.device)
+        x_map = torch.empty(nb, N * N, dtype=xt, device=b.device)
     _check(_lib.damas_gs(int(N), nb, _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
                          _ptr(idx, torch.int32, "idx"), _ptr(off, torch.int64, "off"),
                          int(precision), 1 if unit_diagonal else 0, _ptr(A, dt, "A"),
                          _ptr(b, torch.float64, "b"),
-                         int(iterations), _ptr(x_init, dt, "x_init"),
-                         _ptr(x_map, dt, "x_map"), _stream(stream)))
+                         int(iterations), _ptr(x_init, xt, "x_init"),
+                         _ptr(x_map, xt, "x_map"), _stream(stream)))
     return x_map
 
 
@@ -263,8 +302,8 @@ class Context:
 
     def solve(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
               keep_count=None, iterations=1000, precision=PREC_FP32, batched=True,
-              max_kept=0, x_init=None, x_map=None, b_map=None, idx=None, s_tilde=None,
-              stream=None):
+              max_kept=0, refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
+              s_tilde=None, stream=None):
         """Every step for every bin on the device; returns x_map.
 
         keep_count: an int, or a sequence of per-bin ints (host values)."""
@@ -272,7 +311,7 @@ class Context:
         nb = freq.numel()
         S = g.N * g.N
         if x_map is None:
-            x_map = torch.empty(nb, S, dtype=_DTYPE[precision], device=freq.device)
+            x_map = torch.empty(nb, S, dtype=_XTYPE[precision], device=freq.device)
         kc_arr = None
         kc_all = 0
         if keep_count is not None:
@@ -286,8 +325,8 @@ class Context:
         p = Params(int(select_mode), float(eps),
                    ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
                    int(kc_all), int(iterations), int(precision), 1 if batched else 0,
-                   int(max_kept))
-        dt = _DTYPE[precision]
+                   int(max_kept), int(refine_sweeps))
+        dt = _XTYPE[precision]
         _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
                                     _ptr(freq, torch.float64, "freq"),
                                     _ptr(csm, torch.float64, "csm"), ctypes.byref(p),

@@ -47,6 +47,7 @@ def test_layout_helpers(lib):
     # |G^0| = 4 unless N is a power of two (then only index 0 of each axis)
     assert [lib.damas_coarse_count(n) for n in (1, 2, 3, 4, 5, 16, 17, 21, 41, 101)] == \
         [1, 1, 4, 1, 4, 1, 4, 4, 4, 4]
+    assert [lib.damas_mp(m) for m in (0, 1, 16, 17, 64, 128)] == [0, 16, 16, 32, 64, 128]
 
 
 def test_coarse_count_matches_oracle(lib, orc):
@@ -89,6 +90,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert dm._lib.damas_layout(1, None, 10, 100, fake, None) == dm.EINVAL
     assert dm._lib.damas_psf(0, 1, fake, 10, dm.PREC_FP32, fake, 1000, fake, fake, None) == dm.EINVAL
     assert dm._lib.damas_psf(16, 2, fake, 10, dm.PREC_FP32, fake, 10, fake, fake, None) == dm.EINVAL
+    # bf16 steering / PSF checks; damas_psf stores only double or float
+    gb = ctypes.byref(G(16, 0x1000, 21, -1, 1, -1, 1, 1, 343.0))
+    assert dm._lib.damas_steer_bf16(gb, 2, fake, fake, fake, 100, fake, 10, None) == dm.EINVAL
+    assert dm._lib.damas_steer_bf16(gb, 1, fake, fake, fake, 442, fake, 0, None) == dm.EINVAL
+    assert dm._lib.damas_psf_bf16(129, 1, fake, 10, fake, 0, fake, fake, None) == dm.EINVAL
+    assert dm._lib.damas_psf_bf16(16, 2, fake, 100, fake, 10, fake, fake, None) == dm.EINVAL
+    assert dm._lib.damas_psf(16, 1, fake, 10, dm.PREC_BF16, fake, 1000, fake, fake, None) == dm.EINVAL
+    assert b"damas_psf_bf16" in lib.damas_last_error()
     # whole-path: NULL context / NULL params
     assert dm._lib.damas_solve_dev(None, ctypes.byref(G(16, 0x1000, 21, -1, 1, -1, 1, 1, 343.0)),
                                    1, fake, fake, None, None, fake, None, None, None,

@@ -1,0 +1,223 @@
+"""Parity of the BF16 storage path (bulk sweeps on A in bf16, built on the
+bf16 matrix cores, then FP32 refinement sweeps) with the FP64 oracle.
+
+Bars:
+  - bf16 steering rows: bit-exact, each the double value rounded to float
+    and then to bf16 (nearest even);
+  - bf16 A: within one bf16 ulp (2^-7 relative) plus 2e-5 of the same
+    product formed in double from the same bf16 steering rows (the products
+    are exact in FP32; FP32 accumulation can move a value across a rounding
+    boundary); bitwise symmetric, unit diagonal, zero padding.  A wrong MFMA
+    operand layout gives errors of order 1;
+  - sweeps on a bf16-valued A: within 1e-10 of the oracle's iterate on the
+    same values in double;
+  - whole path with enough refinement sweeps: within 1e-4 relative L2 of the
+    oracle's FP64 iterate; with every sweep refined it equals the FP32 path
+    bitwise.
+"""
+import numpy as np
+import pytest
+
+from paper_1608_05179_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dtype)
+
+
+def _bf16_bits(x):
+    """Round to float, then to bf16 (nearest even): uint16 bit patterns."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def _bf16_value(bits):
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _bits_of(t):
+    import torch
+    return t.view(torch.int16).cpu().numpy().view(np.uint16)
+
+
+def _kept_system(orc, dm, dev, w, f, K):
+    import torch
+    og = orc.Geometry(w.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    b = orc.das_map(og, w.freqs[f], w.csm[f])
+    idx, _, _ = orc.select(w.N, b, orc.SEL_KEEP_COUNT, keep_count=K)
+    return og, b, idx
+
+
+@pytest.mark.parametrize("M,N,K", [(64, 41, 337), (16, 21, 130), (128, 23, 200), (5, 9, 70)])
+def test_steer_and_psf_bf16(orc, dm, dev, M, N, K):
+    import torch
+    if M == 64:
+        w = synth.compressed_fp32(n_bins=3, N=N)
+    else:
+        w = synth.custom(synth.disc_array(M, 0.5, (40 + M,)), N, (-1.0, 1.0, -1.0, 1.0), 1.2,
+                         [2500.0, 6000.0], [3, N * N // 2], [1.0, 0.7])
+    nb = w.n_bins
+    kept = [_kept_system(orc, dm, dev, w, f, K)[1:] for f in range(nb)]
+    st = np.array([len(k[1]) for k in kept], np.int32)
+    mk = int(st.max())
+    idx = np.zeros((nb, N * N), np.int32)
+    for f in range(nb):
+        idx[f, :st[f]] = kept[f][1]
+    mic = _t(w.mic, torch.float64, dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    freq = _t(w.freqs, torch.float64, dev)
+    st_d, idx_d = _t(st, torch.int32, dev), _t(idx, torch.int32, dev)
+    E16 = dm.steer_bf16(g, freq, idx_d, st_d, mk)
+    off = dm.layout(st_d, mk)
+    A16 = dm.psf_bf16(w.M, st_d, mk, E16, off)
+    Eb = _bits_of(E16)
+    Ab = _bits_of(A16)
+    offh = off.cpu().numpy()
+    og = orc.Geometry(w.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    MP = dm.mp(M)
+    for f in range(nb):
+        n = int(st[f])
+        L = dm.ld(n)
+        e = orc.steering(og, w.freqs[f], idx[f, :n])
+        want = np.zeros((L, 2 * MP), np.uint16)
+        want[:n, :M] = _bf16_bits(e.real)
+        want[:n, MP:MP + M] = _bf16_bits(e.imag)
+        assert np.array_equal(Eb[f, :L], want), f
+        # A from the same bf16 rows, in double
+        P = _bf16_value(want[:n])
+        er, ei = P[:, :MP], P[:, MP:]
+        G = (er + 1j * ei).conj() @ (er + 1j * ei).T
+        ref = (np.abs(G) ** 2) / (M * M)
+        Af = _bf16_value(Ab[offh[f]:offh[f + 1]]).reshape(L, L)
+        np.fill_diagonal(ref, 1.0)
+        err = np.abs(Af[:n, :n] - ref)
+        assert (err <= 2.0 ** -7 * ref + 2e-5).all(), (f, err.max())
+        # against the oracle's FP64 A: bf16 inputs and storage only
+        assert np.abs(Af[:n, :n] - orc.psf(e)).max() < 2e-2, f
+        sym = Ab[offh[f]:offh[f + 1]].reshape(L, L)
+        assert np.array_equal(sym, sym.T), f
+        assert (np.diag(Af)[:n] == 1.0).all()
+        assert (Af[n:, :] == 0).all() and (Af[:, n:] == 0).all()
+
+
+@pytest.mark.parametrize("n", [5, 64, 130, 337, 700])
+def test_gs_on_bf16_values(orc, dm, dev, n):
+    """Sweeps read bf16 A exactly: the same iterate as the oracle on the
+    bf16 values in double."""
+    import torch
+    rng = np.random.default_rng(500 + n)
+    e = np.exp(1j * rng.uniform(0, 2 * np.pi, size=(n, 32)))
+    A = _bf16_value(_bf16_bits(orc.psf(e)))
+    bt = np.abs(rng.standard_normal(n)) * 0.3
+    N = int(np.ceil(np.sqrt(n)))
+    L = dm.ld(n)
+    Ap = np.zeros((L, L))
+    Ap[:n, :n] = A
+    bits = _bf16_bits(Ap.ravel())
+    A_d = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16)
+    b = np.zeros((1, N * N))
+    b[0, :n] = bt
+    idx = np.zeros((1, N * N), np.int32)
+    idx[0, :n] = np.arange(n)
+    st = _t(np.array([n], np.int32), torch.int32, dev)
+    off = _t(np.array([0, L * L]), torch.int64, dev)
+    for it in (1, 7, 60):
+        x = dm.gs(N, st, n, _t(idx, torch.int32, dev), off, dm.PREC_BF16, A_d,
+                  _t(b, torch.float64, dev), it, unit_diagonal=True)
+        x = x.double().cpu().numpy()[0, :n]
+        ref = orc.gs(A, bt, it)
+        # x maps are float: one rounding of each value
+        assert np.linalg.norm(x - ref) <= 1e-6 * np.linalg.norm(ref), (n, it)
+
+
+def _solve(dm, dev, w, K, prec, refine=0, iters=None):
+    import torch
+    mic = _t(w.mic, torch.float64, dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    ctx = dm.Context(0)
+    st = torch.zeros(w.n_bins, dtype=torch.int32, device=dev)
+    idx = torch.zeros(w.n_bins, w.S, dtype=torch.int32, device=dev)
+    mode = dm.SEL_KEEP_COUNT if K else dm.SEL_KEEP_ALL
+    x = ctx.solve(g, _t(w.freqs, torch.float64, dev), _t(w.csm, torch.complex128, dev),
+                  select_mode=mode, keep_count=K if K else None,
+                  iterations=iters or w.iterations, precision=prec, refine_sweeps=refine,
+                  idx=idx, s_tilde=st)
+    ctx.check()
+    out = x.double().cpu().numpy(), st.cpu().numpy(), idx.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def _errors_vs_oracle(orc, w, K, x, st, idx, iters):
+    """Per bin: (rel-L2 of x, rel-L2 of A x, relative error of sum x)
+    against the oracle's FP64 iterate; kept indices must match."""
+    og = orc.Geometry(w.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    mode = orc.SEL_KEEP_COUNT if K else orc.SEL_KEEP_ALL
+    out = []
+    for f in range(w.n_bins):
+        ref = orc.solve_bin(og, w.freqs[f], w.csm[f], mode, keep_count=K, iters=iters)
+        if ref["margin"] > 1e-12:
+            assert np.array_equal(idx[f, :st[f]], ref["idx"]), f
+        A = orc.psf(orc.steering(og, w.freqs[f], ref["idx"]))
+        xr, xg = ref["x"][ref["idx"]], x[f][ref["idx"]]
+        out.append((np.linalg.norm(x[f] - ref["x"]) / np.linalg.norm(ref["x"]),
+                    np.linalg.norm(A @ (xg - xr)) / np.linalg.norm(A @ xr),
+                    abs(xg.sum() - xr.sum()) / xr.sum()))
+    return out
+
+
+# With A in bf16 the iterate after I sweeps depends on A's rounding by a
+# factor that grows with the bin's conditioning (wide main lobe, low
+# frequency): refinement sweeps on the FP32 copy bring well-conditioned bins
+# to FP64 parity, while in ill-conditioned bins only A x and the integrated
+# power stay at the bf16 level unless nearly every sweep is refined.
+
+
+def test_solve_bf16_refined_compressed(orc, dm, dev):
+    # 64-mic spiral, 41 x 41 grid, keep 20 %, 400 sweeps of which the last 60
+    # run on the FP32 copy of A; bins at 1.0, 3.3, 5.7 and 8 kHz.
+    full = synth.compressed_fp32(keep_frac=0.2)
+    w = synth.compressed_fp32(keep_frac=0.2)
+    pick = [0, 21, 42, 63]
+    w.freqs, w.csm = full.freqs[pick], full.csm[pick]
+    x, st, idx = _solve(dm, dev, w, w.keep_count, dm.PREC_BF16, refine=60, iters=400)
+    err = _errors_vs_oracle(orc, w, w.keep_count, x, st, idx, 400)
+    for f, (ex, eax, ep) in enumerate(err):
+        assert eax <= 2e-3 and ep <= 2e-3, (f, err[f])
+    assert err[2][0] <= 1e-4 and err[3][0] <= 1e-4, err
+
+
+def test_solve_bf16_refined_keep_all(orc, dm, dev):
+    # The precision workload's array and sources on a 33 x 33 grid, no
+    # compression (1089 unknowns), bins at 6.1 and 10 kHz, 300 sweeps, the
+    # last 60 in FP32.
+    full = synth.precision_bf16(n_bins=32, N=33, iterations=300)
+    w = synth.precision_bf16(n_bins=32, N=33, iterations=300)
+    w.freqs, w.csm = full.freqs[[16, 31]], full.csm[[16, 31]]
+    x, st, idx = _solve(dm, dev, w, 0, dm.PREC_BF16, refine=60)
+    for f, e in enumerate(_errors_vs_oracle(orc, w, 0, x, st, idx, 300)):
+        assert e[0] <= 1e-4, (f, e)
+
+
+def test_bf16_all_refined_equals_fp32(dm, dev):
+    w = synth.compressed_fp32(n_bins=3, N=21, iterations=80)
+    a, _, _ = _solve(dm, dev, w, w.keep_count, dm.PREC_BF16, refine=80)
+    b, _, _ = _solve(dm, dev, w, w.keep_count, dm.PREC_FP32)
+    assert np.array_equal(a, b)
+
+
+def test_bf16_no_refinement_runs_on_bf16(orc, dm, dev):
+    # refine_sweeps = 0: every sweep on the bf16 A; the result is the
+    # oracle's iterate on the bf16-rounded system's neighbourhood, far from
+    # FP64 parity but finite, non-negative and zero off the kept set.
+    w = synth.compressed_fp32(n_bins=2, N=21, iterations=50)
+    x, st, idx = _solve(dm, dev, w, w.keep_count, dm.PREC_BF16, refine=0)
+    assert np.isfinite(x).all() and (x >= 0).all()
+    for f in range(w.n_bins):
+        off = np.ones(w.S, bool)
+        off[idx[f, :st[f]]] = False
+        assert (x[f, off] == 0).all()
