@@ -1,21 +1,30 @@
 """Throughput of the wavelet-compressed DAMAS path on one MI355X.
 
-Workload (the benchmarked configuration): a 64-mic five-arm log-spiral array
-of radius 0.6 m, a 41 x 41 scan grid on a 2 x 2 m plane 1.5 m away, 64
-frequency bins over 1-8 kHz, 5 uncorrelated sources, CSMs averaged over 1024
-complex-Gaussian snapshots at 20 dB SNR; each bin keeps the 20 % of grid
-points with the largest wavelet detail (S~ = 337) and runs 1000 Gauss-Seidel
-sweeps.  A step is one whole solve of all 64 bins: DAS map, selection,
-layout, steering rows, PSF build and sweeps, all on the GPU, with inputs
-already resident in HBM.
+Headline workload (the benchmarked configuration): a 64-mic five-arm
+log-spiral array of radius 0.6 m, a 41 x 41 scan grid on a 2 x 2 m plane
+1.5 m away, 64 frequency bins over 1-8 kHz, 5 uncorrelated sources, CSMs
+averaged over 1024 complex-Gaussian snapshots at 20 dB SNR; each bin keeps
+the 20 % of grid points with the largest wavelet detail (S~ = 337) and runs
+1000 Gauss-Seidel sweeps with A stored in float.  A step is one whole solve
+of all 64 bins: DAS map, selection, layout, steering rows, PSF build and
+sweeps, all on the GPU, with inputs already resident in HBM.
 
-Prints one JSON line.  Extra keys beyond the throughput line:
+Prints one JSON line.  Beyond the throughput keys:
   latency_ms     p50 / p99 of the per-step solve time (HIP events)
   plain          the same solve as one launch per step per bin
   roofline       the sweep kernel's algorithmic A bytes over its measured
-                 launch time (HIP events on the solve's stream), against HBM
+                 launch time (HIP events recorded by the library on the
+                 solve's stream), against HBM peak
   cpu_baseline   the FP64 oracle on the host, on a bounded sample of bins,
                  and the GPU result's relative L2 error against it
+  variants       the other workloads at their full sizes (plain FP64 on a
+                 21 x 21 grid; BF16 storage with FP32 refinement on 81 x 81,
+                 32 bins; uneven compressed grids over 256 bins), each with
+                 throughput, latency and the roofline of its sweeps and, for
+                 BF16, of the PSF build on the bf16 matrix cores.
+
+--workload NAME measures one workload alone (compressed, plain, precision,
+batched) and prints its record as the line.
 """
 import argparse
 import hashlib
@@ -30,6 +39,7 @@ if ROOT not in sys.path:
 
 METRIC = "DAMAS grid-point updates/s + p50/p99 solve latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_traffic.json")
 GS_SOURCE = os.path.join(ROOT, "paper_1608_05179_amd", "csrc", "gs.hip")
 
@@ -39,10 +49,16 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="per-bin (plain) solves timed for the comparison; 0 skips them")
     ap.add_argument("--cpu-bins", type=int, default=64,
                     help="bins of the workload the oracle solves for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--workload", default=None,
+                    choices=["compressed", "plain", "precision", "batched"])
+    ap.add_argument("--refine", type=int, default=60,
+                    help="FP32 refinement sweeps of the precision workload")
     return ap.parse_args()
 
 
@@ -51,7 +67,7 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
-def _traffic(launch_bytes):
+def _traffic():
     """HBM bytes per sweep launch from the committed counter summary, if it
     was taken on the current sweep kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -64,48 +80,71 @@ def _traffic(launch_bytes):
     return t.get("hbm_bytes_per_launch")
 
 
-def main():
-    args = _parse()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(bins shard across GPUs with no exchange, but only the one-GPU path is built)",
-              file=sys.stderr)
-        sys.exit(2)
+def _workload(name, refine):
+    """(synthetic workload, select mode, precision, refine sweeps, label)."""
+    from paper_1608_05179_amd import damas as dm
+    from paper_1608_05179_amd import synth
+    if name == "compressed":
+        w = synth.compressed_fp32(keep_frac=0.2)
+        return (w, dm.SEL_KEEP_COUNT, dm.PREC_FP32, 0,
+                "compressed-fp32: M=64 spiral, 41x41 grid, 64 bins 1-8 kHz, keep 20% "
+                "(S~=337), 1000 sweeps, A stored f32")
+    if name == "plain":
+        w = synth.plain_fp64()
+        return (w, dm.SEL_KEEP_ALL, dm.PREC_FP64, 0,
+                "plain-fp64: M=16 disc, 21x21 grid (S=441), 1 bin 4 kHz, exact CSM, "
+                "500 sweeps, A stored f64")
+    if name == "precision":
+        w = synth.precision_bf16(refine_sweeps=refine)
+        return (w, dm.SEL_KEEP_ALL, dm.PREC_BF16, refine,
+                f"precision-bf16: M=64 spiral, 81x81 grid (S=6561), 32 bins 2-10 kHz, "
+                f"keep all, 1000 sweeps: {1000 - refine} on bf16 A + {refine} on f32 A")
+    w = synth.batched_fp32()
+    return (w, dm.SEL_KEEP_COUNT, dm.PREC_FP32, 0,
+            "batched-fp32: M=128 disc, 101x101 grid, 256 bins 0.5-12 kHz, keep "
+            "U{300..4000} per bin, 2000 sweeps, A stored f32")
 
+
+def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False):
+    """Time `steps` batched solves of a workload; returns its record."""
     import numpy as np
     import torch
 
     from paper_1608_05179_amd import damas as dm
-    from paper_1608_05179_amd import synth
 
+    w, mode, prec, R, label = _workload(name, refine)
     dev = torch.device("cuda:0")
-    w = synth.compressed_fp32(keep_frac=0.2)
-    K = w.keep_count
     I = w.iterations
+    K = None
+    if mode == dm.SEL_KEEP_COUNT:
+        K = [int(v) for v in w.keep_counts] if w.keep_counts is not None else int(w.keep_count)
     mic = torch.tensor(w.mic, dtype=torch.float64, device=dev)
     g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
     freq = torch.tensor(w.freqs, dtype=torch.float64, device=dev)
     csm = torch.view_as_real(torch.tensor(w.csm, dtype=torch.complex128)).contiguous().to(dev)
-    x = torch.empty(w.n_bins, w.S, dtype=torch.float32, device=dev)
+    xt = torch.float64 if prec == dm.PREC_FP64 else torch.float32
+    x = torch.empty(w.n_bins, w.S, dtype=xt, device=dev)
     st = torch.zeros(w.n_bins, dtype=torch.int32, device=dev)
+    idx = torch.zeros(w.n_bins, w.S, dtype=torch.int32, device=dev)
     ctx = dm.Context(0)
     stream = torch.cuda.current_stream()
 
     def step(batched=True):
-        ctx.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=K, iterations=I,
-                  precision=dm.PREC_FP32, batched=batched, x_map=x, s_tilde=st)
+        ctx.solve(g, freq, csm, select_mode=mode, keep_count=K, iterations=I,
+                  precision=prec, batched=batched, refine_sweeps=R, x_map=x, s_tilde=st,
+                  idx=idx)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     ctx.check()
     s_tilde = st.cpu().numpy().astype(np.int64)
     updates = int(s_tilde.sum()) * I
 
-    # ---- timed region: K batched solves ----------------------------------
     ctx.set_timing(True)
-    ctx.gs_time()  # clear
+    ctx.phase_time(dm.PHASE_SWEEPS)
+    ctx.phase_time(dm.PHASE_SYSTEM)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+          for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for e0, e1 in ev:
@@ -115,45 +154,113 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.check()
-    gs_ms, gs_n = ctx.gs_time()
+    gs_ms, gs_n = ctx.phase_time(dm.PHASE_SWEEPS)
+    sys_ms, sys_n = ctx.phase_time(dm.PHASE_SYSTEM)
     ctx.set_timing(False)
     lat = [e0.elapsed_time(e1) for e0, e1 in ev]
-    ms_step = wall * 1e3 / args.steps
-    value = updates / (wall / args.steps)
+    ms_step = wall * 1e3 / steps
 
-    # ---- plain per-bin launches (same work) ------------------------------
-    step(batched=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.plain_steps):
-        step(batched=False)
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
-    ctx.check()
-
-    # ---- roofline of the sweep kernel ------------------------------------
-    a_bytes = int((s_tilde * s_tilde).sum()) * I * 4  # A elements read per launch (float)
-    gs_avg_ms = gs_ms / max(gs_n, 1)
-    achieved = a_bytes / (gs_avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": _traffic(a_bytes), "kernel": "gs_kernel<float,float>",
-            "kernel_avg_ms": round(gs_avg_ms, 4), "algorithmic_bytes": a_bytes}
-
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "grid-point updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "compressed-fp32: M=64 spiral, 41x41 grid, 64 bins 1-8 kHz, "
-                               "keep 20% (S~=337), 1000 sweeps, A stored f32",
-                   "bins": w.n_bins, "s_tilde": int(s_tilde.max()), "iterations": I,
-                   "a_storage": "f32", "updates_per_step": updates},
+    # Sweeps: S~^2 elements of A per sweep per bin, at the storage width
+    # (bf16 bulk sweeps and f32 refinement sweeps for the precision path).
+    sq = int((s_tilde * s_tilde).sum())
+    if prec == dm.PREC_FP64:
+        a_bytes, a_kind = sq * I * 8, "f64"
+    elif prec == dm.PREC_FP32:
+        a_bytes, a_kind = sq * I * 4, "f32"
+    else:
+        a_bytes, a_kind = sq * ((I - R) * 2 + R * 4), "bf16+f32"
+    gs_avg = gs_ms / max(gs_n, 1)
+    achieved = a_bytes / (gs_avg * 1e-3) / 1e9
+    rec = {
+        "workload": label, "bins": w.n_bins, "iterations": I,
+        "s_tilde_min": int(s_tilde.min()), "s_tilde_max": int(s_tilde.max()),
+        "updates_per_step": updates,
+        "value": round(updates / (ms_step * 1e-3), 1), "unit": "grid-point updates/s",
+        "ms_per_step": round(ms_step, 4),
         "latency_ms": {"p50": round(_pct(lat, 50), 4), "p99": round(_pct(lat, 99), 4)},
-        "plain": {"value": round(updates / (plain_ms * 1e-3), 1), "ms_per_step": round(plain_ms, 3),
-                  "batched_speedup": round(plain_ms / ms_step, 2)},
-        "roofline": roof,
+        "sweeps_ms": round(gs_avg, 4), "system_build_ms": round(sys_ms / max(sys_n, 1), 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "kernel": f"gs_kernel (A {a_kind})", "kernel_avg_ms": round(gs_avg, 4),
+                     "algorithmic_bytes": a_bytes},
     }
+
+    if plain_steps > 0:
+        step(batched=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(plain_steps):
+            step(batched=False)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3 / plain_steps
+        ctx.check()
+        rec["plain"] = {"value": round(updates / (plain_ms * 1e-3), 1),
+                        "ms_per_step": round(plain_ms, 3),
+                        "batched_speedup": round(plain_ms / ms_step, 2)}
+
+    if psf_kernel_time and prec == dm.PREC_BF16:
+        # The bf16 PSF kernel alone (step-level call on the same kept sets),
+        # timed with events on the stream it is launched on.
+        mk = int(s_tilde.max())
+        E16 = dm.steer_bf16(g, freq, idx, st, mk)
+        off = dm.layout(st, mk)
+        A16 = dm.psf_bf16(w.M, st, mk, E16, off)
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dm.psf_bf16(w.M, st, mk, E16, off, A=A16)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        psf_ms = e0.elapsed_time(e1) / reps
+        ent = int(sum(v * (v + 1) // 2 for v in s_tilde))   # distinct entries
+        flops = ent * 8 * w.M                                # 8M flops per entry
+        wbytes = sq * 2                                      # both triangles, bf16
+        tf = flops / (psf_ms * 1e-3) / 1e12
+        rec["psf_bf16"] = {"bound": "mfma", "achieved": round(tf, 2),
+                           "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4),
+                           "kernel_avg_ms": round(psf_ms, 4), "algorithmic_flops": flops,
+                           "write_GBs": round(wbytes / (psf_ms * 1e-3) / 1e9, 1),
+                           "write_frac_of_hbm": round(wbytes / (psf_ms * 1e-3) / 1e9
+                                                      / HBM_PEAK_GBS, 4)}
+        del A16, E16
+    ctx.close()
+    return rec, w, x, st
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(bins shard across GPUs with no exchange, but only the one-GPU path is built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch  # noqa: F401
+
+    if args.workload is not None:
+        rec, _, _, _ = measure(args.workload, args.steps, args.warmup, args.plain_steps,
+                               refine=args.refine, psf_kernel_time=True)
+        print(json.dumps(rec), flush=True)
+        return
+
+    rec, w, x, st = measure("compressed", args.steps, args.warmup, args.plain_steps)
+    rec["roofline"]["traffic"] = _traffic()
+    out = {
+        "metric": METRIC, "value": rec["value"], "unit": rec["unit"],
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": rec["workload"], "bins": rec["bins"],
+                   "s_tilde": rec["s_tilde_max"], "iterations": rec["iterations"],
+                   "a_storage": "f32", "updates_per_step": rec["updates_per_step"]},
+        "latency_ms": rec["latency_ms"],
+        "roofline": rec["roofline"],
+    }
+    if "plain" in rec:
+        out["plain"] = rec["plain"]
 
     # ---- CPU baseline: the oracle on a bounded sample of bins ------------
     if not args.no_cpu:
@@ -168,17 +275,25 @@ def main():
         refs = []
         for f in bins:
             refs.append(oracle.solve_bin(og, w.freqs[f], w.csm[f], oracle.SEL_KEEP_COUNT,
-                                         keep_count=K, iters=I))
+                                         keep_count=w.keep_count, iters=w.iterations))
         cpu_t = time.perf_counter() - t0
         for f, r in zip(bins, refs):
             worst = max(worst, float(np.linalg.norm(xg[f] - r["x"]) / np.linalg.norm(r["x"])))
-        cpu_updates = sum(len(r["idx"]) for r in refs) * I
+        cpu_updates = sum(len(r["idx"]) for r in refs) * w.iterations
         out["cpu_baseline"] = {"value": round(cpu_updates / cpu_t, 1),
                                "unit": "grid-point updates/s", "cores": 1, "kind": "oracle",
                                "sample": f"{nb} of {w.n_bins} bins, whole path per bin, "
                                          f"{cpu_t:.1f} s single-threaded FP64 C",
                                "gpu_max_rel_l2_vs_oracle": float(f"{worst:.3e}")}
-    ctx.close()
+
+    # ---- the other workloads at full size ---------------------------------
+    if not args.no_variants:
+        out["variants"] = {}
+        for name, steps in (("plain", 5), ("precision", 2), ("batched", 2)):
+            v, _, _, _ = measure(name, steps, 1, 0, refine=args.refine,
+                                 psf_kernel_time=True)
+            out["variants"][name] = v
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -233,12 +233,19 @@ typedef struct damas_ctx damas_ctx;
 int damas_ctx_create(int32_t device, damas_ctx **out);
 void damas_ctx_destroy(damas_ctx *ctx);
 
-/* Timing of the Gauss-Seidel launches: when enabled, each damas_solve_dev
- * records HIP events around its sweep launch(es) on the solve's stream;
- * damas_ctx_gs_time returns the summed milliseconds and launch count of the
- * recorded launches that have completed (it synchronises on them) and
- * clears the record. */
+/* Timing of the phases of a solve: when enabled, each damas_solve_dev
+ * records HIP events on the solve's stream around
+ *   DAMAS_PHASE_SWEEPS  its Gauss-Seidel launch(es) (bulk and refinement),
+ *   DAMAS_PHASE_SYSTEM  its steering and PSF launches (the system build),
+ * once per batched solve or once per bin of a plain solve.
+ * damas_ctx_phase_time returns the summed milliseconds and count of the
+ * recorded intervals of one phase (it synchronises on them) and clears that
+ * phase's record; damas_ctx_gs_time is the sweeps phase. */
+#define DAMAS_PHASE_SWEEPS 0
+#define DAMAS_PHASE_SYSTEM 1
+#define DAMAS_PHASES 2
 int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled);
+int damas_ctx_phase_time(damas_ctx *ctx, int32_t phase, double *ms, int64_t *launches);
 int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches);
 
 /* Parameters of a solve (host struct). */

@@ -399,7 +399,8 @@ struct damas_ctx {
     size_t kc_pinned_n = 0;
     hipEvent_t kc_done = nullptr;
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> gs_events, event_pool;
+    // recorded (start, end) event pairs per timed phase, and spare pairs
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> phase_events[DAMAS_PHASES], event_pool;
 };
 
 namespace {
@@ -476,7 +477,7 @@ extern "C" void damas_ctx_destroy(damas_ctx *ctx)
         (void)hipHostFree(ctx->kc_pinned);
     if (ctx->kc_done)
         (void)hipEventDestroy(ctx->kc_done);
-    for (auto *v : {&ctx->gs_events, &ctx->event_pool})
+    for (auto *v : {&ctx->phase_events[0], &ctx->phase_events[1], &ctx->event_pool})
         for (auto &e : *v) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -492,13 +493,17 @@ extern "C" int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled)
     return DAMAS_OK;
 }
 
-extern "C" int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches)
+extern "C" int damas_ctx_phase_time(damas_ctx *ctx, int32_t phase, double *ms,
+                                    int64_t *launches)
 {
     if (!ctx || !ms || !launches)
         return fail(DAMAS_EINVAL, "NULL argument");
+    if (phase < 0 || phase >= DAMAS_PHASES)
+        return fail(DAMAS_EINVAL, "unknown phase %d", phase);
     double total = 0.0;
     int64_t n = 0;
-    for (auto &e : ctx->gs_events) {
+    auto &evs = ctx->phase_events[phase];
+    for (auto &e : evs) {
         HIP_TRY(hipEventSynchronize(e.second), "hipEventSynchronize");
         float t = 0.f;
         HIP_TRY(hipEventElapsedTime(&t, e.first, e.second), "hipEventElapsedTime");
@@ -506,10 +511,15 @@ extern "C" int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches)
         ++n;
         ctx->event_pool.push_back(e);
     }
-    ctx->gs_events.clear();
+    evs.clear();
     *ms = total;
     *launches = n;
     return DAMAS_OK;
+}
+
+extern "C" int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches)
+{
+    return damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, ms, launches);
 }
 
 extern "C" int damas_check(damas_ctx *ctx, void *stream)
@@ -559,6 +569,13 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
     const damas_params *p = P.p;
     HIP_TRY(launch_layout(nb, st, max_kept, P.a_elems, P.off, P.fault, s), "layout launch");
     const bool bf16 = p->precision == DAMAS_PREC_BF16;
+    int rc;
+    std::pair<hipEvent_t, hipEvent_t> evb{};
+    if (ctx->timing) {
+        if ((rc = pop_events(ctx, &evb)))
+            return rc;
+        HIP_TRY(hipEventRecord(evb.first, s), "hipEventRecord");
+    }
     // Storage-precision system (bulk sweeps) and, for BF16, the FP32 copy.
     if (!bf16 || P.refine > 0) {
         HIP_TRY(launch_steer(P.kg, nb, freq, ix, st, max_kept, (double *)ctx->E.p, P.e_stride,
@@ -578,8 +595,9 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
                 "psf16 launch");
     }
     std::pair<hipEvent_t, hipEvent_t> ev{};
-    int rc;
     if (ctx->timing) {
+        HIP_TRY(hipEventRecord(evb.second, s), "hipEventRecord");
+        ctx->phase_events[DAMAS_PHASE_SYSTEM].push_back(evb);
         if ((rc = pop_events(ctx, &ev)))
             return rc;
         HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
@@ -605,7 +623,7 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
     }
     if (ctx->timing) {
         HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
-        ctx->gs_events.push_back(ev);
+        ctx->phase_events[DAMAS_PHASE_SWEEPS].push_back(ev);
     }
     return DAMAS_OK;
 }

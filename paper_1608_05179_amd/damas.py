@@ -87,6 +87,10 @@ _sig("damas_ctx_create", ctypes.c_int, c_i32, ctypes.POINTER(c_vp))
 _sig("damas_ctx_destroy", None, c_vp)
 _sig("damas_ctx_set_timing", ctypes.c_int, c_vp, c_i32)
 _sig("damas_ctx_gs_time", ctypes.c_int, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64))
+_sig("damas_ctx_phase_time", ctypes.c_int, c_vp, c_i32, ctypes.POINTER(c_dbl),
+     ctypes.POINTER(c_i64))
+PHASE_SWEEPS = 0
+PHASE_SYSTEM = 1
 _sig("damas_solve_dev", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
      c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_check", ctypes.c_int, c_vp, c_vp)
@@ -296,8 +300,14 @@ class Context:
     def gs_time(self):
         """(milliseconds, launches) of the timed sweep launches since the
         last call."""
+        return self.phase_time(PHASE_SWEEPS)
+
+    def phase_time(self, phase: int):
+        """(milliseconds, intervals) of a timed phase (PHASE_SWEEPS or
+        PHASE_SYSTEM) since its last read."""
         ms, n = c_dbl(), c_i64()
-        _check(_lib.damas_ctx_gs_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        _check(_lib.damas_ctx_phase_time(self._h, int(phase), ctypes.byref(ms),
+                                         ctypes.byref(n)))
         return ms.value, n.value
 
     def solve(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
