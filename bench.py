@@ -21,7 +21,10 @@ Prints one JSON line.  Beyond the throughput keys:
                  21 x 21 grid; BF16 storage with FP32 refinement on 81 x 81,
                  32 bins; uneven compressed grids over 256 bins), each with
                  throughput, latency and the roofline of its sweeps and, for
-                 BF16, of the PSF build on the bf16 matrix cores.
+                 BF16, of the PSF build on the bf16 matrix cores; and the
+                 served workload (Poisson arrivals on the request server) with
+                 p50/p99 latency and updates/s at the specified and at a
+                 sustainable rate.
 
 --workload NAME measures one workload alone (compressed, plain, precision,
 batched) and prints its record as the line.
@@ -56,7 +59,7 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--workload", default=None,
-                    choices=["compressed", "plain", "precision", "batched"])
+                    choices=["compressed", "plain", "precision", "batched", "served"])
     ap.add_argument("--refine", type=int, default=60,
                     help="FP32 refinement sweeps of the precision workload")
     return ap.parse_args()
@@ -229,6 +232,65 @@ def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False):
     return rec, w, x, st
 
 
+def measure_served(n_pool=24, n_trace=40, rate=200.0, n_sustained=16, slots=4):
+    """The served workload: requests arrive as a Poisson process and run on
+    the request server (footprint admission, PSF cache, `slots` concurrent
+    streams).  Two traces: the specified arrival rate (oversubscribed, so
+    latency is mostly queueing), then a sustainable rate of 0.6 x the
+    completion rate the first trace measured.  Requests are drawn in turn
+    from a pool of distinct synthetic scenes, so repeats can hit the cache."""
+    import numpy as np
+
+    from paper_1608_05179_amd import damas as dm
+    from paper_1608_05179_amd import synth
+
+    pool = [synth.served_request(i) for i in range(n_pool)]
+    srv = dm.Server(device=0, hbm_budget=200 << 30, cache_budget=48 << 30, slots=slots,
+                    max_queue=4096)
+
+    def submit(w):
+        return srv.submit(w.mic, w.N, (w.x0, w.x1, w.y0, w.y1), w.z0, w.freqs, w.csm,
+                          select_mode=dm.SEL_KEEP_COUNT, keep_count=w.keep_count,
+                          iterations=w.iterations, precision=dm.PREC_FP32)
+
+    def trace(lam, n, seed):
+        rng = np.random.default_rng(np.random.SeedSequence([5, 100 + seed]))
+        arrive = np.cumsum(rng.exponential(1.0 / lam, size=n))
+        t0 = time.perf_counter()
+        sub = []
+        for i in range(n):
+            delay = t0 + arrive[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            w = pool[(seed * 7 + i) % n_pool]
+            sub.append((submit(w), w))
+        lat, upd, hits = [], 0, 0
+        for t, w in sub:
+            _, st, info = srv.wait(t)
+            lat.append(info["total_ms"])
+            upd += int(st.sum()) * w.iterations
+            hits += info["cache_hit"]
+        wall = time.perf_counter() - t0
+        return {"offered_req_s": lam, "requests": n,
+                "completed_req_s": round(n / wall, 3),
+                "value": round(upd / wall, 1), "unit": "grid-point updates/s",
+                "latency_ms": {"p50": round(_pct(lat, 50), 1), "p99": round(_pct(lat, 99), 1)},
+                "cache_hits": hits, "wall_s": round(wall, 2)}
+
+    # one warm request so library set-up is not in the first latency
+    srv.wait(submit(pool[0]))
+    spec = trace(rate, n_trace, 0)
+    lam_s = max(0.6 * spec["completed_req_s"], 0.05)
+    sus = trace(lam_s, n_sustained, 1)
+    stats = srv.stats()
+    srv.close()
+    return {"workload": f"served: Poisson arrivals, pool of {n_pool} requests (M=64 spiral, "
+                        "N 41-101, 1-64 bins of the 1-8 kHz table, K 200-6000, 1000 sweeps, "
+                        f"f32), {slots} stream slots",
+            "specified_rate": spec, "sustainable_rate": sus,
+            "cache": {"hits": stats["cache_hits"], "misses": stats["cache_misses"]}}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -240,6 +302,9 @@ def main():
     import numpy as np
     import torch  # noqa: F401
 
+    if args.workload == "served":
+        print(json.dumps(measure_served()), flush=True)
+        return
     if args.workload is not None:
         rec, _, _, _ = measure(args.workload, args.steps, args.warmup, args.plain_steps,
                                refine=args.refine, psf_kernel_time=True)
@@ -294,6 +359,7 @@ def main():
                                  psf_kernel_time=True)
             out["variants"][name] = v
             torch.cuda.empty_cache()
+        out["variants"]["served"] = measure_served()
     print(json.dumps(out), flush=True)
 
 

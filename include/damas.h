@@ -286,6 +286,97 @@ int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
  * capacity failure (DAMAS_ECAPACITY) or a HIP error. */
 int damas_check(damas_ctx *ctx, void *stream);
 
+/* Device bytes a whole-path solve of this shape holds (host only, no device
+ * work): inputs (mic, freq, CSM), the x map and s_tilde, and a context's
+ * workspace (b, kept indices, offsets, steering rows, the A arena(s)).
+ * EPS_REL is sized by params->max_kept (0 = N*N).  The request server
+ * admits requests by this figure. */
+int damas_query_footprint(int32_t M, int32_t N, int32_t n_bins, const damas_params *p,
+                          uint64_t *bytes);
+
+/* ---- request server ---------------------------------------------------- */
+
+/* A server runs whole-path solves submitted from any host thread.  Worker
+ * threads, one per stream slot, take requests in arrival order; a request
+ * starts when its footprint (damas_query_footprint) fits the HBM budget
+ * beside the workspaces the slots hold and the PSF cache (least recently
+ * used cache entries are dropped, and idle slots release their workspaces,
+ * to make room).  Slots keep their device workspace (the A arenas) between
+ * requests.  The PSF cache keeps built systems in HBM, keyed by geometry,
+ * frequencies, precision and the kept points of every bin, so a repeated
+ * scene skips its steering and PSF launches (the key needs the kept points
+ * on the host: one stream synchronisation per cached request).  Batched
+ * solves only.  The server is thread-safe. */
+typedef struct damas_server damas_server;
+
+typedef struct {
+    int32_t device;        /* HIP device ordinal                            */
+    uint64_t hbm_budget;   /* bytes the server may hold on the device
+                              (workspaces, in-flight inputs and the cache)   */
+    uint64_t cache_budget; /* bytes of the PSF cache (0 disables it)         */
+    int32_t slots;         /* concurrent requests (streams), >= 1            */
+    int32_t max_queue;     /* waiting requests at most (DAMAS_EBUSY beyond)  */
+} damas_server_opts;
+
+/* One solve request; every pointer is HOST memory.  Inputs are copied at
+ * submission.  The outputs are written by the server and must stay valid
+ * until damas_wait retires the ticket (or damas_poll reports it done). */
+typedef struct {
+    int32_t M;
+    const double *mic; /* M x 3 */
+    int32_t N;
+    double x0, x1, y0, y1, z0, c;
+    int32_t n_bins;
+    const double *freq; /* n_bins */
+    const double *csm;  /* n_bins x M x M complex, interleaved */
+    damas_params params; /* params.keep_count, if set, is copied too;
+                            params.batched is ignored (always batched)    */
+    void *x_map;         /* output, n_bins x N*N (double for FP64, else float) */
+    int32_t *s_tilde;    /* output, n_bins kept counts, or NULL           */
+} damas_request;
+
+/* Timing and outcome of a finished request. */
+typedef struct {
+    int32_t status;    /* DAMAS_OK or the solve's error code              */
+    int32_t cache_hit; /* the systems came from the PSF cache             */
+    double queue_ms;   /* submission to start                            */
+    double run_ms;     /* start to results on the host                   */
+    double total_ms;   /* submission to results on the host              */
+} damas_request_info;
+
+typedef struct {
+    uint64_t submitted, completed, rejected;
+    uint64_t cache_hits, cache_misses;
+    uint64_t held_bytes;  /* workspaces and inputs held by the slots       */
+    uint64_t cache_bytes; /* bytes in the PSF cache                       */
+    int32_t queued, running;
+} damas_server_stats;
+
+int damas_server_create(const damas_server_opts *o, damas_server **out);
+
+/* Stops the workers after the running requests; waiting requests finish
+ * with status DAMAS_EBUSY.  Frees every device buffer of the server. */
+void damas_server_destroy(damas_server *srv);
+
+/* Queue a request.  DAMAS_EINVAL: invalid request (validated as for
+ * damas_solve_dev); DAMAS_EADMIT: its footprint exceeds the HBM budget, so
+ * it can never run; DAMAS_EBUSY: the queue is full.  On success *ticket
+ * identifies the request. */
+int damas_submit(damas_server *srv, const damas_request *req, uint64_t *ticket);
+
+/* Wait up to timeout_ms (< 0: no limit) for a request.  Returns the
+ * request's status and retires the ticket, DAMAS_ETIMEDOUT if it is still
+ * queued or running (the ticket stays valid), DAMAS_EINVAL for an unknown
+ * ticket.  `info` (may be NULL) receives its timing. */
+int damas_wait(damas_server *srv, uint64_t ticket, int32_t timeout_ms,
+               damas_request_info *info);
+
+/* 1 if the request has finished, 0 if it is queued or running, DAMAS_EINVAL
+ * for an unknown ticket.  Does not retire the ticket. */
+int damas_poll(damas_server *srv, uint64_t ticket);
+
+int damas_server_get_stats(damas_server *srv, damas_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "common.h"
+#include "ctx_internal.h"
 
 using namespace damas;
 
@@ -383,28 +384,6 @@ extern "C" int damas_gs(int32_t N, int32_t n_bins, const int32_t *s_tilde,
 
 namespace {
 
-struct Buffer {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-} // namespace
-
-struct damas_ctx {
-    int device = 0;
-    Buffer b, idx, st, kc, off, E, A, E16, A32;
-    // keep counts last uploaded to kc (skip identical re-uploads)
-    std::vector<int32_t> kc_host;
-    int32_t *kc_pinned = nullptr;
-    size_t kc_pinned_n = 0;
-    hipEvent_t kc_done = nullptr;
-    bool timing = false;
-    // recorded (start, end) event pairs per timed phase, and spare pairs
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> phase_events[DAMAS_PHASES], event_pool;
-};
-
-namespace {
-
 int ensure(damas_ctx *ctx, Buffer &buf, size_t bytes, hipStream_t s, const char *what)
 {
     if (buf.bytes >= bytes)
@@ -544,14 +523,19 @@ extern "C" int damas_check(damas_ctx *ctx, void *stream)
 
 namespace {
 
-// Device buffers and launch parameters of one solve.
+// Validated shape and device buffers of one solve.
 struct SolvePlan {
     Geom kg;
-    int32_t N, M, S;
+    int32_t N, M, S, n_bins;
     const damas_params *p;
-    int32_t bulk, refine;       // sweeps on the storage precision / FP32 copy
+    bool batched, bf16, need64, need16;
+    int32_t max_kept;
+    std::vector<int32_t> st_host; // kept points per bin, where the host knows them
+    int32_t bulk, refine;         // sweeps on the storage precision / FP32 copy
     int64_t e_stride, e16_stride;
     int64_t a_elems;
+    int nb_ws;                    // bins the workspace holds at once
+    size_t es, xs;                // bytes per A element / x element
     double *bm;
     int32_t *ix, *st;
     int64_t *off;
@@ -559,16 +543,170 @@ struct SolvePlan {
     int *fault;
 };
 
+// Host-side validation and sizes of a solve (no device work).  The
+// geometry's mic pointer is not read here.
+int make_plan(int32_t M, int32_t N, int32_t n_bins, const damas_params *p, SolvePlan &P)
+{
+    int rc;
+    if (!p)
+        return fail(DAMAS_EINVAL, "params are NULL");
+    if ((rc = check_mode(p->select_mode, p->eps)) || (rc = check_precision(p->precision)))
+        return rc;
+    if (n_bins < 0 || p->iterations < 0)
+        return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
+    P.bf16 = p->precision == DAMAS_PREC_BF16;
+    if (P.bf16 && (p->refine_sweeps < 0 || p->refine_sweeps > p->iterations))
+        return fail(DAMAS_EINVAL, "refine_sweeps = %d outside [0, iterations = %d]",
+                    p->refine_sweeps, p->iterations);
+    P.N = N;
+    P.M = M;
+    P.S = N * N;
+    P.n_bins = n_bins;
+    P.p = p;
+    const int n0 = coarse_count(N);
+    P.st_host.clear();
+    P.max_kept = 0;
+    if (p->select_mode == DAMAS_SEL_KEEP_ALL) {
+        P.max_kept = P.S;
+        P.st_host.assign(n_bins, P.S);
+    } else if (p->select_mode == DAMAS_SEL_KEEP_COUNT) {
+        P.st_host.resize(n_bins);
+        for (int f = 0; f < n_bins; ++f) {
+            int32_t K = p->keep_count ? p->keep_count[f] : p->keep_count_all;
+            if (K < 0)
+                return fail(DAMAS_EINVAL, "keep_count[%d] = %d < 0", f, K);
+            P.st_host[f] = std::min(std::max(K, (int32_t)n0), P.S);
+            P.max_kept = std::max(P.max_kept, P.st_host[f]);
+        }
+    } else {
+        P.max_kept = p->max_kept > 0 ? std::min(p->max_kept, P.S) : P.S;
+    }
+    if ((rc = check_kept(P.max_kept, P.S, p->precision)))
+        return rc;
+    P.batched = p->batched != 0;
+    P.es = elem_size(p->precision);
+    P.xs = x_size(p->precision);
+    const int64_t ldm = ld_of(P.max_kept);
+    P.refine = P.bf16 ? p->refine_sweeps : 0;
+    P.bulk = p->iterations - P.refine;
+    P.e_stride = ldm * 2 * M;
+    P.e16_stride = ldm * 2 * mp_of(M);
+    if (!P.batched) {
+        P.a_elems = ldm * ldm;
+    } else if (!P.st_host.empty()) {
+        P.a_elems = 0;
+        for (int32_t v : P.st_host)
+            P.a_elems += ld_of(v) * ld_of(v);
+    } else {
+        P.a_elems = (int64_t)n_bins * ldm * ldm;
+    }
+    P.nb_ws = P.batched ? n_bins : 1;
+    P.need64 = !P.bf16 || P.refine > 0;
+    P.need16 = P.bf16 && P.bulk > 0;
+    return DAMAS_OK;
+}
+
+// Context workspace bytes of a plan: b, idx and s_tilde (when the caller
+// does not supply them), keep counts, offsets, steering rows and arenas.
+size_t plan_workspace_bytes(const SolvePlan &P, bool own_b, bool own_idx, bool own_st)
+{
+    size_t t = 0;
+    const size_t nb = (size_t)P.n_bins, S = (size_t)P.S;
+    if (own_b)
+        t += sizeof(double) * nb * S;
+    if (own_idx)
+        t += sizeof(int32_t) * nb * S;
+    if (own_st)
+        t += sizeof(int32_t) * nb;
+    if (P.p->select_mode == DAMAS_SEL_KEEP_COUNT)
+        t += sizeof(int32_t) * nb;
+    t += sizeof(int64_t) * (size_t)(P.nb_ws + 1);
+    if (P.need64)
+        t += sizeof(double) * (size_t)P.e_stride * P.nb_ws;
+    if (P.need16)
+        t += sizeof(uint16_t) * (size_t)P.e16_stride * P.nb_ws;
+    if (P.need16 || !P.bf16)
+        t += P.es * (size_t)P.a_elems;
+    if (P.bf16 && P.refine > 0)
+        t += sizeof(float) * (size_t)P.a_elems;
+    return t;
+}
+
+// Workspace, keep counts and the fault word of a plan on the context.
+int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *s_tilde,
+            hipStream_t s)
+{
+    int rc;
+    const damas_params *p = P.p;
+    const int32_t n_bins = P.n_bins, S = P.S;
+    if (!b_map && (rc = ensure(ctx, ctx->b, sizeof(double) * (size_t)n_bins * S, s, "b")))
+        return rc;
+    if (!idx && (rc = ensure(ctx, ctx->idx, sizeof(int32_t) * (size_t)n_bins * S, s, "idx")))
+        return rc;
+    if (!s_tilde && (rc = ensure(ctx, ctx->st, sizeof(int32_t) * (size_t)n_bins, s, "s_tilde")))
+        return rc;
+    if ((rc = ensure(ctx, ctx->off, sizeof(int64_t) * (size_t)(P.nb_ws + 1), s, "offsets")))
+        return rc;
+    if (P.need64 && (rc = ensure(ctx, ctx->E, sizeof(double) * (size_t)P.e_stride * P.nb_ws, s,
+                                 "steering rows")))
+        return rc;
+    if (P.need16 && (rc = ensure(ctx, ctx->E16,
+                                 sizeof(uint16_t) * (size_t)P.e16_stride * P.nb_ws, s,
+                                 "bf16 steering rows")))
+        return rc;
+    if ((P.need16 || !P.bf16) &&
+        (rc = ensure(ctx, ctx->A, P.es * (size_t)P.a_elems, s, "A arena")))
+        return rc;
+    if (P.bf16 && P.refine > 0 &&
+        (rc = ensure(ctx, ctx->A32, sizeof(float) * (size_t)P.a_elems, s, "FP32 A arena")))
+        return rc;
+    P.bm = b_map ? b_map : (double *)ctx->b.p;
+    P.ix = idx ? idx : (int32_t *)ctx->idx.p;
+    P.st = s_tilde ? s_tilde : (int32_t *)ctx->st.p;
+    P.off = (int64_t *)ctx->off.p;
+
+    P.kc = nullptr;
+    if (p->select_mode == DAMAS_SEL_KEEP_COUNT) {
+        std::vector<int32_t> want(n_bins);
+        for (int f = 0; f < n_bins; ++f)
+            want[f] = p->keep_count ? p->keep_count[f] : p->keep_count_all;
+        if (want != ctx->kc_host) {
+            if ((rc = ensure(ctx, ctx->kc, sizeof(int32_t) * (size_t)n_bins, s, "keep counts")))
+                return rc;
+            // The staging buffer may still feed the previous upload.
+            HIP_TRY(hipEventSynchronize(ctx->kc_done), "hipEventSynchronize");
+            if (ctx->kc_pinned_n < (size_t)n_bins) {
+                if (ctx->kc_pinned)
+                    HIP_TRY(hipHostFree(ctx->kc_pinned), "hipHostFree");
+                ctx->kc_pinned = nullptr;
+                ctx->kc_pinned_n = 0;
+                HIP_TRY(hipHostMalloc((void **)&ctx->kc_pinned, sizeof(int32_t) * n_bins),
+                        "hipHostMalloc");
+                ctx->kc_pinned_n = n_bins;
+            }
+            memcpy(ctx->kc_pinned, want.data(), sizeof(int32_t) * n_bins);
+            HIP_TRY(hipMemcpyAsync(ctx->kc.p, ctx->kc_pinned, sizeof(int32_t) * n_bins,
+                                   hipMemcpyHostToDevice, s),
+                    "upload keep counts");
+            HIP_TRY(hipEventRecord(ctx->kc_done, s), "hipEventRecord");
+            ctx->kc_host = want;
+        }
+        P.kc = (const int32_t *)ctx->kc.p;
+    }
+    return fault_word(&P.fault);
+}
+
 // Everything after the DAS map and the selection for bins [f0, f0 + nb)
-// (arrays offset by the caller): layout, steering, PSF(s) and sweeps.
+// (arrays offset by the caller): layout, steering and PSF(s) when `build`,
+// then the sweeps.
 int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
                               int32_t max_kept, const double *freq, double *bm,
                               int32_t *ix, int32_t *st, const void *x_init, void *x_map,
-                              hipStream_t s)
+                              hipStream_t s, bool build = true)
 {
     const damas_params *p = P.p;
     HIP_TRY(launch_layout(nb, st, max_kept, P.a_elems, P.off, P.fault, s), "layout launch");
-    const bool bf16 = p->precision == DAMAS_PREC_BF16;
+    const bool bf16 = P.bf16;
     int rc;
     std::pair<hipEvent_t, hipEvent_t> evb{};
     if (ctx->timing) {
@@ -577,7 +715,7 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
         HIP_TRY(hipEventRecord(evb.first, s), "hipEventRecord");
     }
     // Storage-precision system (bulk sweeps) and, for BF16, the FP32 copy.
-    if (!bf16 || P.refine > 0) {
+    if (build && P.need64) {
         HIP_TRY(launch_steer(P.kg, nb, freq, ix, st, max_kept, (double *)ctx->E.p, P.e_stride,
                              P.fault, s),
                 "steer launch");
@@ -586,7 +724,7 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
                            bf16 ? ctx->A32.p : ctx->A.p, P.fault, s),
                 "psf launch");
     }
-    if (bf16 && P.bulk > 0) {
+    if (build && P.need16) {
         HIP_TRY(launch_steer16(P.kg, nb, freq, ix, st, max_kept, (uint16_t *)ctx->E16.p,
                                P.e16_stride, P.fault, s),
                 "steer16 launch");
@@ -630,6 +768,29 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
 
 } // namespace
 
+extern "C" int damas_query_footprint(int32_t M, int32_t N, int32_t n_bins,
+                                     const damas_params *p, uint64_t *bytes)
+{
+    if (!bytes)
+        return fail(DAMAS_EINVAL, "bytes is NULL");
+    if (M < 1 || M > 128)
+        return fail(DAMAS_EINVAL, "M = %d outside [1, 128]", M);
+    if (N < 1 || N > 46340)
+        return fail(DAMAS_EINVAL, "N = %d outside [1, 46340]", N);
+    SolvePlan P;
+    int rc = make_plan(M, N, n_bins, p, P);
+    if (rc)
+        return rc;
+    const size_t nb = (size_t)n_bins, S = (size_t)P.S;
+    // Inputs (mic, freq, CSM), the x map and s_tilde, plus the workspace
+    // of a context that keeps b and idx itself.
+    size_t t = sizeof(double) * (3 * (size_t)M + nb + nb * (size_t)M * M * 2);
+    t += P.xs * nb * S + sizeof(int32_t) * nb;
+    t += plan_workspace_bytes(P, true, true, false);
+    *bytes = t;
+    return DAMAS_OK;
+}
+
 extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
                                int32_t n_bins, const double *freq,
                                const double *csm, const damas_params *p,
@@ -641,151 +802,251 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
     int rc = check_geometry(g);
     if (rc)
         return rc;
-    if (!p)
-        return fail(DAMAS_EINVAL, "params are NULL");
-    if ((rc = check_mode(p->select_mode, p->eps)) || (rc = check_precision(p->precision)))
+    SolvePlan P;
+    if ((rc = make_plan(g->M, g->N, n_bins, p, P)))
         return rc;
-    if (n_bins < 0 || p->iterations < 0)
-        return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
-    const bool bf16 = p->precision == DAMAS_PREC_BF16;
-    if (bf16 && (p->refine_sweeps < 0 || p->refine_sweeps > p->iterations))
-        return fail(DAMAS_EINVAL, "refine_sweeps = %d outside [0, iterations = %d]",
-                    p->refine_sweeps, p->iterations);
     if (n_bins == 0)
         return DAMAS_OK;
     if (!freq || !csm || !x_map)
         return fail(DAMAS_EINVAL, "freq, csm and x_map must be non-NULL");
-    const int32_t N = g->N, M = g->M;
-    const int32_t S = N * N;
-    const int n0 = coarse_count(N);
-
-    // Kept points per bin, where the host can know them.
-    std::vector<int32_t> st_host;
-    int32_t max_kept = 0;
-    if (p->select_mode == DAMAS_SEL_KEEP_ALL) {
-        max_kept = S;
-        st_host.assign(n_bins, S);
-    } else if (p->select_mode == DAMAS_SEL_KEEP_COUNT) {
-        st_host.resize(n_bins);
-        for (int f = 0; f < n_bins; ++f) {
-            int32_t K = p->keep_count ? p->keep_count[f] : p->keep_count_all;
-            if (K < 0)
-                return fail(DAMAS_EINVAL, "keep_count[%d] = %d < 0", f, K);
-            st_host[f] = std::min(std::max(K, (int32_t)n0), S);
-            max_kept = std::max(max_kept, st_host[f]);
-        }
-    } else {
-        max_kept = p->max_kept > 0 ? std::min(p->max_kept, S) : S;
-    }
-    if ((rc = check_kept(max_kept, S, p->precision)))
-        return rc;
-
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    const size_t es = elem_size(p->precision), xs = x_size(p->precision);
-    const bool batched = p->batched != 0;
-    const int64_t ldm = ld_of(max_kept);
-    SolvePlan P;
     P.kg = make_geom(*g);
-    P.N = N;
-    P.M = M;
-    P.S = S;
-    P.p = p;
-    P.refine = bf16 ? p->refine_sweeps : 0;
-    P.bulk = p->iterations - P.refine;
-    P.e_stride = ldm * 2 * M;
-    P.e16_stride = ldm * 2 * mp_of(M);
-    if (!batched) {
-        P.a_elems = ldm * ldm;
-    } else if (!st_host.empty()) {
-        P.a_elems = 0;
-        for (int32_t v : st_host)
-            P.a_elems += ld_of(v) * ld_of(v);
-    } else {
-        P.a_elems = (int64_t)n_bins * ldm * ldm;
-    }
-    const int nb_ws = batched ? n_bins : 1;
-    const bool need64 = !bf16 || P.refine > 0, need16 = bf16 && P.bulk > 0;
+    if ((rc = prepare(ctx, P, b_map, idx, s_tilde, s)))
+        return rc;
+    const int32_t S = P.S, M = P.M;
 
-    if (!b_map && (rc = ensure(ctx, ctx->b, sizeof(double) * (size_t)n_bins * S, s, "b")))
-        return rc;
-    if (!idx && (rc = ensure(ctx, ctx->idx, sizeof(int32_t) * (size_t)n_bins * S, s, "idx")))
-        return rc;
-    if (!s_tilde && (rc = ensure(ctx, ctx->st, sizeof(int32_t) * (size_t)n_bins, s, "s_tilde")))
-        return rc;
-    if ((rc = ensure(ctx, ctx->off, sizeof(int64_t) * (size_t)(nb_ws + 1), s, "offsets")))
-        return rc;
-    if (need64 && (rc = ensure(ctx, ctx->E, sizeof(double) * (size_t)P.e_stride * nb_ws, s,
-                               "steering rows")))
-        return rc;
-    if (need16 && (rc = ensure(ctx, ctx->E16, sizeof(uint16_t) * (size_t)P.e16_stride * nb_ws,
-                               s, "bf16 steering rows")))
-        return rc;
-    if ((need16 || !bf16) &&
-        (rc = ensure(ctx, ctx->A, es * (size_t)P.a_elems, s, "A arena")))
-        return rc;
-    if (bf16 && P.refine > 0 &&
-        (rc = ensure(ctx, ctx->A32, sizeof(float) * (size_t)P.a_elems, s, "FP32 A arena")))
-        return rc;
-    P.bm = b_map ? b_map : (double *)ctx->b.p;
-    P.ix = idx ? idx : (int32_t *)ctx->idx.p;
-    P.st = s_tilde ? s_tilde : (int32_t *)ctx->st.p;
-    P.off = (int64_t *)ctx->off.p;
-
-    P.kc = nullptr;
-    if (p->select_mode == DAMAS_SEL_KEEP_COUNT) {
-        std::vector<int32_t> want(n_bins);
-        for (int f = 0; f < n_bins; ++f)
-            want[f] = p->keep_count ? p->keep_count[f] : p->keep_count_all;
-        if (want != ctx->kc_host) {
-            if ((rc = ensure(ctx, ctx->kc, sizeof(int32_t) * (size_t)n_bins, s, "keep counts")))
-                return rc;
-            // The staging buffer may still feed the previous upload.
-            HIP_TRY(hipEventSynchronize(ctx->kc_done), "hipEventSynchronize");
-            if (ctx->kc_pinned_n < (size_t)n_bins) {
-                if (ctx->kc_pinned)
-                    HIP_TRY(hipHostFree(ctx->kc_pinned), "hipHostFree");
-                ctx->kc_pinned = nullptr;
-                ctx->kc_pinned_n = 0;
-                HIP_TRY(hipHostMalloc((void **)&ctx->kc_pinned, sizeof(int32_t) * n_bins),
-                        "hipHostMalloc");
-                ctx->kc_pinned_n = n_bins;
-            }
-            memcpy(ctx->kc_pinned, want.data(), sizeof(int32_t) * n_bins);
-            HIP_TRY(hipMemcpyAsync(ctx->kc.p, ctx->kc_pinned, sizeof(int32_t) * n_bins,
-                                   hipMemcpyHostToDevice, s),
-                    "upload keep counts");
-            HIP_TRY(hipEventRecord(ctx->kc_done, s), "hipEventRecord");
-            ctx->kc_host = want;
-        }
-        P.kc = (const int32_t *)ctx->kc.p;
-    }
-    if ((rc = fault_word(&P.fault)))
-        return rc;
-
-    if (batched) {
+    if (P.batched) {
         HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s), "das launch");
-        HIP_TRY(launch_select(N, n_bins, P.bm, p->select_mode, p->eps, P.kc, P.ix, P.st, s),
+        HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, P.kc, P.ix, P.st, s),
                 "select launch");
-        return enqueue_system_and_sweeps(ctx, P, n_bins, max_kept, freq, P.bm, P.ix, P.st,
+        return enqueue_system_and_sweeps(ctx, P, n_bins, P.max_kept, freq, P.bm, P.ix, P.st,
                                          x_init, x_map, s);
     }
 
     // Plain: each bin on its own, one launch per step; A, E and the layout
     // are reused from bin to bin.
     for (int f = 0; f < n_bins; ++f) {
-        const int32_t mk = st_host.empty() ? max_kept : st_host[f];
+        const int32_t mk = P.st_host.empty() ? P.max_kept : P.st_host[f];
         const size_t fS = (size_t)f * S;
-        const char *xi = x_init ? (const char *)x_init + xs * fS : nullptr;
-        char *xm = (char *)x_map + xs * fS;
+        const char *xi = x_init ? (const char *)x_init + P.xs * fS : nullptr;
+        char *xm = (char *)x_map + P.xs * fS;
         HIP_TRY(launch_das(P.kg, 1, freq + f, csm + (size_t)f * M * M * 2, P.bm + fS, s),
                 "das launch");
-        HIP_TRY(launch_select(N, 1, P.bm + fS, p->select_mode, p->eps, P.kc ? P.kc + f : nullptr,
-                              P.ix + fS, P.st + f, s),
+        HIP_TRY(launch_select(P.N, 1, P.bm + fS, p->select_mode, p->eps,
+                              P.kc ? P.kc + f : nullptr, P.ix + fS, P.st + f, s),
                 "select launch");
         if ((rc = enqueue_system_and_sweeps(ctx, P, 1, mk, freq + f, P.bm + fS, P.ix + fS,
                                             P.st + f, xi, xm, s)))
             return rc;
     }
+    return DAMAS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// internal: context bytes, trimming, cache, cached solve
+
+size_t damas::ctx_bytes(const damas_ctx *ctx)
+{
+    size_t t = 0;
+    for (const Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
+                            &ctx->E16, &ctx->A32})
+        t += b->bytes;
+    return t;
+}
+
+int damas::ctx_trim(damas_ctx *ctx)
+{
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->off, &ctx->E, &ctx->A, &ctx->E16,
+                      &ctx->A32}) {
+        if (b->p)
+            HIP_TRY(hipFree(b->p), "hipFree");
+        b->p = nullptr;
+        b->bytes = 0;
+    }
+    return DAMAS_OK;
+}
+
+int damas::set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+bool damas::PsfCache::make_room(size_t need)
+{
+    return need <= budget && shrink_to(budget - need);
+}
+
+bool damas::PsfCache::shrink_to(size_t room)
+{
+    while (used > room && !lru.empty()) {
+        const std::string *k = lru.back();
+        auto it = map.find(*k);
+        lru.pop_back();
+        if (it == map.end())
+            continue;
+        for (Buffer *b : {&it->second.A, &it->second.A32})
+            if (b->p) {
+                (void)hipFree(b->p); // synchronises: no copy still reads it
+                used -= b->bytes;
+            }
+        if (it->second.ready)
+            (void)hipEventDestroy(it->second.ready);
+        map.erase(it);
+    }
+    return used <= room;
+}
+
+void damas::PsfCache::clear()
+{
+    for (auto &kv : map) {
+        for (Buffer *b : {&kv.second.A, &kv.second.A32})
+            if (b->p)
+                (void)hipFree(b->p);
+        if (kv.second.ready)
+            (void)hipEventDestroy(kv.second.ready);
+    }
+    map.clear();
+    lru.clear();
+    used = 0;
+}
+
+namespace {
+
+template <typename T> void append(std::string &k, const T *v, size_t n)
+{
+    k.append(reinterpret_cast<const char *>(v), sizeof(T) * n);
+}
+
+} // namespace
+
+int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
+                        const double *freq, const double *csm, const damas_params *p,
+                        void *x_map, int32_t *s_tilde, PsfCache *cache, int *hit, hipStream_t s)
+{
+    *hit = 0;
+    int rc = check_geometry(g);
+    if (rc)
+        return rc;
+    SolvePlan P;
+    if ((rc = make_plan(g->M, g->N, n_bins, p, P)))
+        return rc;
+    if (!P.batched)
+        return fail(DAMAS_EINVAL, "cached solves are batched");
+    if (n_bins == 0)
+        return DAMAS_OK;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    P.kg = make_geom(*g);
+    if ((rc = prepare(ctx, P, nullptr, nullptr, s_tilde, s)))
+        return rc;
+    HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s), "das launch");
+    HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, P.kc, P.ix, P.st, s),
+            "select launch");
+    if (!cache)
+        return enqueue_system_and_sweeps(ctx, P, n_bins, P.max_kept, freq, P.bm, P.ix, P.st,
+                                         nullptr, x_map, s);
+
+    // The key: geometry, frequencies, precision and arithmetic split, and
+    // every bin's kept points.
+    std::vector<int32_t> st(n_bins);
+    std::vector<int32_t> ix((size_t)n_bins * P.S);
+    std::vector<double> mic(3 * (size_t)g->M), fr(n_bins);
+    HIP_TRY(hipMemcpyAsync(st.data(), P.st, sizeof(int32_t) * n_bins, hipMemcpyDeviceToHost, s),
+            "read s_tilde");
+    HIP_TRY(hipMemcpyAsync(ix.data(), P.ix, sizeof(int32_t) * ix.size(), hipMemcpyDeviceToHost, s),
+            "read idx");
+    HIP_TRY(hipMemcpyAsync(mic.data(), g->mic, sizeof(double) * mic.size(),
+                           hipMemcpyDeviceToHost, s),
+            "read mic");
+    HIP_TRY(hipMemcpyAsync(fr.data(), freq, sizeof(double) * n_bins, hipMemcpyDeviceToHost, s),
+            "read freq");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::string key;
+    const int32_t hdr[5] = {g->M, g->N, p->precision, P.need64, P.need16};
+    const double box[6] = {g->x0, g->x1, g->y0, g->y1, g->z0, g->c};
+    append(key, hdr, 5);
+    append(key, box, 6);
+    append(key, mic.data(), mic.size());
+    append(key, fr.data(), fr.size());
+    append(key, st.data(), st.size());
+    for (int f = 0; f < n_bins; ++f)
+        append(key, ix.data() + (size_t)f * P.S, (size_t)std::max(st[f], 0));
+
+    const size_t a_bytes = (P.need16 || !P.bf16) ? P.es * (size_t)P.a_elems : 0;
+    const size_t a32_bytes = (P.bf16 && P.refine > 0) ? sizeof(float) * (size_t)P.a_elems : 0;
+    {
+        std::lock_guard<std::mutex> lk(cache->mu);
+        auto it = cache->map.find(key);
+        if (it != cache->map.end()) {
+            ++cache->hits;
+            cache->lru.erase(it->second.lru);
+            cache->lru.push_front(&it->first);
+            it->second.lru = cache->lru.begin();
+            // The entry may have been filled on another stream.
+            HIP_TRY(hipStreamWaitEvent(s, it->second.ready, 0), "hipStreamWaitEvent");
+            if (a_bytes)
+                HIP_TRY(hipMemcpyAsync(ctx->A.p, it->second.A.p, a_bytes,
+                                       hipMemcpyDeviceToDevice, s),
+                        "cached A");
+            if (a32_bytes)
+                HIP_TRY(hipMemcpyAsync(ctx->A32.p, it->second.A32.p, a32_bytes,
+                                       hipMemcpyDeviceToDevice, s),
+                        "cached FP32 A");
+            // The copies must finish before the entry can be evicted.
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+            *hit = 1;
+        } else {
+            ++cache->misses;
+        }
+    }
+    if ((rc = enqueue_system_and_sweeps(ctx, P, n_bins, P.max_kept, freq, P.bm, P.ix, P.st,
+                                        nullptr, x_map, s, !*hit)))
+        return rc;
+    if (*hit)
+        return DAMAS_OK;
+    // Store a copy of the systems just built, if they fit the budget.
+    std::lock_guard<std::mutex> lk(cache->mu);
+    if (cache->map.count(key) || !cache->make_room(a_bytes + a32_bytes))
+        return DAMAS_OK;
+    PsfCache::Entry e;
+    e.key = key;
+    for (auto pr : {std::make_pair(&e.A, std::make_pair(ctx->A.p, a_bytes)),
+                    std::make_pair(&e.A32, std::make_pair(ctx->A32.p, a32_bytes))}) {
+        if (!pr.second.second)
+            continue;
+        if (hipMalloc(&pr.first->p, pr.second.second) != hipSuccess) {
+            (void)hipGetLastError();
+            if (e.A.p)
+                (void)hipFree(e.A.p); // synchronises with its pending copy
+            return DAMAS_OK;          // no room on the device: skip caching
+        }
+        pr.first->bytes = pr.second.second;
+        HIP_TRY(hipMemcpyAsync(pr.first->p, pr.second.first, pr.second.second,
+                               hipMemcpyDeviceToDevice, s),
+                "cache copy");
+    }
+    if (hipEventCreateWithFlags(&e.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(e.ready, s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        for (Buffer *b : {&e.A, &e.A32})
+            if (b->p)
+                (void)hipFree(b->p);
+        if (e.ready)
+            (void)hipEventDestroy(e.ready);
+        return DAMAS_OK;
+    }
+    cache->used += a_bytes + a32_bytes;
+    auto ins = cache->map.emplace(key, std::move(e));
+    cache->lru.push_front(&ins.first->first);
+    ins.first->second.lru = cache->lru.begin();
     return DAMAS_OK;
 }

@@ -1,0 +1,85 @@
+// Private to the library: the device workspace of a context, the cache of
+// built systems, and the internal solve entry the request server uses.
+#pragma once
+
+#include <stdint.h>
+
+#include <list>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+
+namespace damas {
+
+struct Buffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Device copies of built compressed systems (the A arena of a solve and,
+// for DAMAS_PREC_BF16, its FP32 copy), keyed by everything they are a
+// function of: geometry, frequencies, precision, and the kept points of
+// every bin.  Entries are compared by their whole key, never by hash alone.
+// Least recently used entries go first when the byte budget is exceeded.
+struct PsfCache {
+    struct Entry {
+        std::string key;
+        Buffer A, A32;
+        hipEvent_t ready = nullptr; // recorded after the copies that fill A, A32
+        std::list<const std::string *>::iterator lru;
+    };
+    size_t budget = 0;
+    size_t used = 0;
+    uint64_t hits = 0, misses = 0;
+    std::mutex mu;
+    std::unordered_map<std::string, Entry> map;
+    std::list<const std::string *> lru; // front: most recently used
+
+    // Free entries (least recent first) until `need` more bytes fit the
+    // budget; returns false if they cannot.  Caller holds mu.
+    bool make_room(size_t need);
+    // Free entries (least recent first) until at most `room` bytes remain
+    // cached; returns whether that holds.  Caller holds mu.
+    bool shrink_to(size_t room);
+    void clear();
+};
+
+// Record a failure for damas_last_error() of the calling thread; returns
+// `code`.
+int set_error(int code, const char *fmt, ...);
+
+} // namespace damas
+
+struct damas_ctx {
+    int device = 0;
+    damas::Buffer b, idx, st, kc, off, E, A, E16, A32;
+    // keep counts last uploaded to kc (skip identical re-uploads)
+    std::vector<int32_t> kc_host;
+    int32_t *kc_pinned = nullptr;
+    size_t kc_pinned_n = 0;
+    hipEvent_t kc_done = nullptr;
+    bool timing = false;
+    // recorded (start, end) event pairs per timed phase, and spare pairs
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> phase_events[DAMAS_PHASES], event_pool;
+};
+
+namespace damas {
+
+// Device bytes a context currently holds, and release of its workspace.
+size_t ctx_bytes(const damas_ctx *ctx);
+int ctx_trim(damas_ctx *ctx);
+
+// damas_solve_dev (batched) with the system build looked up in `cache`
+// first: after the selection the kept sets come to the host (one stream
+// synchronisation), and a hit copies the cached systems into the arena in
+// place of steering and PSF launches; a miss builds them and stores a copy
+// when the cache budget allows.  *hit reports which happened.
+int solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins, const double *freq,
+                 const double *csm, const damas_params *p, void *x_map, int32_t *s_tilde,
+                 PsfCache *cache, int *hit, hipStream_t s);
+
+} // namespace damas

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -94,6 +95,40 @@ PHASE_SYSTEM = 1
 _sig("damas_solve_dev", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
      c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_check", ctypes.c_int, c_vp, c_vp)
+_sig("damas_query_footprint", ctypes.c_int, c_i32, c_i32, c_i32, ctypes.POINTER(Params),
+     ctypes.POINTER(ctypes.c_uint64))
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", c_i32), ("hbm_budget", ctypes.c_uint64),
+                ("cache_budget", ctypes.c_uint64), ("slots", c_i32), ("max_queue", c_i32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("M", c_i32), ("mic", c_vp), ("N", c_i32), ("x0", c_dbl), ("x1", c_dbl),
+                ("y0", c_dbl), ("y1", c_dbl), ("z0", c_dbl), ("c", c_dbl), ("n_bins", c_i32),
+                ("freq", c_vp), ("csm", c_vp), ("params", Params), ("x_map", c_vp),
+                ("s_tilde", c_vp)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("cache_hit", c_i32), ("queue_ms", c_dbl),
+                ("run_ms", c_dbl), ("total_ms", c_dbl)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64),
+                ("cache_misses", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64),
+                ("cache_bytes", ctypes.c_uint64), ("queued", c_i32), ("running", c_i32)]
+
+
+_sig("damas_server_create", ctypes.c_int, ctypes.POINTER(ServerOpts), ctypes.POINTER(c_vp))
+_sig("damas_server_destroy", None, c_vp)
+_sig("damas_submit", ctypes.c_int, c_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64))
+_sig("damas_wait", ctypes.c_int, c_vp, ctypes.c_uint64, c_i32, ctypes.POINTER(RequestInfo))
+_sig("damas_poll", ctypes.c_int, c_vp, ctypes.c_uint64)
+_sig("damas_server_get_stats", ctypes.c_int, c_vp, ctypes.POINTER(ServerStats))
 
 
 class DamasError(RuntimeError):
@@ -322,20 +357,8 @@ class Context:
         S = g.N * g.N
         if x_map is None:
             x_map = torch.empty(nb, S, dtype=_XTYPE[precision], device=freq.device)
-        kc_arr = None
-        kc_all = 0
-        if keep_count is not None:
-            if isinstance(keep_count, int):
-                kc_all = keep_count
-            else:
-                vals = [int(v) for v in keep_count]
-                if len(vals) != nb:
-                    raise ValueError("keep_count needs one value per bin")
-                kc_arr = (c_i32 * nb)(*vals)
-        p = Params(int(select_mode), float(eps),
-                   ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
-                   int(kc_all), int(iterations), int(precision), 1 if batched else 0,
-                   int(max_kept), int(refine_sweeps))
+        p, kc_arr = _params(nb, select_mode, eps, keep_count, iterations, precision, batched,
+                            max_kept, refine_sweeps)
         dt = _XTYPE[precision]
         _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
                                     _ptr(freq, torch.float64, "freq"),
@@ -348,6 +371,112 @@ class Context:
 
     def check(self, stream=None):
         check(self, stream)
+
+
+def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, max_kept,
+            refine_sweeps):
+    """Params struct and the ctypes array that keeps per-bin counts alive."""
+    kc_arr = None
+    kc_all = 0
+    if keep_count is not None:
+        if isinstance(keep_count, (int, np.integer)):
+            kc_all = int(keep_count)
+        else:
+            vals = [int(v) for v in keep_count]
+            if len(vals) != nb:
+                raise ValueError("keep_count needs one value per bin")
+            kc_arr = (c_i32 * nb)(*vals)
+    p = Params(int(select_mode), float(eps),
+               ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
+               int(kc_all), int(iterations), int(precision), 1 if batched else 0,
+               int(max_kept), int(refine_sweeps))
+    return p, kc_arr
+
+
+def query_footprint(M: int, N: int, n_bins: int, *, select_mode=SEL_KEEP_ALL, eps=0.0,
+                    keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
+                    refine_sweeps=0) -> int:
+    """Device bytes of a whole-path solve of this shape (no device work)."""
+    p, _kc = _params(n_bins, select_mode, eps, keep_count, iterations, precision, True,
+                     max_kept, refine_sweeps)
+    out = ctypes.c_uint64()
+    _check(_lib.damas_query_footprint(int(M), int(N), int(n_bins), ctypes.byref(p),
+                                      ctypes.byref(out)))
+    return int(out.value)
+
+
+class Server:
+    """damas_server: whole-path solves from host arrays, run by worker
+    threads on stream slots, admitted by device footprint, with a PSF cache.
+    Inputs are numpy arrays (copied at submission); results come back as
+    numpy arrays from wait()."""
+
+    def __init__(self, device=0, hbm_budget=64 << 30, cache_budget=8 << 30, slots=2,
+                 max_queue=256):
+        o = ServerOpts(int(device), int(hbm_budget), int(cache_budget), int(slots),
+                       int(max_queue))
+        h = c_vp()
+        _check(_lib.damas_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._out = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.damas_server_destroy(self._h)
+            self._h = None
+            self._out.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, mic, N, extent, z0, freqs, csm, *, select_mode=SEL_KEEP_COUNT, eps=0.0,
+               keep_count=None, iterations=1000, precision=PREC_FP32, refine_sweeps=0,
+               max_kept=0, c=343.0) -> int:
+        """Queue one solve; returns its ticket.  csm: complex (n_bins, M, M)."""
+        mic = np.ascontiguousarray(mic, dtype=np.float64)
+        freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+        nb = freqs.size
+        csm = np.ascontiguousarray(np.asarray(csm, dtype=np.complex128).view(np.float64))
+        p, kc = _params(nb, select_mode, eps, keep_count, iterations, precision, True,
+                        max_kept, refine_sweeps)
+        x = np.zeros((nb, N * N), np.float64 if precision == PREC_FP64 else np.float32)
+        st = np.zeros(nb, np.int32)
+        x0, x1, y0, y1 = extent
+        r = Request(mic.shape[0], mic.ctypes.data, int(N), float(x0), float(x1), float(y0),
+                    float(y1), float(z0), float(c), nb, freqs.ctypes.data, csm.ctypes.data, p,
+                    x.ctypes.data, st.ctypes.data)
+        t = ctypes.c_uint64()
+        _check(_lib.damas_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._out[t.value] = (x, st)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(x_map, s_tilde, info dict) of a finished request; raises
+        DamasError (code ETIMEDOUT while it is still running)."""
+        info = RequestInfo()
+        rc = _lib.damas_wait(self._h, ctypes.c_uint64(ticket), int(timeout_ms),
+                             ctypes.byref(info))
+        if rc == ETIMEDOUT:
+            _check(rc)
+        x, st = self._out.pop(ticket, (None, None))
+        _check(rc)
+        return x, st, {"status": info.status, "cache_hit": bool(info.cache_hit),
+                       "queue_ms": info.queue_ms, "run_ms": info.run_ms,
+                       "total_ms": info.total_ms}
+
+    def poll(self, ticket: int) -> bool:
+        rc = _lib.damas_poll(self._h, ctypes.c_uint64(ticket))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_lib.damas_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
 
 
 def _as_interleaved(csm):

@@ -264,6 +264,34 @@ def batched_fp32(n_bins: int = 256, N: int = 101, iterations: int = 2000,
                     sources=pts, powers=q)
 
 
+def served_request(seed: int, table_bins: int = 64) -> Workload:
+    """One request of the served workload: the 64-mic spiral, a grid of
+    N in {41, 61, 81, 101} on the 2 x 2 m plane at 1.5 m, 1-64 bins drawn
+    without replacement from the compressed workload's 64-bin table over
+    1-8 kHz, 3-10 sources of power U(0.5, 1), 1024 snapshots at an SNR of
+    U(10, 30) dB, and a keep count K ~ U{200 .. min(6000, N^2)}; 1000
+    sweeps, FP32."""
+    cfg = 5
+    rng = _rng(cfg, seed, _SOURCES)
+    mic = spiral_array(64, 0.6)
+    N = int(rng.choice([41, 61, 81, 101]))
+    S = N * N
+    nb = int(rng.integers(1, table_bins + 1))
+    table = np.linspace(1000.0, 8000.0, table_bins)
+    freqs = np.sort(rng.choice(table, size=nb, replace=False))
+    n_src = int(rng.integers(3, 11))
+    pts = np.sort(rng.choice(S, size=n_src, replace=False))
+    q = rng.uniform(0.5, 1.0, size=n_src)
+    snr = float(rng.uniform(10.0, 30.0))
+    K = int(rng.integers(200, min(6000, S) + 1))
+    xyz = grid_xyz(N, -1.0, 1.0, -1.0, 1.0, 1.5, pts)
+    csm = np.stack([snapshot_csm(mic, xyz, q, f, 1024, snr, (cfg, seed, b))
+                    for b, f in enumerate(freqs)])
+    return Workload(f"served M64 N{N} {nb}bins K{K}", mic, N, -1.0, 1.0, -1.0, 1.0, 1.5,
+                    freqs, csm, SEL_KEEP_COUNT, keep_count=K, iterations=1000,
+                    precision="fp32", sources=pts, powers=q)
+
+
 def custom(mic, N, extent, z0, freqs, src_pts, powers, *, snapshots=None,
            snr_db=None, seed=99, select_mode=SEL_KEEP_ALL, eps=0.0,
            keep_count=0, iterations=100, precision="fp32") -> Workload:

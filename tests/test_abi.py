@@ -102,3 +102,31 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert dm._lib.damas_solve_dev(None, ctypes.byref(G(16, 0x1000, 21, -1, 1, -1, 1, 1, 343.0)),
                                    1, fake, fake, None, None, fake, None, None, None,
                                    None) == dm.EINVAL
+
+
+def test_query_footprint_closed_form(lib):
+    """Footprint of a solve = inputs + x map + s_tilde + the context's b,
+    idx, offsets, steering rows and A arena (host-only call)."""
+    from paper_1608_05179_amd import damas as dm
+    M, N, S = 16, 21, 441
+    L = dm.ld(S)
+    want = 8 * (3 * M + 1 + M * M * 2)            # mic, freq, CSM
+    want += 8 * S + 4                              # x map (double), s_tilde
+    want += 8 * S + 4 * S + 8 * 2                  # b, idx, offsets
+    want += 8 * L * 2 * M + 8 * L * L              # steering rows, A (double)
+    assert dm.query_footprint(M, N, 1, precision=dm.PREC_FP64, iterations=10) == want
+    # float A, two bins of KEEP_COUNT 100 (ld 104): per-bin arenas packed
+    L2 = dm.ld(100)
+    want2 = 8 * (3 * M + 2 + 2 * M * M * 2) + 4 * 2 * S + 4 * 2
+    want2 += 8 * 2 * S + 4 * 2 * S + 4 * 2 + 8 * 3
+    want2 += 8 * 2 * L2 * 2 * M + 4 * 2 * L2 * L2
+    assert dm.query_footprint(M, N, 2, select_mode=dm.SEL_KEEP_COUNT, keep_count=100,
+                              iterations=10) == want2
+    # BF16 with refinement holds both arenas and both steering tables
+    fb = dm.query_footprint(M, N, 1, precision=dm.PREC_BF16, refine_sweeps=5, iterations=10)
+    f32 = dm.query_footprint(M, N, 1, precision=dm.PREC_FP32, iterations=10)
+    assert fb == f32 + 2 * L * L + 2 * L * 2 * dm.mp(M)
+    with pytest.raises(dm.DamasError):
+        dm.query_footprint(0, N, 1)
+    with pytest.raises(dm.DamasError):
+        dm.query_footprint(M, N, 1, precision=dm.PREC_BF16, refine_sweeps=11, iterations=10)
