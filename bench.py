@@ -160,6 +160,7 @@ def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False):
     gs_ms, gs_n = ctx.phase_time(dm.PHASE_SWEEPS)
     sys_ms, sys_n = ctx.phase_time(dm.PHASE_SYSTEM)
     ctx.set_timing(False)
+    wg = ctx.last_workgroups()
     lat = [e0.elapsed_time(e1) for e0, e1 in ev]
     ms_step = wall * 1e3 / steps
 
@@ -182,6 +183,7 @@ def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False):
         "ms_per_step": round(ms_step, 4),
         "latency_ms": {"p50": round(_pct(lat, 50), 4), "p99": round(_pct(lat, 99), 4)},
         "sweeps_ms": round(gs_avg, 4), "system_build_ms": round(sys_ms / max(sys_n, 1), 4),
+        "sweep_workgroups": wg,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "kernel": f"gs_kernel (A {a_kind})", "kernel_avg_ms": round(gs_avg, 4),

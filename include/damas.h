@@ -248,6 +248,22 @@ int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled);
 int damas_ctx_phase_time(damas_ctx *ctx, int32_t phase, double *ms, int64_t *launches);
 int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches);
 
+/* Cooperative sweeps: in a batched solve whose kept counts the host knows
+ * (KEEP_ALL, KEEP_COUNT), bins with long strips get several workgroups that
+ * share each sweep's sums (one owner runs the rows; helpers sum slices of
+ * every strip and exchange through device memory), so few or uneven bins
+ * still use the whole chip.  The same iteration; only the summation order
+ * of each residual changes.  max_workgroups bounds the workgroups one solve
+ * launches: -1 (default) what the device holds at once, 0 never cooperate,
+ * n > 0 at most n (several contexts sharing a device at once should split
+ * it).  Cooperation is used only where it helps (at least 320 rows per
+ * workgroup and three tiles per bin). */
+int damas_ctx_set_coop(damas_ctx *ctx, int32_t max_workgroups);
+
+/* Workgroups of the context's last sweep launch (the bins' count when no
+ * bin cooperated). */
+int damas_ctx_last_workgroups(const damas_ctx *ctx, int32_t *workgroups);
+
 /* Parameters of a solve (host struct). */
 typedef struct {
     int32_t select_mode;       /* DAMAS_SEL_*                               */

@@ -434,7 +434,10 @@ extern "C" int damas_ctx_create(int32_t device, damas_ctx **out)
     if (!c)
         return fail(DAMAS_ENOMEM, "context allocation");
     c->device = device;
-    if (hipEventCreateWithFlags(&c->kc_done, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&c->kc_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->coop_done, hipEventDisableTiming) != hipSuccess) {
+        if (c->kc_done)
+            (void)hipEventDestroy(c->kc_done);
         delete c;
         return fail(DAMAS_EDEVICE, "hipEventCreate");
     }
@@ -449,19 +452,41 @@ extern "C" void damas_ctx_destroy(damas_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
-                      &ctx->E16, &ctx->A32})
+                      &ctx->E16, &ctx->A32, &ctx->coop_ws, &ctx->coop_tab})
         if (b->p)
             (void)hipFree(b->p);
     if (ctx->kc_pinned)
         (void)hipHostFree(ctx->kc_pinned);
+    if (ctx->coop_pinned)
+        (void)hipHostFree(ctx->coop_pinned);
     if (ctx->kc_done)
         (void)hipEventDestroy(ctx->kc_done);
+    if (ctx->coop_done)
+        (void)hipEventDestroy(ctx->coop_done);
     for (auto *v : {&ctx->phase_events[0], &ctx->phase_events[1], &ctx->event_pool})
         for (auto &e : *v) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
     delete ctx;
+}
+
+extern "C" int damas_ctx_set_coop(damas_ctx *ctx, int32_t max_workgroups)
+{
+    if (!ctx)
+        return fail(DAMAS_EINVAL, "ctx is NULL");
+    if (max_workgroups < -1)
+        return fail(DAMAS_EINVAL, "max_workgroups must be >= -1");
+    ctx->coop_budget = max_workgroups;
+    return DAMAS_OK;
+}
+
+extern "C" int damas_ctx_last_workgroups(const damas_ctx *ctx, int32_t *workgroups)
+{
+    if (!ctx || !workgroups)
+        return fail(DAMAS_EINVAL, "NULL argument");
+    *workgroups = ctx->last_workgroups;
+    return DAMAS_OK;
 }
 
 extern "C" int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled)
@@ -696,6 +721,89 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
     return fault_word(&P.fault);
 }
 
+// Cooperative schedule of a batched solve: ranks per bin by longest
+// processing time on ld^2 (the A bytes of a sweep), within the context's
+// workgroup budget and the device's co-resident capacity.  Fills tab
+// (bin, rank, ranks per workgroup) and returns the workgroup count, or 0
+// when no bin would get a helper.
+constexpr int kCoopMinRows = 320; // rows per workgroup below which a helper does not pay
+
+int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int *gpw)
+{
+    if (ctx->coop_budget == 0 || !P.batched || P.st_host.empty())
+        return 0;
+    const int nb = P.n_bins;
+    int cap = gs_coop_capacity(P.bf16 ? DAMAS_PREC_BF16 : P.p->precision, P.max_kept);
+    if (P.bf16 && P.refine > 0)
+        cap = std::min(cap, gs_coop_capacity(DAMAS_PREC_FP32, P.max_kept));
+    const int G = ctx->coop_budget < 0 ? cap : std::min(ctx->coop_budget, cap);
+    if (nb > G)
+        return 0;
+    std::vector<int> W(nb, 1);
+    auto eligible = [&](int f) {
+        const int st = P.st_host[f];
+        return (st + 63) / 64 >= 3 && st / (W[f] + 1) >= kCoopMinRows && W[f] < gs_max_ranks();
+    };
+    int used = nb;
+    while (used < G) {
+        int best = -1;
+        double bw = 0.0;
+        for (int f = 0; f < nb; ++f) {
+            if (!eligible(f))
+                continue;
+            const double l = (double)ld_of(P.st_host[f]);
+            const double v = l * l / W[f];
+            if (v > bw) {
+                bw = v;
+                best = f;
+            }
+        }
+        if (best < 0)
+            break;
+        ++W[best];
+        ++used;
+    }
+    if (*std::max_element(W.begin(), W.end()) == 1)
+        return 0;
+    tab.clear();
+    int g = 0;
+    for (int f = 0; f < nb; ++f) {
+        for (int h = 0; h < W[f]; ++h) {
+            tab.push_back(f);
+            tab.push_back(h);
+            tab.push_back(W[f]);
+        }
+        for (int prec : {P.p->precision, (int)DAMAS_PREC_FP32})
+            g = std::max(g, gs_groups_per_wave(prec, P.st_host[f], W[f]));
+    }
+    *gpw = g;
+    return used;
+}
+
+// Upload a cooperative schedule to the context's table (pinned staging).
+int upload_tab(damas_ctx *ctx, const std::vector<int32_t> &tab, hipStream_t s)
+{
+    int rc;
+    if ((rc = ensure(ctx, ctx->coop_tab, sizeof(int32_t) * tab.size(), s, "coop schedule")))
+        return rc;
+    HIP_TRY(hipEventSynchronize(ctx->coop_done), "hipEventSynchronize");
+    if (ctx->coop_pinned_n < tab.size()) {
+        if (ctx->coop_pinned)
+            HIP_TRY(hipHostFree(ctx->coop_pinned), "hipHostFree");
+        ctx->coop_pinned = nullptr;
+        ctx->coop_pinned_n = 0;
+        HIP_TRY(hipHostMalloc((void **)&ctx->coop_pinned, sizeof(int32_t) * tab.size()),
+                "hipHostMalloc");
+        ctx->coop_pinned_n = tab.size();
+    }
+    memcpy(ctx->coop_pinned, tab.data(), sizeof(int32_t) * tab.size());
+    HIP_TRY(hipMemcpyAsync(ctx->coop_tab.p, ctx->coop_pinned, sizeof(int32_t) * tab.size(),
+                           hipMemcpyHostToDevice, s),
+            "upload coop schedule");
+    HIP_TRY(hipEventRecord(ctx->coop_done, s), "hipEventRecord");
+    return DAMAS_OK;
+}
+
 // Everything after the DAS map and the selection for bins [f0, f0 + nb)
 // (arrays offset by the caller): layout, steering and PSF(s) when `build`,
 // then the sweeps.
@@ -740,23 +848,37 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
             return rc;
         HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
     }
+    // Cooperative schedule (batched solves of host-known kept counts).
+    std::vector<int32_t> tab;
+    int gpw = 0;
+    const int n_wg = nb == P.n_bins ? plan_coop(ctx, P, tab, &gpw) : 0;
+    if (n_wg > 0) {
+        if ((rc = upload_tab(ctx, tab, s)) ||
+            (rc = ensure(ctx, ctx->coop_ws, gs_coop_ws_bytes(nb, max_kept), s,
+                         "coop exchange")))
+            return rc;
+    }
+    ctx->last_workgroups = n_wg > 0 ? n_wg : nb;
+    auto sweeps = [&](int prec, const void *Ap, int iters, const void *xi) -> hipError_t {
+        if (n_wg > 0)
+            return launch_gs_coop(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi,
+                                  x_map, P.fault, (const int32_t *)ctx->coop_tab.p, n_wg, gpw,
+                                  ctx->coop_ws.p, s);
+        return launch_gs(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi, x_map,
+                         P.fault, s);
+    };
     if (!bf16) {
-        HIP_TRY(launch_gs(P.N, nb, st, max_kept, ix, P.off, p->precision, 1, ctx->A.p, bm,
-                          p->iterations, x_init, x_map, P.fault, s),
-                "gs launch");
+        HIP_TRY(sweeps(p->precision, ctx->A.p, p->iterations, x_init), "gs launch");
     } else {
         // Bulk sweeps on bf16 A, then the refinement sweeps on the FP32
         // copy, warm-started from the bulk result in place.
         const void *xi = x_init;
         if (P.bulk > 0 || P.refine == 0) {
-            HIP_TRY(launch_gs(P.N, nb, st, max_kept, ix, P.off, DAMAS_PREC_BF16, 1, ctx->A.p,
-                              bm, P.bulk, xi, x_map, P.fault, s),
-                    "gs launch (bf16)");
+            HIP_TRY(sweeps(DAMAS_PREC_BF16, ctx->A.p, P.bulk, xi), "gs launch (bf16)");
             xi = x_map;
         }
         if (P.refine > 0)
-            HIP_TRY(launch_gs(P.N, nb, st, max_kept, ix, P.off, DAMAS_PREC_FP32, 1,
-                              ctx->A32.p, bm, P.refine, xi, x_map, P.fault, s),
+            HIP_TRY(sweeps(DAMAS_PREC_FP32, ctx->A32.p, P.refine, xi),
                     "gs launch (fp32 refinement)");
     }
     if (ctx->timing) {
@@ -850,7 +972,7 @@ size_t damas::ctx_bytes(const damas_ctx *ctx)
 {
     size_t t = 0;
     for (const Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
-                            &ctx->E16, &ctx->A32})
+                            &ctx->E16, &ctx->A32, &ctx->coop_ws, &ctx->coop_tab})
         t += b->bytes;
     return t;
 }
@@ -860,7 +982,7 @@ int damas::ctx_trim(damas_ctx *ctx)
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->off, &ctx->E, &ctx->A, &ctx->E16,
-                      &ctx->A32}) {
+                      &ctx->A32, &ctx->coop_ws, &ctx->coop_tab}) {
         if (b->p)
             HIP_TRY(hipFree(b->p), "hipFree");
         b->p = nullptr;

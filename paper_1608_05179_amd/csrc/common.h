@@ -118,4 +118,19 @@ hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
 // Largest s_tilde the sweep kernel holds on chip for a precision.
 int gs_max_kept(int precision);
 
+// Cooperative sweeps (several workgroups per bin).  tab: per workgroup the
+// bin, its rank and the bin's rank count (device, 3 n_wg int32);
+// groups_per_wave: the most row groups any stream wave sums per strip;
+// ws: gs_coop_ws_bytes of device workspace.  Every bin needs >= 2 tiles.
+size_t gs_coop_ws_bytes(int n_bins, int max_kept);
+int gs_max_ranks();
+int gs_groups_per_wave(int precision, int s_tilde, int ranks);
+// Workgroups of the cooperative kernel that can be resident at once.
+int gs_coop_capacity(int precision, int max_kept);
+hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kept,
+                          const int32_t *idx, const int64_t *off, int precision,
+                          int unit_diagonal, const void *A, const double *b, int iterations,
+                          const void *x_init, void *x_map, int *fault, const int32_t *tab,
+                          int n_wg, int groups_per_wave, void *ws, hipStream_t s);
+
 } // namespace damas

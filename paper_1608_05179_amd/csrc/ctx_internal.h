@@ -63,6 +63,14 @@ struct damas_ctx {
     size_t kc_pinned_n = 0;
     hipEvent_t kc_done = nullptr;
     bool timing = false;
+    // cooperative sweeps: workgroup budget (-1: what fits the device, 0:
+    // never), exchange workspace, schedule table and its pinned staging
+    int coop_budget = -1;
+    int last_workgroups = 0; // of the last sweep launch (one per bin alone)
+    damas::Buffer coop_ws, coop_tab;
+    int32_t *coop_pinned = nullptr;
+    size_t coop_pinned_n = 0;
+    hipEvent_t coop_done = nullptr;
     // recorded (start, end) event pairs per timed phase, and spare pairs
     std::vector<std::pair<hipEvent_t, hipEvent_t>> phase_events[DAMAS_PHASES], event_pool;
 };

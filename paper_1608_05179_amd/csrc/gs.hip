@@ -134,21 +134,26 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     __amdgpu_buffer_rsrc_t rsrc;
     int64_t ld;
     int St, sw, lane, jp, cl;
+    int gsw, nwt;     // the sums interleave groups gsw + nwt k over every
+                      // stream wave of the bin (hand-over: this workgroup's)
     int nk;           // groups of this wave per strip
     int xcap;         // last row group start with x on chip (ld - CPL)
     uint32_t gstride; // bytes per group
     VT head[NH], hu[NU], hc[NU];
 
-    __device__ __forceinline__ void init(const TA *A, int64_t ld_, int St_, int sw_, int lane_)
+    __device__ __forceinline__ void init(const TA *A, int64_t ld_, int St_, int sw_, int lane_,
+                                         int gsw_, int nwt_)
     {
         ld = ld_;
         St = St_;
         sw = sw_;
         lane = lane_;
+        gsw = gsw_;
+        nwt = nwt_;
         jp = lane / LPJ;
         cl = (lane % LPJ) * CPL;
         const int ngroup = (St + CPL - 1) / CPL;
-        nk = ngroup > sw ? (ngroup - sw + NW - 1) / NW : 0;
+        nk = ngroup > gsw ? (ngroup - gsw + nwt - 1) / nwt : 0;
         xcap = (int)max(ld - CPL, (int64_t)0);
         gstride = (uint32_t)(CPL * ld * (int64_t)sizeof(TA));
         rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<TA *>(A), (short)0,
@@ -169,18 +174,20 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
             VT, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)vo, (int)(g * gstride), 0));
     }
 
-    // The head of strip T0 and the rows of its hand-over blocks (tile T0
-    // and tile TN0).
-    __device__ __forceinline__ void prefetch(int T0, int TN0)
+    // The head of strip T0 and, with `hand`, the rows of its hand-over
+    // blocks (tile T0 and tile TN0).
+    __device__ __forceinline__ void prefetch(int T0, int TN0, bool hand = true)
     {
         const uint32_t vo = voff(T0);
 #pragma unroll
         for (int n = 0; n < NH; ++n)
-            head[n] = load(sw + NW * n, vo);
+            head[n] = load(gsw + nwt * n, vo);
+        if (hand) {
 #pragma unroll
-        for (int m = 0; m < NU; ++m) {
-            hu[m] = load(T0 / CPL + sw + NW * m, vo);
-            hc[m] = load(TN0 / CPL + sw + NW * m, vo);
+            for (int m = 0; m < NU; ++m) {
+                hu[m] = load(T0 / CPL + sw + NW * m, vo);
+                hc[m] = load(TN0 / CPL + sw + NW * m, vo);
+            }
         }
     }
 
@@ -194,7 +201,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         return jb >= X0 && jb < X0 + kGsTile ? xold + (jb - X0) : xs + min(jb, xcap);
     }
 
-    // acc += the groups in v[0..n) (groups g0, g0 + NW, ...), in chunks of
+    // acc += the groups in v[0..n) (groups g0, g0 + nwt, ...), in chunks of
     // eight: the x reads of a chunk are issued together, and sched_barrier
     // keeps the scheduler from widening every group of a long head at once.
     template <int n>
@@ -207,7 +214,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
             double xj[C];
 #pragma unroll
             for (int k = k0; k < k0 + C && k < n; ++k)
-                xj[k - k0] = xrow(g0 + NW * k, xs, xold, X0)[jp];
+                xj[k - k0] = xrow(g0 + nwt * k, xs, xold, X0)[jp];
 #pragma unroll
             for (int k = k0; k < k0 + C && k < n; ++k)
 #pragma unroll
@@ -242,12 +249,12 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     }
 
     // The period that sums strip T while tile X0 (-2 tiles: none) is being
-    // updated and hands over the blocks of T and of the tile TN after it;
-    // when `next`, it also issues the head of strip NT0 (with hand-over
-    // tile NTN0) for the following period.
+    // updated and, with `hand`, hands over the blocks of T and of the tile
+    // TN after it; when `next`, it also issues the head of strip NT0 (with
+    // hand-over tile NTN0) for the following period.
     __device__ __forceinline__ void period(const double *xs, const double *xold, int T0, int X0,
                                            int TN0, bool next, int NT0, int NTN0, double *part,
-                                           TileBlocks<TA> *blk)
+                                           TileBlocks<TA> *blk, bool hand = true)
     {
         double acc[CPL];
         bool colok[CPL];
@@ -260,11 +267,12 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         // from hoisting every group's offset into a scalar register of its
         // own for the whole loop.
         asm volatile("" : "+s"(gstride), "+s"(xcap));
-        sum(head, sw, acc, xs, xold, X0);
-        handover(T0, TN0, colok, blk);
+        sum(head, gsw, acc, xs, xold, X0);
+        if (hand)
+            handover(T0, TN0, colok, blk);
         __builtin_amdgcn_sched_barrier(0);
         if (next)
-            prefetch(NT0, NTN0);
+            prefetch(NT0, NTN0, hand);
         __builtin_amdgcn_sched_barrier(0);
 
         // Tail: groups NH .. nk-1 in batches of NB, two batches in flight.
@@ -277,17 +285,17 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
             auto fill = [&](VT(&dst)[NB], int k0) {
 #pragma unroll
                 for (int n = 0; n < NB; ++n)
-                    dst[n] = load(sw + NW * (k0 + n), vo);
+                    dst[n] = load(gsw + nwt * (k0 + n), vo);
             };
             fill(b0, NH);
             for (int k0 = NH; k0 < nk; k0 += 2 * NB) {
                 fill(b1, k0 + NB);
                 __builtin_amdgcn_sched_barrier(0);
-                sum(b0, sw + NW * k0, acc, xs, xold, X0);
+                sum(b0, gsw + nwt * k0, acc, xs, xold, X0);
                 __builtin_amdgcn_sched_barrier(0);
                 fill(b0, k0 + 2 * NB);
                 __builtin_amdgcn_sched_barrier(0);
-                sum(b1, sw + NW * (k0 + NB), acc, xs, xold, X0);
+                sum(b1, gsw + nwt * (k0 + NB), acc, xs, xold, X0);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -317,12 +325,85 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
 // start at rho = 0, x = 0 and so never move.  The b~ of each tile is
 // gathered two tiles ahead (grid index one period, value the next), with
 // the loads issued at the end of a period, off the step chain.
+// Exchange area of the cooperative sweeps (global memory, zeroed before
+// the launch), per bin f with R = kGsFlagStride flag words:
+//   flags[f R]       tiles the owner has published
+//   flags[f R + h]   2 + the last period whose partial sums helper h has
+//                    published (a helper's first period is -1)
+//   flags[f R + kGsAbort]  set by a wait that gave up: every later wait of
+//                    the bin returns at once, so a broken exchange costs one
+//                    time-out, not one per period
+//   part[(f R + h) 128 + (q & 1) 64 + c]  helper h's sums of column c of
+//                    the strip of period q's tile
+//   xpub[f xstride + i]  x~_i as the owner last published it
+// Exchanged values go through agent-scope atomics, which are coherent across
+// the XCDs' L2 caches; a release fence orders them before the flag.
+constexpr int kGsMaxRanks = 16;
+constexpr int kGsFlagStride = 32;
+constexpr int kGsAbort = kGsMaxRanks;
+constexpr long long kGsSpinMax = 1ll << 21; // polls (~0.2 s) before a wait gives up
+
+struct GsCoop {
+    const int32_t *tab; // per workgroup: bin, rank, ranks of the bin
+    uint32_t *flags;
+    double *part;
+    double *xpub;
+    int64_t xstride;
+};
+
+__device__ __forceinline__ uint32_t coop_ld(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double coop_ld(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coop_st(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Publish a flag after this wave's earlier exchanged stores.
+__device__ __forceinline__ void coop_flag(uint32_t *p, uint32_t v)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wave-uniform bounded wait until *p >= v (p within a bin's flags, whose
+// abort word is `ab`); false if it gave up or the bin was aborted.  Data
+// loads after it are control-dependent on the flag (no speculation) and
+// are themselves coherent atomics.
+__device__ __forceinline__ bool coop_wait(const uint32_t *p, uint32_t v, uint32_t *ab)
+{
+    for (long long it = 0; it < kGsSpinMax; ++it) {
+        if (coop_ld(p) >= v) {
+            asm volatile("" ::: "memory");
+            return true;
+        }
+        if (coop_ld(ab) != 0u)
+            return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_store(ab, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+}
+
+// The owner's side of a cooperative bin (nullptr: the bin is alone).
+struct OwnerLink {
+    uint32_t *flags; // this bin's flags
+    double *part;    // this bin's partial-sum slots
+    double *xpub;    // this bin's published x
+    int ranks;
+    int *fault;
+};
+
 template <typename TA, int NW, bool UNIT>
 __device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xold,
                                             const TileBlocks<TA> *blks,
                                             const int32_t *__restrict__ id,
                                             const double *__restrict__ bf, int St, int ntile,
-                                            long long total, int lane)
+                                            long long total, int lane,
+                                            const OwnerLink *co = nullptr)
 {
     __builtin_amdgcn_s_setprio(3);
     auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
@@ -345,6 +426,14 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
 #pragma unroll
         for (int k = 0; k < NW; ++k)
             r += pt[k * kGsTile + lane];
+        if (co) {
+            // The helpers' sums of this tile's strip (their period q - 1).
+            for (int h = 1; h < co->ranks; ++h) {
+                if (!coop_wait(co->flags + h, (uint32_t)(q + 1), co->flags + kGsAbort))
+                    atomicOr(co->fault, 8);
+                r += coop_ld(co->part + h * 2 * kGsTile + (q & 1) * kGsTile + lane);
+            }
+        }
         double il = 1.0;
         if (!UNIT)
             il = mine ? 1.0 / widen(bk.dg[lane]) : 0.0;
@@ -394,6 +483,12 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         if (mine)
             xs[t0 + lane] = xl - fmin(rho, xl);
+        if (co) {
+            // Publish the tile's new values for the helpers.
+            if (mine)
+                coop_st(co->xpub + t0 + lane, xl - fmin(rho, xl));
+            coop_flag(co->flags, (uint32_t)(q + 1));
+        }
         // Snapshot of the next tile's values for the stream waves, which
         // read it while this wave overwrites that tile.
         xold[((q + 1) & 1) * kGsTile + lane] = tn0 + lane < St ? xs[tn0 + lane] : 0.0;
@@ -470,7 +565,7 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_kernel(
             serial_role<TA, NW, UNIT>(xs, parts, xold, blks, id, bf, St, ntile, total, lane);
         } else {
             StreamWave<TA, NW, NH, NB> sw;
-            sw.init(A, ld, St, w - 1, lane);
+            sw.init(A, ld, St, w - 1, lane, w - 1, NW);
             const int t1 = nxt(0), t2 = nxt(t1);
             sw.prefetch(0, t1 * kGsTile);
             sw.period(xs, xold, 0, -2 * kGsTile, t1 * kGsTile, total > 1, t1 * kGsTile,
@@ -492,6 +587,157 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_kernel(
 
     // Scatter: x_map[n] = x~_i at n = idx[i], 0 in the gaps between kept
     // points, so every grid point is written exactly once.
+    TX *xo = x_map + (int64_t)f * S;
+    if (St == 0) {
+        for (int n = tid; n < S; n += nthr)
+            xo[n] = (TX)0;
+        return;
+    }
+    for (int i = tid; i < St; i += nthr) {
+        const int n = id[i];
+        const int prev = i == 0 ? -1 : id[i - 1];
+        for (int q = prev + 1; q < n; ++q)
+            xo[q] = (TX)0;
+        xo[n] = (TX)xs[i];
+        if (i == St - 1)
+            for (int q = n + 1; q < S; ++q)
+                xo[q] = (TX)0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative sweeps: `ranks` workgroups share one bin.  Rank 0 (the owner)
+// runs the kernel above with its stream waves summing only every
+// ranks-th slice of each strip's row groups, adds the helpers' sums to its
+// residuals and publishes each tile's new x.  A helper (rank h >= 1) holds
+// its own copy of x~ in LDS, refreshed one tile behind the owner -- so the
+// tile being updated is seen at its old values, as through the owner's
+// snapshot -- and its stream waves sum the groups
+//   g = h NW + sw + (ranks NW) k
+// of the strip one tile ahead; wave 0 waits, refreshes, reduces the waves'
+// sums and publishes them.  The residual each row receives is the same sum
+// over the same values, in another order.  Every wait is bounded (a time-out
+// sets fault bit 8 and the sweeps go on with what is there), the launch is
+// cooperative (all workgroups resident), and needs at least two tiles per
+// bin.
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
+__global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
+    int N, const int32_t *__restrict__ s_tilde, int max_kept,
+    const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
+    const TA *__restrict__ A_all, const double *__restrict__ b, int iters,
+    const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault, GsCoop co)
+{
+    extern __shared__ double xs[];
+    const int64_t ld_cap = ld_of(max_kept);
+    double *parts = xs + ld_cap;
+    double *xold = parts + 2 * kGsMaxStreamWaves * kGsTile;
+    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xold + 2 * kGsTile);
+
+    const int f = co.tab[3 * blockIdx.x], rank = co.tab[3 * blockIdx.x + 1];
+    const int ranks = co.tab[3 * blockIdx.x + 2];
+    const int S = N * N;
+    int St = s_tilde[f];
+    if (St > max_kept) {
+        if (threadIdx.x == 0)
+            atomicOr(fault, 4);
+        St = 0;
+    }
+    const int64_t ld = ld_of(St);
+    const TA *A = A_all + (St > 0 ? off[f] : 0);
+    const int32_t *id = idx + (int64_t)f * S;
+    const double *bf = b + (int64_t)f * S;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int nthr = 64 * (1 + NW);
+    uint32_t *flags = co.flags + (int64_t)f * kGsFlagStride;
+    double *part = co.part + (int64_t)f * kGsMaxRanks * 2 * kGsTile;
+    double *xpub = co.xpub + (int64_t)f * co.xstride;
+
+    for (int64_t i = tid; i < ld; i += nthr)
+        xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
+    if (rank == 0) {
+        TA *z = reinterpret_cast<TA *>(blks);
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / sizeof(TA)); i += nthr)
+            z[i] = zero_of<TA>();
+    }
+    __syncthreads();
+
+    const int ntile = (St + kGsTile - 1) / kGsTile;
+    const long long total = (long long)iters * ntile;
+    auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
+
+    if (rank > 0) {
+        // Helper: period p sums strip t_{p+1}; tile t_{p-1} was published at
+        // the end of the owner's period p - 1.  Wave 0 and the stream waves
+        // run separate loops with two barriers per period each.
+        if (w == 0) {
+            int tp = ntile - 1, tc = ntile - 1; // tiles of periods p - 1 and p
+            for (long long p = -1; p + 1 < total; ++p) {
+                if (p >= 1) {
+                    if (!coop_wait(flags, (uint32_t)p, flags + kGsAbort))
+                        atomicOr(fault, 8);
+                    const int i = tp * kGsTile + lane;
+                    if (i < St)
+                        xs[i] = coop_ld(xpub + i);
+                }
+                __syncthreads();
+                __syncthreads();
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < NW; ++k)
+                    v += parts[k * kGsTile + lane];
+                coop_st(part + rank * 2 * kGsTile + ((p + 1) & 1) * kGsTile + lane, v);
+                coop_flag(flags + rank, (uint32_t)(p + 2));
+                tp = tc;
+                tc = nxt(tc);
+            }
+        } else {
+            StreamWave<TA, NW, NH, NB> sw;
+            sw.init(A, ld, St, w - 1, lane, rank * NW + w - 1, ranks * NW);
+            sw.prefetch(0, 0, false);
+            int tc = ntile - 1;
+            for (long long p = -1; p + 1 < total; ++p) {
+                const int tn = nxt(tc), tnn = nxt(tn);
+                __syncthreads();
+                sw.period(xs, xs, tn * kGsTile, -2 * kGsTile, tn * kGsTile, p + 2 < total,
+                          tnn * kGsTile, tnn * kGsTile, parts, nullptr, false);
+                __syncthreads();
+                tc = tn;
+            }
+        }
+        return;
+    }
+
+    // Owner.
+    if (total > 0) {
+        if (w == 0) {
+            xold[lane] = lane < St ? xs[lane] : 0.0;
+            __syncthreads();
+            OwnerLink link{flags, part, xpub, ranks, fault};
+            serial_role<TA, NW, UNIT>(xs, parts, xold, blks, id, bf, St, ntile, total, lane,
+                                      &link);
+        } else {
+            StreamWave<TA, NW, NH, NB> sw;
+            sw.init(A, ld, St, w - 1, lane, w - 1, ranks * NW);
+            const int t1 = nxt(0), t2 = nxt(t1);
+            sw.prefetch(0, t1 * kGsTile);
+            sw.period(xs, xold, 0, -2 * kGsTile, t1 * kGsTile, total > 1, t1 * kGsTile,
+                      t2 * kGsTile, parts, &blks[0]);
+            __syncthreads();
+            int t = 0;
+            for (long long q = 0; q < total; ++q) {
+                const int tn = nxt(t), tnn = nxt(tn), tn3 = nxt(tnn);
+                if (q + 1 < total)
+                    sw.period(xs, xold + (q & 1) * kGsTile, tn * kGsTile, t * kGsTile,
+                              tnn * kGsTile, q + 2 < total, tnn * kGsTile, tn3 * kGsTile,
+                              parts + ((q + 1) & 1) * NW * kGsTile, &blks[(q + 1) & 1]);
+                t = tn;
+                __syncthreads();
+            }
+        }
+    }
+
     TX *xo = x_map + (int64_t)f * S;
     if (St == 0) {
         for (int n = tid; n < S; n += nthr)
@@ -582,6 +828,121 @@ static hipError_t launch_gs_u(int N, int n_bins, const int32_t *s_tilde, int max
     return shrt ? DAMAS_GS_LAUNCH(false, SH::short_nh, SH::short_nb)
                 : DAMAS_GS_LAUNCH(false, SH::long_nh, SH::long_nb);
 #undef DAMAS_GS_LAUNCH
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative launches.
+
+__global__ void zero_u32_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Byte offsets of the exchange area within the workspace.
+static size_t coop_flags_bytes(int n_bins)
+{
+    return ((size_t)n_bins * kGsFlagStride * sizeof(uint32_t) + 255) & ~(size_t)255;
+}
+static size_t coop_part_bytes(int n_bins)
+{
+    return (size_t)n_bins * kGsMaxRanks * 2 * kGsTile * sizeof(double);
+}
+
+size_t gs_coop_ws_bytes(int n_bins, int max_kept)
+{
+    return coop_flags_bytes(n_bins) + coop_part_bytes(n_bins) +
+           (size_t)n_bins * ld_of(max_kept) * sizeof(double);
+}
+
+int gs_max_ranks() { return kGsMaxRanks; }
+
+int gs_groups_per_wave(int precision, int s_tilde, int ranks)
+{
+    const int cpl = precision == DAMAS_PREC_FP64 ? 2 : precision == DAMAS_PREC_BF16 ? 8 : 4;
+    const int ng = (s_tilde + cpl - 1) / cpl, nwt = ranks * GsShapes<float>::nw;
+    return (ng + nwt - 1) / nwt;
+}
+
+template <typename TA, typename TX, bool UNIT, int NH, int NB>
+static const void *coop_fn()
+{
+    return (const void *)gs_coop_kernel<TA, TX, UNIT, GsShapes<TA>::nw, NH, NB>;
+}
+
+// The kernel instance for a precision and the most groups any stream
+// wave sums per strip (short shape when they fit its head).
+static const void *coop_pick(int precision, int unit, int groups_per_wave)
+{
+#define DAMAS_COOP_PICK(TA, TX)                                                                \
+    {                                                                                          \
+        typedef GsShapes<TA> SH;                                                               \
+        const bool shrt = groups_per_wave <= SH::short_nh;                                    \
+        if (unit)                                                                              \
+            return shrt ? coop_fn<TA, TX, true, SH::short_nh, SH::short_nb>()                 \
+                        : coop_fn<TA, TX, true, SH::long_nh, SH::long_nb>();                  \
+        return shrt ? coop_fn<TA, TX, false, SH::short_nh, SH::short_nb>()                    \
+                    : coop_fn<TA, TX, false, SH::long_nh, SH::long_nb>();                     \
+    }
+    if (precision == DAMAS_PREC_FP64)
+        DAMAS_COOP_PICK(double, double)
+    if (precision == DAMAS_PREC_BF16)
+        DAMAS_COOP_PICK(bf16s, float)
+    DAMAS_COOP_PICK(float, float)
+#undef DAMAS_COOP_PICK
+}
+
+int gs_coop_capacity(int precision, int max_kept)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int nw = GsShapes<float>::nw; // the same for every storage type
+    const void *fn = coop_pick(precision, 1, 1 << 30);
+    (void)allow_big_lds(fn);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * (1 + nw),
+                                                     gs_lds_bytes(precision, max_kept)) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
+hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kept,
+                          const int32_t *idx, const int64_t *off, int precision,
+                          int unit_diagonal, const void *A, const double *b, int iterations,
+                          const void *x_init, void *x_map, int *fault, const int32_t *tab,
+                          int n_wg, int groups_per_wave, void *ws, hipStream_t s)
+{
+    if (n_bins == 0 || n_wg == 0)
+        return hipSuccess;
+    char *base = (char *)ws;
+    GsCoop co;
+    co.tab = tab;
+    co.flags = (uint32_t *)base;
+    co.part = (double *)(base + coop_flags_bytes(n_bins));
+    co.xpub = (double *)(base + coop_flags_bytes(n_bins) + coop_part_bytes(n_bins));
+    co.xstride = ld_of(max_kept);
+    // Flags start at zero (a kernel, so the launch sequence stays
+    // capturable in a graph).
+    const int64_t nflags = (int64_t)n_bins * kGsFlagStride;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, s,
+                       co.flags, nflags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const void *fn = coop_pick(precision, unit_diagonal, groups_per_wave);
+    (void)allow_big_lds(fn);
+    const int nw = GsShapes<float>::nw;
+    size_t lds = gs_lds_bytes(precision, max_kept);
+    void *args[] = {&N,  (void *)&s_tilde, &max_kept, (void *)&idx, (void *)&off,
+                    (void *)&A, (void *)&b, &iterations, (void *)&x_init, &x_map,
+                    &fault, &co};
+    return hipLaunchCooperativeKernel(fn, dim3(n_wg), dim3(64 * (1 + nw)), args,
+                                      (unsigned)lds, s);
 }
 
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,

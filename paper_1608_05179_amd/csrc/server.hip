@@ -249,8 +249,15 @@ extern "C" int damas_server_create(const damas_server_opts *o, damas_server **ou
     srv->o = *o;
     srv->cache.budget = o->cache_budget;
     srv->slots.resize(o->slots);
+    // Cooperative sweeps of concurrent requests share the device: each slot
+    // launches at most its share of the compute units, so every launched
+    // workgroup can be resident at once.
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o->device);
     for (Slot &sl : srv->slots) {
         int rc = damas_ctx_create(o->device, &sl.ctx);
+        if (rc == DAMAS_OK)
+            rc = damas_ctx_set_coop(sl.ctx, cus / o->slots);
         if (rc == DAMAS_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
             rc = set_error(DAMAS_EDEVICE, "hipStreamCreate");
         if (rc) {

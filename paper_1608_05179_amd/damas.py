@@ -87,6 +87,8 @@ _sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i
 _sig("damas_ctx_create", ctypes.c_int, c_i32, ctypes.POINTER(c_vp))
 _sig("damas_ctx_destroy", None, c_vp)
 _sig("damas_ctx_set_timing", ctypes.c_int, c_vp, c_i32)
+_sig("damas_ctx_set_coop", ctypes.c_int, c_vp, c_i32)
+_sig("damas_ctx_last_workgroups", ctypes.c_int, c_vp, ctypes.POINTER(c_i32))
 _sig("damas_ctx_gs_time", ctypes.c_int, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64))
 _sig("damas_ctx_phase_time", ctypes.c_int, c_vp, c_i32, ctypes.POINTER(c_dbl),
      ctypes.POINTER(c_i64))
@@ -328,6 +330,17 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_coop(self, max_workgroups: int):
+        """Workgroup budget of cooperative sweeps: -1 what fits the device,
+        0 never, n at most n."""
+        _check(_lib.damas_ctx_set_coop(self._h, int(max_workgroups)))
+
+    def last_workgroups(self) -> int:
+        """Workgroups of the last sweep launch (bins when none cooperated)."""
+        v = c_i32()
+        _check(_lib.damas_ctx_last_workgroups(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_timing(self, enabled: bool):
         _check(_lib.damas_ctx_set_timing(self._h, 1 if enabled else 0))
