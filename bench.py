@@ -27,7 +27,8 @@ Prints one JSON line.  Beyond the throughput keys:
                  sustainable rate.
 
 --workload NAME measures one workload alone (compressed, plain, precision,
-batched) and prints its record as the line.
+batched, served) and prints its record as the line; --workload copy runs one
+1 GiB device-to-device copy, the calibration of the HBM byte counters.
 """
 import argparse
 import hashlib
@@ -59,7 +60,8 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--workload", default=None,
-                    choices=["compressed", "plain", "precision", "batched", "served"])
+                    choices=["compressed", "plain", "precision", "batched", "served",
+                             "copy"])
     ap.add_argument("--refine", type=int, default=60,
                     help="FP32 refinement sweeps of the precision workload")
     return ap.parse_args()
@@ -304,6 +306,16 @@ def main():
     import numpy as np
     import torch  # noqa: F401
 
+    if args.workload == "copy":
+        # Counter calibration: one device-to-device copy of 1 GiB (a plain
+        # copy kernel of known size; FETCH_SIZE and WRITE_SIZE should read
+        # 1 GiB each).
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes": src.numel() * 4}), flush=True)
+        return
     if args.workload == "served":
         print(json.dumps(measure_served()), flush=True)
         return
