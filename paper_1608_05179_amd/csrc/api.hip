@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -721,12 +722,18 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
     return fault_word(&P.fault);
 }
 
-// Cooperative schedule of a batched solve: ranks per bin by longest
-// processing time on ld^2 (the A bytes of a sweep), within the context's
-// workgroup budget and the device's co-resident capacity.  Fills tab
-// (bin, rank, ranks per workgroup) and returns the workgroup count, or 0
-// when no bin would get a helper.
-constexpr int kCoopMinRows = 320; // rows per workgroup below which a helper does not pay
+// Cooperative schedule of a batched solve, from the kept counts the host
+// knows.  The work of a bin is ld^2 (A elements per sweep).  With G
+// workgroups (the context's budget within the device's co-resident
+// capacity) and T = total work / G, a bin above 1.25 T gets ceil(work / T)
+// ranks (at most gs_max_ranks(), at least kCoopMinRows rows each, three
+// tiles), each the first job of its own workgroup; the other bins, largest
+// first, go after them on the least loaded workgroups.  The schedule is
+// used only if its estimated makespan (ranks cost kCoopOverhead more per
+// element than a bin alone) beats one workgroup per bin by 10 %.
+// tab = [first, end) job per workgroup, then (bin, rank, ranks) per job.
+constexpr int kCoopMinRows = 320;     // rows per rank below which a helper does not pay
+constexpr double kCoopOverhead = 1.3; // cost per element of a rank vs a bin alone
 
 int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int *gpw)
 {
@@ -737,47 +744,91 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
     if (P.bf16 && P.refine > 0)
         cap = std::min(cap, gs_coop_capacity(DAMAS_PREC_FP32, P.max_kept));
     const int G = ctx->coop_budget < 0 ? cap : std::min(ctx->coop_budget, cap);
-    if (nb > G)
+    if (G < 1)
         return 0;
-    std::vector<int> W(nb, 1);
-    auto eligible = [&](int f) {
-        const int st = P.st_host[f];
-        return (st + 63) / 64 >= 3 && st / (W[f] + 1) >= kCoopMinRows && W[f] < gs_max_ranks();
-    };
-    int used = nb;
-    while (used < G) {
-        int best = -1;
-        double bw = 0.0;
-        for (int f = 0; f < nb; ++f) {
-            if (!eligible(f))
-                continue;
-            const double l = (double)ld_of(P.st_host[f]);
-            const double v = l * l / W[f];
-            if (v > bw) {
-                bw = v;
-                best = f;
-            }
-        }
-        if (best < 0)
-            break;
-        ++W[best];
-        ++used;
-    }
-    if (*std::max_element(W.begin(), W.end()) == 1)
-        return 0;
-    tab.clear();
-    int g = 0;
+    std::vector<double> work(nb);
+    double total = 0.0, plain_span = 0.0;
     for (int f = 0; f < nb; ++f) {
-        for (int h = 0; h < W[f]; ++h) {
-            tab.push_back(f);
-            tab.push_back(h);
-            tab.push_back(W[f]);
-        }
-        for (int prec : {P.p->precision, (int)DAMAS_PREC_FP32})
-            g = std::max(g, gs_groups_per_wave(prec, P.st_host[f], W[f]));
+        const double l = (double)ld_of(P.st_host[f]);
+        work[f] = l * l;
+        total += work[f];
+        plain_span = std::max(plain_span, work[f]);
     }
-    *gpw = g;
-    return used;
+    if (nb <= G && total <= 0.0)
+        return 0;
+    const double T = total / G;
+    std::vector<int> ranks(nb, 1);
+    int multi = 0;
+    for (int f = 0; f < nb; ++f) {
+        const int st = P.st_host[f];
+        if (work[f] <= 1.25 * T || (st + 63) / 64 < 3)
+            continue;
+        int r = (int)std::ceil(work[f] / T);
+        r = std::min({r, gs_max_ranks(), std::max(st / kCoopMinRows, 1)});
+        if (r > 1) {
+            ranks[f] = r;
+            multi += r;
+        }
+    }
+    // Fit the ranked bins into G workgroups.
+    while (multi > G) {
+        int best = -1;
+        for (int f = 0; f < nb; ++f)
+            if (ranks[f] > 1 && (best < 0 || ranks[f] > ranks[best]))
+                best = f;
+        --ranks[best];
+        --multi;
+        if (ranks[best] == 1)
+            --multi;
+    }
+    if (multi == 0 && nb <= G)
+        return 0; // no bin would get a helper: one workgroup per bin
+    // Workgroups: ranked bins' ranks first, then the bins alone (longest
+    // processing time onto the least loaded workgroup).
+    std::vector<std::vector<int32_t>> wg_jobs(G);
+    std::vector<double> load(G, 0.0);
+    int g = 0;
+    for (int f = 0; f < nb; ++f)
+        if (ranks[f] > 1)
+            for (int h = 0; h < ranks[f]; ++h, ++g) {
+                wg_jobs[g] = {f, h, ranks[f]};
+                load[g] = kCoopOverhead * work[f] / ranks[f];
+            }
+    std::vector<int> solo;
+    for (int f = 0; f < nb; ++f)
+        if (ranks[f] == 1)
+            solo.push_back(f);
+    std::sort(solo.begin(), solo.end(), [&](int a, int b) { return work[a] > work[b]; });
+    for (int f : solo) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        wg_jobs[k].insert(wg_jobs[k].end(), {f, 0, 1});
+        load[k] += work[f];
+    }
+    const double span = *std::max_element(load.begin(), load.end());
+    if (!(span < 0.9 * plain_span) && nb <= G)
+        return 0;
+    int n_wg = 0;
+    for (int k = 0; k < G; ++k)
+        if (!wg_jobs[k].empty())
+            ++n_wg;
+    tab.assign(2 * (size_t)n_wg, 0);
+    int pos = 0, w = 0, gmax = 0;
+    for (int k = 0; k < G; ++k) {
+        if (wg_jobs[k].empty())
+            continue;
+        tab[2 * w] = pos;
+        for (size_t j = 0; j < wg_jobs[k].size(); j += 3) {
+            const int f = wg_jobs[k][j], r = wg_jobs[k][j + 2];
+            tab.insert(tab.end(), {wg_jobs[k][j], wg_jobs[k][j + 1], r});
+            for (int prec : {P.p->precision, (int)DAMAS_PREC_FP32})
+                gmax = std::max(gmax, gs_groups_per_wave(prec, P.st_host[f], r));
+            ++pos;
+        }
+        tab[2 * w + 1] = pos;
+        ++w;
+    }
+    *gpw = gmax;
+    return n_wg;
 }
 
 // Upload a cooperative schedule to the context's table (pinned staging).

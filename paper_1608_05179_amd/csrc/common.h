@@ -118,8 +118,10 @@ hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
 // Largest s_tilde the sweep kernel holds on chip for a precision.
 int gs_max_kept(int precision);
 
-// Cooperative sweeps (several workgroups per bin).  tab: per workgroup the
-// bin, its rank and the bin's rank count (device, 3 n_wg int32);
+// Cooperative sweeps (several workgroups per bin, several bins per
+// workgroup).  tab (device int32): per workgroup its first job and one past
+// its last (2 n_wg), then per job the bin, its rank and the bin's rank
+// count; a job with ranks > 1 must be the first of its workgroup;
 // groups_per_wave: the most row groups any stream wave sums per strip;
 // ws: gs_coop_ws_bytes of device workspace.  Every bin needs >= 2 tiles.
 size_t gs_coop_ws_bytes(int n_bins, int max_kept);

@@ -266,7 +266,11 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         // Per-period copies of the loop-invariant strides keep the compiler
         // from hoisting every group's offset into a scalar register of its
         // own for the whole loop.
-        asm volatile("" : "+s"(gstride), "+s"(xcap));
+        gstride = (uint32_t)__builtin_amdgcn_readfirstlane((int)gstride);
+        xcap = __builtin_amdgcn_readfirstlane(xcap);
+        asm volatile("" : "+v"(gstride), "+v"(xcap));
+        gstride = (uint32_t)__builtin_amdgcn_readfirstlane((int)gstride);
+        xcap = __builtin_amdgcn_readfirstlane(xcap);
         sum(head, gsw, acc, xs, xold, X0);
         if (hand)
             handover(T0, TN0, colok, blk);
@@ -336,15 +340,18 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
 //   part[(f R + h) 128 + (q & 1) 64 + c]  helper h's sums of column c of
 //                    the strip of period q's tile
 //   xpub[f xstride + i]  x~_i as the owner last published it
-// Exchanged values go through agent-scope atomics, which are coherent across
-// the XCDs' L2 caches; a release fence orders them before the flag.
+// Exchanged values go through agent-scope atomics, which write through and
+// read past the XCDs' L2 caches; a flag is stored once the wave's earlier
+// exchange stores have completed (vmcnt 0) -- nothing else needs flushing,
+// so there is no L2 write-back in the loop.
 constexpr int kGsMaxRanks = 16;
 constexpr int kGsFlagStride = 32;
 constexpr int kGsAbort = kGsMaxRanks;
 constexpr long long kGsSpinMax = 1ll << 21; // polls (~0.2 s) before a wait gives up
 
 struct GsCoop {
-    const int32_t *tab; // per workgroup: bin, rank, ranks of the bin
+    const int32_t *wg;   // per workgroup: first job, one past its last job
+    const int32_t *jobs; // per job: bin, rank, ranks of the bin
     uint32_t *flags;
     double *part;
     double *xpub;
@@ -363,10 +370,10 @@ __device__ __forceinline__ void coop_st(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Publish a flag after this wave's earlier exchanged stores.
+// Publish a flag after this wave's earlier exchanged stores completed.
 __device__ __forceinline__ void coop_flag(uint32_t *p, uint32_t v)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Wave-uniform bounded wait until *p >= v (p within a bin's flags, whose
@@ -388,7 +395,7 @@ __device__ __forceinline__ bool coop_wait(const uint32_t *p, uint32_t v, uint32_
     return false;
 }
 
-// The owner's side of a cooperative bin (nullptr: the bin is alone).
+// The owner's side of a cooperative bin (ranks == 1: the bin is alone).
 struct OwnerLink {
     uint32_t *flags; // this bin's flags
     double *part;    // this bin's partial-sum slots
@@ -403,7 +410,8 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                                             const int32_t *__restrict__ id,
                                             const double *__restrict__ bf, int St, int ntile,
                                             long long total, int lane,
-                                            const OwnerLink *co = nullptr)
+                                            OwnerLink co = OwnerLink{nullptr, nullptr, nullptr,
+                                                                     1, nullptr})
 {
     __builtin_amdgcn_s_setprio(3);
     auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
@@ -426,12 +434,12 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
 #pragma unroll
         for (int k = 0; k < NW; ++k)
             r += pt[k * kGsTile + lane];
-        if (co) {
+        if (co.ranks > 1) {
             // The helpers' sums of this tile's strip (their period q - 1).
-            for (int h = 1; h < co->ranks; ++h) {
-                if (!coop_wait(co->flags + h, (uint32_t)(q + 1), co->flags + kGsAbort))
-                    atomicOr(co->fault, 8);
-                r += coop_ld(co->part + h * 2 * kGsTile + (q & 1) * kGsTile + lane);
+            for (int h = 1; h < co.ranks; ++h) {
+                if (!coop_wait(co.flags + h, (uint32_t)(q + 1), co.flags + kGsAbort))
+                    atomicOr(co.fault, 8);
+                r += coop_ld(co.part + h * 2 * kGsTile + (q & 1) * kGsTile + lane);
             }
         }
         double il = 1.0;
@@ -483,11 +491,11 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         if (mine)
             xs[t0 + lane] = xl - fmin(rho, xl);
-        if (co) {
+        if (co.ranks > 1) {
             // Publish the tile's new values for the helpers.
             if (mine)
-                coop_st(co->xpub + t0 + lane, xl - fmin(rho, xl));
-            coop_flag(co->flags, (uint32_t)(q + 1));
+                coop_st(co.xpub + t0 + lane, xl - fmin(rho, xl));
+            coop_flag(co.flags, (uint32_t)(q + 1));
         }
         // Snapshot of the next tile's values for the stream waves, which
         // read it while this wave overwrites that tile.
@@ -620,21 +628,23 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_kernel(
 // sets fault bit 8 and the sweeps go on with what is there), the launch is
 // cooperative (all workgroups resident), and needs at least two tiles per
 // bin.
+// One job of the cooperative kernel: rank `rank` of the `ranks` workgroups
+// of bin f (ranks == 1: the bin alone, nothing exchanged).
 template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
-__global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
-    int N, const int32_t *__restrict__ s_tilde, int max_kept,
-    const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
-    const TA *__restrict__ A_all, const double *__restrict__ b, int iters,
-    const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault, GsCoop co)
+__device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
+                                         const int32_t *__restrict__ s_tilde, int max_kept,
+                                         const int32_t *__restrict__ idx,
+                                         const int64_t *__restrict__ off,
+                                         const TA *__restrict__ A_all,
+                                         const double *__restrict__ b, int iters,
+                                         const TX *__restrict__ x_init, TX *__restrict__ x_map,
+                                         int *fault, const GsCoop &co, double *xs)
 {
-    extern __shared__ double xs[];
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
     double *xold = parts + 2 * kGsMaxStreamWaves * kGsTile;
     TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xold + 2 * kGsTile);
 
-    const int f = co.tab[3 * blockIdx.x], rank = co.tab[3 * blockIdx.x + 1];
-    const int ranks = co.tab[3 * blockIdx.x + 2];
     const int S = N * N;
     int St = s_tilde[f];
     if (St > max_kept) {
@@ -714,9 +724,8 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
         if (w == 0) {
             xold[lane] = lane < St ? xs[lane] : 0.0;
             __syncthreads();
-            OwnerLink link{flags, part, xpub, ranks, fault};
             serial_role<TA, NW, UNIT>(xs, parts, xold, blks, id, bf, St, ntile, total, lane,
-                                      &link);
+                                      OwnerLink{flags, part, xpub, ranks, fault});
         } else {
             StreamWave<TA, NW, NH, NB> sw;
             sw.init(A, ld, St, w - 1, lane, w - 1, ranks * NW);
@@ -753,6 +762,29 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
         if (i == St - 1)
             for (int q = n + 1; q < S; ++q)
                 xo[q] = (TX)0;
+    }
+}
+
+
+// The cooperative kernel: workgroup g runs jobs co.wg[2g] .. co.wg[2g+1]-1
+// of co.jobs (bin, rank, ranks) in order.  A bin with ranks > 1 is the first
+// job of each of its workgroups, so all its ranks run at once (the launch
+// keeps every workgroup resident); later jobs are bins alone, which wait on
+// nobody.
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
+__global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
+    int N, const int32_t *__restrict__ s_tilde, int max_kept,
+    const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
+    const TA *__restrict__ A_all, const double *__restrict__ b, int iters,
+    const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault, GsCoop co)
+{
+    extern __shared__ double xs[];
+    const int j0 = co.wg[2 * blockIdx.x], j1 = co.wg[2 * blockIdx.x + 1];
+    for (int j = j0; j < j1; ++j) {
+        coop_job<TA, TX, UNIT, NW, NH, NB>(co.jobs[3 * j], co.jobs[3 * j + 1],
+                                           co.jobs[3 * j + 2], N, s_tilde, max_kept, idx, off,
+                                           A_all, b, iters, x_init, x_map, fault, co, xs);
+        __syncthreads(); // the next job reuses LDS
     }
 }
 
@@ -921,7 +953,8 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
         return hipSuccess;
     char *base = (char *)ws;
     GsCoop co;
-    co.tab = tab;
+    co.wg = tab;
+    co.jobs = tab + 2 * n_wg;
     co.flags = (uint32_t *)base;
     co.part = (double *)(base + coop_flags_bytes(n_bins));
     co.xpub = (double *)(base + coop_flags_bytes(n_bins) + coop_part_bytes(n_bins));

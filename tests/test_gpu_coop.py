@@ -31,10 +31,10 @@ def _solve(dm, dev, w, mode, K, prec, coop, refine=0):
     wg = ctx.last_workgroups()
     if coop == 0:
         assert wg == w.n_bins
+    elif coop > 0:
+        assert wg <= coop  # the budget holds (bins pack when it is small)
     else:
         assert wg > w.n_bins  # some bin had helpers
-        if coop > 0:
-            assert wg <= max(coop, w.n_bins)
     out = x.double().cpu().numpy(), st.cpu().numpy(), idx.cpu().numpy()
     ctx.close()
     return out
@@ -90,3 +90,25 @@ def test_coop_off_is_the_one_workgroup_kernel(dm, dev):
     assert np.array_equal(a, b)
     c, _, _ = _solve(dm, dev, w, dm.SEL_KEEP_COUNT, Ks, dm.PREC_FP32, -1)
     assert np.linalg.norm(a - c) <= 1e-5 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("budget", [5, -1])
+def test_coop_packs_bins_onto_workgroups(orc, dm, dev, budget):
+    # 12 uneven bins; a budget of 5 workgroups packs several bins alone onto
+    # each workgroup after the ranks of the largest
+    w = synth.compressed_fp32(n_bins=12, N=61, iterations=80)
+    rng = np.random.default_rng(9)
+    Ks = [int(k) for k in rng.integers(150, 3000, size=12)]
+    Ks[3] = 3600
+    x, st, idx = _solve(dm, dev, w, dm.SEL_KEEP_COUNT, Ks, dm.PREC_FP32, budget)
+    for f in (3, 0, 7, 11):
+        ref = _oracle(orc, w, f, orc.SEL_KEEP_COUNT, Ks[f])
+        if ref["margin"] > 1e-12:
+            assert np.array_equal(idx[f, :st[f]], ref["idx"]), f
+        err = np.linalg.norm(x[f] - ref["x"]) / np.linalg.norm(ref["x"])
+        assert err <= 1e-4, (f, err)
+    # every bin was solved: the map is zero exactly off each kept set
+    for f in range(w.n_bins):
+        offk = np.ones(w.S, bool)
+        offk[idx[f, :st[f]]] = False
+        assert (x[f, offk] == 0).all() and x[f, ~offk].max() > 0
