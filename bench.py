@@ -64,6 +64,8 @@ def _parse():
                              "copy"])
     ap.add_argument("--refine", type=int, default=60,
                     help="FP32 refinement sweeps of the precision workload")
+    ap.add_argument("--tune-sweeps", type=int, default=20,
+                    help="sweeps per autotuner trial before a variant is timed (0: no tuning)")
     return ap.parse_args()
 
 
@@ -110,7 +112,8 @@ def _workload(name, refine):
             "U{300..4000} per bin, 2000 sweeps, A stored f32")
 
 
-def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False):
+def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False,
+            tune_sweeps=0):
     """Time `steps` batched solves of a workload; returns its record."""
     import numpy as np
     import torch
@@ -139,6 +142,11 @@ def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False):
                   precision=prec, batched=batched, refine_sweeps=R, x_map=x, s_tilde=st,
                   idx=idx)
 
+    tune = None
+    if tune_sweeps > 0:
+        # Set-up, not timed: the schedule autotuner on this problem.
+        tune = ctx.autotune(g, freq, csm, select_mode=mode, keep_count=K, precision=prec,
+                            trial_sweeps=tune_sweeps)
     for _ in range(warmup):
         step()
     ctx.check()
@@ -186,6 +194,7 @@ def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False):
         "latency_ms": {"p50": round(_pct(lat, 50), 4), "p99": round(_pct(lat, 99), 4)},
         "sweeps_ms": round(gs_avg, 4), "system_build_ms": round(sys_ms / max(sys_n, 1), 4),
         "sweep_workgroups": wg,
+        "autotune": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "kernel": f"gs_kernel (A {a_kind})", "kernel_avg_ms": round(gs_avg, 4),
@@ -321,7 +330,8 @@ def main():
         return
     if args.workload is not None:
         rec, _, _, _ = measure(args.workload, args.steps, args.warmup, args.plain_steps,
-                               refine=args.refine, psf_kernel_time=True)
+                               refine=args.refine, psf_kernel_time=True,
+                               tune_sweeps=args.tune_sweeps)
         print(json.dumps(rec), flush=True)
         return
 
@@ -370,7 +380,7 @@ def main():
         out["variants"] = {}
         for name, steps in (("plain", 5), ("precision", 2), ("batched", 2)):
             v, _, _, _ = measure(name, steps, 1, 0, refine=args.refine,
-                                 psf_kernel_time=True)
+                                 psf_kernel_time=True, tune_sweeps=args.tune_sweeps)
             out["variants"][name] = v
             torch.cuda.empty_cache()
         out["variants"]["served"] = measure_served()

@@ -52,7 +52,7 @@ extern "C" {
 #define DAMAS_ENOMEM (-2)    /* device or host allocation failed          */
 #define DAMAS_EDEVICE (-3)   /* HIP runtime or kernel error               */
 #define DAMAS_EADMIT (-4)    /* request can never fit the memory budget   */
-#define DAMAS_EBUSY (-5)     /* queue full                                */
+#define DAMAS_EBUSY (-5)     /* queue full, or a resource in use (graph)  */
 #define DAMAS_ETIMEDOUT (-6) /* wait timed out                            */
 #define DAMAS_ECAPACITY (-7) /* a device-side capacity bound was exceeded */
 
@@ -265,7 +265,22 @@ int damas_ctx_set_coop(damas_ctx *ctx, int32_t max_workgroups);
 int damas_ctx_last_workgroups(const damas_ctx *ctx, int32_t *workgroups);
 
 /* Parameters of a solve (host struct). */
+typedef struct damas_params damas_params;
+
+/* Outcome of damas_ctx_autotune. */
 typedef struct {
+    int32_t coop;            /* cooperative sweeps chosen (1) or not (0)   */
+    int32_t coop_min_rows;   /* rows per rank at least                     */
+    double coop_split;       /* bins above coop_split x the mean work per
+                                workgroup get ranks                        */
+    double coop_overhead;    /* assumed cost per element of a rank
+                                relative to a bin alone (schedule choice) */
+    double best_ms_per_sweep;    /* sweep time of the choice              */
+    double default_ms_per_sweep; /* of the untuned knobs                  */
+    int32_t candidates_timed;    /* distinct schedules timed              */
+} damas_tune_result;
+
+struct damas_params {
     int32_t select_mode;       /* DAMAS_SEL_*                               */
     double eps;                /* EPS_REL threshold (relative to max |b|)   */
     const int32_t *keep_count; /* HOST, n_bins int32 (KEEP_COUNT), or NULL:
@@ -282,7 +297,7 @@ typedef struct {
                                   `iterations` sweeps run last, on the FP32
                                   copy of A (0 .. iterations); ignored
                                   otherwise                                 */
-} damas_params;
+};
 
 /* Every step for every bin, device-resident, enqueued on `stream`.
  *   freq, csm   device, as for damas_das_map
@@ -301,6 +316,35 @@ int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
 /* Synchronise with the context's last solve and report a device-side
  * capacity failure (DAMAS_ECAPACITY) or a HIP error. */
 int damas_check(damas_ctx *ctx, void *stream);
+
+/* Autotuner of the cooperative sweep schedule: times trial solves of this
+ * problem (batched, trial_sweeps sweeps each, into a scratch map; for BF16
+ * all sweeps on the bf16 system) for one workgroup per bin and for a grid
+ * of schedule knobs (minimum rows per rank, split threshold, rank cost),
+ * timing each distinct schedule once, keeps the fastest on the context for
+ * its later solves and reports it.  Inputs as for damas_solve_dev;
+ * synchronises on `stream`. */
+int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
+                       const double *freq, const double *csm, const damas_params *p,
+                       int32_t trial_sweeps, void *stream, damas_tune_result *out);
+
+/* ---- graphs: one whole-path solve captured, replayed on any stream ------ */
+
+/* Capture the batched launches of damas_solve_dev with these arguments into
+ * a HIP graph (after one eager solve that sizes the workspace).  Every
+ * replay runs the same launches on the same buffers, so it reads the
+ * current contents of freq, csm and x_init: a new CSM in place gives a new
+ * solve.  Captured solves use one workgroup per bin (cooperative launches
+ * are not captured).  While a graph exists its context refuses solves that
+ * would grow the workspace (DAMAS_EBUSY).  The launch sequence holds no
+ * memset nodes. */
+typedef struct damas_graph damas_graph;
+int damas_graph_capture(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
+                        const double *freq, const double *csm, const damas_params *p,
+                        const void *x_init, void *x_map, double *b_map, int32_t *idx,
+                        int32_t *s_tilde, damas_graph **out);
+int damas_graph_launch(damas_graph *gr, void *stream);
+void damas_graph_destroy(damas_graph *gr);
 
 /* Device bytes a whole-path solve of this shape holds (host only, no device
  * work): inputs (mic, freq, CSM), the x map and s_tilde, and a context's

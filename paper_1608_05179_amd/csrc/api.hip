@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -182,7 +183,7 @@ extern "C" const char *damas_strerror(int code)
     case DAMAS_ENOMEM: return "out of memory";
     case DAMAS_EDEVICE: return "device error";
     case DAMAS_EADMIT: return "request exceeds the memory budget";
-    case DAMAS_EBUSY: return "queue full";
+    case DAMAS_EBUSY: return "busy (queue full or resource in use)";
     case DAMAS_ETIMEDOUT: return "timed out";
     case DAMAS_ECAPACITY: return "device-side capacity exceeded";
     default: return "unknown status";
@@ -389,6 +390,9 @@ int ensure(damas_ctx *ctx, Buffer &buf, size_t bytes, hipStream_t s, const char 
 {
     if (buf.bytes >= bytes)
         return DAMAS_OK;
+    if (ctx->graphs > 0 || ctx->in_capture)
+        return fail(DAMAS_EBUSY,
+                    "%s would grow while a graph captured on this context exists", what);
     if (buf.p) {
         // Work already enqueued may still read the old buffer.
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -732,13 +736,13 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
 // used only if its estimated makespan (ranks cost kCoopOverhead more per
 // element than a bin alone) beats one workgroup per bin by 10 %.
 // tab = [first, end) job per workgroup, then (bin, rank, ranks) per job.
-constexpr int kCoopMinRows = 320;     // rows per rank below which a helper does not pay
-constexpr double kCoopOverhead = 1.3; // cost per element of a rank vs a bin alone
-
 int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int *gpw)
 {
-    if (ctx->coop_budget == 0 || !P.batched || P.st_host.empty())
+    if (ctx->coop_budget == 0 || !ctx->tune.coop || ctx->capturing || !P.batched ||
+        P.st_host.empty())
         return 0;
+    const int kCoopMinRows = ctx->tune.min_rows;
+    const double kCoopOverhead = ctx->tune.overhead, kSplit = ctx->tune.split;
     const int nb = P.n_bins;
     int cap = gs_coop_capacity(P.bf16 ? DAMAS_PREC_BF16 : P.p->precision, P.max_kept);
     if (P.bf16 && P.refine > 0)
@@ -761,7 +765,7 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
     int multi = 0;
     for (int f = 0; f < nb; ++f) {
         const int st = P.st_host[f];
-        if (work[f] <= 1.25 * T || (st + 63) / 64 < 3)
+        if (work[f] <= kSplit * T || (st + 63) / 64 < 3)
             continue;
         int r = (int)std::ceil(work[f] / T);
         r = std::min({r, gs_max_ranks(), std::max(st / kCoopMinRows, 1)});
@@ -835,6 +839,8 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
 int upload_tab(damas_ctx *ctx, const std::vector<int32_t> &tab, hipStream_t s)
 {
     int rc;
+    if (tab == ctx->coop_tab_host && ctx->coop_tab.p)
+        return DAMAS_OK; // the device table already holds it
     if ((rc = ensure(ctx, ctx->coop_tab, sizeof(int32_t) * tab.size(), s, "coop schedule")))
         return rc;
     HIP_TRY(hipEventSynchronize(ctx->coop_done), "hipEventSynchronize");
@@ -852,6 +858,7 @@ int upload_tab(damas_ctx *ctx, const std::vector<int32_t> &tab, hipStream_t s)
                            hipMemcpyHostToDevice, s),
             "upload coop schedule");
     HIP_TRY(hipEventRecord(ctx->coop_done, s), "hipEventRecord");
+    ctx->coop_tab_host = tab;
     return DAMAS_OK;
 }
 
@@ -1032,6 +1039,9 @@ int damas::ctx_trim(damas_ctx *ctx)
 {
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (ctx->graphs > 0)
+        return fail(DAMAS_EBUSY, "a graph captured on this context still uses its workspace");
+    ctx->coop_tab_host.clear();
     for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->off, &ctx->E, &ctx->A, &ctx->E16,
                       &ctx->A32, &ctx->coop_ws, &ctx->coop_tab}) {
         if (b->p)
@@ -1222,4 +1232,206 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
     cache->lru.push_front(&ins.first->first);
     ins.first->second.lru = cache->lru.begin();
     return DAMAS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: the cooperative schedule's knobs, by timing trial solves
+
+extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
+                                  const double *freq, const double *csm, const damas_params *p,
+                                  int32_t trial_sweeps, void *stream, damas_tune_result *out)
+{
+    if (!ctx || !out || !p)
+        return fail(DAMAS_EINVAL, "ctx, params and out must be non-NULL");
+    if (trial_sweeps < 1)
+        return fail(DAMAS_EINVAL, "trial_sweeps must be >= 1");
+    int rc = check_geometry(g);
+    if (rc)
+        return rc;
+    SolvePlan P;
+    if ((rc = make_plan(g->M, g->N, n_bins, p, P)))
+        return rc;
+    if (n_bins == 0 || !freq || !csm)
+        return fail(DAMAS_EINVAL, "nothing to tune (n_bins, freq, csm)");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    // Trials: the caller's solve, batched, with trial_sweeps sweeps (for
+    // BF16, all on the storage precision), into a scratch map.
+    damas_params tp = *p;
+    tp.batched = 1;
+    tp.iterations = trial_sweeps;
+    tp.refine_sweeps = 0;
+    void *xm = nullptr;
+    const size_t xbytes = P.xs * (size_t)n_bins * P.S;
+    if (hipMalloc(&xm, std::max(xbytes, (size_t)256)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DAMAS_ENOMEM, "autotune map (%zu bytes)", xbytes);
+    }
+    const auto saved = ctx->tune;
+    const bool saved_timing = ctx->timing;
+    struct Cand {
+        bool coop;
+        int min_rows;
+        double split, overhead;
+    };
+    std::vector<Cand> cands = {{false, 320, 1.25, 1.3}, {true, 320, 1.25, 1.3}};
+    for (int mr : {256, 320, 512, 1024})
+        for (double sp : {1.0, 1.25, 2.0})
+            for (double ov : {1.1, 1.3, 1.6})
+                cands.push_back({true, mr, sp, ov});
+    // Candidates that produce the same schedule are timed once.
+    std::map<std::vector<int32_t>, double> timed;
+    double best = 1e300, dflt = 0.0;
+    size_t bi = 0;
+    int ran = 0;
+    ctx->timing = true;
+    for (size_t c = 0; c < cands.size() && rc == DAMAS_OK; ++c) {
+        ctx->tune.coop = cands[c].coop;
+        ctx->tune.min_rows = cands[c].min_rows;
+        ctx->tune.split = cands[c].split;
+        ctx->tune.overhead = cands[c].overhead;
+        std::vector<int32_t> tab;
+        int gpw = 0;
+        if (plan_coop(ctx, P, tab, &gpw) == 0)
+            tab.clear(); // one workgroup per bin
+        double ms;
+        auto it = timed.find(tab);
+        if (it != timed.end()) {
+            ms = it->second;
+        } else {
+            ms = 0.0;
+            int64_t n = 0;
+            for (int rep = 0; rep < 2 && rc == DAMAS_OK; ++rep) {
+                double t = 0.0;
+                (void)damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, &t, &n);
+                rc = damas_solve_dev(ctx, g, n_bins, freq, csm, &tp, nullptr, xm, nullptr,
+                                     nullptr, nullptr, s);
+                if (rc == DAMAS_OK)
+                    rc = damas_check(ctx, s);
+                if (rc == DAMAS_OK)
+                    rc = damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, &ms, &n);
+            }
+            if (rc)
+                break;
+            timed[tab] = ms;
+            ++ran;
+        }
+        if (c == 1)
+            dflt = ms; // the untuned knobs
+        if (ms < best) {
+            best = ms;
+            bi = c;
+        }
+    }
+    double t = 0.0;
+    int64_t n = 0;
+    (void)damas_ctx_phase_time(ctx, DAMAS_PHASE_SYSTEM, &t, &n);
+    ctx->timing = saved_timing;
+    (void)hipFree(xm);
+    if (rc) {
+        ctx->tune = saved;
+        return rc;
+    }
+    ctx->tune.coop = cands[bi].coop;
+    ctx->tune.min_rows = cands[bi].min_rows;
+    ctx->tune.split = cands[bi].split;
+    ctx->tune.overhead = cands[bi].overhead;
+    out->coop = cands[bi].coop;
+    out->coop_min_rows = cands[bi].min_rows;
+    out->coop_split = cands[bi].split;
+    out->coop_overhead = cands[bi].overhead;
+    out->best_ms_per_sweep = best / trial_sweeps;
+    out->default_ms_per_sweep = dflt / trial_sweeps;
+    out->candidates_timed = ran;
+    return DAMAS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graphs: a whole-path solve captured once, replayed on any stream
+
+struct damas_graph {
+    damas_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int damas_graph_capture(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
+                                   const double *freq, const double *csm,
+                                   const damas_params *p, const void *x_init, void *x_map,
+                                   double *b_map, int32_t *idx, int32_t *s_tilde,
+                                   damas_graph **out)
+{
+    if (!ctx || !out)
+        return fail(DAMAS_EINVAL, "ctx and out must be non-NULL");
+    if (ctx->timing)
+        return fail(DAMAS_EINVAL, "timing must be off while capturing");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+    // One eager solve sizes every buffer and uploads the keep counts; the
+    // captured launches then find the workspace ready.
+    ctx->capturing = true; // the same (one-workgroup) launches as the capture
+    int rc = damas_solve_dev(ctx, g, n_bins, freq, csm, p, x_init, x_map, b_map, idx, s_tilde,
+                             s);
+    ctx->capturing = false;
+    if (rc == DAMAS_OK)
+        rc = damas_check(ctx, s);
+    hipGraph_t graph = nullptr;
+    if (rc == DAMAS_OK) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(DAMAS_EDEVICE, "hipStreamBeginCapture");
+        } else {
+            ctx->capturing = ctx->in_capture = true;
+            rc = damas_solve_dev(ctx, g, n_bins, freq, csm, p, x_init, x_map, b_map, idx,
+                                 s_tilde, s);
+            ctx->capturing = ctx->in_capture = false;
+            const hipError_t e = hipStreamEndCapture(s, &graph);
+            if (rc == DAMAS_OK && e != hipSuccess)
+                rc = fail(DAMAS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        }
+    }
+    (void)hipStreamDestroy(s);
+    if (rc) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    damas_graph *gr = new (std::nothrow) damas_graph();
+    if (!gr) {
+        (void)hipGraphDestroy(graph);
+        return fail(DAMAS_ENOMEM, "graph allocation");
+    }
+    if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete gr;
+        return fail(DAMAS_EDEVICE, "hipGraphInstantiate");
+    }
+    gr->graph = graph;
+    gr->ctx = ctx;
+    ++ctx->graphs;
+    *out = gr;
+    return DAMAS_OK;
+}
+
+extern "C" int damas_graph_launch(damas_graph *gr, void *stream)
+{
+    if (!gr)
+        return fail(DAMAS_EINVAL, "graph is NULL");
+    HIP_TRY(hipSetDevice(gr->ctx->device), "hipSetDevice");
+    HIP_TRY(hipGraphLaunch(gr->exec, (hipStream_t)stream), "hipGraphLaunch");
+    return DAMAS_OK;
+}
+
+extern "C" void damas_graph_destroy(damas_graph *gr)
+{
+    if (!gr)
+        return;
+    (void)hipSetDevice(gr->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (gr->exec)
+        (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph)
+        (void)hipGraphDestroy(gr->graph);
+    --gr->ctx->graphs;
+    delete gr;
 }

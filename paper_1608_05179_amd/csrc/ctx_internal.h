@@ -67,6 +67,19 @@ struct damas_ctx {
     // never), exchange workspace, schedule table and its pinned staging
     int coop_budget = -1;
     int last_workgroups = 0; // of the last sweep launch (one per bin alone)
+    // schedule knobs of the cooperative sweeps (set by damas_ctx_autotune)
+    struct {
+        bool coop = true;
+        int min_rows = 320;    // rows per rank at least
+        double split = 1.25;   // bins above split x the mean work per workgroup get ranks
+        double overhead = 1.3; // cost per element of a rank relative to a bin alone
+    } tune;
+    // graph capture: `capturing` turns cooperation off (cooperative launches
+    // are not captured), for the sizing solve too; `in_capture` refuses
+    // workspace growth inside the captured solve
+    bool capturing = false, in_capture = false;
+    int graphs = 0;
+    std::vector<int32_t> coop_tab_host; // last uploaded schedule
     damas::Buffer coop_ws, coop_tab;
     int32_t *coop_pinned = nullptr;
     size_t coop_pinned_n = 0;

@@ -101,6 +101,20 @@ _sig("damas_query_footprint", ctypes.c_int, c_i32, c_i32, c_i32, ctypes.POINTER(
      ctypes.POINTER(ctypes.c_uint64))
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("coop", c_i32), ("coop_min_rows", c_i32), ("coop_split", c_dbl),
+                ("coop_overhead", c_dbl), ("best_ms_per_sweep", c_dbl),
+                ("default_ms_per_sweep", c_dbl), ("candidates_timed", c_i32)]
+
+
+_sig("damas_ctx_autotune", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
+     c_i32, c_vp, ctypes.POINTER(TuneResult))
+_sig("damas_graph_capture", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
+     c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_vp))
+_sig("damas_graph_launch", ctypes.c_int, c_vp, c_vp)
+_sig("damas_graph_destroy", None, c_vp)
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("device", c_i32), ("hbm_budget", ctypes.c_uint64),
                 ("cache_budget", ctypes.c_uint64), ("slots", c_i32), ("max_queue", c_i32)]
@@ -384,6 +398,71 @@ class Context:
 
     def check(self, stream=None):
         check(self, stream)
+
+    def autotune(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
+                 keep_count=None, precision=PREC_FP32, max_kept=0, trial_sweeps=30,
+                 stream=None) -> dict:
+        """Tune the cooperative sweep schedule on this problem (trial solves
+        of trial_sweeps sweeps); the choice stays on the context."""
+        csm = _as_interleaved(csm)
+        nb = freq.numel()
+        p, _kc = _params(nb, select_mode, eps, keep_count, trial_sweeps, precision, True,
+                         max_kept, 0)
+        r = TuneResult()
+        _check(_lib.damas_ctx_autotune(self._h, ctypes.byref(g), nb,
+                                       _ptr(freq, torch.float64, "freq"),
+                                       _ptr(csm, torch.float64, "csm"), ctypes.byref(p),
+                                       int(trial_sweeps), _stream(stream), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in TuneResult._fields_}
+
+    def capture(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
+                keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
+                refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
+                s_tilde=None):
+        """Capture this batched solve into a Graph (csm must be float64
+        interleaved (n_bins, M, M, 2) so that in-place updates reach the
+        graph)."""
+        if csm.dtype != torch.float64:
+            raise ValueError("capture needs csm as float64 (n_bins, M, M, 2)")
+        nb = freq.numel()
+        if x_map is None:
+            x_map = torch.empty(nb, g.N * g.N, dtype=_XTYPE[precision], device=freq.device)
+        p, kc = _params(nb, select_mode, eps, keep_count, iterations, precision, True,
+                        max_kept, refine_sweeps)
+        dt = _XTYPE[precision]
+        h = c_vp()
+        _check(_lib.damas_graph_capture(self._h, ctypes.byref(g), nb,
+                                        _ptr(freq, torch.float64, "freq"),
+                                        _ptr(csm, torch.float64, "csm"), ctypes.byref(p),
+                                        _ptr(x_init, dt, "x_init"), _ptr(x_map, dt, "x_map"),
+                                        _ptr(b_map, torch.float64, "b_map"),
+                                        _ptr(idx, torch.int32, "idx"),
+                                        _ptr(s_tilde, torch.int32, "s_tilde"), ctypes.byref(h)))
+        return Graph(h, self, x_map)
+
+
+class Graph:
+    """A captured whole-path solve (damas_graph); launch() replays it."""
+
+    def __init__(self, h, ctx, x_map):
+        self._h = h
+        self._ctx = ctx  # the context must outlive the graph
+        self.x_map = x_map
+
+    def launch(self, stream=None):
+        _check(_lib.damas_graph_launch(self._h, _stream(stream)))
+        return self.x_map
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.damas_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, max_kept,

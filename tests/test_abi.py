@@ -98,6 +98,12 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert dm._lib.damas_psf_bf16(16, 2, fake, 100, fake, 10, fake, fake, None) == dm.EINVAL
     assert dm._lib.damas_psf(16, 1, fake, 10, dm.PREC_BF16, fake, 1000, fake, fake, None) == dm.EINVAL
     assert b"damas_psf_bf16" in lib.damas_last_error()
+    # autotuner and graphs: NULL handles are refused on the host
+    assert dm._lib.damas_ctx_autotune(None, gb, 1, fake, fake, None, 10, None, None) == dm.EINVAL
+    assert dm._lib.damas_graph_launch(None, None) == dm.EINVAL
+    assert dm._lib.damas_graph_capture(None, gb, 1, fake, fake, None, None, fake, None, None,
+                                       None, None) == dm.EINVAL
+    assert dm._lib.damas_ctx_set_coop(None, -1) == dm.EINVAL
     # whole-path: NULL context / NULL params
     assert dm._lib.damas_solve_dev(None, ctypes.byref(G(16, 0x1000, 21, -1, 1, -1, 1, 1, 343.0)),
                                    1, fake, fake, None, None, fake, None, None, None,

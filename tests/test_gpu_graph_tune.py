@@ -1,0 +1,89 @@
+"""Graph capture and the schedule autotuner.
+
+A captured solve replays bitwise like the eager solve it captured (one
+workgroup per bin), on every replay, with eager work and synchronisations
+in between; a CSM changed in place gives the eager solve of the new CSM.
+The autotuner's choice stays on the context and its solves still match the
+oracle."""
+import numpy as np
+import pytest
+
+from paper_1608_05179_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dtype)
+
+
+def _setup(dm, dev, w):
+    import torch
+    mic = _t(w.mic, torch.float64, dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    freq = _t(w.freqs, torch.float64, dev)
+    csm = torch.view_as_real(torch.tensor(w.csm, dtype=torch.complex128)).contiguous().to(dev)
+    return mic, g, freq, csm
+
+
+def test_graph_replays_match_eager(dm, dev):
+    import torch
+    w = synth.compressed_fp32(n_bins=6, N=41, iterations=150)
+    mic, g, freq, csm = _setup(dm, dev, w)
+    eager_ctx = dm.Context(0)
+    eager_ctx.set_coop(0)
+    ref = eager_ctx.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT,
+                          keep_count=w.keep_count, iterations=w.iterations).clone()
+    ctx = dm.Context(0)
+    graph = ctx.capture(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=w.keep_count,
+                        iterations=w.iterations)
+    for _ in range(4):
+        graph.x_map.fill_(-1.0)
+        out = graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        # eager work between replays
+        eager_ctx.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=w.keep_count,
+                        iterations=20)
+        torch.cuda.synchronize()
+    # a new CSM in place: the replay is the eager solve of the new CSM
+    w2 = synth.compressed_fp32(n_bins=6, N=41, iterations=150)
+    w2.csm = w2.csm[::-1].copy()
+    csm.copy_(torch.view_as_real(torch.tensor(w2.csm, dtype=torch.complex128)))
+    ref2 = eager_ctx.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT,
+                           keep_count=w.keep_count, iterations=w.iterations).clone()
+    out = graph.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref2) and not torch.equal(ref, ref2)
+    # the workspace is pinned while the graph exists
+    with pytest.raises(dm.DamasError) as ei:
+        big = synth.compressed_fp32(n_bins=6, N=61, iterations=5)
+        m2, g2, f2, c2 = _setup(dm, dev, big)
+        ctx.solve(g2, f2, c2, select_mode=dm.SEL_KEEP_COUNT, keep_count=2000, iterations=5)
+    assert ei.value.code == dm.EBUSY
+    graph.close()
+    ctx.close()
+    eager_ctx.close()
+
+
+def test_autotune_keeps_a_valid_choice(orc, dm, dev):
+    w = synth.compressed_fp32(n_bins=4, N=61, iterations=120)
+    Ks = [2400, 700, 3600, 150]
+    mic, g, freq, csm = _setup(dm, dev, w)
+    ctx = dm.Context(0)
+    r = ctx.autotune(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=Ks,
+                     trial_sweeps=10)
+    assert r["candidates_timed"] >= 2
+    assert 0 < r["best_ms_per_sweep"] <= r["default_ms_per_sweep"]
+    x = ctx.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=Ks,
+                  iterations=w.iterations)
+    ctx.check()
+    x = x.double().cpu().numpy()
+    og = orc.Geometry(w.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    for f in (0, 2):
+        ref = orc.solve_bin(og, w.freqs[f], w.csm[f], orc.SEL_KEEP_COUNT, keep_count=Ks[f],
+                            iters=w.iterations)
+        err = np.linalg.norm(x[f] - ref["x"]) / np.linalg.norm(ref["x"])
+        assert err <= 1e-4, (f, err)
+    ctx.close()
