@@ -40,7 +40,7 @@
 namespace damas {
 
 constexpr int kGsTile = 64;
-constexpr int kGsMaxStreamWaves = 7;    // stream waves per workgroup, at most
+constexpr int kGsMaxStreamWaves = 15;   // stream waves per workgroup, at most
 constexpr int kGsCtPitch = kGsTile + 1; // rows of the coupling block
 constexpr int kGsBatch = 8;             // tail loads per batch (two batches in flight)
 constexpr int kGsPre = 8;               // serial wave: LDS reads issued this many steps ahead
@@ -85,6 +85,14 @@ template <> struct Vec16<bf16s> {
 __device__ inline double widen(double v) { return v; }
 __device__ inline double widen(float v) { return (double)v; }
 __device__ inline double widen(bf16s v) { return (double)bf16_to_float(v); }
+// A value of A's storage type in the hand-over blocks' type.
+template <typename TB, typename TA> __device__ inline TB to_block(TA v);
+template <> __device__ inline double to_block<double, double>(double v) { return v; }
+template <> __device__ inline double to_block<double, float>(float v) { return (double)v; }
+template <> __device__ inline double to_block<double, bf16s>(bf16s v) { return widen(v); }
+template <> __device__ inline float to_block<float, float>(float v) { return v; }
+template <> __device__ inline bf16s to_block<bf16s, bf16s>(bf16s v) { return v; }
+
 template <typename TA> __device__ inline TA zero_of();
 template <> __device__ inline double zero_of<double>() { return 0.0; }
 template <> __device__ inline float zero_of<float>() { return 0.0f; }
@@ -191,14 +199,28 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         }
     }
 
-    // LDS address of x for the rows of group g: the snapshot inside the
-    // tile being updated, the live values elsewhere (clamped to the rows on
-    // chip; rows past S~ carry zero A).
-    __device__ __forceinline__ const double *xrow(int g, const double *xs, const double *xold,
-                                                  int X0) const
+    // LDS address of x for the rows of group g (clamped to the rows on
+    // chip; rows past S~ carry zero A).  While the serial wave updates a
+    // tile, x~ still holds that tile's old values: new values reach x~ only
+    // through commit(), one period later.
+    __device__ __forceinline__ const double *xrow(int g, const double *xs) const
     {
-        const int jb = g * CPL; // wave-uniform
-        return jb >= X0 && jb < X0 + kGsTile ? xold + (jb - X0) : xs + min(jb, xcap);
+        return xs + min(g * CPL, xcap); // wave-uniform
+    }
+
+    // Copy the rows of tile P0 that this wave reads (its groups
+    // g = sw mod NW, the same set in every workgroup of a bin) from the
+    // serial wave's staging xnew[0..64) into x~.  Every wave copies its own
+    // rows before it reads them, so the copy needs no barrier; rows read by
+    // no wave of this workgroup (a cooperating helper's) are copied by the
+    // wave whose residue class holds them, for the serial wave.
+    __device__ __forceinline__ void commit(const double *xnew, double *xs, int P0) const
+    {
+        const int ga = P0 / CPL; // first group of the tile
+        const int g = ga + ((sw - ga) % NW + NW) % NW + NW * (lane / CPL);
+        const int row = g * CPL + lane % CPL;
+        if (g < ga + GT && row < St)
+            xs[row] = xnew[row - P0];
     }
 
     // acc += the groups in v[0..n) (groups g0, g0 + nwt, ...), in chunks of
@@ -206,7 +228,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     // keeps the scheduler from widening every group of a long head at once.
     template <int n>
     __device__ __forceinline__ void sum(const VT (&v)[n], int g0, double (&acc)[CPL],
-                                        const double *xs, const double *xold, int X0) const
+                                        const double *xs) const
     {
         constexpr int C = 8;
 #pragma unroll
@@ -214,7 +236,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
             double xj[C];
 #pragma unroll
             for (int k = k0; k < k0 + C && k < n; ++k)
-                xj[k - k0] = xrow(g0 + nwt * k, xs, xold, X0)[jp];
+                xj[k - k0] = xrow(g0 + nwt * k, xs)[jp];
 #pragma unroll
             for (int k = k0; k < k0 + C && k < n; ++k)
 #pragma unroll
@@ -224,9 +246,12 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         }
     }
 
-    // Blocks of tile T for the serial wave, from hu / hc (zero outside S~).
+    // Blocks of tile T for the serial wave, from hu / hc (zero outside S~),
+    // in the blocks' element type TB (A's type, or double so that the
+    // serial wave reads them without conversions).
+    template <typename TB>
     __device__ __forceinline__ void handover(int T0, int TN0, const bool (&colok)[CPL],
-                                             TileBlocks<TA> *blk) const
+                                             TileBlocks<TB> *blk) const
     {
 #pragma unroll
         for (int m = 0; m < NU; ++m) {
@@ -241,20 +266,28 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
                 const TA v = VA::raw(hu[m], s);
                 u[s] = rowu && colok[s] && c > i ? v : zero_of<TA>();
                 if (c == i)
-                    blk->dg[i] = v;
-                blk->Ct[i * kGsCtPitch + c] = rowc && colok[s] ? VA::raw(hc[m], s) : zero_of<TA>();
+                    blk->dg[i] = to_block<TB>(v);
+                blk->Ct[i * kGsCtPitch + c] =
+                    rowc && colok[s] ? to_block<TB>(VA::raw(hc[m], s)) : zero_of<TB>();
             }
-            *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
+            if constexpr (sizeof(TB) == sizeof(TA)) {
+                *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
+            } else {
+#pragma unroll
+                for (int s = 0; s < CPL; ++s)
+                    blk->U[i * kGsTile + cl + s] = to_block<TB>(u[s]);
+            }
         }
     }
 
-    // The period that sums strip T while tile X0 (-2 tiles: none) is being
-    // updated and, with `hand`, hands over the blocks of T and of the tile
-    // TN after it; when `next`, it also issues the head of strip NT0 (with
-    // hand-over tile NTN0) for the following period.
-    __device__ __forceinline__ void period(const double *xs, const double *xold, int T0, int X0,
-                                           int TN0, bool next, int NT0, int NTN0, double *part,
-                                           TileBlocks<TA> *blk, bool hand = true)
+    // The period that sums strip T and, with `hand`, hands over the blocks
+    // of T and of the tile TN after it; it also issues the head of strip
+    // NT0 (with hand-over tile NTN0) for the following period (after the
+    // last period those loads go unused: issuing them unconditionally keeps
+    // the head in the same registers from one period to the next).
+    template <typename TB>
+    __device__ __forceinline__ void period(const double *xs, int T0, int TN0, int NT0, int NTN0,
+                                           double *part, TileBlocks<TB> *blk, bool hand = true)
     {
         double acc[CPL];
         bool colok[CPL];
@@ -271,12 +304,11 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         asm volatile("" : "+v"(gstride), "+v"(xcap));
         gstride = (uint32_t)__builtin_amdgcn_readfirstlane((int)gstride);
         xcap = __builtin_amdgcn_readfirstlane(xcap);
-        sum(head, gsw, acc, xs, xold, X0);
+        sum(head, gsw, acc, xs);
         if (hand)
             handover(T0, TN0, colok, blk);
         __builtin_amdgcn_sched_barrier(0);
-        if (next)
-            prefetch(NT0, NTN0, hand);
+        prefetch(NT0, NTN0, hand);
         __builtin_amdgcn_sched_barrier(0);
 
         // Tail: groups NH .. nk-1 in batches of NB, two batches in flight.
@@ -295,11 +327,11 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
             for (int k0 = NH; k0 < nk; k0 += 2 * NB) {
                 fill(b1, k0 + NB);
                 __builtin_amdgcn_sched_barrier(0);
-                sum(b0, gsw + nwt * k0, acc, xs, xold, X0);
+                sum(b0, gsw + nwt * k0, acc, xs);
                 __builtin_amdgcn_sched_barrier(0);
                 fill(b0, k0 + 2 * NB);
                 __builtin_amdgcn_sched_barrier(0);
-                sum(b1, gsw + nwt * (k0 + NB), acc, xs, xold, X0);
+                sum(b1, gsw + nwt * (k0 + NB), acc, xs);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -405,8 +437,8 @@ struct OwnerLink {
 };
 
 template <typename TA, int NW, bool UNIT>
-__device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xold,
-                                            const TileBlocks<TA> *blks,
+__device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xnew,
+                                            const TileBlocks<TA> *blks, // TA: blocks' type
                                             const int32_t *__restrict__ id,
                                             const double *__restrict__ bf, int St, int ntile,
                                             long long total, int lane,
@@ -420,7 +452,8 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
     double bt = lane < St ? bf[id[lane]] : 0.0;               // tile t
     double bq1 = t1 * kGsTile + lane < St ? bf[id[t1 * kGsTile + lane]] : 0.0; // tile t+1
     int iq2 = t2 * kGsTile + lane < St ? id[t2 * kGsTile + lane] : 0;         // tile t+2
-    double rn = 0.0; // change of the next tile's residuals from this tile
+    double rn = 0.0;    // change of the next tile's residuals from this tile
+    double xkeep = 0.0; // the tile's new values (read back when it is the only tile)
     for (long long q = 0; q < total; ++q) {
         const int t0 = t * kGsTile;
         const int tn = nxt(t);
@@ -445,7 +478,10 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         double il = 1.0;
         if (!UNIT)
             il = mine ? 1.0 / widen(bk.dg[lane]) : 0.0;
-        const double xl = mine ? xs[t0 + lane] : 0.0;
+        // x~ holds the tile's latest values once the stream waves have
+        // committed them, a period after they were formed; with a single
+        // tile that is the period running now, so they come from registers.
+        const double xl = !mine ? 0.0 : (ntile == 1 && q > 0) ? xkeep : xs[t0 + lane];
         double rho = mine ? (UNIT ? r : r * il) : 0.0;
         // Software pipeline: the block entries of step i + kGsPre are read
         // from LDS during step i (raw storage type), and those of step i + 1
@@ -489,17 +525,16 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
             }
         }
         rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
-        if (mine)
-            xs[t0 + lane] = xl - fmin(rho, xl);
+        // New values to the staging slot of this period (0 on lanes past
+        // the tile); the stream waves copy them into x~ next period.
+        xkeep = xl - fmin(rho, xl);
+        xnew[(q & 1) * kGsTile + lane] = xkeep;
         if (co.ranks > 1) {
             // Publish the tile's new values for the helpers.
             if (mine)
-                coop_st(co.xpub + t0 + lane, xl - fmin(rho, xl));
+                coop_st(co.xpub + t0 + lane, xkeep);
             coop_flag(co.flags, (uint32_t)(q + 1));
         }
-        // Snapshot of the next tile's values for the stream waves, which
-        // read it while this wave overwrites that tile.
-        xold[((q + 1) & 1) * kGsTile + lane] = tn0 + lane < St ? xs[tn0 + lane] : 0.0;
         // b~ two tiles ahead: value of tile t+2 (its grid index arrived a
         // period ago), grid index of tile t+3 (tn = t+1).
         const int ta = nxt(tn), tb = nxt(ta);
@@ -509,29 +544,97 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         t = tn;
         __syncthreads();
     }
+    // The last tile's values: every stream wave is past its last read.
+    if (total > 0) {
+        const int tl0 = (int)((total - 1) % ntile) * kGsTile;
+        if (tl0 + lane < St)
+            xs[tl0 + lane] = xkeep;
+    }
 }
 
-template <typename TA> constexpr size_t gs_lds_fixed()
+// One bin's sweeps on a workgroup of WAVES waves: wave 0 runs the rows
+// (serial_role), NW stream waves sum the strips of their row groups (groups
+// sw + nwt k; nwt > NW when helper workgroups sum the others) and hand over
+// the blocks.  With WAVES > 1 + NW the waves w = 4, 8, .. only pass the
+// barriers: waves are placed on the CU's four SIMDs in turn, so those are
+// the ones that would share wave 0's SIMD and slow the step chain.
+// Barriers: one before the first period, one per period, one at the end,
+// the same count on every wave.  LDS: x~ [ld_cap], the partial sums
+// `parts` [2][NW][64], the staging `xnew` [2][64], the blocks [2].
+template <int NW, int WAVES> constexpr bool gs_spare_waves()
 {
-    return sizeof(double) * (2 * kGsMaxStreamWaves * kGsTile + 2 * kGsTile) +
-           2 * sizeof(TileBlocks<TA>);
+    static_assert(WAVES == 1 + NW || (WAVES % 4 == 0 && NW == WAVES - WAVES / 4),
+                  "either every wave but the first streams, or all but w = 0 mod 4");
+    static_assert(NW <= kGsMaxStreamWaves, "at most kGsMaxStreamWaves stream waves");
+    return WAVES > 1 + NW;
 }
 
-template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
-__global__ __launch_bounds__(64 * (1 + NW)) void gs_kernel(
+template <typename TA, typename TB, int NW, int WAVES, int NH, int NB, bool UNIT>
+__device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xnew,
+                                          TileBlocks<TB> *blks, const TA *A, int64_t ld, int St,
+                                          const int32_t *__restrict__ id,
+                                          const double *__restrict__ bf, long long total,
+                                          int ntile, int w, int lane, int nwt,
+                                          OwnerLink co = OwnerLink{nullptr, nullptr, nullptr, 1,
+                                                                   nullptr})
+{
+    auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
+    constexpr bool spare = gs_spare_waves<NW, WAVES>();
+    if (w == 0) {
+        __syncthreads();
+        serial_role<TB, NW, UNIT>(xs, parts, xnew, blks, id, bf, St, ntile, total, lane, co);
+    } else if (spare && (w & 3) == 0) {
+        for (long long q = 0; q <= total; ++q)
+            __syncthreads();
+    } else {
+        // Period -1 (prologue): strip 0 and its blocks.  Period q (serial
+        // wave on tile t): copy the previous tile's new values into x~,
+        // then sum strip t+1 and hand over its blocks.  The last period
+        // only copies.
+        const int si = spare ? w - 1 - (w - 1) / 4 : w - 1; // stream wave index
+        StreamWave<TA, NW, NH, NB> sw;
+        sw.init(A, ld, St, si, lane, si, nwt);
+        const int t1 = nxt(0), t2 = nxt(t1);
+        sw.prefetch(0, t1 * kGsTile);
+        sw.period(xs, 0, t1 * kGsTile, t1 * kGsTile, t2 * kGsTile, parts, &blks[0]);
+        __syncthreads();
+        int tp = 0, t = 0;
+        for (long long q = 0; q + 1 < total; ++q) {
+            const int tn = nxt(t), tnn = nxt(tn), tn3 = nxt(tnn);
+            if (q > 0)
+                sw.commit(xnew + ((q - 1) & 1) * kGsTile, xs, tp * kGsTile);
+            sw.period(xs, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, tn3 * kGsTile,
+                      parts + ((q + 1) & 1) * NW * kGsTile, &blks[(q + 1) & 1]);
+            __syncthreads();
+            tp = t;
+            t = tn;
+        }
+        if (total > 1)
+            sw.commit(xnew + ((total - 2) & 1) * kGsTile, xs, tp * kGsTile);
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
+template <typename TB, int NW> constexpr size_t gs_lds_fixed()
+{
+    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TB>);
+}
+
+template <typename TA, typename TB, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
+__global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     int N, const int32_t *__restrict__ s_tilde, int max_kept,
     const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
     const TA *__restrict__ A_all, const double *__restrict__ b, int iters,
     const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault)
 {
-    // LDS: x~ [ld_cap] | partial sums [2][NW][64] (room for the widest
-    //      shape) | snapshots [2][64] |
+    // LDS: x~ [ld_cap] | partial sums [2][NW][64] | staging [2][64] |
     //      tile blocks [2]
     extern __shared__ double xs[];
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
-    double *xold = parts + 2 * kGsMaxStreamWaves * kGsTile;
-    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xold + 2 * kGsTile);
+    double *xnew = parts + 2 * NW * kGsTile;
+    TileBlocks<TB> *blks = reinterpret_cast<TileBlocks<TB> *>(xnew + 2 * kGsTile);
 
     const int f = blockIdx.x;
     const int S = N * N;
@@ -549,49 +652,21 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_kernel(
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    constexpr int nthr = 64 * (1 + NW);
+    constexpr int nthr = 64 * WAVES;
     for (int64_t i = tid; i < ld; i += nthr)
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     {
-        TA *z = reinterpret_cast<TA *>(blks);
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / sizeof(TA)); i += nthr)
-            z[i] = zero_of<TA>();
+        TB *z = reinterpret_cast<TB *>(blks);
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TB>) / sizeof(TB)); i += nthr)
+            z[i] = zero_of<TB>();
     }
     __syncthreads();
 
     const int ntile = (St + kGsTile - 1) / kGsTile;
     const long long total = (long long)iters * ntile;
-    if (total > 0) {
-        // The two roles run separate loops (w is wave-uniform) so that each
-        // allocates only its own registers; both pass exactly one barrier
-        // per period.  Period -1 (prologue): the stream waves sum strip 0
-        // and hand over its blocks; wave 0 takes the snapshot of tile 0.
-        auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
-        if (w == 0) {
-            xold[lane] = lane < St ? xs[lane] : 0.0;
-            __syncthreads();
-            serial_role<TA, NW, UNIT>(xs, parts, xold, blks, id, bf, St, ntile, total, lane);
-        } else {
-            StreamWave<TA, NW, NH, NB> sw;
-            sw.init(A, ld, St, w - 1, lane, w - 1, NW);
-            const int t1 = nxt(0), t2 = nxt(t1);
-            sw.prefetch(0, t1 * kGsTile);
-            sw.period(xs, xold, 0, -2 * kGsTile, t1 * kGsTile, total > 1, t1 * kGsTile,
-                      t2 * kGsTile, parts, &blks[0]);
-            __syncthreads();
-            int t = 0;
-            for (long long q = 0; q < total; ++q) {
-                const int tn = nxt(t), tnn = nxt(tn), tn3 = nxt(tnn);
-                if (q + 1 < total)
-                    sw.period(xs, xold + (q & 1) * kGsTile, tn * kGsTile, t * kGsTile,
-                              tnn * kGsTile, q + 2 < total, tnn * kGsTile, tn3 * kGsTile,
-                              parts + ((q + 1) & 1) * NW * kGsTile,
-                              &blks[(q + 1) & 1]);
-                t = tn;
-                __syncthreads();
-            }
-        }
-    }
+    if (total > 0)
+        sweep_bin<TA, TB, NW, WAVES, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
+                                            ntile, w, lane, NW);
 
     // Scatter: x_map[n] = x~_i at n = idx[i], 0 in the gaps between kept
     // points, so every grid point is written exactly once.
@@ -642,8 +717,8 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
 {
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
-    double *xold = parts + 2 * kGsMaxStreamWaves * kGsTile;
-    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xold + 2 * kGsTile);
+    double *xnew = parts + 2 * NW * kGsTile;
+    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xnew + 2 * kGsTile);
 
     const int S = N * N;
     int St = s_tilde[f];
@@ -710,8 +785,8 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
             for (long long p = -1; p + 1 < total; ++p) {
                 const int tn = nxt(tc), tnn = nxt(tn);
                 __syncthreads();
-                sw.period(xs, xs, tn * kGsTile, -2 * kGsTile, tn * kGsTile, p + 2 < total,
-                          tnn * kGsTile, tnn * kGsTile, parts, nullptr, false);
+                sw.period(xs, tn * kGsTile, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, parts,
+                          (TileBlocks<TA> *)nullptr, false);
                 __syncthreads();
                 tc = tn;
             }
@@ -720,32 +795,10 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
     }
 
     // Owner.
-    if (total > 0) {
-        if (w == 0) {
-            xold[lane] = lane < St ? xs[lane] : 0.0;
-            __syncthreads();
-            serial_role<TA, NW, UNIT>(xs, parts, xold, blks, id, bf, St, ntile, total, lane,
-                                      OwnerLink{flags, part, xpub, ranks, fault});
-        } else {
-            StreamWave<TA, NW, NH, NB> sw;
-            sw.init(A, ld, St, w - 1, lane, w - 1, ranks * NW);
-            const int t1 = nxt(0), t2 = nxt(t1);
-            sw.prefetch(0, t1 * kGsTile);
-            sw.period(xs, xold, 0, -2 * kGsTile, t1 * kGsTile, total > 1, t1 * kGsTile,
-                      t2 * kGsTile, parts, &blks[0]);
-            __syncthreads();
-            int t = 0;
-            for (long long q = 0; q < total; ++q) {
-                const int tn = nxt(t), tnn = nxt(tn), tn3 = nxt(tnn);
-                if (q + 1 < total)
-                    sw.period(xs, xold + (q & 1) * kGsTile, tn * kGsTile, t * kGsTile,
-                              tnn * kGsTile, q + 2 < total, tnn * kGsTile, tn3 * kGsTile,
-                              parts + ((q + 1) & 1) * NW * kGsTile, &blks[(q + 1) & 1]);
-                t = tn;
-                __syncthreads();
-            }
-        }
-    }
+    if (total > 0)
+        sweep_bin<TA, TA, NW, 1 + NW, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
+                                            ntile, w, lane, ranks * NW,
+                                            OwnerLink{flags, part, xpub, ranks, fault});
 
     TX *xo = x_map + (int64_t)f * S;
     if (St == 0) {
@@ -788,57 +841,88 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
     }
 }
 
-template <typename TA> static size_t gs_lds_bytes_t(int max_kept)
+// Launch shapes.  Plain kernel: WAVES waves per workgroup of which NW
+// stream; cooperative kernel: 1 + CNW waves.  Head groups NH and tail
+// batch NB: short strips keep a whole strip in the head; long strips keep
+// a short head and a deep tail.
+template <typename TA> struct GsShapes;
+template <> struct GsShapes<float> {
+    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 4, long_nh = 6, long_nb = 8;
+    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 4, c_long_nh = 6, c_long_nb = 8;
+};
+template <> struct GsShapes<double> {
+    // 8 waves: LDS for the partial sums of more stream waves would cut the
+    // unknowns a workgroup holds beside its double blocks.
+    static constexpr int waves = 8, nw = 7, short_nh = 12, short_nb = 4, long_nh = 6, long_nb = 6;
+    static constexpr int cnw = 7, c_short_nh = 12, c_short_nb = 4, c_long_nh = 6, c_long_nb = 6;
+};
+template <> struct GsShapes<bf16s> {
+    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 4, long_nh = 6, long_nb = 8;
+    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 4, c_long_nh = 6, c_long_nb = 8;
+};
+
+// Dynamic LDS of a launch: blocks of type TB, NW stream waves.
+template <typename TB, int NW> static size_t gs_lds_bytes_t(int max_kept)
 {
-    return gs_lds_fixed<TA>() + sizeof(double) * (size_t)ld_of(max_kept);
+    return gs_lds_fixed<TB, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
 }
 
-static size_t gs_lds_bytes(int precision, int max_kept)
+// LDS the sweep kernels may use (the 160 KB of a CU, less a margin).
+constexpr size_t kGsLdsLimit = 160 * 1024 - 512;
+
+// Of the cooperative kernel (blocks in A's storage type).
+static size_t gs_coop_lds_bytes(int precision, int max_kept)
 {
     switch (precision) {
-    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double>(max_kept);
-    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float>(max_kept);
-    default: return gs_lds_bytes_t<bf16s>(max_kept);
+    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, GsShapes<double>::cnw>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::cnw>(max_kept);
+    default: return gs_lds_bytes_t<bf16s, GsShapes<bf16s>::cnw>(max_kept);
+    }
+}
+
+// Of the plain kernel with blocks in A's storage type (its largest need).
+static size_t gs_plain_lds_bytes(int precision, int max_kept)
+{
+    switch (precision) {
+    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, GsShapes<double>::nw>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::nw>(max_kept);
+    default: return gs_lds_bytes_t<bf16s, GsShapes<bf16s>::nw>(max_kept);
     }
 }
 
 int gs_max_kept(int precision)
 {
-    // Everything in the 160 KB of LDS of one CU, less a margin.
-    const size_t lds = 160 * 1024 - 512;
-    const size_t fixed = gs_lds_bytes(precision, 0);
-    return (int)(((lds - fixed) / sizeof(double)) & ~(size_t)7);
+    // Everything in the 160 KB of LDS of one CU, less a margin, for both
+    // kernels.
+    const size_t fixed = std::max(gs_plain_lds_bytes(precision, 0), gs_coop_lds_bytes(precision, 0));
+    return (int)(((kGsLdsLimit - fixed) / sizeof(double)) & ~(size_t)7);
 }
 
-// Launch shapes (stream waves NW, head groups NH, tail batch NB): short
-// strips keep a whole strip in the head; long strips keep a short head and
-// a deep tail.
-template <typename TA> struct GsShapes;
-template <> struct GsShapes<float> {
-    static constexpr int nw = 7, short_nh = 14, short_nb = 4, long_nh = 6, long_nb = 8;
-};
-template <> struct GsShapes<double> {
-    static constexpr int nw = 7, short_nh = 12, short_nb = 4, long_nh = 6, long_nb = 6;
-};
-template <> struct GsShapes<bf16s> {
-    static constexpr int nw = 7, short_nh = 14, short_nb = 4, long_nh = 6, long_nb = 8;
-};
-
-template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
+// Hand-over blocks in double when they fit beside x~ and `wide` allows
+// (the serial wave then reads them without conversions), else in A's type.
+template <typename TA, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
 static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                               const int32_t *idx, const int64_t *off, const void *A,
                               const double *b, int iterations, const void *x_init,
-                              void *x_map, int *fault, hipStream_t s)
+                              void *x_map, int *fault, bool wide, hipStream_t s)
 {
-    static_assert(NW <= kGsMaxStreamWaves, "LDS holds the partial sums of at most kGsMaxStreamWaves waves");
-    static const hipError_t attr =
-        allow_big_lds((const void *)gs_kernel<TA, TX, UNIT, NW, NH, NB>);
-    if (attr != hipSuccess)
-        return attr;
-    hipLaunchKernelGGL((gs_kernel<TA, TX, UNIT, NW, NH, NB>), dim3(n_bins), dim3(64 * (1 + NW)),
-                       gs_lds_bytes_t<TA>(max_kept), s, N, s_tilde, max_kept, idx, off,
-                       (const TA *)A, b, iterations, (const TX *)x_init, (TX *)x_map, fault);
-    return hipGetLastError();
+    wide = wide && gs_lds_bytes_t<double, NW>(max_kept) <= kGsLdsLimit;
+#define DAMAS_GS_TB(TB)                                                                         \
+    {                                                                                          \
+        static const hipError_t attr =                                                         \
+            allow_big_lds((const void *)gs_kernel<TA, TB, TX, UNIT, NW, WAVES, NH, NB>);      \
+        if (attr != hipSuccess)                                                                \
+            return attr;                                                                       \
+        hipLaunchKernelGGL((gs_kernel<TA, TB, TX, UNIT, NW, WAVES, NH, NB>), dim3(n_bins),    \
+                           dim3(64 * WAVES), (gs_lds_bytes_t<TB, NW>(max_kept)), s, N, s_tilde, \
+                           max_kept, idx, off, (const TA *)A, b, iterations,                  \
+                           (const TX *)x_init, (TX *)x_map, fault);                           \
+        return hipGetLastError();                                                              \
+    }
+    if (wide)
+        DAMAS_GS_TB(double)
+    DAMAS_GS_TB(TA)
+#undef DAMAS_GS_TB
 }
 
 template <typename TA, typename TX>
@@ -851,9 +935,14 @@ static hipError_t launch_gs_u(int N, int n_bins, const int32_t *s_tilde, int max
     // A strip fits the short shape's head when every wave's groups do.
     const bool shrt =
         ld_of(max_kept) <= (int64_t)SH::short_nh * SH::nw * Vec16<TA>::n;
+    // Double blocks: the serial wave's steps lose their conversions, the
+    // stream waves write twice the bytes; measured a loss while the
+    // stream waves set the period, so off.
+    const bool wide = false;
 #define DAMAS_GS_LAUNCH(U, NH, NB)                                                               \
-    launch_gs_t<TA, TX, U, SH::nw, NH, NB>(N, n_bins, s_tilde, max_kept, idx, off, A, b,       \
-                                           iterations, x_init, x_map, fault, s)
+    launch_gs_t<TA, TX, U, SH::nw, SH::waves, NH, NB>(N, n_bins, s_tilde, max_kept, idx, off,  \
+                                                      A, b, iterations, x_init, x_map, fault,  \
+                                                      wide, s)
     if (unit_diagonal)
         return shrt ? DAMAS_GS_LAUNCH(true, SH::short_nh, SH::short_nb)
                     : DAMAS_GS_LAUNCH(true, SH::long_nh, SH::long_nb);
@@ -893,14 +982,14 @@ int gs_max_ranks() { return kGsMaxRanks; }
 int gs_groups_per_wave(int precision, int s_tilde, int ranks)
 {
     const int cpl = precision == DAMAS_PREC_FP64 ? 2 : precision == DAMAS_PREC_BF16 ? 8 : 4;
-    const int ng = (s_tilde + cpl - 1) / cpl, nwt = ranks * GsShapes<float>::nw;
+    const int ng = (s_tilde + cpl - 1) / cpl, nwt = ranks * GsShapes<float>::cnw;
     return (ng + nwt - 1) / nwt;
 }
 
 template <typename TA, typename TX, bool UNIT, int NH, int NB>
 static const void *coop_fn()
 {
-    return (const void *)gs_coop_kernel<TA, TX, UNIT, GsShapes<TA>::nw, NH, NB>;
+    return (const void *)gs_coop_kernel<TA, TX, UNIT, GsShapes<TA>::cnw, NH, NB>;
 }
 
 // The kernel instance for a precision and the most groups any stream
@@ -910,12 +999,12 @@ static const void *coop_pick(int precision, int unit, int groups_per_wave)
 #define DAMAS_COOP_PICK(TA, TX)                                                                \
     {                                                                                          \
         typedef GsShapes<TA> SH;                                                               \
-        const bool shrt = groups_per_wave <= SH::short_nh;                                    \
+        const bool shrt = groups_per_wave <= SH::c_short_nh;                                  \
         if (unit)                                                                              \
-            return shrt ? coop_fn<TA, TX, true, SH::short_nh, SH::short_nb>()                 \
-                        : coop_fn<TA, TX, true, SH::long_nh, SH::long_nb>();                  \
-        return shrt ? coop_fn<TA, TX, false, SH::short_nh, SH::short_nb>()                    \
-                    : coop_fn<TA, TX, false, SH::long_nh, SH::long_nb>();                     \
+            return shrt ? coop_fn<TA, TX, true, SH::c_short_nh, SH::c_short_nb>()             \
+                        : coop_fn<TA, TX, true, SH::c_long_nh, SH::c_long_nb>();              \
+        return shrt ? coop_fn<TA, TX, false, SH::c_short_nh, SH::c_short_nb>()                \
+                    : coop_fn<TA, TX, false, SH::c_long_nh, SH::c_long_nb>();                 \
     }
     if (precision == DAMAS_PREC_FP64)
         DAMAS_COOP_PICK(double, double)
@@ -931,11 +1020,11 @@ int gs_coop_capacity(int precision, int max_kept)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    const int nw = GsShapes<float>::nw; // the same for every storage type
+    const int nw = GsShapes<float>::cnw; // the same for every storage type
     const void *fn = coop_pick(precision, 1, 1 << 30);
     (void)allow_big_lds(fn);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * (1 + nw),
-                                                     gs_lds_bytes(precision, max_kept)) !=
+                                                     gs_coop_lds_bytes(precision, max_kept)) !=
         hipSuccess) {
         (void)hipGetLastError();
         return 0;
@@ -969,8 +1058,8 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
         return e;
     const void *fn = coop_pick(precision, unit_diagonal, groups_per_wave);
     (void)allow_big_lds(fn);
-    const int nw = GsShapes<float>::nw;
-    size_t lds = gs_lds_bytes(precision, max_kept);
+    const int nw = GsShapes<float>::cnw;
+    size_t lds = gs_coop_lds_bytes(precision, max_kept);
     void *args[] = {&N,  (void *)&s_tilde, &max_kept, (void *)&idx, (void *)&off,
                     (void *)&A, (void *)&b, &iterations, (void *)&x_init, &x_map,
                     &fault, &co};
