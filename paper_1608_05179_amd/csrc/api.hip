@@ -544,8 +544,15 @@ extern "C" int damas_check(damas_ctx *ctx, void *stream)
     HIP_TRY(hipMemcpy(&v, fault, sizeof v, hipMemcpyDeviceToHost), "read fault word");
     if (v) {
         HIP_TRY(hipMemset(fault, 0, sizeof(int)), "clear fault word");
+        // Bits: 4 a bin kept more points than max_kept; 8 a cooperative
+        // exchange gave up waiting; 16 a sweep launch shape did not cover
+        // a bin's strip.
         return fail(DAMAS_ECAPACITY,
-                    "a bin kept more points than max_kept (fault bits 0x%x)", v);
+                    "%s (fault bits 0x%x)",
+                    (v & 4) ? "a bin kept more points than max_kept"
+                    : (v & 8) ? "a cooperative sweep exchange timed out"
+                              : "a sweep launch shape did not cover a bin",
+                    v);
     }
     HIP_TRY(hipGetLastError(), "pending HIP error");
     return DAMAS_OK;

@@ -41,7 +41,6 @@ namespace damas {
 
 constexpr int kGsTile = 64;
 constexpr int kGsMaxStreamWaves = 15;   // stream waves per workgroup, at most
-constexpr int kGsCtPitch = kGsTile + 1; // rows of the coupling block
 constexpr int kGsBatch = 8;             // tail loads per batch (two batches in flight)
 constexpr int kGsPre = 8;               // serial wave: LDS reads issued this many steps ahead
 
@@ -104,17 +103,26 @@ template <> __device__ inline bf16s zero_of<bf16s>()
 }
 
 // LDS blocks handed from the stream waves to the serial wave for tile t
-// (tn = the tile after it):
+// (tn = the tile after it), U and dg in type TB, C in A's storage type TA:
 //   U[i][l]   = A_{t0+i, t0+l} for l > i, 0 for l <= i (strict upper)
 //   dg[l]     = A_{t0+l, t0+l}
-//   Ct[l][i]  = A_{tn0+l, t0+i} (pitch 65: lane l reads row l)
-// Entries outside S~ are 0.  The serial wave reads kGsPre rows / columns
-// past the last step it runs, hence the padding.
-template <typename TA> struct alignas(16) TileBlocks {
-    TA U[(kGsTile + kGsPre) * kGsTile];
-    TA Ct[kGsTile * kGsCtPitch + kGsPre];
-    TA dg[kGsTile];
+//   C[i][l]   = A_{t0+i, tn0+l} (= A_{tn0+l, t0+i}: step i's coupling to
+//               the next tile's row l)
+// Entries of U and dg outside S~ are 0; so are C's rows past S~ (zero
+// padding of A, or past its end).  C's columns past S~ may hold other
+// entries of A: they feed only lanes past S~, which the serial wave masks.
+// The serial wave reads kGsPre rows past the last step it runs and never
+// uses them: U has zero padding rows for that, and C's reads past its end
+// land in U (finite values).  C keeps A's row layout, so a stream wave
+// stores each loaded 16-byte piece of a row as it is.
+template <typename TB, typename TA> struct alignas(16) TileBlocks {
+    TA C[kGsTile * kGsTile];
+    TB U[(kGsTile + kGsPre) * kGsTile];
+    TB dg[kGsTile];
 };
+static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
+                  sizeof(bf16s) * kGsTile * kGsTile % 16 == 0,
+              "U starts 16-byte aligned after C");
 
 // ---------------------------------------------------------------------------
 // Stream role: one of NW waves (sw = 0..).  A period computes
@@ -183,7 +191,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     }
 
     // The head of strip T0 and, with `hand`, the rows of its hand-over
-    // blocks (tile T0 and tile TN0).
+    // blocks (columns of tile T0 for U, of tile TN0 for C).
     __device__ __forceinline__ void prefetch(int T0, int TN0, bool hand = true)
     {
         const uint32_t vo = voff(T0);
@@ -194,7 +202,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
 #pragma unroll
             for (int m = 0; m < NU; ++m) {
                 hu[m] = load(T0 / CPL + sw + NW * m, vo);
-                hc[m] = load(TN0 / CPL + sw + NW * m, vo);
+                hc[m] = load(T0 / CPL + sw + NW * m, voff(TN0));
             }
         }
     }
@@ -246,19 +254,19 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         }
     }
 
-    // Blocks of tile T for the serial wave, from hu / hc (zero outside S~),
-    // in the blocks' element type TB (A's type, or double so that the
-    // serial wave reads them without conversions).
+    // Blocks of tile T for the serial wave: U and dg from hu (zero outside
+    // S~), in the blocks' element type TB (A's type, or double so that the
+    // serial wave reads them without conversions); C from hc as loaded.
     template <typename TB>
-    __device__ __forceinline__ void handover(int T0, int TN0, const bool (&colok)[CPL],
-                                             TileBlocks<TB> *blk) const
+    __device__ __forceinline__ void handover(int T0, const bool (&colok)[CPL],
+                                             TileBlocks<TB, TA> *blk) const
     {
 #pragma unroll
         for (int m = 0; m < NU; ++m) {
             if (sw + NW * m >= GT) // wave-uniform: this wave has one group fewer
                 break;
             const int i = (sw + NW * m) * CPL + jp; // row within the tile
-            const bool rowu = T0 + i < St, rowc = TN0 + i < St;
+            const bool rowu = T0 + i < St;
             TA u[CPL];
 #pragma unroll
             for (int s = 0; s < CPL; ++s) {
@@ -267,9 +275,8 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
                 u[s] = rowu && colok[s] && c > i ? v : zero_of<TA>();
                 if (c == i)
                     blk->dg[i] = to_block<TB>(v);
-                blk->Ct[i * kGsCtPitch + c] =
-                    rowc && colok[s] ? to_block<TB>(VA::raw(hc[m], s)) : zero_of<TB>();
             }
+            *reinterpret_cast<VT *>(&blk->C[i * kGsTile + cl]) = hc[m];
             if constexpr (sizeof(TB) == sizeof(TA)) {
                 *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
             } else {
@@ -281,13 +288,15 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     }
 
     // The period that sums strip T and, with `hand`, hands over the blocks
-    // of T and of the tile TN after it; it also issues the head of strip
-    // NT0 (with hand-over tile NTN0) for the following period (after the
-    // last period those loads go unused: issuing them unconditionally keeps
-    // the head in the same registers from one period to the next).
+    // of T (coupled to the tile after it); it also issues the head of strip
+    // NT0 (and, with `hand`, its hand-over rows, coupled to tile NTN0) for
+    // the following period (after the last period those loads go unused:
+    // issuing them unconditionally keeps the head in the same registers
+    // from one period to the next).
     template <typename TB>
-    __device__ __forceinline__ void period(const double *xs, int T0, int TN0, int NT0, int NTN0,
-                                           double *part, TileBlocks<TB> *blk, bool hand = true)
+    __device__ __forceinline__ void period(const double *xs, int T0, int NT0, int NTN0,
+                                           double *part, TileBlocks<TB, TA> *blk,
+                                           bool hand = true)
     {
         double acc[CPL];
         bool colok[CPL];
@@ -306,7 +315,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         xcap = __builtin_amdgcn_readfirstlane(xcap);
         sum(head, gsw, acc, xs);
         if (hand)
-            handover(T0, TN0, colok, blk);
+            handover(T0, colok, blk);
         __builtin_amdgcn_sched_barrier(0);
         prefetch(NT0, NTN0, hand);
         __builtin_amdgcn_sched_barrier(0);
@@ -314,25 +323,30 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         // Tail: groups NH .. nk-1 in batches of NB, two batches in flight.
         // sched_barrier keeps each batch's loads issued ahead of the
         // arithmetic on the other batch (the scheduler would otherwise sink
-        // them to their uses and leave one or two loads in flight).
-        if (nk > NH) {
-            const uint32_t vo = voff(T0);
-            VT b0[NB], b1[NB];
-            auto fill = [&](VT(&dst)[NB], int k0) {
+        // them to their uses and leave one or two loads in flight).  Shapes
+        // whose head holds every group (NB = 0) have no tail: the last
+        // batch's unused loads would otherwise make the code after the loop
+        // wait for every load in flight, the next head included.
+        if constexpr (NB > 0) {
+            if (nk > NH) {
+                const uint32_t vo = voff(T0);
+                VT b0[NB], b1[NB];
+                auto fill = [&](VT(&dst)[NB], int k0) {
 #pragma unroll
-                for (int n = 0; n < NB; ++n)
-                    dst[n] = load(gsw + nwt * (k0 + n), vo);
-            };
-            fill(b0, NH);
-            for (int k0 = NH; k0 < nk; k0 += 2 * NB) {
-                fill(b1, k0 + NB);
-                __builtin_amdgcn_sched_barrier(0);
-                sum(b0, gsw + nwt * k0, acc, xs);
-                __builtin_amdgcn_sched_barrier(0);
-                fill(b0, k0 + 2 * NB);
-                __builtin_amdgcn_sched_barrier(0);
-                sum(b1, gsw + nwt * (k0 + NB), acc, xs);
-                __builtin_amdgcn_sched_barrier(0);
+                    for (int n = 0; n < NB; ++n)
+                        dst[n] = load(gsw + nwt * (k0 + n), vo);
+                };
+                fill(b0, NH);
+                for (int k0 = NH; k0 < nk; k0 += 2 * NB) {
+                    fill(b1, k0 + NB);
+                    __builtin_amdgcn_sched_barrier(0);
+                    sum(b0, gsw + nwt * k0, acc, xs);
+                    __builtin_amdgcn_sched_barrier(0);
+                    fill(b0, k0 + 2 * NB);
+                    __builtin_amdgcn_sched_barrier(0);
+                    sum(b1, gsw + nwt * (k0 + NB), acc, xs);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
 
@@ -436,9 +450,9 @@ struct OwnerLink {
     int *fault;
 };
 
-template <typename TA, int NW, bool UNIT>
+template <typename TA, typename TB, int NW, bool UNIT>
 __device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xnew,
-                                            const TileBlocks<TA> *blks, // TA: blocks' type
+                                            const TileBlocks<TB, TA> *blks,
                                             const int32_t *__restrict__ id,
                                             const double *__restrict__ bf, int St, int ntile,
                                             long long total, int lane,
@@ -461,7 +475,7 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         const int rows = min(kGsTile, St - t0);
         const int steps = (rows + 7) & ~7;
         const bool mine = lane < rows;
-        const TileBlocks<TA> &bk = blks[q & 1];
+        const TileBlocks<TB, TA> &bk = blks[q & 1];
         const double *pt = parts + (q & 1) * NW * kGsTile;
         double r = -bt + rn;
 #pragma unroll
@@ -484,16 +498,18 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         const double xl = !mine ? 0.0 : (ntile == 1 && q > 0) ? xkeep : xs[t0 + lane];
         double rho = mine ? (UNIT ? r : r * il) : 0.0;
         // Software pipeline: the block entries of step i + kGsPre are read
-        // from LDS during step i (raw storage type), and those of step i + 1
-        // are widened to double at the end of step i, off the serial chain
+        // from LDS during step i (raw storage types), and those of step
+        // i + 1 are widened to double at the end of step i, off the serial
+        // chain
         //   min -> readlane -> fma;
         // sched_barrier keeps each step's instructions together, and the
         // four independent coupling sums fill the chain's latency.
-        TA ur[kGsPre], cr[kGsPre];
+        TB ur[kGsPre];
+        TA cr[kGsPre];
 #pragma unroll
         for (int i = 0; i < kGsPre; ++i) {
             ur[i] = bk.U[i * kGsTile + lane];
-            cr[i] = bk.Ct[lane * kGsCtPitch + i];
+            cr[i] = bk.C[i * kGsTile + lane];
         }
         double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il, cd = widen(cr[0]);
         double rn4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -516,7 +532,7 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                 rn4[u & 3] -= cd * mc;
                 asm volatile("" : "+v"(rn4[u & 3]));
                 ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
-                cr[u] = bk.Ct[lane * kGsCtPitch + i + kGsPre];
+                cr[u] = bk.C[(i + kGsPre) * kGsTile + lane];
                 ud = widen(ur[(u + 1) % kGsPre]);
                 if (!UNIT)
                     ud *= il;
@@ -571,7 +587,7 @@ template <int NW, int WAVES> constexpr bool gs_spare_waves()
 
 template <typename TA, typename TB, int NW, int WAVES, int NH, int NB, bool UNIT>
 __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xnew,
-                                          TileBlocks<TB> *blks, const TA *A, int64_t ld, int St,
+                                          TileBlocks<TB, TA> *blks, const TA *A, int64_t ld, int St,
                                           const int32_t *__restrict__ id,
                                           const double *__restrict__ bf, long long total,
                                           int ntile, int w, int lane, int nwt,
@@ -582,7 +598,8 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
     constexpr bool spare = gs_spare_waves<NW, WAVES>();
     if (w == 0) {
         __syncthreads();
-        serial_role<TB, NW, UNIT>(xs, parts, xnew, blks, id, bf, St, ntile, total, lane, co);
+        serial_role<TA, TB, NW, UNIT>(xs, parts, xnew, blks, id, bf, St, ntile, total, lane,
+                                      co);
     } else if (spare && (w & 3) == 0) {
         for (long long q = 0; q <= total; ++q)
             __syncthreads();
@@ -592,18 +609,26 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
         // then sum strip t+1 and hand over its blocks.  The last period
         // only copies.
         const int si = spare ? w - 1 - (w - 1) / 4 : w - 1; // stream wave index
+        // Waves share a SIMD in groups w = k, k + 4, k + 8 (placed in turn)
+        // and the issue arbiter favours the oldest; raising the later
+        // ones' priority keeps the stream waves of a SIMD in step, so the
+        // last to reach the barrier is not always the youngest.
+        if (w >= 8)
+            __builtin_amdgcn_s_setprio(2);
+        else if (w >= 4)
+            __builtin_amdgcn_s_setprio(1);
         StreamWave<TA, NW, NH, NB> sw;
         sw.init(A, ld, St, si, lane, si, nwt);
         const int t1 = nxt(0), t2 = nxt(t1);
         sw.prefetch(0, t1 * kGsTile);
-        sw.period(xs, 0, t1 * kGsTile, t1 * kGsTile, t2 * kGsTile, parts, &blks[0]);
+        sw.period(xs, 0, t1 * kGsTile, t2 * kGsTile, parts, &blks[0]);
         __syncthreads();
         int tp = 0, t = 0;
         for (long long q = 0; q + 1 < total; ++q) {
             const int tn = nxt(t), tnn = nxt(tn), tn3 = nxt(tnn);
             if (q > 0)
                 sw.commit(xnew + ((q - 1) & 1) * kGsTile, xs, tp * kGsTile);
-            sw.period(xs, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, tn3 * kGsTile,
+            sw.period(xs, tn * kGsTile, tnn * kGsTile, tn3 * kGsTile,
                       parts + ((q + 1) & 1) * NW * kGsTile, &blks[(q + 1) & 1]);
             __syncthreads();
             tp = t;
@@ -616,9 +641,9 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
     __syncthreads();
 }
 
-template <typename TB, int NW> constexpr size_t gs_lds_fixed()
+template <typename TB, typename TA, int NW> constexpr size_t gs_lds_fixed()
 {
-    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TB>);
+    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TB, TA>);
 }
 
 template <typename TA, typename TB, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
@@ -634,7 +659,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
     double *xnew = parts + 2 * NW * kGsTile;
-    TileBlocks<TB> *blks = reinterpret_cast<TileBlocks<TB> *>(xnew + 2 * kGsTile);
+    TileBlocks<TB, TA> *blks = reinterpret_cast<TileBlocks<TB, TA> *>(xnew + 2 * kGsTile);
 
     const int f = blockIdx.x;
     const int S = N * N;
@@ -642,6 +667,12 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     if (St > max_kept) {
         if (threadIdx.x == 0)
             atomicOr(fault, 4);
+        St = 0;
+    }
+    if (NB == 0 && (St + Vec16<TA>::n - 1) / Vec16<TA>::n > NH * NW) {
+        // A shape without tail must hold every row group in its head.
+        if (threadIdx.x == 0)
+            atomicOr(fault, 16);
         St = 0;
     }
     const int64_t ld = ld_of(St);
@@ -656,9 +687,9 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     for (int64_t i = tid; i < ld; i += nthr)
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     {
-        TB *z = reinterpret_cast<TB *>(blks);
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TB>) / sizeof(TB)); i += nthr)
-            z[i] = zero_of<TB>();
+        uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TB, TA>) / 4); i += nthr)
+            z[i] = 0u;
     }
     __syncthreads();
 
@@ -718,13 +749,19 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
     double *xnew = parts + 2 * NW * kGsTile;
-    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xnew + 2 * kGsTile);
+    TileBlocks<TA, TA> *blks = reinterpret_cast<TileBlocks<TA, TA> *>(xnew + 2 * kGsTile);
 
     const int S = N * N;
     int St = s_tilde[f];
     if (St > max_kept) {
         if (threadIdx.x == 0)
             atomicOr(fault, 4);
+        St = 0;
+    }
+    if (NB == 0 && (St + Vec16<TA>::n - 1) / Vec16<TA>::n > NH * NW * ranks) {
+        // A shape without tail must hold every row group in its head.
+        if (threadIdx.x == 0)
+            atomicOr(fault, 16);
         St = 0;
     }
     const int64_t ld = ld_of(St);
@@ -742,9 +779,9 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
     for (int64_t i = tid; i < ld; i += nthr)
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     if (rank == 0) {
-        TA *z = reinterpret_cast<TA *>(blks);
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / sizeof(TA)); i += nthr)
-            z[i] = zero_of<TA>();
+        uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA, TA>) / 4); i += nthr)
+            z[i] = 0u;
     }
     __syncthreads();
 
@@ -785,8 +822,8 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
             for (long long p = -1; p + 1 < total; ++p) {
                 const int tn = nxt(tc), tnn = nxt(tn);
                 __syncthreads();
-                sw.period(xs, tn * kGsTile, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, parts,
-                          (TileBlocks<TA> *)nullptr, false);
+                sw.period(xs, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, parts,
+                          (TileBlocks<TA, TA> *)nullptr, false);
                 __syncthreads();
                 tc = tn;
             }
@@ -847,24 +884,25 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
 // a short head and a deep tail.
 template <typename TA> struct GsShapes;
 template <> struct GsShapes<float> {
-    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 4, long_nh = 6, long_nb = 8;
-    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 4, c_long_nh = 6, c_long_nb = 8;
+    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 8;
+    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
 };
 template <> struct GsShapes<double> {
     // 8 waves: LDS for the partial sums of more stream waves would cut the
     // unknowns a workgroup holds beside its double blocks.
-    static constexpr int waves = 8, nw = 7, short_nh = 12, short_nb = 4, long_nh = 6, long_nb = 6;
-    static constexpr int cnw = 7, c_short_nh = 12, c_short_nb = 4, c_long_nh = 6, c_long_nb = 6;
+    static constexpr int waves = 8, nw = 7, short_nh = 12, short_nb = 0, long_nh = 6, long_nb = 6;
+    static constexpr int cnw = 7, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 6;
 };
 template <> struct GsShapes<bf16s> {
-    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 4, long_nh = 6, long_nb = 8;
-    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 4, c_long_nh = 6, c_long_nb = 8;
+    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 8;
+    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
 };
 
-// Dynamic LDS of a launch: blocks of type TB, NW stream waves.
-template <typename TB, int NW> static size_t gs_lds_bytes_t(int max_kept)
+// Dynamic LDS of a launch: blocks U, dg of type TB, A of type TA, NW
+// stream waves.
+template <typename TB, typename TA, int NW> static size_t gs_lds_bytes_t(int max_kept)
 {
-    return gs_lds_fixed<TB, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
+    return gs_lds_fixed<TB, TA, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
 }
 
 // LDS the sweep kernels may use (the 160 KB of a CU, less a margin).
@@ -874,9 +912,9 @@ constexpr size_t kGsLdsLimit = 160 * 1024 - 512;
 static size_t gs_coop_lds_bytes(int precision, int max_kept)
 {
     switch (precision) {
-    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, GsShapes<double>::cnw>(max_kept);
-    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::cnw>(max_kept);
-    default: return gs_lds_bytes_t<bf16s, GsShapes<bf16s>::cnw>(max_kept);
+    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, double, GsShapes<double>::cnw>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, float, GsShapes<float>::cnw>(max_kept);
+    default: return gs_lds_bytes_t<bf16s, bf16s, GsShapes<bf16s>::cnw>(max_kept);
     }
 }
 
@@ -884,9 +922,9 @@ static size_t gs_coop_lds_bytes(int precision, int max_kept)
 static size_t gs_plain_lds_bytes(int precision, int max_kept)
 {
     switch (precision) {
-    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, GsShapes<double>::nw>(max_kept);
-    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::nw>(max_kept);
-    default: return gs_lds_bytes_t<bf16s, GsShapes<bf16s>::nw>(max_kept);
+    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, double, GsShapes<double>::nw>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, float, GsShapes<float>::nw>(max_kept);
+    default: return gs_lds_bytes_t<bf16s, bf16s, GsShapes<bf16s>::nw>(max_kept);
     }
 }
 
@@ -906,7 +944,7 @@ static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max
                               const double *b, int iterations, const void *x_init,
                               void *x_map, int *fault, bool wide, hipStream_t s)
 {
-    wide = wide && gs_lds_bytes_t<double, NW>(max_kept) <= kGsLdsLimit;
+    wide = wide && gs_lds_bytes_t<double, TA, NW>(max_kept) <= kGsLdsLimit;
 #define DAMAS_GS_TB(TB)                                                                         \
     {                                                                                          \
         static const hipError_t attr =                                                         \
@@ -914,7 +952,7 @@ static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max
         if (attr != hipSuccess)                                                                \
             return attr;                                                                       \
         hipLaunchKernelGGL((gs_kernel<TA, TB, TX, UNIT, NW, WAVES, NH, NB>), dim3(n_bins),    \
-                           dim3(64 * WAVES), (gs_lds_bytes_t<TB, NW>(max_kept)), s, N, s_tilde, \
+                           dim3(64 * WAVES), (gs_lds_bytes_t<TB, TA, NW>(max_kept)), s, N, s_tilde, \
                            max_kept, idx, off, (const TA *)A, b, iterations,                  \
                            (const TX *)x_init, (TX *)x_map, fault);                           \
         return hipGetLastError();                                                              \
