@@ -102,8 +102,29 @@ template <> __device__ inline bf16s zero_of<bf16s>()
     return z;
 }
 
+// v at lane l ^ M, without LDS, in the lanes a reduction over 64 / M row
+// groups reads: every lane for M = 8 (DPP row rotation by 8), lanes whose
+// 16-lane row is even for M = 16 (v_permlane16_swap), lanes below 32 for
+// M = 32 (v_permlane32_swap).
+template <int M> __device__ __forceinline__ uint32_t lane_xor_u32(uint32_t v)
+{
+    static_assert(M == 8 || M == 16 || M == 32, "row groups of 8, 16 or 32 lanes");
+    if constexpr (M == 8)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);
+    else if constexpr (M == 16)
+        return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
+    else
+        return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+}
+template <int M> __device__ __forceinline__ double lane_xor(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = lane_xor_u32<M>((uint32_t)u), hi = lane_xor_u32<M>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
 // LDS blocks handed from the stream waves to the serial wave for tile t
-// (tn = the tile after it), U and dg in type TB, C in A's storage type TA:
+// (tn = the tile after it), in type TB (A's storage type, or double):
 //   U[i][l]   = A_{t0+i, t0+l} for l > i, 0 for l <= i (strict upper)
 //   dg[l]     = A_{t0+l, t0+l}
 //   C[i][l]   = A_{t0+i, tn0+l} (= A_{tn0+l, t0+i}: step i's coupling to
@@ -114,9 +135,10 @@ template <> __device__ inline bf16s zero_of<bf16s>()
 // The serial wave reads kGsPre rows past the last step it runs and never
 // uses them: U has zero padding rows for that, and C's reads past its end
 // land in U (finite values).  C keeps A's row layout, so a stream wave
-// stores each loaded 16-byte piece of a row as it is.
-template <typename TB, typename TA> struct alignas(16) TileBlocks {
-    TA C[kGsTile * kGsTile];
+// stores each loaded 16-byte piece of a row as it is (widened when the
+// blocks are double).
+template <typename TB> struct alignas(16) TileBlocks {
+    TB C[kGsTile * kGsTile];
     TB U[(kGsTile + kGsPre) * kGsTile];
     TB dg[kGsTile];
 };
@@ -254,12 +276,12 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         }
     }
 
-    // Blocks of tile T for the serial wave: U and dg from hu (zero outside
-    // S~), in the blocks' element type TB (A's type, or double so that the
-    // serial wave reads them without conversions); C from hc as loaded.
+    // Blocks of tile T for the serial wave, in the blocks' element type TB
+    // (A's type, or double so that the serial wave reads them without
+    // conversions): U and dg from hu (zero outside S~), C from hc.
     template <typename TB>
     __device__ __forceinline__ void handover(int T0, const bool (&colok)[CPL],
-                                             TileBlocks<TB, TA> *blk) const
+                                             TileBlocks<TB> *blk) const
     {
 #pragma unroll
         for (int m = 0; m < NU; ++m) {
@@ -276,13 +298,15 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
                 if (c == i)
                     blk->dg[i] = to_block<TB>(v);
             }
-            *reinterpret_cast<VT *>(&blk->C[i * kGsTile + cl]) = hc[m];
             if constexpr (sizeof(TB) == sizeof(TA)) {
+                *reinterpret_cast<VT *>(&blk->C[i * kGsTile + cl]) = hc[m];
                 *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
             } else {
 #pragma unroll
-                for (int s = 0; s < CPL; ++s)
+                for (int s = 0; s < CPL; ++s) {
+                    blk->C[i * kGsTile + cl + s] = to_block<TB>(VA::raw(hc[m], s));
                     blk->U[i * kGsTile + cl + s] = to_block<TB>(u[s]);
+                }
             }
         }
     }
@@ -295,7 +319,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     // from one period to the next).
     template <typename TB>
     __device__ __forceinline__ void period(const double *xs, int T0, int NT0, int NTN0,
-                                           double *part, TileBlocks<TB, TA> *blk,
+                                           double *part, TileBlocks<TB> *blk,
                                            bool hand = true)
     {
         double acc[CPL];
@@ -352,11 +376,18 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
 
         // Sum the CPL row groups (lanes l, l + LPJ, ...), then lanes
         // 0..LPJ-1 hold the partial sums of the tile's 64 columns.
-#pragma unroll
-        for (int m = LPJ; m < 64; m <<= 1)
+        static_assert(LPJ >= 8, "at most 8 elements per lane");
+        if constexpr (LPJ <= 8)
 #pragma unroll
             for (int s = 0; s < CPL; ++s)
-                acc[s] += __shfl_xor(acc[s], m);
+                acc[s] += lane_xor<8>(acc[s]);
+        if constexpr (LPJ <= 16)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+                acc[s] += lane_xor<16>(acc[s]);
+#pragma unroll
+        for (int s = 0; s < CPL; ++s)
+            acc[s] += lane_xor<32>(acc[s]);
         if (lane < LPJ)
 #pragma unroll
             for (int s = 0; s < CPL; ++s)
@@ -452,7 +483,7 @@ struct OwnerLink {
 
 template <typename TA, typename TB, int NW, bool UNIT>
 __device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xnew,
-                                            const TileBlocks<TB, TA> *blks,
+                                            const TileBlocks<TB> *blks,
                                             const int32_t *__restrict__ id,
                                             const double *__restrict__ bf, int St, int ntile,
                                             long long total, int lane,
@@ -475,7 +506,7 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         const int rows = min(kGsTile, St - t0);
         const int steps = (rows + 7) & ~7;
         const bool mine = lane < rows;
-        const TileBlocks<TB, TA> &bk = blks[q & 1];
+        const TileBlocks<TB> &bk = blks[q & 1];
         const double *pt = parts + (q & 1) * NW * kGsTile;
         double r = -bt + rn;
 #pragma unroll
@@ -498,20 +529,27 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         const double xl = !mine ? 0.0 : (ntile == 1 && q > 0) ? xkeep : xs[t0 + lane];
         double rho = mine ? (UNIT ? r : r * il) : 0.0;
         // Software pipeline: the block entries of step i + kGsPre are read
-        // from LDS during step i (raw storage types), and those of step
-        // i + 1 are widened to double at the end of step i, off the serial
-        // chain
-        //   min -> readlane -> fma;
-        // sched_barrier keeps each step's instructions together, and the
-        // four independent coupling sums fill the chain's latency.
-        TB ur[kGsPre];
-        TA cr[kGsPre];
+        // from LDS during step i (raw storage types).  A step issues, in
+        // this order (sched_barrier between them):
+        //   min(rho, x)                     chain
+        //   widen U of step i + 1           fills the min's latency
+        //   readlane x2 (broadcast)         chain
+        //   coupling fma of step i - 1      fills the scalar operands' latency
+        //   rho fma                         chain
+        //   widen C of step i, LDS reads    fill the fma's latency
+        // so the off-chain work fills the chain's gaps instead of following
+        // it.  The coupling of a step is applied one step late (and the
+        // last one after the loop); four independent sums keep its fmas
+        // apart.  rho itself is never passed through asm: the min would
+        // then canonicalise it first.
+        TB ur[kGsPre], cr[kGsPre];
 #pragma unroll
         for (int i = 0; i < kGsPre; ++i) {
             ur[i] = bk.U[i * kGsTile + lane];
             cr[i] = bk.C[i * kGsTile + lane];
         }
-        double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il, cd = widen(cr[0]);
+        double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il;
+        double cdp = 0.0, mp = 0.0; // coupling of the previous step
         double rn4[4] = {0.0, 0.0, 0.0, 0.0};
         for (int i0 = 0; i0 < steps; i0 += kGsPre) {
 #pragma unroll
@@ -519,27 +557,28 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                 const int i = i0 + u; // wave-uniform
                 // d = max(-rho, -x) = -min(rho, x): the broadcast carries
                 // min(rho, x) and the updates subtract.
-                const double m = lane_bcast(fmin(rho, xl), i);
-                rho -= ud * m;
-                // The coupling sum takes the broadcast through an empty asm
-                // that depends on the new rho, so the chain's fma issues
-                // first; its own pin keeps it in this step (otherwise it is
-                // sunk past the loop and the broadcasts stay live in scalar
-                // registers).  rho itself is never passed through asm: the
-                // min would then canonicalise it first.
-                double mc = m;
-                asm volatile("" : "+s"(mc) : "v"(rho));
-                rn4[u & 3] -= cd * mc;
+                const double mn = fmin(rho, xl);
+                __builtin_amdgcn_sched_barrier(0);
+                double udn = widen(ur[(u + 1) % kGsPre]);
+                if (!UNIT)
+                    udn *= il;
+                __builtin_amdgcn_sched_barrier(0);
+                const double m = lane_bcast(mn, i);
+                __builtin_amdgcn_sched_barrier(0);
+                rn4[u & 3] -= cdp * mp;
                 asm volatile("" : "+v"(rn4[u & 3]));
+                __builtin_amdgcn_sched_barrier(0);
+                rho -= ud * m;
+                __builtin_amdgcn_sched_barrier(0);
+                cdp = widen(cr[u]);
+                mp = m;
+                ud = udn;
                 ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
                 cr[u] = bk.C[(i + kGsPre) * kGsTile + lane];
-                ud = widen(ur[(u + 1) % kGsPre]);
-                if (!UNIT)
-                    ud *= il;
-                cd = widen(cr[(u + 1) % kGsPre]);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+        rn4[0] -= cdp * mp;
         rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         // New values to the staging slot of this period (0 on lanes past
         // the tile); the stream waves copy them into x~ next period.
@@ -587,7 +626,7 @@ template <int NW, int WAVES> constexpr bool gs_spare_waves()
 
 template <typename TA, typename TB, int NW, int WAVES, int NH, int NB, bool UNIT>
 __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xnew,
-                                          TileBlocks<TB, TA> *blks, const TA *A, int64_t ld, int St,
+                                          TileBlocks<TB> *blks, const TA *A, int64_t ld, int St,
                                           const int32_t *__restrict__ id,
                                           const double *__restrict__ bf, long long total,
                                           int ntile, int w, int lane, int nwt,
@@ -641,9 +680,9 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
     __syncthreads();
 }
 
-template <typename TB, typename TA, int NW> constexpr size_t gs_lds_fixed()
+template <typename TB, int NW> constexpr size_t gs_lds_fixed()
 {
-    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TB, TA>);
+    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TB>);
 }
 
 template <typename TA, typename TB, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
@@ -659,7 +698,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
     double *xnew = parts + 2 * NW * kGsTile;
-    TileBlocks<TB, TA> *blks = reinterpret_cast<TileBlocks<TB, TA> *>(xnew + 2 * kGsTile);
+    TileBlocks<TB> *blks = reinterpret_cast<TileBlocks<TB> *>(xnew + 2 * kGsTile);
 
     const int f = blockIdx.x;
     const int S = N * N;
@@ -688,7 +727,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     {
         uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TB, TA>) / 4); i += nthr)
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TB>) / 4); i += nthr)
             z[i] = 0u;
     }
     __syncthreads();
@@ -749,7 +788,7 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
     double *xnew = parts + 2 * NW * kGsTile;
-    TileBlocks<TA, TA> *blks = reinterpret_cast<TileBlocks<TA, TA> *>(xnew + 2 * kGsTile);
+    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xnew + 2 * kGsTile);
 
     const int S = N * N;
     int St = s_tilde[f];
@@ -780,7 +819,7 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     if (rank == 0) {
         uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA, TA>) / 4); i += nthr)
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / 4); i += nthr)
             z[i] = 0u;
     }
     __syncthreads();
@@ -823,7 +862,7 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
                 const int tn = nxt(tc), tnn = nxt(tn);
                 __syncthreads();
                 sw.period(xs, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, parts,
-                          (TileBlocks<TA, TA> *)nullptr, false);
+                          (TileBlocks<TA> *)nullptr, false);
                 __syncthreads();
                 tc = tn;
             }
@@ -898,11 +937,10 @@ template <> struct GsShapes<bf16s> {
     static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
 };
 
-// Dynamic LDS of a launch: blocks U, dg of type TB, A of type TA, NW
-// stream waves.
-template <typename TB, typename TA, int NW> static size_t gs_lds_bytes_t(int max_kept)
+// Dynamic LDS of a launch: blocks of type TB, NW stream waves.
+template <typename TB, int NW> static size_t gs_lds_bytes_t(int max_kept)
 {
-    return gs_lds_fixed<TB, TA, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
+    return gs_lds_fixed<TB, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
 }
 
 // LDS the sweep kernels may use (the 160 KB of a CU, less a margin).
@@ -912,9 +950,9 @@ constexpr size_t kGsLdsLimit = 160 * 1024 - 512;
 static size_t gs_coop_lds_bytes(int precision, int max_kept)
 {
     switch (precision) {
-    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, double, GsShapes<double>::cnw>(max_kept);
-    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, float, GsShapes<float>::cnw>(max_kept);
-    default: return gs_lds_bytes_t<bf16s, bf16s, GsShapes<bf16s>::cnw>(max_kept);
+    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, GsShapes<double>::cnw>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::cnw>(max_kept);
+    default: return gs_lds_bytes_t<bf16s, GsShapes<bf16s>::cnw>(max_kept);
     }
 }
 
@@ -922,9 +960,9 @@ static size_t gs_coop_lds_bytes(int precision, int max_kept)
 static size_t gs_plain_lds_bytes(int precision, int max_kept)
 {
     switch (precision) {
-    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, double, GsShapes<double>::nw>(max_kept);
-    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, float, GsShapes<float>::nw>(max_kept);
-    default: return gs_lds_bytes_t<bf16s, bf16s, GsShapes<bf16s>::nw>(max_kept);
+    case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, GsShapes<double>::nw>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::nw>(max_kept);
+    default: return gs_lds_bytes_t<bf16s, GsShapes<bf16s>::nw>(max_kept);
     }
 }
 
@@ -944,7 +982,7 @@ static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max
                               const double *b, int iterations, const void *x_init,
                               void *x_map, int *fault, bool wide, hipStream_t s)
 {
-    wide = wide && gs_lds_bytes_t<double, TA, NW>(max_kept) <= kGsLdsLimit;
+    wide = wide && gs_lds_bytes_t<double, NW>(max_kept) <= kGsLdsLimit;
 #define DAMAS_GS_TB(TB)                                                                         \
     {                                                                                          \
         static const hipError_t attr =                                                         \
@@ -952,7 +990,7 @@ static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max
         if (attr != hipSuccess)                                                                \
             return attr;                                                                       \
         hipLaunchKernelGGL((gs_kernel<TA, TB, TX, UNIT, NW, WAVES, NH, NB>), dim3(n_bins),    \
-                           dim3(64 * WAVES), (gs_lds_bytes_t<TB, TA, NW>(max_kept)), s, N, s_tilde, \
+                           dim3(64 * WAVES), (gs_lds_bytes_t<TB, NW>(max_kept)), s, N, s_tilde, \
                            max_kept, idx, off, (const TA *)A, b, iterations,                  \
                            (const TX *)x_init, (TX *)x_map, fault);                           \
         return hipGetLastError();                                                              \
