@@ -37,6 +37,8 @@
 // wave starts such rows at a zero residual, so their change is always 0.
 #include "common.h"
 
+#include <type_traits>
+
 namespace damas {
 
 constexpr int kGsTile = 64;
@@ -508,10 +510,26 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         const bool mine = lane < rows;
         const TileBlocks<TB> &bk = blks[q & 1];
         const double *pt = parts + (q & 1) * NW * kGsTile;
-        double r = -bt + rn;
+        // The first block entries of the tile are read before the partial
+        // sums, so their latency overlaps the sum.
+        TB ur[kGsPre], cr[kGsPre];
+#pragma unroll
+        for (int i = 0; i < kGsPre; ++i) {
+            ur[i] = bk.U[i * kGsTile + lane];
+            cr[i] = bk.C[i * kGsTile + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // The stream waves' partial sums, added as a tree (depth log2 NW).
+        double pk[NW];
 #pragma unroll
         for (int k = 0; k < NW; ++k)
-            r += pt[k * kGsTile + lane];
+            pk[k] = pt[k * kGsTile + lane];
+#pragma unroll
+        for (int w = 1; w < NW; w <<= 1)
+#pragma unroll
+            for (int k = 0; k + w < NW; k += 2 * w)
+                pk[k] += pk[k + w];
+        double r = (rn - bt) + pk[0];
         if (co.ranks > 1) {
             // The helpers' sums of this tile's strip (their period q - 1).
             for (int h = 1; h < co.ranks; ++h) {
@@ -541,17 +559,12 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         // it.  The coupling of a step is applied one step late (and the
         // last one after the loop); four independent sums keep its fmas
         // apart.  rho itself is never passed through asm: the min would
-        // then canonicalise it first.
-        TB ur[kGsPre], cr[kGsPre];
-#pragma unroll
-        for (int i = 0; i < kGsPre; ++i) {
-            ur[i] = bk.U[i * kGsTile + lane];
-            cr[i] = bk.C[i * kGsTile + lane];
-        }
+        // then canonicalise it first.  The tile's last block reads nothing
+        // ahead (rows past the tile would only hold the barrier up).
         double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il;
         double cdp = 0.0, mp = 0.0; // coupling of the previous step
         double rn4[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int i0 = 0; i0 < steps; i0 += kGsPre) {
+        auto block = [&](int i0, auto reads) {
 #pragma unroll
             for (int u = 0; u < kGsPre; ++u) {
                 const int i = i0 + u; // wave-uniform
@@ -573,11 +586,17 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                 cdp = widen(cr[u]);
                 mp = m;
                 ud = udn;
-                ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
-                cr[u] = bk.C[(i + kGsPre) * kGsTile + lane];
+                if constexpr (decltype(reads)::value) {
+                    ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
+                    cr[u] = bk.C[(i + kGsPre) * kGsTile + lane];
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
-        }
+        };
+        int i0 = 0;
+        for (; i0 + kGsPre < steps; i0 += kGsPre)
+            block(i0, std::true_type{});
+        block(i0, std::false_type{});
         rn4[0] -= cdp * mp;
         rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         // New values to the staging slot of this period (0 on lanes past
