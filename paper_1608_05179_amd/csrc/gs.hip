@@ -346,13 +346,14 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         prefetch(NT0, NTN0, hand);
         __builtin_amdgcn_sched_barrier(0);
 
-        // Tail: groups NH .. nk-1 in batches of NB, two batches in flight.
+        // Tail: groups NH .. nk-1 in batches of NB, two batches in flight
+        // while more than two remain, then the last one or two with nothing
+        // loaded past them (an unused batch would make the code after the
+        // loop wait for every load in flight, the next head included).
         // sched_barrier keeps each batch's loads issued ahead of the
         // arithmetic on the other batch (the scheduler would otherwise sink
         // them to their uses and leave one or two loads in flight).  Shapes
-        // whose head holds every group (NB = 0) have no tail: the last
-        // batch's unused loads would otherwise make the code after the loop
-        // wait for every load in flight, the next head included.
+        // whose head holds every group (NB = 0) have no tail.
         if constexpr (NB > 0) {
             if (nk > NH) {
                 const uint32_t vo = voff(T0);
@@ -363,7 +364,8 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
                         dst[n] = load(gsw + nwt * (k0 + n), vo);
                 };
                 fill(b0, NH);
-                for (int k0 = NH; k0 < nk; k0 += 2 * NB) {
+                int k0 = NH;
+                for (; k0 + 2 * NB < nk; k0 += 2 * NB) {
                     fill(b1, k0 + NB);
                     __builtin_amdgcn_sched_barrier(0);
                     sum(b0, gsw + nwt * k0, acc, xs);
@@ -372,6 +374,15 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
                     __builtin_amdgcn_sched_barrier(0);
                     sum(b1, gsw + nwt * (k0 + NB), acc, xs);
                     __builtin_amdgcn_sched_barrier(0);
+                }
+                if (k0 + NB < nk) {
+                    fill(b1, k0 + NB);
+                    __builtin_amdgcn_sched_barrier(0);
+                    sum(b0, gsw + nwt * k0, acc, xs);
+                    __builtin_amdgcn_sched_barrier(0);
+                    sum(b1, gsw + nwt * (k0 + NB), acc, xs);
+                } else {
+                    sum(b0, gsw + nwt * k0, acc, xs);
                 }
             }
         }
@@ -942,7 +953,7 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
 // a short head and a deep tail.
 template <typename TA> struct GsShapes;
 template <> struct GsShapes<float> {
-    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 8;
+    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 6;
     static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
 };
 template <> struct GsShapes<double> {
@@ -952,7 +963,7 @@ template <> struct GsShapes<double> {
     static constexpr int cnw = 7, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 6;
 };
 template <> struct GsShapes<bf16s> {
-    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 8;
+    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 4;
     static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
 };
 
