@@ -485,6 +485,29 @@ __device__ __forceinline__ bool coop_wait(const uint32_t *p, uint32_t v, uint32_
     return false;
 }
 
+// Bounded wait until every helper h (1 <= h < ranks) of a bin has flag
+// flags[h] >= v: lane h polls helper h and lane 0 the bin's abort word, so
+// one load per poll round covers every helper.  Same guarantees as
+// coop_wait; wave-uniform result.
+__device__ __forceinline__ bool coop_wait_all(uint32_t *flags, int ranks, uint32_t v, int lane)
+{
+    const bool helper = lane >= 1 && lane < ranks;
+    const uint32_t *p = lane == 0 ? flags + kGsAbort : flags + min(lane, kGsMaxRanks - 1);
+    for (long long it = 0; it < kGsSpinMax; ++it) {
+        const uint32_t f = lane < ranks ? coop_ld(p) : 0u;
+        if (__all(!helper || f >= v)) {
+            asm volatile("" ::: "memory");
+            return true;
+        }
+        if (__any(lane == 0 && f != 0u))
+            return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if (lane == 0)
+        __hip_atomic_store(flags + kGsAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+}
+
 // The owner's side of a cooperative bin (ranks == 1: the bin is alone).
 struct OwnerLink {
     uint32_t *flags; // this bin's flags
@@ -542,12 +565,22 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                 pk[k] += pk[k + w];
         double r = (rn - bt) + pk[0];
         if (co.ranks > 1) {
-            // The helpers' sums of this tile's strip (their period q - 1).
-            for (int h = 1; h < co.ranks; ++h) {
-                if (!coop_wait(co.flags + h, (uint32_t)(q + 1), co.flags + kGsAbort))
-                    atomicOr(co.fault, 8);
-                r += coop_ld(co.part + h * 2 * kGsTile + (q & 1) * kGsTile + lane);
-            }
+            // The helpers' sums of this tile's strip (their period q - 1):
+            // one wait for all flags, then every helper's slot loaded before
+            // any is added (in helper order), so the exchange costs two
+            // round trips to memory rather than two per helper.
+            if (!coop_wait_all(co.flags, co.ranks, (uint32_t)(q + 1), lane))
+                atomicOr(co.fault, 8);
+            double hs[kGsMaxRanks];
+            const double *slot = co.part + (q & 1) * kGsTile + lane;
+#pragma unroll
+            for (int h = 1; h < kGsMaxRanks; ++h)
+                if (h < co.ranks)
+                    hs[h] = coop_ld(slot + h * 2 * kGsTile);
+#pragma unroll
+            for (int h = 1; h < kGsMaxRanks; ++h)
+                if (h < co.ranks)
+                    r += hs[h];
         }
         double il = 1.0;
         if (!UNIT)
@@ -954,17 +987,17 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
 template <typename TA> struct GsShapes;
 template <> struct GsShapes<float> {
     static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 6;
-    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
+    static constexpr int cnw = 7, c_short_nh = 24, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
 };
 template <> struct GsShapes<double> {
     // 8 waves: LDS for the partial sums of more stream waves would cut the
     // unknowns a workgroup holds beside its double blocks.
-    static constexpr int waves = 8, nw = 7, short_nh = 12, short_nb = 0, long_nh = 6, long_nb = 6;
+    static constexpr int waves = 8, nw = 7, short_nh = 32, short_nb = 0, long_nh = 6, long_nb = 6;
     static constexpr int cnw = 7, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 6;
 };
 template <> struct GsShapes<bf16s> {
     static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 4;
-    static constexpr int cnw = 7, c_short_nh = 14, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
+    static constexpr int cnw = 7, c_short_nh = 24, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
 };
 
 // Dynamic LDS of a launch: blocks of type TB, NW stream waves.
