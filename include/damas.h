@@ -278,6 +278,10 @@ typedef struct {
     double best_ms_per_sweep;    /* sweep time of the choice              */
     double default_ms_per_sweep; /* of the untuned knobs                  */
     int32_t candidates_timed;    /* distinct schedules timed              */
+    int32_t coop_floor_rows;     /* cost model of a bin's (or a rank's)
+                                    tile: max(floor, rows it sums), so that
+                                    short bins, bound by the row chain, are
+                                    not under-weighted; 0: rows alone     */
 } damas_tune_result;
 
 struct damas_params {

@@ -750,6 +750,13 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
         return 0;
     const int kCoopMinRows = ctx->tune.min_rows;
     const double kCoopOverhead = ctx->tune.overhead, kSplit = ctx->tune.split;
+    // Cost of a bin: tiles x max(floor, rows summed per tile).  A tile's
+    // period is the larger of the row chain (about a fixed time) and the
+    // strip sum (proportional to its rows); floor = 0 keeps ld^2.
+    const double kFloor = ctx->tune.floor_rows;
+    auto cost = [&](int st, double rows) {
+        return (double)((st + 63) / 64) * std::max(kFloor, rows);
+    };
     const int nb = P.n_bins;
     int cap = gs_coop_capacity(P.bf16 ? DAMAS_PREC_BF16 : P.p->precision, P.max_kept);
     if (P.bf16 && P.refine > 0)
@@ -761,7 +768,7 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
     double total = 0.0, plain_span = 0.0;
     for (int f = 0; f < nb; ++f) {
         const double l = (double)ld_of(P.st_host[f]);
-        work[f] = l * l;
+        work[f] = kFloor > 0.0 ? cost(P.st_host[f], l) : l * l;
         total += work[f];
         plain_span = std::max(plain_span, work[f]);
     }
@@ -776,6 +783,8 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
             continue;
         int r = (int)std::ceil(work[f] / T);
         r = std::min({r, gs_max_ranks(), std::max(st / kCoopMinRows, 1)});
+        if (kFloor > 0.0) // ranks past ld / floor would not shorten the tiles
+            r = std::min(r, std::max((int)(ld_of(st) / kFloor), 1));
         if (r > 1) {
             ranks[f] = r;
             multi += r;
@@ -803,7 +812,9 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
         if (ranks[f] > 1)
             for (int h = 0; h < ranks[f]; ++h, ++g) {
                 wg_jobs[g] = {f, h, ranks[f]};
-                load[g] = kCoopOverhead * work[f] / ranks[f];
+                load[g] = kCoopOverhead *
+                          (kFloor > 0.0 ? cost(P.st_host[f], (double)ld_of(P.st_host[f]) / ranks[f])
+                                        : work[f] / ranks[f]);
             }
     std::vector<int> solo;
     for (int f = 0; f < nb; ++f)
@@ -1280,12 +1291,14 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
         bool coop;
         int min_rows;
         double split, overhead;
+        int floor_rows;
     };
-    std::vector<Cand> cands = {{false, 320, 1.25, 1.3}, {true, 320, 1.25, 1.3}};
-    for (int mr : {256, 320, 512, 1024})
-        for (double sp : {1.0, 1.25, 2.0})
-            for (double ov : {1.1, 1.3, 1.6})
-                cands.push_back({true, mr, sp, ov});
+    std::vector<Cand> cands = {{false, 320, 1.25, 1.3, 0}, {true, 320, 1.25, 1.3, 0}};
+    for (int fl : {0, 640, 1280})
+        for (int mr : {256, 320, 512, 1024})
+            for (double sp : {1.0, 1.25, 2.0})
+                for (double ov : {1.1, 1.3, 1.6})
+                    cands.push_back({true, mr, sp, ov, fl});
     // Candidates that produce the same schedule are timed once.
     std::map<std::vector<int32_t>, double> timed;
     double best = 1e300, dflt = 0.0;
@@ -1297,6 +1310,7 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
         ctx->tune.min_rows = cands[c].min_rows;
         ctx->tune.split = cands[c].split;
         ctx->tune.overhead = cands[c].overhead;
+        ctx->tune.floor_rows = cands[c].floor_rows;
         std::vector<int32_t> tab;
         int gpw = 0;
         if (plan_coop(ctx, P, tab, &gpw) == 0)
@@ -1343,6 +1357,7 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
     ctx->tune.min_rows = cands[bi].min_rows;
     ctx->tune.split = cands[bi].split;
     ctx->tune.overhead = cands[bi].overhead;
+    ctx->tune.floor_rows = cands[bi].floor_rows;
     out->coop = cands[bi].coop;
     out->coop_min_rows = cands[bi].min_rows;
     out->coop_split = cands[bi].split;
@@ -1350,6 +1365,7 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
     out->best_ms_per_sweep = best / trial_sweeps;
     out->default_ms_per_sweep = dflt / trial_sweeps;
     out->candidates_timed = ran;
+    out->coop_floor_rows = cands[bi].floor_rows;
     return DAMAS_OK;
 }
 

@@ -73,6 +73,7 @@ struct damas_ctx {
         int min_rows = 320;    // rows per rank at least
         double split = 1.25;   // bins above split x the mean work per workgroup get ranks
         double overhead = 1.3; // cost per element of a rank relative to a bin alone
+        int floor_rows = 0;    // cost model: a tile costs max(floor_rows, ld) (0: ld)
     } tune;
     // graph capture: `capturing` turns cooperation off (cooperative launches
     // are not captured), for the sizing solve too; `in_capture` refuses

@@ -987,7 +987,7 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
 template <typename TA> struct GsShapes;
 template <> struct GsShapes<float> {
     static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 6;
-    static constexpr int cnw = 7, c_short_nh = 24, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
+    static constexpr int cnw = 11, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 4;
 };
 template <> struct GsShapes<double> {
     // 8 waves: LDS for the partial sums of more stream waves would cut the
@@ -997,7 +997,7 @@ template <> struct GsShapes<double> {
 };
 template <> struct GsShapes<bf16s> {
     static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 4;
-    static constexpr int cnw = 7, c_short_nh = 24, c_short_nb = 0, c_long_nh = 6, c_long_nb = 8;
+    static constexpr int cnw = 11, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 4;
 };
 
 // Dynamic LDS of a launch: blocks of type TB, NW stream waves.
@@ -1118,10 +1118,18 @@ size_t gs_coop_ws_bytes(int n_bins, int max_kept)
 
 int gs_max_ranks() { return kGsMaxRanks; }
 
+// Stream waves of the cooperative kernel for a storage precision.
+static int coop_stream_waves(int precision)
+{
+    return precision == DAMAS_PREC_FP64   ? GsShapes<double>::cnw
+           : precision == DAMAS_PREC_BF16 ? GsShapes<bf16s>::cnw
+                                          : GsShapes<float>::cnw;
+}
+
 int gs_groups_per_wave(int precision, int s_tilde, int ranks)
 {
     const int cpl = precision == DAMAS_PREC_FP64 ? 2 : precision == DAMAS_PREC_BF16 ? 8 : 4;
-    const int ng = (s_tilde + cpl - 1) / cpl, nwt = ranks * GsShapes<float>::cnw;
+    const int ng = (s_tilde + cpl - 1) / cpl, nwt = ranks * coop_stream_waves(precision);
     return (ng + nwt - 1) / nwt;
 }
 
@@ -1159,7 +1167,7 @@ int gs_coop_capacity(int precision, int max_kept)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    const int nw = GsShapes<float>::cnw; // the same for every storage type
+    const int nw = coop_stream_waves(precision);
     const void *fn = coop_pick(precision, 1, 1 << 30);
     (void)allow_big_lds(fn);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * (1 + nw),
@@ -1197,7 +1205,7 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
         return e;
     const void *fn = coop_pick(precision, unit_diagonal, groups_per_wave);
     (void)allow_big_lds(fn);
-    const int nw = GsShapes<float>::cnw;
+    const int nw = coop_stream_waves(precision);
     size_t lds = gs_coop_lds_bytes(precision, max_kept);
     void *args[] = {&N,  (void *)&s_tilde, &max_kept, (void *)&idx, (void *)&off,
                     (void *)&A, (void *)&b, &iterations, (void *)&x_init, &x_map,
