@@ -637,10 +637,19 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                 __builtin_amdgcn_sched_barrier(0);
             }
         };
-        int i0 = 0;
-        for (; i0 + kGsPre < steps; i0 += kGsPre)
-            block(i0, std::true_type{});
-        block(i0, std::false_type{});
+        // Fully unrolled over the tile's blocks, so that every broadcast's
+        // lane index is an immediate (a lane index computed by a scalar add
+        // just before the readlane delays it); a tile of fewer steps leaves
+        // at its last block, which reads nothing ahead.
+#pragma unroll
+        for (int k = 0; k < kGsTile / kGsPre; ++k) {
+            if (k * kGsPre + kGsPre < steps) {
+                block(k * kGsPre, std::true_type{});
+            } else {
+                block(k * kGsPre, std::false_type{});
+                break;
+            }
+        }
         rn4[0] -= cdp * mp;
         rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         // New values to the staging slot of this period (0 on lanes past
