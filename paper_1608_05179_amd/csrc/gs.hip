@@ -990,12 +990,13 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
 }
 
 // Launch shapes.  Plain kernel: WAVES waves per workgroup of which NW
-// stream; cooperative kernel: 1 + CNW waves.  Head groups NH and tail
+// stream (12 and 9: the two waves that would share the serial wave's SIMD
+// stay idle); cooperative kernel: 1 + CNW waves.  Head groups NH and tail
 // batch NB: short strips keep a whole strip in the head; long strips keep
 // a short head and a deep tail.
 template <typename TA> struct GsShapes;
 template <> struct GsShapes<float> {
-    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 6;
+    static constexpr int waves = 12, nw = 9, short_nh = 10, short_nb = 0, long_nh = 6, long_nb = 6;
     static constexpr int cnw = 11, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 4;
 };
 template <> struct GsShapes<double> {
@@ -1005,7 +1006,7 @@ template <> struct GsShapes<double> {
     static constexpr int cnw = 7, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 6;
 };
 template <> struct GsShapes<bf16s> {
-    static constexpr int waves = 12, nw = 11, short_nh = 8, short_nb = 0, long_nh = 6, long_nb = 4;
+    static constexpr int waves = 12, nw = 9, short_nh = 10, short_nb = 0, long_nh = 6, long_nb = 4;
     static constexpr int cnw = 11, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 4;
 };
 

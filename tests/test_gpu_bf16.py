@@ -107,7 +107,7 @@ def test_steer_and_psf_bf16(orc, dm, dev, M, N, K):
 @pytest.mark.parametrize("n", [5, 64, 130, 337, 700, 1500, 2300])
 def test_gs_on_bf16_values(orc, dm, dev, n):
     """Sweeps read bf16 A exactly: the same iterate as the oracle on the
-    bf16 values in double.  Up to 704 rows a stream wave's head holds its
+    bf16 values in double.  Up to 720 rows a stream wave's head holds its
     whole strip; 1500 and 2300 stream a tail that ends on one batch or two."""
     import torch
     rng = np.random.default_rng(500 + n)

@@ -219,9 +219,9 @@ def test_gs_hand_cases(dm, dev):
 
 # Sizes span one and several 64-row tiles, S~ a multiple of 8 with a partial
 # last tile (72, 136), and strips longer than the part of a strip the stream
-# waves hold in their head (168 rows for double A, 352 for float A), whose
-# tails end on one batch or two depending on the wave (257 .. 1000).
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 72, 130, 136, 257, 337, 385, 441, 1000])
+# waves hold in their head (448 rows for double A, 360 for float A), whose
+# tails end on one batch or two depending on the wave (385 .. 1100).
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 72, 130, 136, 257, 337, 385, 441, 1000, 1100])
 def test_gs_matches_oracle(orc, dm, dev, n):
     rng = np.random.default_rng(n)
     M = 24
