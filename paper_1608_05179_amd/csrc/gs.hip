@@ -86,13 +86,6 @@ template <> struct Vec16<bf16s> {
 __device__ inline double widen(double v) { return v; }
 __device__ inline double widen(float v) { return (double)v; }
 __device__ inline double widen(bf16s v) { return (double)bf16_to_float(v); }
-// A value of A's storage type in the hand-over blocks' type.
-template <typename TB, typename TA> __device__ inline TB to_block(TA v);
-template <> __device__ inline double to_block<double, double>(double v) { return v; }
-template <> __device__ inline double to_block<double, float>(float v) { return (double)v; }
-template <> __device__ inline double to_block<double, bf16s>(bf16s v) { return widen(v); }
-template <> __device__ inline float to_block<float, float>(float v) { return v; }
-template <> __device__ inline bf16s to_block<bf16s, bf16s>(bf16s v) { return v; }
 
 template <typename TA> __device__ inline TA zero_of();
 template <> __device__ inline double zero_of<double>() { return 0.0; }
@@ -126,7 +119,7 @@ template <int M> __device__ __forceinline__ double lane_xor(double v)
 }
 
 // LDS blocks handed from the stream waves to the serial wave for tile t
-// (tn = the tile after it), in type TB (A's storage type, or double):
+// (tn = the tile after it), in A's storage type TA:
 //   U[i][l]   = A_{t0+i, t0+l} for l > i, 0 for l <= i (strict upper)
 //   dg[l]     = A_{t0+l, t0+l}
 //   C[i][l]   = A_{t0+i, tn0+l} (= A_{tn0+l, t0+i}: step i's coupling to
@@ -137,12 +130,13 @@ template <int M> __device__ __forceinline__ double lane_xor(double v)
 // The serial wave reads kGsPre rows past the last step it runs and never
 // uses them: U has zero padding rows for that, and C's reads past its end
 // land in U (finite values).  C keeps A's row layout, so a stream wave
-// stores each loaded 16-byte piece of a row as it is (widened when the
-// blocks are double).
-template <typename TB> struct alignas(16) TileBlocks {
-    TB C[kGsTile * kGsTile];
-    TB U[(kGsTile + kGsPre) * kGsTile];
-    TB dg[kGsTile];
+// stores each loaded 16-byte piece of a row as it is.  (Blocks widened to
+// double would spare the serial wave its conversions, but their LDS
+// traffic delays its reads by more: measured slower.)
+template <typename TA> struct alignas(16) TileBlocks {
+    TA C[kGsTile * kGsTile];
+    TA U[(kGsTile + kGsPre) * kGsTile];
+    TA dg[kGsTile];
 };
 static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
                   sizeof(bf16s) * kGsTile * kGsTile % 16 == 0,
@@ -278,12 +272,10 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         }
     }
 
-    // Blocks of tile T for the serial wave, in the blocks' element type TB
-    // (A's type, or double so that the serial wave reads them without
-    // conversions): U and dg from hu (zero outside S~), C from hc.
-    template <typename TB>
+    // Blocks of tile T for the serial wave: U and dg from hu (zero outside
+    // S~), C from hc.
     __device__ __forceinline__ void handover(int T0, const bool (&colok)[CPL],
-                                             TileBlocks<TB> *blk) const
+                                             TileBlocks<TA> *blk) const
     {
 #pragma unroll
         for (int m = 0; m < NU; ++m) {
@@ -298,18 +290,10 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
                 const TA v = VA::raw(hu[m], s);
                 u[s] = rowu && colok[s] && c > i ? v : zero_of<TA>();
                 if (c == i)
-                    blk->dg[i] = to_block<TB>(v);
+                    blk->dg[i] = v;
             }
-            if constexpr (sizeof(TB) == sizeof(TA)) {
-                *reinterpret_cast<VT *>(&blk->C[i * kGsTile + cl]) = hc[m];
-                *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
-            } else {
-#pragma unroll
-                for (int s = 0; s < CPL; ++s) {
-                    blk->C[i * kGsTile + cl + s] = to_block<TB>(VA::raw(hc[m], s));
-                    blk->U[i * kGsTile + cl + s] = to_block<TB>(u[s]);
-                }
-            }
+            *reinterpret_cast<VT *>(&blk->C[i * kGsTile + cl]) = hc[m];
+            *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
         }
     }
 
@@ -319,9 +303,8 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     // the following period (after the last period those loads go unused:
     // issuing them unconditionally keeps the head in the same registers
     // from one period to the next).
-    template <typename TB>
     __device__ __forceinline__ void period(const double *xs, int T0, int NT0, int NTN0,
-                                           double *part, TileBlocks<TB> *blk,
+                                           double *part, TileBlocks<TA> *blk,
                                            bool hand = true)
     {
         double acc[CPL];
@@ -517,9 +500,9 @@ struct OwnerLink {
     int *fault;
 };
 
-template <typename TA, typename TB, int NW, bool UNIT>
+template <typename TA, int NW, bool UNIT>
 __device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xnew,
-                                            const TileBlocks<TB> *blks,
+                                            const TileBlocks<TA> *blks,
                                             const int32_t *__restrict__ id,
                                             const double *__restrict__ bf, int St, int ntile,
                                             long long total, int lane,
@@ -542,11 +525,11 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         const int rows = min(kGsTile, St - t0);
         const int steps = (rows + 7) & ~7;
         const bool mine = lane < rows;
-        const TileBlocks<TB> &bk = blks[q & 1];
+        const TileBlocks<TA> &bk = blks[q & 1];
         const double *pt = parts + (q & 1) * NW * kGsTile;
         // The first block entries of the tile are read before the partial
         // sums, so their latency overlaps the sum.
-        TB ur[kGsPre], cr[kGsPre];
+        TA ur[kGsPre], cr[kGsPre];
 #pragma unroll
         for (int i = 0; i < kGsPre; ++i) {
             ur[i] = bk.U[i * kGsTile + lane];
@@ -696,9 +679,9 @@ template <int NW, int WAVES> constexpr bool gs_spare_waves()
     return WAVES > 1 + NW;
 }
 
-template <typename TA, typename TB, int NW, int WAVES, int NH, int NB, bool UNIT>
+template <typename TA, int NW, int WAVES, int NH, int NB, bool UNIT>
 __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xnew,
-                                          TileBlocks<TB> *blks, const TA *A, int64_t ld, int St,
+                                          TileBlocks<TA> *blks, const TA *A, int64_t ld, int St,
                                           const int32_t *__restrict__ id,
                                           const double *__restrict__ bf, long long total,
                                           int ntile, int w, int lane, int nwt,
@@ -709,7 +692,7 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
     constexpr bool spare = gs_spare_waves<NW, WAVES>();
     if (w == 0) {
         __syncthreads();
-        serial_role<TA, TB, NW, UNIT>(xs, parts, xnew, blks, id, bf, St, ntile, total, lane,
+        serial_role<TA, NW, UNIT>(xs, parts, xnew, blks, id, bf, St, ntile, total, lane,
                                       co);
     } else if (spare && (w & 3) == 0) {
         for (long long q = 0; q <= total; ++q)
@@ -752,12 +735,12 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
     __syncthreads();
 }
 
-template <typename TB, int NW> constexpr size_t gs_lds_fixed()
+template <typename TA, int NW> constexpr size_t gs_lds_fixed()
 {
-    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TB>);
+    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TA>);
 }
 
-template <typename TA, typename TB, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
+template <typename TA, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
 __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     int N, const int32_t *__restrict__ s_tilde, int max_kept,
     const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
@@ -770,7 +753,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
     double *xnew = parts + 2 * NW * kGsTile;
-    TileBlocks<TB> *blks = reinterpret_cast<TileBlocks<TB> *>(xnew + 2 * kGsTile);
+    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xnew + 2 * kGsTile);
 
     const int f = blockIdx.x;
     const int S = N * N;
@@ -799,7 +782,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     {
         uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TB>) / 4); i += nthr)
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / 4); i += nthr)
             z[i] = 0u;
     }
     __syncthreads();
@@ -807,7 +790,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     const int ntile = (St + kGsTile - 1) / kGsTile;
     const long long total = (long long)iters * ntile;
     if (total > 0)
-        sweep_bin<TA, TB, NW, WAVES, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
+        sweep_bin<TA, NW, WAVES, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
                                             ntile, w, lane, NW);
 
     // Scatter: x_map[n] = x~_i at n = idx[i], 0 in the gaps between kept
@@ -944,7 +927,7 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
 
     // Owner.
     if (total > 0)
-        sweep_bin<TA, TA, NW, 1 + NW, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
+        sweep_bin<TA, NW, 1 + NW, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
                                             ntile, w, lane, ranks * NW,
                                             OwnerLink{flags, part, xpub, ranks, fault});
 
@@ -1010,10 +993,10 @@ template <> struct GsShapes<bf16s> {
     static constexpr int cnw = 11, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 4;
 };
 
-// Dynamic LDS of a launch: blocks of type TB, NW stream waves.
-template <typename TB, int NW> static size_t gs_lds_bytes_t(int max_kept)
+// Dynamic LDS of a launch: A's storage type TA, NW stream waves.
+template <typename TA, int NW> static size_t gs_lds_bytes_t(int max_kept)
 {
-    return gs_lds_fixed<TB, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
+    return gs_lds_fixed<TA, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
 }
 
 // LDS the sweep kernels may use (the 160 KB of a CU, less a margin).
@@ -1047,31 +1030,21 @@ int gs_max_kept(int precision)
     return (int)(((kGsLdsLimit - fixed) / sizeof(double)) & ~(size_t)7);
 }
 
-// Hand-over blocks in double when they fit beside x~ and `wide` allows
-// (the serial wave then reads them without conversions), else in A's type.
 template <typename TA, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
 static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                               const int32_t *idx, const int64_t *off, const void *A,
                               const double *b, int iterations, const void *x_init,
-                              void *x_map, int *fault, bool wide, hipStream_t s)
+                              void *x_map, int *fault, hipStream_t s)
 {
-    wide = wide && gs_lds_bytes_t<double, NW>(max_kept) <= kGsLdsLimit;
-#define DAMAS_GS_TB(TB)                                                                         \
-    {                                                                                          \
-        static const hipError_t attr =                                                         \
-            allow_big_lds((const void *)gs_kernel<TA, TB, TX, UNIT, NW, WAVES, NH, NB>);      \
-        if (attr != hipSuccess)                                                                \
-            return attr;                                                                       \
-        hipLaunchKernelGGL((gs_kernel<TA, TB, TX, UNIT, NW, WAVES, NH, NB>), dim3(n_bins),    \
-                           dim3(64 * WAVES), (gs_lds_bytes_t<TB, NW>(max_kept)), s, N, s_tilde, \
-                           max_kept, idx, off, (const TA *)A, b, iterations,                  \
-                           (const TX *)x_init, (TX *)x_map, fault);                           \
-        return hipGetLastError();                                                              \
-    }
-    if (wide)
-        DAMAS_GS_TB(double)
-    DAMAS_GS_TB(TA)
-#undef DAMAS_GS_TB
+    static const hipError_t attr =
+        allow_big_lds((const void *)gs_kernel<TA, TX, UNIT, NW, WAVES, NH, NB>);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL((gs_kernel<TA, TX, UNIT, NW, WAVES, NH, NB>), dim3(n_bins),
+                       dim3(64 * WAVES), (gs_lds_bytes_t<TA, NW>(max_kept)), s, N, s_tilde,
+                       max_kept, idx, off, (const TA *)A, b, iterations, (const TX *)x_init,
+                       (TX *)x_map, fault);
+    return hipGetLastError();
 }
 
 template <typename TA, typename TX>
@@ -1084,14 +1057,9 @@ static hipError_t launch_gs_u(int N, int n_bins, const int32_t *s_tilde, int max
     // A strip fits the short shape's head when every wave's groups do.
     const bool shrt =
         ld_of(max_kept) <= (int64_t)SH::short_nh * SH::nw * Vec16<TA>::n;
-    // Double blocks: the serial wave's steps lose their conversions, the
-    // stream waves write twice the bytes; measured a loss while the
-    // stream waves set the period, so off.
-    const bool wide = false;
 #define DAMAS_GS_LAUNCH(U, NH, NB)                                                               \
     launch_gs_t<TA, TX, U, SH::nw, SH::waves, NH, NB>(N, n_bins, s_tilde, max_kept, idx, off,  \
-                                                      A, b, iterations, x_init, x_map, fault,  \
-                                                      wide, s)
+                                                      A, b, iterations, x_init, x_map, fault, s)
     if (unit_diagonal)
         return shrt ? DAMAS_GS_LAUNCH(true, SH::short_nh, SH::short_nb)
                     : DAMAS_GS_LAUNCH(true, SH::long_nh, SH::long_nb);
