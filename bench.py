@@ -341,7 +341,8 @@ def main():
         "metric": METRIC, "value": rec["value"], "unit": rec["unit"],
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "dtype_detail": "A stored f32, partial strip sums f32; residuals, x and row updates f64",
         "config": {"workload": rec["workload"], "bins": rec["bins"],
                    "s_tilde": rec["s_tilde_max"], "iterations": rec["iterations"],
                    "a_storage": "f32", "updates_per_step": rec["updates_per_step"]},

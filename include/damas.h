@@ -68,13 +68,16 @@ extern "C" {
 #define DAMAS_PREC_FP64 0 /* A stored in double                          */
 #define DAMAS_PREC_FP32 1 /* A stored in float (half the bytes the sweeps
                              stream); steering, the PSF products, b, x and
-                             every sweep sum stay double                   */
+                             the row residuals stay double; the partial
+                             residual sums over a wave's share of a strip
+                             are accumulated in FP32                       */
 #define DAMAS_PREC_BF16 2 /* bulk sweeps on A stored in bf16 (a quarter of
                              the bytes of double), built on the bf16 matrix
                              cores with FP32 accumulation; then the last
                              refine_sweeps sweeps on an FP32 copy of A built
                              as for DAMAS_PREC_FP32.  x maps are float;
-                             the sweep state and sums stay double          */
+                             the sweep state and row residuals stay
+                             double, partial sums FP32 as above            */
 
 /* Scan geometry (section "Beamforming").  The struct itself is host memory;
  * `mic` is a DEVICE pointer to M x 3 doubles (metres, row-major, array in

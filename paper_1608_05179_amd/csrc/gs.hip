@@ -4,8 +4,11 @@
 // followed by the scatter of x~ back onto the full grid (zero elsewhere).
 //
 // One workgroup owns one bin for all its sweeps; x~ lives in LDS in double,
-// whatever A's storage type (double, float or bf16): the sweep state, b~ and
-// every sum are double, and a narrow A only rounds its entries once.
+// whatever A's storage type (double, float or bf16): the sweep state, b~,
+// the row residuals and their updates are double.  Each stream wave's share
+// of a residual sum (a few of its terms) is accumulated in A's arithmetic
+// type -- FP32 for a float or bf16 A, double for a double A -- and the serial
+// wave adds the shares in double.
 //
 // Rows go in tiles of 64, and the tiles of all sweeps form one stream
 // q = 0, 1, ... (tile q mod T of sweep q div T).  Two roles run side by side:
@@ -14,7 +17,7 @@
 //     adds A_li d_i, so row l sees the new value of each earlier row of the
 //     tile.  The same broadcast d_i also accumulates, for the next tile's
 //     rows, the change A_{q+1,i} d_i of their residuals.
-//   waves 1-4 (stream): meanwhile compute the residuals of tile q+1 over
+//   the other waves (stream): meanwhile compute the residuals of tile q+1 over
 //     every column, taking tile q's columns at their values before this
 //     tile's update (a snapshot, so the serial wave may overwrite them), and
 //     by symmetry reading row r's sum down column r: each j is a contiguous
@@ -50,23 +53,28 @@ constexpr int kGsPre = 8;               // serial wave: LDS reads issued this ma
 template <typename TA> struct Vec16;
 template <> struct Vec16<double> {
     typedef double2 type;
+    typedef double acc; // accumulation type of the strip sums
     static constexpr int n = 2;
     __device__ static double raw(const double2 &v, int s) { return s == 0 ? v.x : v.y; }
     __device__ static double wide(double r) { return r; }
+    __device__ static double toacc(double r) { return r; }
     __device__ static double2 pack(const double (&r)[2]) { return make_double2(r[0], r[1]); }
 };
 template <> struct Vec16<float> {
     typedef float4 type;
+    typedef float acc;
     static constexpr int n = 4;
     __device__ static float raw(const float4 &v, int s)
     {
         return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
     }
     __device__ static double wide(float r) { return (double)r; }
+    __device__ static float toacc(float r) { return r; }
     __device__ static float4 pack(const float (&r)[4]) { return make_float4(r[0], r[1], r[2], r[3]); }
 };
 template <> struct Vec16<bf16s> {
     typedef uint4 type;
+    typedef float acc;
     static constexpr int n = 8;
     __device__ static bf16s raw(const uint4 &v, int s)
     {
@@ -76,6 +84,7 @@ template <> struct Vec16<bf16s> {
         return r;
     }
     __device__ static double wide(bf16s r) { return (double)bf16_to_float(r); }
+    __device__ static float toacc(bf16s r) { return bf16_to_float(r); }
     __device__ static uint4 pack(const bf16s (&r)[8])
     {
         return make_uint4(r[0].u | ((uint32_t)r[1].u << 16), r[2].u | ((uint32_t)r[3].u << 16),
@@ -116,6 +125,10 @@ template <int M> __device__ __forceinline__ double lane_xor(double v)
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
     const uint64_t lo = lane_xor_u32<M>((uint32_t)u), hi = lane_xor_u32<M>((uint32_t)(u >> 32));
     return __builtin_bit_cast(double, lo | (hi << 32));
+}
+template <int M> __device__ __forceinline__ float lane_xor(float v)
+{
+    return __builtin_bit_cast(float, lane_xor_u32<M>(__builtin_bit_cast(uint32_t, v)));
 }
 
 // LDS blocks handed from the stream waves to the serial wave for tile t
@@ -160,6 +173,7 @@ static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
 template <typename TA, int NW, int NH, int NB> struct StreamWave {
     typedef Vec16<TA> VA;
     typedef typename VA::type VT;
+    typedef typename VA::acc AT;
     static constexpr int CPL = VA::n;
     static constexpr int LPJ = kGsTile / CPL;
     static constexpr int GT = kGsTile / CPL;         // row groups per tile
@@ -252,22 +266,26 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
     // acc += the groups in v[0..n) (groups g0, g0 + nwt, ...), in chunks of
     // eight: the x reads of a chunk are issued together, and sched_barrier
     // keeps the scheduler from widening every group of a long head at once.
+    // The sums accumulate in AT: FP32 for a narrow A (one conversion of x per
+    // group, then single-rate FMAs; FP64 would cost a widening and a
+    // half-rate FMA per element, which left the stream waves' SIMDs busy for
+    // most of a period), FP64 for a double A.
     template <int n>
-    __device__ __forceinline__ void sum(const VT (&v)[n], int g0, double (&acc)[CPL],
+    __device__ __forceinline__ void sum(const VT (&v)[n], int g0, AT (&acc)[CPL],
                                         const double *xs) const
     {
         constexpr int C = 8;
 #pragma unroll
         for (int k0 = 0; k0 < n; k0 += C) {
-            double xj[C];
+            AT xj[C];
 #pragma unroll
             for (int k = k0; k < k0 + C && k < n; ++k)
-                xj[k - k0] = xrow(g0 + nwt * k, xs)[jp];
+                xj[k - k0] = (AT)xrow(g0 + nwt * k, xs)[jp];
 #pragma unroll
             for (int k = k0; k < k0 + C && k < n; ++k)
 #pragma unroll
                 for (int s = 0; s < CPL; ++s)
-                    acc[s] += VA::wide(VA::raw(v[k], s)) * xj[k - k0];
+                    acc[s] += VA::toacc(VA::raw(v[k], s)) * xj[k - k0];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -307,11 +325,11 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
                                            double *part, TileBlocks<TA> *blk,
                                            bool hand = true)
     {
-        double acc[CPL];
+        AT acc[CPL];
         bool colok[CPL];
 #pragma unroll
         for (int s = 0; s < CPL; ++s) {
-            acc[s] = 0.0;
+            acc[s] = AT(0);
             colok[s] = T0 + cl + s < St;
         }
         // Per-period copies of the loop-invariant strides keep the compiler
@@ -387,7 +405,7 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
         if (lane < LPJ)
 #pragma unroll
             for (int s = 0; s < CPL; ++s)
-                part[sw * kGsTile + cl + s] = colok[s] ? acc[s] : 0.0;
+                part[sw * kGsTile + cl + s] = colok[s] ? (double)acc[s] : 0.0;
     }
 };
 
