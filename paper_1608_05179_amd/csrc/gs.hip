@@ -46,7 +46,6 @@ namespace damas {
 
 constexpr int kGsTile = 64;
 constexpr int kGsMaxStreamWaves = 15;   // stream waves per workgroup, at most
-constexpr int kGsBatch = 8;             // tail loads per batch (two batches in flight)
 constexpr int kGsPre = 8;               // serial wave: LDS reads issued this many steps ahead
 
 // 16 bytes of A per lane: CPL = 2 doubles, 4 floats or 8 bf16.
@@ -56,7 +55,6 @@ template <> struct Vec16<double> {
     typedef double acc; // accumulation type of the strip sums
     static constexpr int n = 2;
     __device__ static double raw(const double2 &v, int s) { return s == 0 ? v.x : v.y; }
-    __device__ static double wide(double r) { return r; }
     __device__ static double toacc(double r) { return r; }
     __device__ static double2 pack(const double (&r)[2]) { return make_double2(r[0], r[1]); }
 };
@@ -68,7 +66,6 @@ template <> struct Vec16<float> {
     {
         return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
     }
-    __device__ static double wide(float r) { return (double)r; }
     __device__ static float toacc(float r) { return r; }
     __device__ static float4 pack(const float (&r)[4]) { return make_float4(r[0], r[1], r[2], r[3]); }
 };
@@ -83,7 +80,6 @@ template <> struct Vec16<bf16s> {
         r.u = (uint16_t)((s & 1) ? (w >> 16) : (w & 0xffffu));
         return r;
     }
-    __device__ static double wide(bf16s r) { return (double)bf16_to_float(r); }
     __device__ static float toacc(bf16s r) { return bf16_to_float(r); }
     __device__ static uint4 pack(const bf16s (&r)[8])
     {
