@@ -103,6 +103,14 @@ const char *damas_last_error(void);
  * columns j >= s_tilde of the padding are zero. */
 int64_t damas_ld(int32_t s_tilde);
 
+/* The largest max_kept the sweeps accept at `precision` (DAMAS_PREC_*):
+ * the unknowns one sweep workgroup holds in LDS beside its partial sums
+ * and hand-over blocks, whichever of the one-workgroup and cooperative
+ * kernels needs more; for DAMAS_PREC_BF16 also within what the FP32
+ * refinement sweeps hold.  0 for an unknown precision.  Host only, no
+ * device work. */
+int32_t damas_gs_capacity(int32_t precision);
+
 /* Number of points on the coarsest grid G^0 of Algorithm 1 for an N x N
  * grid; every compressed grid keeps them, so KEEP_COUNT keeps
  * clamp(keep_count, |G^0|, N*N) points. */
@@ -218,8 +226,12 @@ int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
  *                  damas_psf's output); the sweeps then skip the scaling by
  *                  1 / A_ii.  Zero accepts any positive diagonal.
  * A must be symmetric (as the PSF matrix is).  The sweep state x~, b~ and
- * all sums are double at both precisions.  One workgroup owns one bin for
- * all its sweeps; bins run concurrently. */
+ * the row residuals are double at every precision; the partial sums a
+ * stream wave forms over its share of a strip are FP32 for a float or bf16
+ * A, double for a double A.  max_kept may not exceed
+ * damas_gs_capacity(precision).  One workgroup owns one bin for all its
+ * sweeps; bins run concurrently (the context's solves may also split a
+ * long bin over several workgroups). */
 int damas_gs(int32_t N, int32_t n_bins, const int32_t *s_tilde,
              int32_t max_kept, const int32_t *idx, const int64_t *off,
              int32_t precision, int32_t unit_diagonal, const void *A,

@@ -198,6 +198,15 @@ extern "C" int32_t damas_coarse_count(int32_t N) { return N < 1 ? 0 : coarse_cou
 
 extern "C" int32_t damas_mp(int32_t M) { return M < 1 ? 0 : mp_of(M); }
 
+extern "C" int32_t damas_gs_capacity(int32_t precision)
+{
+    if (precision != DAMAS_PREC_FP64 && precision != DAMAS_PREC_FP32 &&
+        precision != DAMAS_PREC_BF16)
+        return 0;
+    const int c = gs_max_kept(precision);
+    return precision == DAMAS_PREC_BF16 ? std::min(c, gs_max_kept(DAMAS_PREC_FP32)) : c;
+}
+
 // ---------------------------------------------------------------------------
 // step-level calls
 

@@ -74,6 +74,7 @@ _sig("damas_last_error", ctypes.c_char_p)
 _sig("damas_ld", c_i64, c_i32)
 _sig("damas_coarse_count", c_i32, c_i32)
 _sig("damas_mp", c_i32, c_i32)
+_sig("damas_gs_capacity", c_i32, c_i32)
 _G = ctypes.POINTER(Geometry)
 _sig("damas_das_map", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_select", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp, c_vp)
@@ -180,6 +181,11 @@ def coarse_count(N: int) -> int:
 def mp(M: int) -> int:
     """Half-width of a bf16 steering row (M rounded up to 16)."""
     return int(_lib.damas_mp(int(M)))
+
+
+def gs_capacity(precision: int) -> int:
+    """Largest max_kept the sweeps accept at this precision (0 if unknown)."""
+    return int(_lib.damas_gs_capacity(int(precision)))
 
 
 def _ptr(t, dtype=None, name="tensor"):

@@ -50,6 +50,22 @@ def test_layout_helpers(lib):
     assert [lib.damas_mp(m) for m in (0, 1, 16, 17, 64, 128)] == [0, 16, 16, 32, 64, 128]
 
 
+def test_gs_capacity(lib):
+    from paper_1608_05179_amd import damas as dm
+    # One sweep workgroup's LDS (160 KB less a margin) beside the partial sums
+    # and the two hand-over blocks of the larger (cooperative) kernel: x~ of
+    # 1,856 unknowns with double A, 10,112 with float A; bf16 sweeps would
+    # hold 14,496 but a bf16 solve ends with FP32 sweeps.
+    assert [lib.damas_gs_capacity(p) for p in (dm.PREC_FP64, dm.PREC_FP32, dm.PREC_BF16)] == \
+        [1856, 10112, 10112]
+    assert lib.damas_gs_capacity(9) == 0 and lib.damas_gs_capacity(-1) == 0
+    fake = ctypes.c_void_p(0x1000)
+    for p in (dm.PREC_FP64, dm.PREC_FP32, dm.PREC_BF16):
+        cap = lib.damas_gs_capacity(p)
+        assert dm._lib.damas_gs(101, 1, fake, cap + 8, fake, fake, p, 1, fake, fake, 1,
+                                None, fake, None) == dm.EINVAL
+
+
 def test_coarse_count_matches_oracle(lib, orc):
     for N in (1, 2, 3, 7, 8, 9, 33, 50, 64, 101):
         n0 = sum(orc.level(N, ix, iy)[0] == 0 for ix in range(N) for iy in range(N))

@@ -259,6 +259,59 @@ def test_gs_general_diagonal(orc, dm, dev, n):
         assert np.linalg.norm(x32 - ref) <= 1e-5 * np.linalg.norm(ref), (n, it)
 
 
+def _bf16_round(a32):
+    """bf16 bit patterns of float32 values (round to nearest even; finite)."""
+    u = a32.view(np.uint32)
+    return ((u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) >> np.uint32(16)).astype(np.uint16)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_gs_at_capacity(orc, dm, dev, prec):
+    """A bin of exactly damas_gs_capacity unknowns (x~ filling the LDS left
+    beside the sums and blocks): the sweeps match the oracle run on the very
+    values of A the GPU reads.  A: symmetric, unit diagonal, small
+    non-negative off-diagonal entries (PSF-like); two sweeps."""
+    import torch
+    p = {"fp64": dm.PREC_FP64, "fp32": dm.PREC_FP32, "bf16": dm.PREC_BF16}[prec]
+    n = dm.gs_capacity(p)
+    assert n > 0 and dm.ld(n) == n
+    N = int(np.ceil(np.sqrt(n)))
+    rng = np.random.default_rng(n + p)
+    R = np.abs(rng.standard_normal((n, n), dtype=np.float32)) * np.float32(0.5 / np.sqrt(n))
+    A32 = R + R.T
+    del R
+    np.fill_diagonal(A32, 1.0)
+    if p == dm.PREC_FP64:
+        A_host = A32.astype(np.float64)
+        A_d = torch.from_numpy(A_host.ravel()).to(dev)
+    elif p == dm.PREC_FP32:
+        A_host = A32
+        A_d = torch.from_numpy(A32.ravel()).to(dev)
+    else:
+        bits = _bf16_round(A32)
+        A_host = (bits.astype(np.uint32) << np.uint32(16)).view(np.float32)
+        A_d = torch.from_numpy(bits.ravel().view(np.int16)).to(dev).view(torch.bfloat16)
+    del A32
+    bt = np.abs(rng.standard_normal(n)) * 0.5
+    b = np.zeros((1, N * N))
+    b[0, :n] = bt
+    idx = np.zeros((1, N * N), np.int32)
+    idx[0, :n] = np.arange(n)
+    st = _t(np.array([n], np.int32), torch.int32, dev)
+    off = _t(np.array([0, n * n]), torch.int64, dev)
+    A64 = np.asarray(A_host, dtype=np.float64)
+    for it in (1, 2):
+        x = dm.gs(N, st, n, _t(idx, torch.int32, dev), off, p, A_d, _t(b, torch.float64, dev),
+                  it, unit_diagonal=True)
+        x = x.double().cpu().numpy()[0]
+        assert (x[n:] == 0).all()
+        ref = orc.gs(A64, bt, it)
+        err = np.linalg.norm(x[:n] - ref) / np.linalg.norm(ref)
+        # double A: summation order only; float and bf16 A: FP32 partial sums
+        # (each of a few hundred terms) and float x maps
+        assert err <= (1e-10 if p == dm.PREC_FP64 else 1e-5), (prec, it, err)
+
+
 def test_gs_identity_one_sweep(dm, dev):
     bt = np.random.default_rng(0).standard_normal(200)
     x = _gpu_gs(dm, dev, np.eye(200), bt, 1, dm.PREC_FP64)
