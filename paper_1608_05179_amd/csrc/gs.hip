@@ -384,24 +384,67 @@ template <typename TA, int NW, int NH, int NB> struct StreamWave {
             }
         }
 
-        // Sum the CPL row groups (lanes l, l + LPJ, ...), then lanes
-        // 0..LPJ-1 hold the partial sums of the tile's 64 columns.
-        static_assert(LPJ >= 8, "at most 8 elements per lane");
-        if constexpr (LPJ <= 8)
+        // Sum the CPL row groups (lanes l, l + LPJ, ...) of each column.
+        // With 16 or 32 lanes per row the columns are reduced in pairs: a
+        // swap of two columns' halves between two registers followed by one
+        // add reduces both (one instruction pair per two columns, no copies),
+        // and every lane ends with one column's sum, which it stores.
+        // (Not with a head of more than 10 groups: the cooperative kernel's
+        // 12-group head and the paired registers would then spill.)
+        if constexpr (LPJ == 16 && sizeof(AT) == 4 && NH <= 10) {
+            // Swapping 32-lane halves of columns (0, 1) and (2, 3), then the
+            // 16-lane rows of the two results: lane l holds column
+            // (l % 16) * 4 + s with s = 0, 2, 1, 3 for its 16-lane row.
+            auto pair = [](AT a, AT b, auto swapper) {
+                const auto r = swapper(__builtin_bit_cast(uint32_t, a),
+                                       __builtin_bit_cast(uint32_t, b));
+                return __builtin_bit_cast(AT, (uint32_t)r[0]) +
+                       __builtin_bit_cast(AT, (uint32_t)r[1]);
+            };
+            auto sw32 = [](uint32_t a, uint32_t b) {
+                return __builtin_amdgcn_permlane32_swap(a, b, false, false);
+            };
+            auto sw16 = [](uint32_t a, uint32_t b) {
+                return __builtin_amdgcn_permlane16_swap(a, b, false, false);
+            };
+            const AT q01 = pair(acc[0], acc[1], sw32);
+            const AT q23 = pair(acc[2], acc[3], sw32);
+            const AT r = pair(q01, q23, sw16);
+            const int c = (lane & 15) * 4 + ((lane >> 4) & 1) * 2 + (lane >> 5);
+            part[sw * kGsTile + c] = T0 + c < St ? (double)r : 0.0;
+        } else if constexpr (LPJ == 32 && sizeof(AT) == 8) {
+            // Columns (0, 1), each 64-bit value swapped as two halves: lane
+            // l holds column (l % 32) * 2 + l / 32.
+            const uint64_t a = __builtin_bit_cast(uint64_t, acc[0]);
+            const uint64_t b = __builtin_bit_cast(uint64_t, acc[1]);
+            const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+            const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32),
+                                                             false, false);
+            const double r =
+                __builtin_bit_cast(double, (uint64_t)(uint32_t)lo[0] | ((uint64_t)(uint32_t)hi[0] << 32)) +
+                __builtin_bit_cast(double, (uint64_t)(uint32_t)lo[1] | ((uint64_t)(uint32_t)hi[1] << 32));
+            const int c = (lane & 31) * 2 + (lane >> 5);
+            part[sw * kGsTile + c] = T0 + c < St ? r : 0.0;
+        } else {
+            // Each column reduced on its own, then lanes 0..LPJ-1 hold the
+            // sums of the tile's 64 columns.
+            static_assert(LPJ >= 8, "at most 8 elements per lane");
+            if constexpr (LPJ <= 8)
+#pragma unroll
+                for (int s = 0; s < CPL; ++s)
+                    acc[s] += lane_xor<8>(acc[s]);
+            if constexpr (LPJ <= 16)
+#pragma unroll
+                for (int s = 0; s < CPL; ++s)
+                    acc[s] += lane_xor<16>(acc[s]);
 #pragma unroll
             for (int s = 0; s < CPL; ++s)
-                acc[s] += lane_xor<8>(acc[s]);
-        if constexpr (LPJ <= 16)
+                acc[s] += lane_xor<32>(acc[s]);
+            if (lane < LPJ)
 #pragma unroll
-            for (int s = 0; s < CPL; ++s)
-                acc[s] += lane_xor<16>(acc[s]);
-#pragma unroll
-        for (int s = 0; s < CPL; ++s)
-            acc[s] += lane_xor<32>(acc[s]);
-        if (lane < LPJ)
-#pragma unroll
-            for (int s = 0; s < CPL; ++s)
-                part[sw * kGsTile + cl + s] = colok[s] ? (double)acc[s] : 0.0;
+                for (int s = 0; s < CPL; ++s)
+                    part[sw * kGsTile + cl + s] = colok[s] ? (double)acc[s] : 0.0;
+        }
     }
 };
 
