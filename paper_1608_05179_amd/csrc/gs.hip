@@ -47,6 +47,7 @@ namespace damas {
 constexpr int kGsTile = 64;
 constexpr int kGsMaxStreamWaves = 15;   // stream waves per workgroup, at most
 constexpr int kGsPre = 8;               // serial wave: LDS reads issued this many steps ahead
+constexpr int kGsSparseRows = 12;       // a tile with at most this many moving rows visits only them
 
 // 16 bytes of A per lane: CPL = 2 doubles, 4 floats or 8 bf16.
 template <typename TA> struct Vec16;
@@ -646,53 +647,91 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         // apart.  rho itself is never passed through asm: the min would
         // then canonicalise it first.  The tile's last block reads nothing
         // ahead (rows past the tile would only hold the barrier up).
-        double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il;
-        double cdp = 0.0, mp = 0.0; // coupling of the previous step
-        double rn4[4] = {0.0, 0.0, 0.0, 0.0};
-        auto block = [&](int i0, auto reads) {
-#pragma unroll
-            for (int u = 0; u < kGsPre; ++u) {
-                const int i = i0 + u; // wave-uniform
-                // d = max(-rho, -x) = -min(rho, x): the broadcast carries
-                // min(rho, x) and the updates subtract.
+        // Rows that move: m_i = min(rho_i, x_i) is zero whenever x_i is at 0
+        // with a positive residual, which is most rows once the map is
+        // sparse, and such a row changes nothing.  A tile with few moving
+        // rows visits only those (below); the others step through every row
+        // (the fixed loop after it), whose cost does not depend on the data.
+        const uint64_t live = rows >= 64 ? ~0ull : (rows > 0 ? (1ull << rows) - 1 : 0ull);
+        const uint64_t moving = __builtin_amdgcn_ballot_w64(fmin(rho, xl) != 0.0) & live;
+        if (__builtin_popcountll(moving) <= kGsSparseRows) {
+            // rho changes only at rows that move, so between two of them
+            // every pending row's m is already final: one min over all lanes
+            // and a ballot of the non-zero ones give the next row that
+            // moves, and the rows before it are skipped (their updates would
+            // add +-0 and change nothing, so this is the row-by-row
+            // iteration exactly).  That row's U and C entries are read from
+            // LDS, its m is broadcast and applied to the tile's later rows
+            // (U is zero on and below the diagonal) and to the next tile's
+            // residuals.
+            double rnext = 0.0;
+            uint64_t pend = live; // rows not yet passed
+            for (int guard = 0; guard < kGsTile; ++guard) {
                 const double mn = fmin(rho, xl);
-                __builtin_amdgcn_sched_barrier(0);
-                double udn = widen(ur[(u + 1) % kGsPre]);
+                const uint64_t nz = __builtin_amdgcn_ballot_w64(mn != 0.0) & pend;
+                if (nz == 0)
+                    break;
+                const int j = __builtin_ctzll(nz); // wave-uniform
+                const TA uj = bk.U[j * kGsTile + lane];
+                const TA cj = bk.C[j * kGsTile + lane];
+                const double m = lane_bcast(mn, j);
+                double udj = widen(uj);
                 if (!UNIT)
-                    udn *= il;
-                __builtin_amdgcn_sched_barrier(0);
-                const double m = lane_bcast(mn, i);
-                __builtin_amdgcn_sched_barrier(0);
-                rn4[u & 3] -= cdp * mp;
-                asm volatile("" : "+v"(rn4[u & 3]));
-                __builtin_amdgcn_sched_barrier(0);
-                rho -= ud * m;
-                __builtin_amdgcn_sched_barrier(0);
-                cdp = widen(cr[u]);
-                mp = m;
-                ud = udn;
-                if constexpr (decltype(reads)::value) {
-                    ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
-                    cr[u] = bk.C[(i + kGsPre) * kGsTile + lane];
+                    udj *= il;
+                rho -= udj * m;
+                rnext -= widen(cj) * m;
+                pend = j >= 63 ? 0ull : (pend & (~0ull << (j + 1)));
+            }
+            rn = rnext;
+        } else {
+            double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il;
+            double cdp = 0.0, mp = 0.0; // coupling of the previous step
+            double rn4[4] = {0.0, 0.0, 0.0, 0.0};
+            auto block = [&](int i0, auto reads) {
+    #pragma unroll
+                for (int u = 0; u < kGsPre; ++u) {
+                    const int i = i0 + u; // wave-uniform
+                    // d = max(-rho, -x) = -min(rho, x): the broadcast carries
+                    // min(rho, x) and the updates subtract.
+                    const double mn = fmin(rho, xl);
+                    __builtin_amdgcn_sched_barrier(0);
+                    double udn = widen(ur[(u + 1) % kGsPre]);
+                    if (!UNIT)
+                        udn *= il;
+                    __builtin_amdgcn_sched_barrier(0);
+                    const double m = lane_bcast(mn, i);
+                    __builtin_amdgcn_sched_barrier(0);
+                    rn4[u & 3] -= cdp * mp;
+                    asm volatile("" : "+v"(rn4[u & 3]));
+                    __builtin_amdgcn_sched_barrier(0);
+                    rho -= ud * m;
+                    __builtin_amdgcn_sched_barrier(0);
+                    cdp = widen(cr[u]);
+                    mp = m;
+                    ud = udn;
+                    if constexpr (decltype(reads)::value) {
+                        ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
+                        cr[u] = bk.C[(i + kGsPre) * kGsTile + lane];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
+            };
+            // Fully unrolled over the tile's blocks, so that every broadcast's
+            // lane index is an immediate (a lane index computed by a scalar add
+            // just before the readlane delays it); a tile of fewer steps leaves
+            // at its last block, which reads nothing ahead.
+    #pragma unroll
+            for (int k = 0; k < kGsTile / kGsPre; ++k) {
+                if (k * kGsPre + kGsPre < steps) {
+                    block(k * kGsPre, std::true_type{});
+                } else {
+                    block(k * kGsPre, std::false_type{});
+                    break;
+                }
             }
-        };
-        // Fully unrolled over the tile's blocks, so that every broadcast's
-        // lane index is an immediate (a lane index computed by a scalar add
-        // just before the readlane delays it); a tile of fewer steps leaves
-        // at its last block, which reads nothing ahead.
-#pragma unroll
-        for (int k = 0; k < kGsTile / kGsPre; ++k) {
-            if (k * kGsPre + kGsPre < steps) {
-                block(k * kGsPre, std::true_type{});
-            } else {
-                block(k * kGsPre, std::false_type{});
-                break;
-            }
+            rn4[0] -= cdp * mp;
+            rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         }
-        rn4[0] -= cdp * mp;
-        rn = (rn4[0] + rn4[1]) + (rn4[2] + rn4[3]);
         // New values to the staging slot of this period (0 on lanes past
         // the tile); the stream waves copy them into x~ next period.
         xkeep = xl - fmin(rho, xl);
