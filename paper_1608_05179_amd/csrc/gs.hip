@@ -16,7 +16,10 @@
 //     the residual of row l; after row i moves by d_i every later row l
 //     adds A_li d_i, so row l sees the new value of each earlier row of the
 //     tile.  The same broadcast d_i also accumulates, for the next tile's
-//     rows, the change A_{q+1,i} d_i of their residuals.
+//     rows, the change A_{q+1,i} d_i of their residuals.  A row whose d_i is
+//     zero (x_i at 0 with a positive residual, most rows once the map is
+//     sparse) changes nothing; a tile with few moving rows visits only
+//     those.
 //   the other waves (stream): meanwhile compute the residuals of tile q+1 over
 //     every column, taking tile q's columns at their values before this
 //     tile's update (a snapshot, so the serial wave may overwrite them), and

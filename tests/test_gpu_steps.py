@@ -312,6 +312,32 @@ def test_gs_at_capacity(orc, dm, dev, prec):
         assert err <= (1e-10 if p == dm.PREC_FP64 else 1e-5), (prec, it, err)
 
 
+@pytest.mark.parametrize("n", [64, 200, 337])
+def test_gs_sparse_tiles(orc, dm, dev, n):
+    """Tiles with few moving rows visit only those (the rest stay at zero
+    with a positive residual): b~ negative on about 85 % of the rows keeps
+    those rows at 0 from the first sweep, so almost every tile takes that
+    path; the iterate must still be the row-by-row one."""
+    rng = np.random.default_rng(900 + n)
+    e = np.exp(1j * rng.uniform(0, 2 * np.pi, size=(n, 24)))
+    A = orc.psf(e)
+    bt = np.abs(rng.standard_normal(n)) * 0.5
+    bt[rng.uniform(size=n) < 0.85] *= -1.0
+    for it in (1, 4, 30):
+        ref = orc.gs(A, bt, it)
+        scale = max(np.linalg.norm(ref), 1e-300)
+        x64 = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP64, unit=True)
+        assert np.linalg.norm(x64 - ref) / scale < 1e-10, (n, it)
+        x32 = _gpu_gs(dm, dev, A, bt, it, dm.PREC_FP32, unit=True)
+        assert np.linalg.norm(x32 - ref) / scale < 1e-4, (n, it)
+    # a general diagonal scales each row by 1 / A_ii on the same path
+    D = np.diag(rng.uniform(0.5, 2.0, n))
+    A2 = np.sqrt(D) @ A @ np.sqrt(D)
+    ref = orc.gs(A2, bt, 12)
+    x = _gpu_gs(dm, dev, A2, bt, 12, dm.PREC_FP64)
+    assert np.linalg.norm(x - ref) <= 1e-10 * max(np.linalg.norm(ref), 1e-300), n
+
+
 def test_gs_identity_one_sweep(dm, dev):
     bt = np.random.default_rng(0).standard_normal(200)
     x = _gpu_gs(dm, dev, np.eye(200), bt, 1, dm.PREC_FP64)
