@@ -812,10 +812,9 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
         else if (w >= 4)
             __builtin_amdgcn_s_setprio(1);
         // The diagonal's stores are left out where the sweeps do not read
-        // it for a double A (plain FP64 sweeps 10.5 -> 10.0 ms); a float A
-        // measured 0.8 % slower without them (the code around them is
-        // scheduled differently), so narrow A keeps them.
-        constexpr bool dg = !UNIT || sizeof(TA) < sizeof(double);
+        // it (unit diagonal): fewer instructions for the stream waves, which
+        // set the period once most tiles skip their zero rows.
+        constexpr bool dg = !UNIT;
         StreamWave<TA, NW, NH, NB, dg> sw;
         sw.init(A, ld, St, si, lane, si, nwt);
         const int t1 = nxt(0), t2 = nxt(t1);
