@@ -137,9 +137,11 @@ template <int M> __device__ __forceinline__ float lane_xor(float v)
 //   dg[l]     = A_{t0+l, t0+l}
 //   C[i][l]   = A_{t0+i, tn0+l} (= A_{tn0+l, t0+i}: step i's coupling to
 //               the next tile's row l)
-// Entries of U and dg outside S~ are 0; so are C's rows past S~ (zero
-// padding of A, or past its end).  C's columns past S~ may hold other
-// entries of A: they feed only lanes past S~, which the serial wave masks.
+// Rows of U and C past S~ are 0 (zero padding of A, or past its end), and
+// so is dg there; U's and C's columns past S~ may hold other entries of A
+// (a tile can reach past the row stride): they feed only lanes past S~,
+// whose values are never stored, and the steps past S~ that the serial wave
+// runs apply them to zero rows.
 // The serial wave reads kGsPre rows past the last step it runs and never
 // uses them: U has zero padding rows for that, and C's reads past its end
 // land in U (finite values).  C keeps A's row layout, so a stream wave
@@ -189,6 +191,11 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     int xcap;         // last row group start with x on chip (ld - CPL)
     uint32_t gstride; // bytes per group
     VT head[NH], hu[NU], hc[NU];
+    // With a float or bf16 A: per hand-over row, the bits of each 32-bit word
+    // of the lane's 16-byte piece to keep for U's strict upper part (the
+    // columns c > i); the same in every period.
+    static constexpr bool kMaskWords = sizeof(TA) < sizeof(double);
+    uint32_t umask[kMaskWords ? NU : 1][4];
 
     __device__ __forceinline__ void init(const TA *A, int64_t ld_, int St_, int sw_, int lane_,
                                          int gsw_, int nwt_)
@@ -208,6 +215,22 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
         rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<TA *>(A), (short)0,
                                                  (int)(ld * ld * (int64_t)sizeof(TA)),
                                                  0x00020000);
+        if constexpr (kMaskWords) {
+            constexpr int EPW = 4 / sizeof(TA); // elements per 32-bit word
+#pragma unroll
+            for (int m = 0; m < NU; ++m) {
+                const int i = (sw + NW * m) * CPL + jp;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    uint32_t k = 0;
+#pragma unroll
+                    for (int e = 0; e < EPW; ++e)
+                        if (cl + d * EPW + e > i)
+                            k |= (EPW == 1 ? 0xffffffffu : 0xffffu) << (16 * e);
+                    umask[m][d] = k;
+                }
+            }
+        }
     }
 
     // Per-lane byte offset of row jp, columns from T0 + cl.
@@ -301,18 +324,30 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
             if (sw + NW * m >= GT) // wave-uniform: this wave has one group fewer
                 break;
             const int i = (sw + NW * m) * CPL + jp; // row within the tile
-            const bool rowu = T0 + i < St;
-            TA u[CPL];
+            if constexpr (DG) {
 #pragma unroll
-            for (int s = 0; s < CPL; ++s) {
-                const int c = cl + s;
-                const TA v = VA::raw(hu[m], s);
-                u[s] = rowu && colok[s] && c > i ? v : zero_of<TA>();
-                if (DG && c == i)
-                    blk->dg[i] = v;
+                for (int s = 0; s < CPL; ++s)
+                    if (cl + s == i)
+                        blk->dg[i] = VA::raw(hu[m], s);
             }
             *reinterpret_cast<VT *>(&blk->C[i * kGsTile + cl]) = hc[m];
-            *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
+            if constexpr (kMaskWords) {
+                // Entries outside S~ are zero already (padding of A, or
+                // loads past its end), so only the triangle is masked.
+                uint4 w = __builtin_bit_cast(uint4, hu[m]);
+                w.x &= umask[m][0];
+                w.y &= umask[m][1];
+                w.z &= umask[m][2];
+                w.w &= umask[m][3];
+                *reinterpret_cast<uint4 *>(&blk->U[i * kGsTile + cl]) = w;
+            } else {
+                const bool rowu = T0 + i < St;
+                TA u[CPL];
+#pragma unroll
+                for (int s = 0; s < CPL; ++s)
+                    u[s] = rowu && colok[s] && cl + s > i ? VA::raw(hu[m], s) : zero_of<TA>();
+                *reinterpret_cast<VT *>(&blk->U[i * kGsTile + cl]) = VA::pack(u);
+            }
         }
     }
 
