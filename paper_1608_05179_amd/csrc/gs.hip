@@ -181,6 +181,9 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     static constexpr int LPJ = kGsTile / CPL;
     static constexpr int GT = kGsTile / CPL;         // row groups per tile
     static constexpr int NU = (GT + NW - 1) / NW;    // of them per wave, at most
+    // Short strips of a narrow A whose head fits twice in registers issue
+    // the next head as soon as the sums have read this one (see period()).
+    static constexpr bool kEarlyHead = NB == 0 && NH <= 10 && sizeof(TA) < sizeof(double);
 
     __amdgpu_buffer_rsrc_t rsrc;
     int64_t ld;
@@ -248,19 +251,27 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
 
     // The head of strip T0 and, with `hand`, the rows of its hand-over
     // blocks (columns of tile T0 for U, of tile TN0 for C).
-    __device__ __forceinline__ void prefetch(int T0, int TN0, bool hand = true)
+    __device__ __forceinline__ void prefetch_head(int T0)
     {
         const uint32_t vo = voff(T0);
 #pragma unroll
         for (int n = 0; n < NH; ++n)
             head[n] = load(gsw + nwt * n, vo);
-        if (hand) {
+    }
+    __device__ __forceinline__ void prefetch_hand(int T0, int TN0)
+    {
+        const uint32_t vo = voff(T0);
 #pragma unroll
-            for (int m = 0; m < NU; ++m) {
-                hu[m] = load(T0 / CPL + sw + NW * m, vo);
-                hc[m] = load(T0 / CPL + sw + NW * m, voff(TN0));
-            }
+        for (int m = 0; m < NU; ++m) {
+            hu[m] = load(T0 / CPL + sw + NW * m, vo);
+            hc[m] = load(T0 / CPL + sw + NW * m, voff(TN0));
         }
+    }
+    __device__ __forceinline__ void prefetch(int T0, int TN0, bool hand = true)
+    {
+        prefetch_head(T0);
+        if (hand)
+            prefetch_hand(T0, TN0);
     }
 
     // LDS address of x for the rows of group g (clamped to the rows on
@@ -376,11 +387,23 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
         asm volatile("" : "+v"(gstride), "+v"(xcap));
         gstride = (uint32_t)__builtin_amdgcn_readfirstlane((int)gstride);
         xcap = __builtin_amdgcn_readfirstlane(xcap);
+        // The next head is issued once the sums have read this one, ahead
+        // of the hand-over, whose rows were issued a period ago: its loads
+        // then stream while the hand-over is stored instead of after it.
         sum(head, gsw, acc, xs);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (kEarlyHead)
+            prefetch_head(NT0);
+        __builtin_amdgcn_sched_barrier(0);
         if (hand)
             handover(T0, colok, blk);
         __builtin_amdgcn_sched_barrier(0);
-        prefetch(NT0, NTN0, hand);
+        if constexpr (kEarlyHead) {
+            if (hand)
+                prefetch_hand(NT0, NTN0);
+        } else {
+            prefetch(NT0, NTN0, hand);
+        }
         __builtin_amdgcn_sched_barrier(0);
 
         // Tail: groups NH .. nk-1 in batches of NB, two batches in flight
