@@ -38,9 +38,11 @@
 // which each r_i's terms are summed (and, for a diagonal other than 1, the
 // scaling by 1 / A_ii) differ.
 //
-// Rows and columns at or beyond S~ contribute exact zeros: the stream masks
-// them out of the partial sums and of the hand-over blocks, and the serial
-// wave starts such rows at a zero residual, so their change is always 0.
+// Rows at or beyond S~ contribute exact zeros: A's padding rows are zero
+// (loads past a bin's system return 0), and the stream waves mask columns
+// past S~ out of the partial sums.  The serial wave's lanes past S~ may carry
+// other values (hand-over columns past S~ are not masked), but whatever they
+// broadcast multiplies zero rows, and their values are never stored.
 #include "common.h"
 
 #include <type_traits>
@@ -167,7 +169,7 @@ static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
 // A is read through a buffer resource whose range is the bin's system, so a
 // load past its end returns 0: the sums run branch-free over whole batches
 // and groups past S~ add exact zeros (rows S~ .. ld-1 are zero padding).
-// Columns at or past S~ are masked out of every result.
+// Columns at or past S~ are masked out of the partial sums.
 //
 // NH: groups per wave loaded a whole tile ahead (the head), together with
 // the rows of the two hand-over blocks; NB: groups per tail batch, two
@@ -181,8 +183,9 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     static constexpr int LPJ = kGsTile / CPL;
     static constexpr int GT = kGsTile / CPL;         // row groups per tile
     static constexpr int NU = (GT + NW - 1) / NW;    // of them per wave, at most
-    // Short strips of a narrow A whose head fits twice in registers issue
-    // the next head as soon as the sums have read this one (see period()).
+    // Short strips of a narrow A issue the next head as soon as the sums
+    // have read this one (see period()), where the registers allow it: a
+    // head of at most 10 groups (the cooperative kernel's 12 would spill).
     static constexpr bool kEarlyHead = NB == 0 && NH <= 10 && sizeof(TA) < sizeof(double);
 
     __amdgpu_buffer_rsrc_t rsrc;
@@ -518,10 +521,11 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
 // tile takes rho_l += (A_li / A_ll) d_i.  U is zero on and below the
 // diagonal, so lane l's rho stops changing once its own row is done and its
 // new value is formed once after the loop.  UNIT: A_ii = 1, no scaling.
-// Only the tile's rows, rounded up to 8, are stepped through; rows past S~
-// start at rho = 0, x = 0 and so never move.  The b~ of each tile is
-// gathered two tiles ahead (grid index one period, value the next), with
-// the loads issued at the end of a period, off the step chain.
+// Only the tile's rows, rounded up to 8, are stepped through (a tile with
+// few moving rows visits only those); rows past S~ start at rho = 0, x = 0,
+// and whatever they broadcast multiplies zero rows of U and C.  The b~ of
+// each tile is gathered two tiles ahead (grid index one period, value the
+// next), with the loads issued at the end of a period, off the step chain.
 // Exchange area of the cooperative sweeps (global memory, zeroed before
 // the launch), per bin f with R = kGsFlagStride flag words:
 //   flags[f R]       tiles the owner has published
