@@ -57,6 +57,7 @@ def _load():
         lib.orc_grid_point.argtypes = [P(_Geom), i, pd]
         lib.orc_steering.argtypes = [P(_Geom), d, i, pi, pd]
         lib.orc_das_map.argtypes = [P(_Geom), d, pd, pd]
+        lib.orc_csm.argtypes = [i, i, pd, pd]
         lib.orc_level.argtypes = [i, i, i, pi, pi]
         lib.orc_level.restype = i
         lib.orc_select.argtypes = [i, pd, i, d, i, pi, pd, pd]
@@ -123,6 +124,19 @@ def steering(geom: Geometry, freq: float, pts) -> np.ndarray:
     e = np.zeros((len(pts), geom.mic.shape[0], 2))
     _load().orc_steering(ctypes.byref(g), float(freq), len(pts), _pi(pts), _pd(e))
     return e[..., 0] + 1j * e[..., 1]
+
+
+def csm(snap: np.ndarray) -> np.ndarray:
+    """Eq. (1): the cross-spectral matrix averaged over snapshots.
+
+    snap: n_snap x M complex (one row per snapshot); returns M x M complex,
+    C[m, q] = mean_k snap[k, m] conj(snap[k, q])."""
+    snap = np.asarray(snap)
+    K, M = snap.shape
+    s = np.ascontiguousarray(np.stack([snap.real, snap.imag], axis=-1), dtype=np.float64)
+    out = np.zeros((M, M, 2))
+    _load().orc_csm(int(M), int(K), _pd(s), _pd(out))
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def das_map(geom: Geometry, freq: float, csm: np.ndarray) -> np.ndarray:

@@ -73,6 +73,28 @@ void orc_steering(const orc_geom *g, double freq, int n_pts, const int *pts,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Cross-spectral matrix, Eq. (1): C = (1/K) sum_k p_k p_k^H.              */
+
+void orc_csm(int M, int n_snap, const double *snap, double *csm)
+{
+    for (int m = 0; m < M; ++m)
+        for (int q = 0; q < M; ++q) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < n_snap; ++k) {
+                /* p_k[m] conj(p_k[q]) with p_k[m] = a + ib, p_k[q] = c + id */
+                const double a = snap[2 * ((long)k * M + m)];
+                const double b = snap[2 * ((long)k * M + m) + 1];
+                const double c = snap[2 * ((long)k * M + q)];
+                const double d = snap[2 * ((long)k * M + q) + 1];
+                re += a * c + b * d;
+                im += b * c - a * d;
+            }
+            csm[2 * ((long)m * M + q)] = re / n_snap;
+            csm[2 * ((long)m * M + q) + 1] = im / n_snap;
+        }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Delay-and-sum beamforming, Eq. (2): b(r) = v(r)^H C v(r) / M^2.        */
 
 void orc_das_map(const orc_geom *g, double freq, const double *csm, double *b)

@@ -50,6 +50,13 @@ void orc_grid_point(const orc_geom *g, int n, double r[3]);
 void orc_steering(const orc_geom *g, double freq, int n_pts, const int *pts,
                   double *e);
 
+/* Cross-spectral matrix, Eq. (1): the average over n_snap snapshots of
+ * p p^H, C[m][m'] = (1/n_snap) sum_k p_k[m] conj(p_k[m']).  snap is
+ * n_snap x M complex (snapshot k's M microphone spectra contiguous),
+ * interleaved; csm is M x M complex, row-major, interleaved.  Every entry is
+ * its own sum, so C is exactly Hermitian with a real diagonal. */
+void orc_csm(int M, int n_snap, const double *snap, double *csm);
+
 /* Delay-and-sum map, Eq. (2): b_n = Re(e_n^H C e_n) / M^2 for every grid
  * point.  csm is M x M complex, row-major, interleaved (re, im). */
 void orc_das_map(const orc_geom *g, double freq, const double *csm,
