@@ -44,6 +44,7 @@ if ROOT not in sys.path:
 METRIC = "DAMAS grid-point updates/s + p50/p99 solve latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_traffic.json")
 GS_SOURCE = os.path.join(ROOT, "paper_1608_05179_amd", "csrc", "gs.hip")
 
@@ -61,7 +62,7 @@ def _parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--workload", default=None,
                     choices=["compressed", "plain", "precision", "batched", "served",
-                             "copy"])
+                             "csm", "copy"])
     ap.add_argument("--refine", type=int, default=60,
                     help="FP32 refinement sweeps of the precision workload")
     ap.add_argument("--tune-sweeps", type=int, default=20,
@@ -304,6 +305,45 @@ def measure_served(n_pool=24, n_trace=40, rate=200.0, n_sustained=16, slots=4):
             "cache": {"hits": stats["cache_hits"], "misses": stats["cache_misses"]}}
 
 
+def measure_csm(steps=5, warmup=1):
+    """The cross-spectral-matrix step (Eq. (1)) at the batched workload's
+    shape: 256 bins x 2048 snapshots x 128 microphones, FP64."""
+    import torch
+
+    from paper_1608_05179_amd import damas as dm
+    nb, K, M = 256, 2048, 128
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(1608)
+    snap = torch.randn(nb, K, M, 2, dtype=torch.float64, device="cuda:0", generator=gen)
+    out = torch.empty(nb, M, M, dtype=torch.complex128, device="cuda:0")
+    for _ in range(warmup):
+        dm.csm(snap, out=out)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        dm.csm(snap, out=out)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)[steps // 2]
+    # Algorithmic work: the M (M + 1) / 2 entries of the Hermitian matrix,
+    # 8 real flops per complex multiply-add per snapshot.
+    flops = nb * K * (M * (M + 1) // 2) * 8
+    tf = flops / (ms * 1e-3) / 1e12
+    del snap, out
+    torch.cuda.empty_cache()
+    return {"workload": f"csm-fp64: {nb} bins x {K} snapshots x {M} mics, Eq. (1) on the "
+                        "FP64 matrix cores", "ms_per_step": round(ms, 4),
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2),
+                         "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                         "kernel": "csm_kernel", "kernel_avg_ms": round(ms, 4),
+                         "algorithmic_flops": flops,
+                         "input_GBs": round(nb * K * M * 16 / (ms * 1e-3) / 1e9, 1)}}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -327,6 +367,9 @@ def main():
         return
     if args.workload == "served":
         print(json.dumps(measure_served()), flush=True)
+        return
+    if args.workload == "csm":
+        print(json.dumps(measure_csm()), flush=True)
         return
     if args.workload is not None:
         rec, _, _, _ = measure(args.workload, args.steps, args.warmup, args.plain_steps,
@@ -385,6 +428,7 @@ def main():
             out["variants"][name] = v
             torch.cuda.empty_cache()
         out["variants"]["served"] = measure_served()
+        out["variants"]["csm"] = measure_csm()
     print(json.dumps(out), flush=True)
 
 

@@ -118,6 +118,20 @@ int32_t damas_coarse_count(int32_t N);
 
 /* ---- step-level calls (device pointers, enqueue on `stream`) --------- */
 
+/* The step before step 1, Eq. (1): the cross-spectral matrix of each bin
+ * as the average of p p^H over its snapshots,
+ *   csm[f][m][q] = (1/n_snap) sum_k p_{f,k}[m] conj(p_{f,k}[q]).
+ *   snap  device, n_bins x n_snap x M complex (snapshot k of bin f: its M
+ *         microphone spectra, contiguous), interleaved (re, im) doubles
+ *   csm   device, n_bins x M x M complex, row-major, interleaved (output)
+ * Products and sums in double precision on the FP64 matrix cores.  Each
+ * entry with m < q is written with its conjugate at (q, m) and the diagonal
+ * with a zero imaginary part, so csm is exactly Hermitian.
+ * DAMAS_EINVAL: M outside [1, 8192], n_snap < 1, n_bins < 0, or a NULL
+ * pointer with n_bins > 0.  n_bins = 0 enqueues nothing. */
+int damas_csm(int32_t M, int32_t n_snap, int32_t n_bins, const double *snap, double *csm,
+              void *stream);
+
 /* Step 1, Eq. dirty_map_1: b[f*S + n] = Re(e_n^H C_f e_n) / M^2 for every
  * bin f < n_bins and grid point n < S = N*N.
  *   freq  device, n_bins doubles (Hz, > 0)

@@ -210,6 +210,23 @@ extern "C" int32_t damas_gs_capacity(int32_t precision)
 // ---------------------------------------------------------------------------
 // step-level calls
 
+extern "C" int damas_csm(int32_t M, int32_t n_snap, int32_t n_bins, const double *snap,
+                         double *csm, void *stream)
+{
+    if (M < 1 || M > 8192)
+        return fail(DAMAS_EINVAL, "M = %d outside [1, 8192]", M);
+    if (n_snap < 1)
+        return fail(DAMAS_EINVAL, "n_snap = %d < 1", n_snap);
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    if (n_bins > 0 && (!snap || !csm))
+        return fail(DAMAS_EINVAL, "snap and csm must be non-NULL");
+    if ((int64_t)n_bins * csm_upper_blocks(M) > (int64_t)1 << 33)
+        return fail(DAMAS_EINVAL, "n_bins = %d too large for M = %d", n_bins, M);
+    HIP_TRY(launch_csm(M, n_snap, n_bins, snap, csm, (hipStream_t)stream), "csm launch");
+    return DAMAS_OK;
+}
+
 extern "C" int damas_das_map(const damas_geometry *g, int32_t n_bins,
                              const double *freq, const double *csm, double *b,
                              void *stream)

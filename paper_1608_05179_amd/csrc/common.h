@@ -76,6 +76,10 @@ __device__ inline double lane_bcast(double v, int src)
 // ---- launchers (each returns the launch status) ------------------------
 // fault: device word set non-zero by a kernel that met a capacity violation.
 
+hipError_t launch_csm(int M, int K, int n_bins, const double *snap, double *csm,
+                      hipStream_t s);
+int csm_upper_blocks(int M);
+
 hipError_t launch_das(const Geom &g, int n_bins, const double *freq,
                       const double *csm, double *b, hipStream_t s);
 

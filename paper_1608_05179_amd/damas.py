@@ -76,6 +76,7 @@ _sig("damas_coarse_count", c_i32, c_i32)
 _sig("damas_mp", c_i32, c_i32)
 _sig("damas_gs_capacity", c_i32, c_i32)
 _G = ctypes.POINTER(Geometry)
+_sig("damas_csm", ctypes.c_int, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp)
 _sig("damas_das_map", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_select", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_layout", ctypes.c_int, c_i32, c_vp, c_i32, c_i64, c_vp, c_vp)
@@ -218,6 +219,20 @@ def geometry(mic: torch.Tensor, N: int, x0: float, x1: float, y0: float,
 
 
 # ---- step-level calls ------------------------------------------------------
+
+def csm(snap, out=None, stream=None):
+    """Eq. (1): per bin the average of p p^H over its snapshots.
+    snap: complex128 (n_bins, n_snap, M) or float64 (n_bins, n_snap, M, 2);
+    returns complex128 (n_bins, M, M)."""
+    s = _as_interleaved(snap)
+    nb, K, M = s.shape[0], s.shape[1], s.shape[2]
+    if out is None:
+        out = torch.empty(nb, M, M, dtype=torch.complex128, device=s.device)
+    o = torch.view_as_real(out)
+    _check(_lib.damas_csm(M, K, nb, _ptr(s, torch.float64, "snap"),
+                          _ptr(o, torch.float64, "csm"), _stream(stream)))
+    return out
+
 
 def das_map(g: Geometry, freq, csm, b=None, stream=None):
     """b[f, n] = Re(e_n^H C_f e_n) / M^2 (float64, n_bins x N*N).

@@ -152,3 +152,17 @@ def test_query_footprint_closed_form(lib):
         dm.query_footprint(0, N, 1)
     with pytest.raises(dm.DamasError):
         dm.query_footprint(M, N, 1, precision=dm.PREC_BF16, refine_sweeps=11, iterations=10)
+
+
+def test_csm_rejects_invalid_arguments_on_the_host(lib):
+    f = lib.damas_csm
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    p = ctypes.c_void_p(16)  # never dereferenced: every call fails validation
+    assert f(0, 4, 1, p, p, None) == -1
+    assert f(8193, 4, 1, p, p, None) == -1
+    assert f(8, 0, 1, p, p, None) == -1
+    assert f(8, 4, -1, p, p, None) == -1
+    assert f(8, 4, 1, None, p, None) == -1
+    assert f(8, 4, 1, p, None, None) == -1
+    assert f(8, 4, 0, None, None, None) == 0  # nothing to do, nothing launched
