@@ -16,6 +16,7 @@ typedef double dacc4c __attribute__((ext_vector_type(4)));
 
 constexpr int kCsmBlock = 32;  // output block per wave (2 x 2 tiles of 16)
 constexpr int kCsmWaves = 4;   // waves per workgroup, each on its own block
+constexpr int kCsmDepth = 4;   // snapshot steps of 4 loaded ahead
 
 __device__ inline dacc4c mma_csm(double a, double b, dacc4c c)
 {
@@ -73,23 +74,30 @@ __global__ __launch_bounds__(64 * kCsmWaves) void csm_kernel(
             y[a] = kok && cok[a] ? row[cols[a]] : zero2;
         }
     };
-    // One snapshot step ahead in registers: the next step's loads are in
-    // flight during this step's MFMAs.
-    double2 x[2], y[2], xn[2], yn[2];
-    fetch(lk, x, y);
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        fetch(k0 + 4 + lk, xn, yn);
-        for (int a = 0; a < 2; ++a)
-            for (int c = 0; c < 2; ++c) {
-                // p[m] = x = a + ib (rows), p[q] = y = c + id (columns)
-                re[a][c] = mma_csm(x[a].x, y[c].x, re[a][c]);
-                re[a][c] = mma_csm(x[a].y, y[c].y, re[a][c]);
-                im[a][c] = mma_csm(x[a].y, y[c].x, im[a][c]);
-                im[a][c] = mma_csm(-x[a].x, y[c].y, im[a][c]);
-            }
-        for (int a = 0; a < 2; ++a) {
-            x[a] = xn[a];
-            y[a] = yn[a];
+    // kCsmDepth snapshot steps in flight: a ring of register sets, slot d
+    // holding step k0 + 4 d, refilled with step k0 + 4 d + 4 kCsmDepth once
+    // its MFMAs have read it.  A bin's blocks first touch each snapshot row
+    // together, from HBM, so one step ahead would not hide the latency.
+    // Steps past K load zeros and add nothing.
+    double2 x[kCsmDepth][2], y[kCsmDepth][2];
+#pragma unroll
+    for (int d = 0; d < kCsmDepth; ++d)
+        fetch(4 * d + lk, x[d], y[d]);
+    for (int k0 = 0; k0 < K; k0 += 4 * kCsmDepth) {
+#pragma unroll
+        for (int d = 0; d < kCsmDepth; ++d) {
+            // p[m] = x = a + ib (rows), p[q] = y = c + id (columns)
+            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < 2; ++c) {
+                    re[a][c] = mma_csm(x[d][a].x, y[d][c].x, re[a][c]);
+                    im[a][c] = mma_csm(x[d][a].y, y[d][c].x, im[a][c]);
+                }
+            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < 2; ++c) {
+                    re[a][c] = mma_csm(x[d][a].y, y[d][c].y, re[a][c]);
+                    im[a][c] = mma_csm(-x[d][a].x, y[d][c].y, im[a][c]);
+                }
+            fetch(k0 + 4 * (d + kCsmDepth) + lk, x[d], y[d]);
         }
     }
 
