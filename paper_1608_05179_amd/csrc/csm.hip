@@ -5,7 +5,7 @@
 // products over the snapshots, Re = sum (a c + b d) and Im = sum (b c - a d),
 // i.e. two real GEMMs of the M x K matrices of real and imaginary parts,
 // which run on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  A wave owns a
-// 32 x 32 block of the upper block triangle of one bin (2 x 2 MFMA tiles)
+// 16 x 16 block (one MFMA tile) of the upper block triangle of one bin
 // and writes each entry and its conjugate mirror, so C is exactly
 // Hermitian with a real diagonal.
 #include "common.h"
@@ -14,7 +14,8 @@ namespace damas {
 
 typedef double dacc4c __attribute__((ext_vector_type(4)));
 
-constexpr int kCsmBlock = 32;  // output block per wave (2 x 2 tiles of 16)
+constexpr int kCsmTiles = 1;   // MFMA tiles of 16 per block side
+constexpr int kCsmBlock = 16 * kCsmTiles; // output block per wave
 constexpr int kCsmWaves = 4;   // waves per workgroup, each on its own block
 constexpr int kCsmDepth = 4;   // snapshot steps of 4 loaded ahead
 
@@ -49,27 +50,27 @@ __global__ __launch_bounds__(64 * kCsmWaves) void csm_kernel(
 
     const double2 *P = snap + (int64_t)f * K * M;
     const int lr = lane & 15, lk = lane >> 4;
-    int rows[2], cols[2];
-    bool rok[2], cok[2];
-    for (int a = 0; a < 2; ++a) {
+    int rows[kCsmTiles], cols[kCsmTiles];
+    bool rok[kCsmTiles], cok[kCsmTiles];
+    for (int a = 0; a < kCsmTiles; ++a) {
         rows[a] = m0 + a * 16 + lr;
         cols[a] = q0 + a * 16 + lr;
         rok[a] = rows[a] < M;
         cok[a] = cols[a] < M;
     }
 
-    dacc4c re[2][2], im[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c) {
+    dacc4c re[kCsmTiles][kCsmTiles], im[kCsmTiles][kCsmTiles];
+    for (int a = 0; a < kCsmTiles; ++a)
+        for (int c = 0; c < kCsmTiles; ++c) {
             re[a][c] = dacc4c{0, 0, 0, 0};
             im[a][c] = dacc4c{0, 0, 0, 0};
         }
 
     const double2 zero2 = make_double2(0.0, 0.0);
-    auto fetch = [&](int k, double2 (&x)[2], double2 (&y)[2]) {
+    auto fetch = [&](int k, double2 (&x)[kCsmTiles], double2 (&y)[kCsmTiles]) {
         const bool kok = k < K;
         const double2 *row = P + (int64_t)(kok ? k : 0) * M;
-        for (int a = 0; a < 2; ++a) {
+        for (int a = 0; a < kCsmTiles; ++a) {
             x[a] = kok && rok[a] ? row[rows[a]] : zero2;
             y[a] = kok && cok[a] ? row[cols[a]] : zero2;
         }
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(64 * kCsmWaves) void csm_kernel(
     // its MFMAs have read it.  A bin's blocks first touch each snapshot row
     // together, from HBM, so one step ahead would not hide the latency.
     // Steps past K load zeros and add nothing.
-    double2 x[kCsmDepth][2], y[kCsmDepth][2];
+    double2 x[kCsmDepth][kCsmTiles], y[kCsmDepth][kCsmTiles];
 #pragma unroll
     for (int d = 0; d < kCsmDepth; ++d)
         fetch(4 * d + lk, x[d], y[d]);
@@ -87,13 +88,13 @@ __global__ __launch_bounds__(64 * kCsmWaves) void csm_kernel(
 #pragma unroll
         for (int d = 0; d < kCsmDepth; ++d) {
             // p[m] = x = a + ib (rows), p[q] = y = c + id (columns)
-            for (int a = 0; a < 2; ++a)
-                for (int c = 0; c < 2; ++c) {
+            for (int a = 0; a < kCsmTiles; ++a)
+                for (int c = 0; c < kCsmTiles; ++c) {
                     re[a][c] = mma_csm(x[d][a].x, y[d][c].x, re[a][c]);
                     im[a][c] = mma_csm(x[d][a].y, y[d][c].x, im[a][c]);
                 }
-            for (int a = 0; a < 2; ++a)
-                for (int c = 0; c < 2; ++c) {
+            for (int a = 0; a < kCsmTiles; ++a)
+                for (int c = 0; c < kCsmTiles; ++c) {
                     re[a][c] = mma_csm(x[d][a].y, y[d][c].y, re[a][c]);
                     im[a][c] = mma_csm(-x[d][a].x, y[d][c].y, im[a][c]);
                 }
@@ -105,8 +106,8 @@ __global__ __launch_bounds__(64 * kCsmWaves) void csm_kernel(
     // imaginary part is 0 exactly.
     double2 *C = csm + (int64_t)f * M * M;
     const double inv = 1.0 / (double)K;
-    for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c)
+    for (int a = 0; a < kCsmTiles; ++a)
+        for (int c = 0; c < kCsmTiles; ++c)
             for (int v = 0; v < 4; ++v) {
                 const int m = m0 + a * 16 + lk + 4 * v;
                 const int q = q0 + c * 16 + lr;
