@@ -17,7 +17,7 @@ typedef double dacc4c __attribute__((ext_vector_type(4)));
 constexpr int kCsmTiles = 1;   // MFMA tiles of 16 per block side
 constexpr int kCsmBlock = 16 * kCsmTiles; // output block per wave
 constexpr int kCsmWaves = 4;   // waves per workgroup, each on its own block
-constexpr int kCsmDepth = 4;   // snapshot steps of 4 loaded ahead
+constexpr int kCsmDepth = 8;   // snapshot steps of 4 loaded ahead
 
 __device__ inline dacc4c mma_csm(double a, double b, dacc4c c)
 {
