@@ -242,6 +242,30 @@ def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False,
                            "write_frac_of_hbm": round(wbytes / (psf_ms * 1e-3) / 1e9
                                                       / HBM_PEAK_GBS, 4)}
         del A16, E16
+    elif psf_kernel_time:
+        # The PSF kernel of a float or double A alone (f64 MFMA on the
+        # steering rows), on the same kept sets, timed on its stream.
+        mk = int(s_tilde.max())
+        E = dm.steer(g, freq, idx, st, mk)
+        off = dm.layout(st, mk)
+        Ap = dm.psf(w.M, st, mk, prec, E, off)
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dm.psf(w.M, st, mk, prec, E, off, A=Ap)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        psf_ms = e0.elapsed_time(e1) / reps
+        ent = int(sum(v * (v + 1) // 2 for v in s_tilde))   # distinct entries
+        flops = ent * 8 * w.M                                # 8M flops per entry
+        tf = flops / (psf_ms * 1e-3) / 1e12
+        rec["psf_f64_mfma"] = {"bound": "mfma", "achieved": round(tf, 2),
+                               "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                               "kernel": f"psf_kernel (A {a_kind})",
+                               "kernel_avg_ms": round(psf_ms, 4), "algorithmic_flops": flops}
+        del Ap, E
     ctx.close()
     return rec, w, x, st
 
@@ -378,7 +402,8 @@ def main():
         print(json.dumps(rec), flush=True)
         return
 
-    rec, w, x, st = measure("compressed", args.steps, args.warmup, args.plain_steps)
+    rec, w, x, st = measure("compressed", args.steps, args.warmup, args.plain_steps,
+                            psf_kernel_time=True)
     rec["roofline"]["traffic"] = _traffic()
     out = {
         "metric": METRIC, "value": rec["value"], "unit": rec["unit"],
@@ -394,6 +419,8 @@ def main():
     }
     if "plain" in rec:
         out["plain"] = rec["plain"]
+    if "psf_f64_mfma" in rec:
+        out["psf_f64_mfma"] = rec["psf_f64_mfma"]
 
     # ---- CPU baseline: the oracle on a bounded sample of bins ------------
     if not args.no_cpu:
