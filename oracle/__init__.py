@@ -28,6 +28,9 @@ SEL_KEEP_ALL = 0
 SEL_EPS_REL = 1
 SEL_KEEP_COUNT = 2
 
+PRED_HAAR = 0
+PRED_LINEAR = 1
+
 CFLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
           "-fPIC", "-shared", "-Wall", "-Wextra"]
 
@@ -62,6 +65,8 @@ def _load():
         lib.orc_level.restype = i
         lib.orc_select.argtypes = [i, pd, i, d, i, pi, pd, pd]
         lib.orc_select.restype = i
+        lib.orc_select_pred.argtypes = [i, pd, i, d, i, i, pi, pd, pd]
+        lib.orc_select_pred.restype = i
         lib.orc_psf.argtypes = [i, i, pd, pd]
         lib.orc_gs.argtypes = [i, pd, pd, i, pd]
         lib.orc_solve_bin.argtypes = [P(_Geom), d, pd, i, d, i, i, pd, pd, pi,
@@ -158,8 +163,9 @@ def level(N: int, ix: int, iy: int):
 
 
 def select(N: int, b: np.ndarray, mode: int, eps: float = 0.0,
-           keep_count: int = 0):
-    """Algorithm 1 (wavelet compression computational grid).
+           keep_count: int = 0, predictor: int = PRED_HAAR):
+    """Algorithm 1 (wavelet compression computational grid), with the
+    order-0 (HAAR) or the linear interpolating (LINEAR) predictor.
 
     Returns (idx int32 ascending, detail |d| per point, margin)."""
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -167,9 +173,9 @@ def select(N: int, b: np.ndarray, mode: int, eps: float = 0.0,
     idx = np.zeros(N * N, dtype=np.int32)
     det = np.zeros(N * N)
     mg = ctypes.c_double()
-    st = _load().orc_select(int(N), _pd(b), int(mode), float(eps),
-                            int(keep_count), _pi(idx), _pd(det),
-                            ctypes.byref(mg))
+    st = _load().orc_select_pred(int(N), _pd(b), int(mode), float(eps),
+                                 int(keep_count), int(predictor), _pi(idx), _pd(det),
+                                 ctypes.byref(mg))
     return idx[:st].copy(), det, mg.value
 
 

@@ -191,8 +191,33 @@ static int cand_cmp(const void *a, const void *b)
     return (x->n > y->n) - (x->n < y->n);
 }
 
+/* Linear interpolating prediction of a point of level l >= 1 from
+ * G^(l-1): with h the spacing of G^l, the mean of its two neighbours at
+ * distance h along its one odd axis, or of its four diagonal neighbours when
+ * both axes are odd (bilinear interpolation on the coarser grid).  A
+ * neighbour past the last grid line is replaced by its mirror on the other
+ * side. */
+static double linear_prediction(int N, const double *b, int ix, int iy, int level)
+{
+    int h = 1 << (finest_level(N) - level);
+    int ox = ix % (2 * h) != 0, oy = iy % (2 * h) != 0;
+    int xl = ix - h, xr = ix + h <= N - 1 ? ix + h : ix - h;
+    int yl = iy - h, yr = iy + h <= N - 1 ? iy + h : iy - h;
+    if (ox && !oy)
+        return 0.5 * (b[iy * N + xl] + b[iy * N + xr]);
+    if (oy && !ox)
+        return 0.5 * (b[yl * N + ix] + b[yr * N + ix]);
+    return 0.25 * ((b[yl * N + xl] + b[yl * N + xr]) + (b[yr * N + xl] + b[yr * N + xr]));
+}
+
 int orc_select(int N, const double *b, int mode, double eps, int keep_count,
                int *idx, double *detail, double *margin)
+{
+    return orc_select_pred(N, b, mode, eps, keep_count, ORC_PRED_HAAR, idx, detail, margin);
+}
+
+int orc_select_pred(int N, const double *b, int mode, double eps, int keep_count,
+                    int predictor, int *idx, double *detail, double *margin)
 {
     int S = N * N;
     unsigned char *keep = (unsigned char *)calloc((size_t)S, 1);
@@ -206,7 +231,12 @@ int orc_select(int N, const double *b, int mode, double eps, int keep_count,
     for (int p = 0; p < S; ++p) {
         int ix = p % N, iy = p / N, px, py;
         lvl[p] = orc_level(N, ix, iy, &px, &py);
-        d[p] = lvl[p] == 0 ? 0.0 : fabs(b[p] - b[py * N + px]);
+        if (lvl[p] == 0)
+            d[p] = 0.0;
+        else if (predictor == ORC_PRED_LINEAR)
+            d[p] = fabs(b[p] - linear_prediction(N, b, ix, iy, lvl[p]));
+        else
+            d[p] = fabs(b[p] - b[py * N + px]);
         if (lvl[p] == 0)
             keep[p] = 1; /* G^0 is always part of the compressed grid */
     }

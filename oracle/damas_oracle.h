@@ -76,6 +76,15 @@ int orc_level(int N, int ix, int iy, int *parent_ix, int *parent_iy);
 int orc_select(int N, const double *b, int mode, double eps, int keep_count,
                int *idx, double *detail, double *margin);
 
+/* Predictors of a point from the next-coarser grid G^(l-1) (Algorithm 1's
+ * interpolating wavelet): ORC_PRED_HAAR, the ancestor at the lower-left
+ * corner (order 0, what orc_select uses); ORC_PRED_LINEAR, the mean of the
+ * two (one odd axis) or four (both odd) neighbours at the point's own
+ * spacing, a neighbour past the last grid line replaced by its mirror. */
+enum { ORC_PRED_HAAR = 0, ORC_PRED_LINEAR = 1 };
+int orc_select_pred(int N, const double *b, int mode, double eps, int keep_count,
+                    int predictor, int *idx, double *detail, double *margin);
+
 /* Point-spread matrix over St points, A_ij = |e_i^H e_j|^2 / M^2 (section
  * "DAMAS", PSF definition), from their steering vectors e (St x M complex,
  * interleaved).  A is St x St row-major.  Entries with j >= i are computed
