@@ -64,6 +64,16 @@ extern "C" {
                                   largest |d| (ties: lower grid index first)
                                   up to keep_count points in total          */
 
+/* ---- predictors of Algorithm 1's interpolating wavelet ------------- */
+#define DAMAS_PRED_HAAR 0   /* order 0: the lower-left neighbour on G^j     */
+#define DAMAS_PRED_LINEAR 1 /* linear: with h the point's own spacing, the
+                               mean of its two neighbours at distance h
+                               along its odd axis, or of its four diagonal
+                               neighbours when both axes are odd; a
+                               neighbour past the last grid line replaced by
+                               its mirror; 0.5 (a + b) and
+                               0.25 ((a + b) + (c + d)) in double           */
+
 /* ---- arithmetic of the compressed system ---------------------------- */
 #define DAMAS_PREC_FP64 0 /* A stored in double                          */
 #define DAMAS_PREC_FP32 1 /* A stored in float (half the bytes the sweeps
@@ -156,6 +166,14 @@ int damas_das_map(const damas_geometry *g, int32_t n_bins, const double *freq,
 int damas_select(int32_t N, int32_t n_bins, const double *b, int32_t mode,
                  double eps, const int32_t *keep_count, int32_t *idx,
                  int32_t *s_tilde, void *stream);
+
+/* damas_select with a choice of predictor (DAMAS_PRED_*; the detail is
+ * d = b(p) - prediction from G^j), the same arguments otherwise;
+ * DAMAS_EINVAL for an unknown predictor.  damas_select is this call with
+ * DAMAS_PRED_HAAR. */
+int damas_select_pred(int32_t N, int32_t n_bins, const double *b, int32_t mode,
+                      double eps, int32_t predictor, const int32_t *keep_count,
+                      int32_t *idx, int32_t *s_tilde, void *stream);
 
 /* Packed layout of the per-bin compressed systems: off[f] = sum over g < f
  * of damas_ld(s_tilde[g])^2, off[n_bins] = total elements.
@@ -330,6 +348,7 @@ struct damas_params {
                                   `iterations` sweeps run last, on the FP32
                                   copy of A (0 .. iterations); ignored
                                   otherwise                                 */
+    int32_t predictor;         /* DAMAS_PRED_* of Algorithm 1 (0 = HAAR)    */
 };
 
 /* Every step for every bin, device-resident, enqueued on `stream`.

@@ -243,13 +243,15 @@ extern "C" int damas_das_map(const damas_geometry *g, int32_t n_bins,
     return DAMAS_OK;
 }
 
-extern "C" int damas_select(int32_t N, int32_t n_bins, const double *b,
-                            int32_t mode, double eps,
-                            const int32_t *keep_count, int32_t *idx,
-                            int32_t *s_tilde, void *stream)
+extern "C" int damas_select_pred(int32_t N, int32_t n_bins, const double *b,
+                                 int32_t mode, double eps, int32_t predictor,
+                                 const int32_t *keep_count, int32_t *idx,
+                                 int32_t *s_tilde, void *stream)
 {
     if (N < 1 || N > 46340)
         return fail(DAMAS_EINVAL, "N = %d outside [1, 46340]", N);
+    if (predictor != DAMAS_PRED_HAAR && predictor != DAMAS_PRED_LINEAR)
+        return fail(DAMAS_EINVAL, "predictor = %d is not a DAMAS_PRED_* value", predictor);
     if (n_bins < 0)
         return fail(DAMAS_EINVAL, "n_bins < 0");
     int rc = check_mode(mode, eps);
@@ -259,10 +261,18 @@ extern "C" int damas_select(int32_t N, int32_t n_bins, const double *b,
         return fail(DAMAS_EINVAL, "b, idx and s_tilde must be non-NULL");
     if (n_bins > 0 && mode == DAMAS_SEL_KEEP_COUNT && !keep_count)
         return fail(DAMAS_EINVAL, "KEEP_COUNT needs keep_count");
-    HIP_TRY(launch_select(N, n_bins, b, mode, eps, keep_count, idx, s_tilde,
+    HIP_TRY(launch_select(N, n_bins, b, mode, eps, predictor, keep_count, idx, s_tilde,
                           (hipStream_t)stream),
             "select launch");
     return DAMAS_OK;
+}
+
+extern "C" int damas_select(int32_t N, int32_t n_bins, const double *b, int32_t mode,
+                            double eps, const int32_t *keep_count, int32_t *idx,
+                            int32_t *s_tilde, void *stream)
+{
+    return damas_select_pred(N, n_bins, b, mode, eps, DAMAS_PRED_HAAR, keep_count, idx,
+                             s_tilde, stream);
 }
 
 extern "C" int damas_layout(int32_t n_bins, int32_t *s_tilde, int32_t max_kept,
@@ -615,6 +625,8 @@ int make_plan(int32_t M, int32_t N, int32_t n_bins, const damas_params *p, Solve
         return fail(DAMAS_EINVAL, "params are NULL");
     if ((rc = check_mode(p->select_mode, p->eps)) || (rc = check_precision(p->precision)))
         return rc;
+    if (p->predictor != DAMAS_PRED_HAAR && p->predictor != DAMAS_PRED_LINEAR)
+        return fail(DAMAS_EINVAL, "predictor = %d is not a DAMAS_PRED_* value", p->predictor);
     if (n_bins < 0 || p->iterations < 0)
         return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
     P.bf16 = p->precision == DAMAS_PREC_BF16;
@@ -1042,7 +1054,8 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
 
     if (P.batched) {
         HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s), "das launch");
-        HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, P.kc, P.ix, P.st, s),
+        HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, p->predictor, P.kc, P.ix,
+                              P.st, s),
                 "select launch");
         return enqueue_system_and_sweeps(ctx, P, n_bins, P.max_kept, freq, P.bm, P.ix, P.st,
                                          x_init, x_map, s);
@@ -1057,7 +1070,7 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
         char *xm = (char *)x_map + P.xs * fS;
         HIP_TRY(launch_das(P.kg, 1, freq + f, csm + (size_t)f * M * M * 2, P.bm + fS, s),
                 "das launch");
-        HIP_TRY(launch_select(P.N, 1, P.bm + fS, p->select_mode, p->eps,
+        HIP_TRY(launch_select(P.N, 1, P.bm + fS, p->select_mode, p->eps, p->predictor,
                               P.kc ? P.kc + f : nullptr, P.ix + fS, P.st + f, s),
                 "select launch");
         if ((rc = enqueue_system_and_sweeps(ctx, P, 1, mk, freq + f, P.bm + fS, P.ix + fS,
@@ -1175,7 +1188,8 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
     if ((rc = prepare(ctx, P, nullptr, nullptr, s_tilde, s)))
         return rc;
     HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s), "das launch");
-    HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, P.kc, P.ix, P.st, s),
+    HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, p->predictor, P.kc, P.ix,
+                              P.st, s),
             "select launch");
     if (!cache)
         return enqueue_system_and_sweeps(ctx, P, n_bins, P.max_kept, freq, P.bm, P.ix, P.st,

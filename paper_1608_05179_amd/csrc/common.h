@@ -84,7 +84,7 @@ hipError_t launch_das(const Geom &g, int n_bins, const double *freq,
                       const double *csm, double *b, hipStream_t s);
 
 hipError_t launch_select(int N, int n_bins, const double *b, int mode,
-                         double eps, const int32_t *keep_count, int32_t *idx,
+                         double eps, int predictor, const int32_t *keep_count, int32_t *idx,
                          int32_t *s_tilde, hipStream_t s);
 
 hipError_t launch_layout(int n_bins, int32_t *s_tilde, int max_kept,

@@ -1,10 +1,15 @@
 // Wavelet-compressed computational grid (Algorithm 1) and the packed layout
 // of the per-bin compressed systems.
 //
-// Algorithm 1 with the order-0 interpolating predictor: on an N x N grid,
+// Algorithm 1 with an interpolating predictor: on an N x N grid,
 // J = floor(log2 N) and G^j = {points whose two indices are multiples of
-// 2^(J-j)}.  A point first appearing on level j+1 >= 1 is predicted by its
-// lower-left neighbour on G^j; its wavelet detail is d = b(p) - b(parent).
+// 2^(J-j)}.  A point first appearing on level j+1 >= 1 is predicted from
+// G^j and its wavelet detail is d = b(p) - prediction.  Order 0 (HAAR): the
+// lower-left neighbour on G^j.  LINEAR: with h the point's own spacing, the
+// mean of its two neighbours at distance h along its odd axis, or of its
+// four diagonal neighbours when both axes are odd (bilinear interpolation
+// on G^j), a neighbour past the last grid line replaced by its mirror; the
+// sums are formed in the order written below, in double.
 // G^0 is always kept.  The union over levels is written in ascending grid
 // order.
 //
@@ -50,14 +55,30 @@ __device__ inline int point_level(int N, int J, int p, int *parent)
 // |d(p)| as an order-preserving 64-bit key (0 for level-0 points, which are
 // flagged through *coarse).
 __device__ inline unsigned long long detail_key(const double *bb, int N, int J,
-                                                int p, bool *coarse)
+                                                int predictor, int p, bool *coarse)
 {
     int q;
     int lv = point_level(N, J, p, &q);
     *coarse = lv == 0;
     if (lv == 0)
         return 0ull;
-    double d = fabs(bb[p] - bb[q]);
+    double pred;
+    if (predictor == DAMAS_PRED_LINEAR) {
+        const int ix = p % N, iy = p / N, h = 1 << (J - lv);
+        const bool ox = ix % (2 * h) != 0, oy = iy % (2 * h) != 0;
+        const int xl = ix - h, xr = ix + h <= N - 1 ? ix + h : ix - h;
+        const int yl = iy - h, yr = iy + h <= N - 1 ? iy + h : iy - h;
+        if (ox && !oy)
+            pred = 0.5 * (bb[iy * N + xl] + bb[iy * N + xr]);
+        else if (oy && !ox)
+            pred = 0.5 * (bb[yl * N + ix] + bb[yr * N + ix]);
+        else
+            pred = 0.25 * ((bb[yl * N + xl] + bb[yl * N + xr]) +
+                           (bb[yr * N + xl] + bb[yr * N + xr]));
+    } else {
+        pred = bb[q];
+    }
+    double d = fabs(bb[p] - pred);
     return __builtin_bit_cast(unsigned long long, d);
 }
 
@@ -84,7 +105,7 @@ __device__ inline int block_flag_scan(bool flag, int *scratch, int *total)
 }
 
 __global__ __launch_bounds__(kSelThreads) void select_kernel(
-    int N, const double *__restrict__ b, int mode, double eps,
+    int N, const double *__restrict__ b, int mode, double eps, int predictor,
     const int32_t *__restrict__ keep_count, int32_t *__restrict__ idx,
     int32_t *__restrict__ s_tilde)
 {
@@ -151,7 +172,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(
                     shift == 56 ? 0ull : (~0ull << (shift + 8));
                 for (int p = tid; p < S; p += kSelThreads) {
                     bool coarse;
-                    unsigned long long key = detail_key(bb, N, J, p, &coarse);
+                    unsigned long long key = detail_key(bb, N, J, predictor, p, &coarse);
                     if (!coarse && (key & hi_mask) == pre)
                         atomicAdd(&hist[(key >> shift) & 255u], 1u);
                 }
@@ -199,7 +220,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(
         bool keep = false, tie = false;
         if (p < S) {
             bool coarse;
-            unsigned long long key = detail_key(bb, N, J, p, &coarse);
+            unsigned long long key = detail_key(bb, N, J, predictor, p, &coarse);
             if (coarse || kind == 0) {
                 keep = true;
             } else if (kind == 1) {
@@ -283,13 +304,13 @@ __global__ __launch_bounds__(1024) void layout_kernel(
 }
 
 hipError_t launch_select(int N, int n_bins, const double *b, int mode,
-                         double eps, const int32_t *keep_count, int32_t *idx,
+                         double eps, int predictor, const int32_t *keep_count, int32_t *idx,
                          int32_t *s_tilde, hipStream_t s)
 {
     if (n_bins == 0)
         return hipSuccess;
     hipLaunchKernelGGL(select_kernel, dim3(n_bins), dim3(kSelThreads), 0, s, N,
-                       b, mode, eps, keep_count, idx, s_tilde);
+                       b, mode, eps, predictor, keep_count, idx, s_tilde);
     return hipGetLastError();
 }
 

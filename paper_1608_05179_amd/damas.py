@@ -28,6 +28,8 @@ ECAPACITY = -7
 SEL_KEEP_ALL = 0
 SEL_EPS_REL = 1
 SEL_KEEP_COUNT = 2
+PRED_HAAR = 0
+PRED_LINEAR = 1
 
 PREC_FP64 = 0
 PREC_FP32 = 1
@@ -59,7 +61,7 @@ class Params(ctypes.Structure):
     _fields_ = [("select_mode", c_i32), ("eps", c_dbl),
                 ("keep_count", ctypes.POINTER(c_i32)), ("keep_count_all", c_i32),
                 ("iterations", c_i32), ("precision", c_i32), ("batched", c_i32),
-                ("max_kept", c_i32), ("refine_sweeps", c_i32)]
+                ("max_kept", c_i32), ("refine_sweeps", c_i32), ("predictor", c_i32)]
 
 
 def _sig(name, res, *args):
@@ -79,6 +81,8 @@ _G = ctypes.POINTER(Geometry)
 _sig("damas_csm", ctypes.c_int, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp)
 _sig("damas_das_map", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_select", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp, c_vp)
+_sig("damas_select_pred", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_dbl, c_i32, c_vp, c_vp,
+     c_vp, c_vp)
 _sig("damas_layout", ctypes.c_int, c_i32, c_vp, c_i32, c_i64, c_vp, c_vp)
 _sig("damas_steer", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i64, c_vp)
 _sig("damas_psf", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp)
@@ -247,15 +251,18 @@ def das_map(g: Geometry, freq, csm, b=None, stream=None):
     return b
 
 
-def select(N: int, b, mode: int, eps: float = 0.0, keep_count=None, stream=None):
-    """Algorithm 1: returns (idx int32 (n_bins, N*N), s_tilde int32 (n_bins))."""
+def select(N: int, b, mode: int, eps: float = 0.0, keep_count=None, predictor=0,
+           stream=None):
+    """Algorithm 1 with predictor PRED_HAAR or PRED_LINEAR: returns
+    (idx int32 (n_bins, N*N), s_tilde int32 (n_bins))."""
     nb = b.shape[0]
     idx = torch.zeros(nb, N * N, dtype=torch.int32, device=b.device)
     st = torch.zeros(nb, dtype=torch.int32, device=b.device)
-    _check(_lib.damas_select(int(N), nb, _ptr(b, torch.float64, "b"), int(mode), float(eps),
-                             _ptr(keep_count, torch.int32, "keep_count"),
-                             _ptr(idx, torch.int32, "idx"), _ptr(st, torch.int32, "s_tilde"),
-                             _stream(stream)))
+    _check(_lib.damas_select_pred(int(N), nb, _ptr(b, torch.float64, "b"), int(mode),
+                                  float(eps), int(predictor),
+                                  _ptr(keep_count, torch.int32, "keep_count"),
+                                  _ptr(idx, torch.int32, "idx"),
+                                  _ptr(st, torch.int32, "s_tilde"), _stream(stream)))
     return idx, st
 
 
@@ -397,7 +404,7 @@ class Context:
     def solve(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
               keep_count=None, iterations=1000, precision=PREC_FP32, batched=True,
               max_kept=0, refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
-              s_tilde=None, stream=None):
+              s_tilde=None, predictor=0, stream=None):
         """Every step for every bin on the device; returns x_map.
 
         keep_count: an int, or a sequence of per-bin ints (host values)."""
@@ -407,7 +414,7 @@ class Context:
         if x_map is None:
             x_map = torch.empty(nb, S, dtype=_XTYPE[precision], device=freq.device)
         p, kc_arr = _params(nb, select_mode, eps, keep_count, iterations, precision, batched,
-                            max_kept, refine_sweeps)
+                            max_kept, refine_sweeps, predictor)
         dt = _XTYPE[precision]
         _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
                                     _ptr(freq, torch.float64, "freq"),
@@ -488,7 +495,7 @@ class Graph:
 
 
 def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, max_kept,
-            refine_sweeps):
+            refine_sweeps, predictor=0):
     """Params struct and the ctypes array that keeps per-bin counts alive."""
     kc_arr = None
     kc_all = 0
@@ -503,7 +510,7 @@ def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, ma
     p = Params(int(select_mode), float(eps),
                ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
                int(kc_all), int(iterations), int(precision), 1 if batched else 0,
-               int(max_kept), int(refine_sweeps))
+               int(max_kept), int(refine_sweeps), int(predictor))
     return p, kc_arr
 
 

@@ -166,3 +166,14 @@ def test_csm_rejects_invalid_arguments_on_the_host(lib):
     assert f(8, 4, 1, None, p, None) == -1
     assert f(8, 4, 1, p, None, None) == -1
     assert f(8, 4, 0, None, None, None) == 0  # nothing to do, nothing launched
+
+
+def test_select_pred_rejects_unknown_predictor(lib):
+    f = lib.damas_select_pred
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                  ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    p = ctypes.c_void_p(16)  # never dereferenced: the call fails validation
+    assert f(9, 1, p, 1, 0.1, 2, None, p, p, None) == -1
+    assert f(9, 1, p, 1, 0.1, -1, None, p, p, None) == -1
+    assert f(9, 0, None, 1, 0.1, 1, None, None, None, None) == 0
