@@ -369,6 +369,17 @@ int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
  * capacity failure (DAMAS_ECAPACITY) or a HIP error. */
 int damas_check(damas_ctx *ctx, void *stream);
 
+/* damas_solve_dev on HOST memory, synchronously: every pointer, g->mic
+ * included, is host memory of the sizes damas_solve_dev states.  The call
+ * allocates device staging buffers on the context's device, copies the
+ * inputs over, runs the solve on the null stream, waits for it (reporting
+ * any fault damas_check would) and copies x_map and the non-NULL b_map,
+ * idx and s_tilde back; outputs are not written when it fails.  The
+ * PCIe copies are part of its time. */
+int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins, const double *freq,
+                const double *csm, const damas_params *p, const void *x_init, void *x_map,
+                double *b_map, int32_t *idx, int32_t *s_tilde);
+
 /* Autotuner of the cooperative sweep schedule: times trial solves of this
  * problem (batched, trial_sweeps sweeps each, into a scratch map; for BF16
  * all sweeps on the bf16 system) for one workgroup per bin and for a grid

@@ -1080,6 +1080,75 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
     return DAMAS_OK;
 }
 
+// Host-pointer form of damas_solve_dev: the inputs are staged on the
+// context's device, the solve runs on the null stream, and the outputs are
+// copied back once damas_check has reported on it.
+extern "C" int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
+                           const double *freq, const double *csm, const damas_params *p,
+                           const void *x_init, void *x_map, double *b_map, int32_t *idx,
+                           int32_t *s_tilde)
+{
+    if (!ctx || !g || !p)
+        return fail(DAMAS_EINVAL, "ctx, g and p must be non-NULL");
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    int rc = check_precision(p->precision);
+    if (rc)
+        return rc;
+    if (n_bins > 0 && (!freq || !csm || !x_map || !g->mic))
+        return fail(DAMAS_EINVAL, "freq, csm, x_map and g->mic must be non-NULL");
+    if (n_bins == 0)
+        return DAMAS_OK;
+    if (g->M < 1 || g->N < 1 || g->N > 46340)
+        return fail(DAMAS_EINVAL, "M = %d or N = %d out of range", g->M, g->N);
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t nb = (size_t)n_bins, M = (size_t)g->M, S = (size_t)g->N * (size_t)g->N;
+    const size_t xs = x_size(p->precision);
+    struct Buf {
+        void *p = nullptr;
+        ~Buf() { if (p) (void)hipFree(p); }
+    } dmic, dfreq, dcsm, dxi, dx, db, didx, dst;
+    auto alloc = [](Buf &b, size_t n) { return hipMalloc(&b.p, n ? n : 1); };
+    HIP_TRY(alloc(dmic, M * 3 * sizeof(double)), "hipMalloc");
+    HIP_TRY(alloc(dfreq, nb * sizeof(double)), "hipMalloc");
+    HIP_TRY(alloc(dcsm, nb * M * M * 2 * sizeof(double)), "hipMalloc");
+    HIP_TRY(alloc(dx, nb * S * xs), "hipMalloc");
+    if (x_init)
+        HIP_TRY(alloc(dxi, nb * S * xs), "hipMalloc");
+    if (b_map)
+        HIP_TRY(alloc(db, nb * S * sizeof(double)), "hipMalloc");
+    if (idx)
+        HIP_TRY(alloc(didx, nb * S * sizeof(int32_t)), "hipMalloc");
+    if (s_tilde)
+        HIP_TRY(alloc(dst, nb * sizeof(int32_t)), "hipMalloc");
+    HIP_TRY(hipMemcpy(dmic.p, g->mic, M * 3 * sizeof(double), hipMemcpyHostToDevice), "copy");
+    HIP_TRY(hipMemcpy(dfreq.p, freq, nb * sizeof(double), hipMemcpyHostToDevice), "copy");
+    HIP_TRY(hipMemcpy(dcsm.p, csm, nb * M * M * 2 * sizeof(double), hipMemcpyHostToDevice),
+            "copy");
+    if (x_init)
+        HIP_TRY(hipMemcpy(dxi.p, x_init, nb * S * xs, hipMemcpyHostToDevice), "copy");
+    // idx entries past s_tilde are left as the caller had them
+    if (idx)
+        HIP_TRY(hipMemcpy(didx.p, idx, nb * S * sizeof(int32_t), hipMemcpyHostToDevice), "copy");
+    damas_geometry gd = *g;
+    gd.mic = (const double *)dmic.p;
+    rc = damas_solve_dev(ctx, &gd, n_bins, (const double *)dfreq.p, (const double *)dcsm.p, p,
+                         dxi.p, dx.p, (double *)db.p, (int32_t *)didx.p, (int32_t *)dst.p,
+                         nullptr);
+    if (rc)
+        return rc;
+    if ((rc = damas_check(ctx, nullptr)))
+        return rc;
+    HIP_TRY(hipMemcpy(x_map, dx.p, nb * S * xs, hipMemcpyDeviceToHost), "copy");
+    if (b_map)
+        HIP_TRY(hipMemcpy(b_map, db.p, nb * S * sizeof(double), hipMemcpyDeviceToHost), "copy");
+    if (idx)
+        HIP_TRY(hipMemcpy(idx, didx.p, nb * S * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+    if (s_tilde)
+        HIP_TRY(hipMemcpy(s_tilde, dst.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+    return DAMAS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // internal: context bytes, trimming, cache, cached solve
 

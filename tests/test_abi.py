@@ -177,3 +177,10 @@ def test_select_pred_rejects_unknown_predictor(lib):
     assert f(9, 1, p, 1, 0.1, 2, None, p, p, None) == -1
     assert f(9, 1, p, 1, 0.1, -1, None, p, p, None) == -1
     assert f(9, 0, None, 1, 0.1, 1, None, None, None, None) == 0
+
+
+def test_host_solve_validates_on_the_host(lib):
+    f = lib.damas_solve
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 8
+    p = ctypes.c_void_p(16)  # never dereferenced: the call fails validation
+    assert f(None, p, 1, p, p, p, None, p, None, None, None) == -1

@@ -124,3 +124,36 @@ def test_bench_workload_sampled(orc, dm, dev):
     r = _run(dm, dev, w, dm.SEL_KEEP_COUNT, K=w.keep_count)
     assert (r["st"] == w.keep_count).all()
     _compare(orc, w, r, orc.SEL_KEEP_COUNT, K=w.keep_count, bins=[0, 21, 42, 63])
+
+
+def test_host_pointer_solve_equals_device_solve(dm, dev):
+    # damas_solve on host arrays (staged, solved, copied back) gives the
+    # device solve's maps bitwise.
+    import ctypes
+    import torch
+    w = synth.compressed_fp32(n_bins=3, N=33, iterations=80)
+    K = w.keep_count
+    r = _run(dm, dev, w, dm.SEL_KEEP_COUNT, K=K)
+    mic = np.ascontiguousarray(w.mic, dtype=np.float64)
+    g = dm.Geometry(w.M, mic.ctypes.data, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    freq = np.ascontiguousarray(w.freqs, dtype=np.float64)
+    csm = np.ascontiguousarray(np.stack([w.csm.real, w.csm.imag], axis=-1))
+    p, _kc = dm._params(w.n_bins, dm.SEL_KEEP_COUNT, 0.0, K, w.iterations, dm.PREC_FP32,
+                        True, 0, 0)
+    x = np.zeros((w.n_bins, w.S), np.float32)
+    b = np.zeros((w.n_bins, w.S))
+    idx = np.zeros((w.n_bins, w.S), np.int32)
+    st = np.zeros(w.n_bins, np.int32)
+    f = dm._lib.damas_solve
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.POINTER(dm.Geometry), ctypes.c_int32] + \
+        [ctypes.c_void_p] * 2 + [ctypes.POINTER(dm.Params)] + [ctypes.c_void_p] * 5
+    ctx = dm.Context(0)
+    rc = f(ctx._h, ctypes.byref(g), w.n_bins, freq.ctypes.data, csm.ctypes.data,
+           ctypes.byref(p), None, x.ctypes.data, b.ctypes.data, idx.ctypes.data,
+           st.ctypes.data)
+    ctx.close()
+    assert rc == 0, dm.last_error()
+    assert np.array_equal(st, r["st"]) and np.array_equal(idx, r["idx"])
+    assert np.array_equal(b, r["b"])
+    assert np.array_equal(x.astype(np.float64), r["x"])
