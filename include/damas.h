@@ -365,8 +365,12 @@ int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
                     double *b_map, int32_t *idx, int32_t *s_tilde,
                     void *stream);
 
-/* Synchronise with the context's last solve and report a device-side
- * capacity failure (DAMAS_ECAPACITY) or a HIP error. */
+/* Synchronise `stream` and report a device-side capacity failure
+ * (DAMAS_ECAPACITY) or a HIP error.  Every context has a fault word of its
+ * own that only its solves set; damas_check(ctx, ...) reads and clears that
+ * word, so a fault in one context (one request of the server) is never
+ * charged to, or cleared by, another.  damas_check(NULL, stream) reads and
+ * clears the device's word shared by the step-level calls. */
 int damas_check(damas_ctx *ctx, void *stream);
 
 /* damas_solve_dev on HOST memory, synchronously: every pointer, g->mic

@@ -45,8 +45,8 @@ int hip_fail(hipError_t e, const char *what)
             return hip_fail(e_, what);                                         \
     } while (0)
 
-// One zero-initialised fault word per device, for kernels that meet a
-// device-side capacity violation.
+// One zero-initialised fault word per device for the step-level calls,
+// which run without a context (a context's solves use its own word).
 std::mutex g_fault_mu;
 std::unordered_map<int, int *> g_fault;
 
@@ -476,11 +476,18 @@ extern "C" int damas_ctx_create(int32_t device, damas_ctx **out)
         return fail(DAMAS_ENOMEM, "context allocation");
     c->device = device;
     if (hipEventCreateWithFlags(&c->kc_done, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->coop_done, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->coop_done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&c->fault, sizeof(int)) != hipSuccess ||
+        hipMemset(c->fault, 0, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
         if (c->kc_done)
             (void)hipEventDestroy(c->kc_done);
+        if (c->coop_done)
+            (void)hipEventDestroy(c->coop_done);
+        if (c->fault)
+            (void)hipFree(c->fault);
         delete c;
-        return fail(DAMAS_EDEVICE, "hipEventCreate");
+        return fail(DAMAS_EDEVICE, "context set-up (events, fault word)");
     }
     *out = c;
     return DAMAS_OK;
@@ -504,6 +511,8 @@ extern "C" void damas_ctx_destroy(damas_ctx *ctx)
         (void)hipEventDestroy(ctx->kc_done);
     if (ctx->coop_done)
         (void)hipEventDestroy(ctx->coop_done);
+    if (ctx->fault)
+        (void)hipFree(ctx->fault);
     for (auto *v : {&ctx->phase_events[0], &ctx->phase_events[1], &ctx->event_pool})
         for (auto &e : *v) {
             (void)hipEventDestroy(e.first);
@@ -572,10 +581,13 @@ extern "C" int damas_check(damas_ctx *ctx, void *stream)
     if (ctx)
         HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
-    int *fault;
-    int rc = fault_word(&fault);
-    if (rc)
-        return rc;
+    // A context's own word, or the step-level calls' word of the device.
+    int *fault = ctx ? ctx->fault : nullptr;
+    if (!fault) {
+        int rc = fault_word(&fault);
+        if (rc)
+            return rc;
+    }
     int v = 0;
     HIP_TRY(hipMemcpy(&v, fault, sizeof v, hipMemcpyDeviceToHost), "read fault word");
     if (v) {
@@ -768,7 +780,8 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
         }
         P.kc = (const int32_t *)ctx->kc.p;
     }
-    return fault_word(&P.fault);
+    P.fault = ctx->fault;
+    return DAMAS_OK;
 }
 
 // Cooperative schedule of a batched solve, from the kept counts the host
@@ -1290,8 +1303,21 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
     for (int f = 0; f < n_bins; ++f)
         append(key, ix.data() + (size_t)f * P.S, (size_t)std::max(st[f], 0));
 
-    const size_t a_bytes = (P.need16 || !P.bf16) ? P.es * (size_t)P.a_elems : 0;
-    const size_t a32_bytes = (P.bf16 && P.refine > 0) ? sizeof(float) * (size_t)P.a_elems : 0;
+    // Bytes of the packed systems of exactly these kept counts (what the
+    // layout step will give them; part of the key, so every entry under a
+    // key has this size).  A bin over max_kept fails the solve: no caching.
+    int64_t packed = 0;
+    for (int32_t v : st) {
+        if (v < 0 || v > P.max_kept)
+            return enqueue_system_and_sweeps(ctx, P, n_bins, P.max_kept, freq, P.bm, P.ix, P.st,
+                                             nullptr, x_map, s);
+        packed += ld_of(v) * ld_of(v);
+    }
+    if (packed > P.a_elems)
+        return fail(DAMAS_EINVAL, "packed systems (%lld elements) exceed the arena (%lld)",
+                    (long long)packed, (long long)P.a_elems);
+    const size_t a_bytes = (P.need16 || !P.bf16) ? P.es * (size_t)packed : 0;
+    const size_t a32_bytes = (P.bf16 && P.refine > 0) ? sizeof(float) * (size_t)packed : 0;
     {
         std::lock_guard<std::mutex> lk(cache->mu);
         auto it = cache->map.find(key);
@@ -1302,6 +1328,8 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
             it->second.lru = cache->lru.begin();
             // The entry may have been filled on another stream.
             HIP_TRY(hipStreamWaitEvent(s, it->second.ready, 0), "hipStreamWaitEvent");
+            if (it->second.A.bytes < a_bytes || it->second.A32.bytes < a32_bytes)
+                return fail(DAMAS_EINVAL, "cached systems smaller than their key states");
             if (a_bytes)
                 HIP_TRY(hipMemcpyAsync(ctx->A.p, it->second.A.p, a_bytes,
                                        hipMemcpyDeviceToDevice, s),

@@ -56,6 +56,11 @@ int set_error(int code, const char *fmt, ...);
 
 struct damas_ctx {
     int device = 0;
+    // Device word the context's kernels set on a device-side capacity
+    // violation or a cooperative time-out; read and cleared by damas_check
+    // for this context only, so concurrent contexts never see each other's
+    // faults.
+    int *fault = nullptr;
     damas::Buffer b, idx, st, kc, off, E, A, E16, A32;
     // keep counts last uploaded to kc (skip identical re-uploads)
     std::vector<int32_t> kc_host;

@@ -112,3 +112,24 @@ def test_coop_packs_bins_onto_workgroups(orc, dm, dev, budget):
         offk = np.ones(w.S, bool)
         offk[idx[f, :st[f]]] = False
         assert (x[f, offk] == 0).all() and x[f, ~offk].max() > 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_coop_run_to_run_bitwise(dm, dev, prec):
+    # The cooperative kernel's sums are added in a fixed order (the owner's
+    # stream waves as a tree, then the helpers in rank order), so repeated
+    # solves give the same bits; a race in the owner-helper exchange (a sum
+    # read before it is published, an x tile read mid-update) would not.
+    if prec == "fp32":
+        w = synth.compressed_fp32(n_bins=4, N=61, iterations=120)
+        Ks = [2400, 700, 3600, 150]
+        args = (dm.SEL_KEEP_COUNT, Ks, dm.PREC_FP32, -1)
+        kw = {}
+    else:
+        w = synth.precision_bf16(n_bins=3, N=61, iterations=120)
+        args = (dm.SEL_KEEP_ALL, None, dm.PREC_BF16, -1)
+        kw = {"refine": 30}
+    runs = [_solve(dm, dev, w, *args, **kw)[0] for _ in range(3)]
+    assert np.isfinite(runs[0]).all() and runs[0].max() > 0
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])

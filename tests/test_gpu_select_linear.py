@@ -81,3 +81,29 @@ def test_solve_with_linear_predictor(orc, dm, dev):
         ref[kept] = orc.gs(A, b[kept], w.iterations)
         err = np.linalg.norm(x[f] - ref) / np.linalg.norm(ref)
         assert err <= 1e-4, (f, err)
+
+
+def test_select_linear_mirror_fixture(orc, dm, dev):
+    # The hand-derived spike fixture: the mirrored point (20, 0) has detail
+    # exactly 1.0, so eps = 1 keeps it (with the 4 coarse points) and
+    # eps = 0.75 keeps it alone of the fine points; a clamp reading keeps
+    # neither.
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "select_linear_mirror_N21.json")) as fh:
+        g = json.load(fh)
+    N = g["N"]
+    b = np.zeros(N * N)
+    b[g["spike"][1] * N + g["spike"][0]] = 1.0
+    b_d = torch.from_numpy(b[None]).to(dev)
+    coarse = [0, 16, 16 * N, 16 * N + 16]
+    for eps, want in ((1.0, sorted(coarse + [20])), (0.75, sorted(coarse + [20])),
+                      (0.5, None)):
+        idx, st = dm.select(N, b_d, dm.SEL_EPS_REL, eps=eps, predictor=dm.PRED_LINEAR)
+        got = idx[0, :int(st[0])].cpu().numpy()
+        ref, _, _ = orc.select(N, b, orc.SEL_EPS_REL, eps=eps, predictor=orc.PRED_LINEAR)
+        assert np.array_equal(got, ref), eps
+        if want is not None:
+            assert got.tolist() == want, (eps, got.tolist())

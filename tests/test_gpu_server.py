@@ -135,3 +135,61 @@ def test_server_poll_and_timeout(dm, dev):
     with pytest.raises(dm.DamasError):
         srv.poll(t)  # retired
     srv.close()
+
+
+def _submit_eps(srv, dm, w, eps, max_kept, iters):
+    return srv.submit(w.mic, w.N, (w.x0, w.x1, w.y0, w.y1), w.z0, w.freqs, w.csm,
+                      select_mode=dm.SEL_EPS_REL, eps=eps, max_kept=max_kept,
+                      iterations=iters, precision=dm.PREC_FP32)
+
+
+def _direct_eps(dm, dev, w, eps, max_kept, iters):
+    import torch
+    mic = _t(w.mic, torch.float64, dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    ctx = dm.Context(0)
+    x = ctx.solve(g, _t(w.freqs, torch.float64, dev), _t(w.csm, torch.complex128, dev),
+                  select_mode=dm.SEL_EPS_REL, eps=eps, max_kept=max_kept, iterations=iters,
+                  precision=dm.PREC_FP32)
+    ctx.check()
+    out = x.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def test_server_fault_is_charged_to_its_own_request(dm, dev):
+    # Two slots run at once: one request keeps more points than its
+    # max_kept (a device-side capacity fault of its own context), the other
+    # is a long ordinary solve.  Only the faulting request fails, and the
+    # slot that ran it serves the next request cleanly.
+    good, K, it = _requests()[1]
+    want = _direct(dm, dev, good, K, 600)
+    bad = synth.compressed_fp32(n_bins=2, N=21, iterations=50)
+    srv = dm.Server(hbm_budget=8 << 30, cache_budget=0, slots=2)
+    t_good = _submit(srv, dm, good, K, 600)
+    t_bad = _submit_eps(srv, dm, bad, 0.0, 50, 50)  # eps = 0 keeps all 441 points
+    with pytest.raises(dm.DamasError) as ei:
+        srv.wait(t_bad)
+    assert ei.value.code == dm.ECAPACITY
+    x, _, info = srv.wait(t_good)
+    assert info["status"] == 0 and np.array_equal(x, want)
+    w3, K3, it3 = _requests()[0]
+    want3 = _direct(dm, dev, w3, K3, it3)
+    x3, _, info3 = srv.wait(_submit(srv, dm, w3, K3, it3))
+    assert info3["status"] == 0 and np.array_equal(x3, want3)
+    srv.close()
+
+
+def test_server_cache_hit_under_eps_rel_with_a_larger_max_kept(dm, dev):
+    # The same scene under EPS_REL with two arena bounds: the second request
+    # hits the cache (same kept sets) and copies exactly the packed systems
+    # of those kept counts, whatever its max_kept sizes the arena to.
+    w = synth.compressed_fp32(n_bins=4, N=41, iterations=100)
+    srv = dm.Server(hbm_budget=8 << 30, cache_budget=1 << 30, slots=1)
+    x1, st1, i1 = srv.wait(_submit_eps(srv, dm, w, 0.05, 900, 100))
+    x2, st2, i2 = srv.wait(_submit_eps(srv, dm, w, 0.05, w.S, 100))
+    assert not i1["cache_hit"] and i2["cache_hit"]
+    assert np.array_equal(st1, st2) and st1.max() <= 900
+    assert np.array_equal(x1, x2)
+    assert np.array_equal(x2, _direct_eps(dm, dev, w, 0.05, w.S, 100))
+    srv.close()
