@@ -89,6 +89,29 @@ extern "C" {
                              the sweep state and row residuals stay
                              double, partial sums FP32 as above            */
 
+/* ---- per-bin precision policy of a whole-path solve ------------------ */
+#define DAMAS_POLICY_AUTO 0  /* per bin, the storage of A that keeps the
+                                iterate within about 1e-4 of the FP64
+                                iteration, chosen on the device from the
+                                bin's mean PSF row sum over its kept points,
+                                rho = (1/S~) sum_ij A_ij (about the kept
+                                points inside one main lobe):
+                                - DAMAS_PREC_FP32: a bin with rho > rho_wide
+                                  (and at most damas_wide_capacity() kept)
+                                  is "wide": A is held as float hi plus a
+                                  bf16 residual lo = bf16(A - hi), and its
+                                  sweeps form every residual from hi + lo in
+                                  double (A to about 2^-33);
+                                - DAMAS_PREC_BF16: a bin with rho > rho_f32
+                                  runs every sweep on the FP32 system (wide
+                                  above rho_wide as for FP32), the others
+                                  the bf16 bulk plus refine_sweeps FP32
+                                  sweeps;
+                                - DAMAS_PREC_FP64: no classes.            */
+#define DAMAS_POLICY_FIXED 1 /* every bin at `precision` as stated       */
+#define DAMAS_RHO_WIDE_DEFAULT 100.0
+#define DAMAS_RHO_F32_DEFAULT 12.0
+
 /* Scan geometry (section "Beamforming").  The struct itself is host memory;
  * `mic` is a DEVICE pointer to M x 3 doubles (metres, row-major, array in
  * the plane z = 0 centred on the origin). */
@@ -120,6 +143,11 @@ int64_t damas_ld(int32_t s_tilde);
  * refinement sweeps hold.  0 for an unknown precision.  Host only, no
  * device work. */
 int32_t damas_gs_capacity(int32_t precision);
+
+/* The largest kept count of a wide bin (DAMAS_POLICY_AUTO): the unknowns a
+ * sweep workgroup holds in LDS beside the wide (hi + lo) hand-over blocks.
+ * A bin above it stays narrow.  Host only. */
+int32_t damas_wide_capacity(void);
 
 /* Number of points on the coarsest grid G^0 of Algorithm 1 for an N x N
  * grid; every compressed grid keeps them, so KEEP_COUNT keeps
@@ -349,7 +377,21 @@ struct damas_params {
                                   copy of A (0 .. iterations); ignored
                                   otherwise                                 */
     int32_t predictor;         /* DAMAS_PRED_* of Algorithm 1 (0 = HAAR)    */
+    int32_t policy;            /* DAMAS_POLICY_* (0 = AUTO)                 */
+    double rho_wide;           /* AUTO: widening threshold (0: default)     */
+    double rho_f32;            /* AUTO, BF16: bf16 bulk only at rho <= this
+                                  (0: default)                              */
 };
+
+/* Storage class of each bin in the context's last batched solve under
+ * DAMAS_POLICY_AUTO (0: the solve's precision, 1: every sweep on the FP32
+ * system, 2: wide), copied to host `out` (n_bins bytes) after a device
+ * synchronisation.  DAMAS_EINVAL if the context holds no classes of that
+ * many bins. */
+#define DAMAS_CLASS_NARROW 0
+#define DAMAS_CLASS_FP32 1
+#define DAMAS_CLASS_WIDE 2
+int damas_ctx_classes(damas_ctx *ctx, int32_t n_bins, uint8_t *out);
 
 /* Every step for every bin, device-resident, enqueued on `stream`.
  *   freq, csm   device, as for damas_das_map

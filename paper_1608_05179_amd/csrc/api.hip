@@ -198,6 +198,8 @@ extern "C" int32_t damas_coarse_count(int32_t N) { return N < 1 ? 0 : coarse_cou
 
 extern "C" int32_t damas_mp(int32_t M) { return M < 1 ? 0 : mp_of(M); }
 
+extern "C" int32_t damas_wide_capacity(void) { return gs_wide_capacity(); }
+
 extern "C" int32_t damas_gs_capacity(int32_t precision)
 {
     if (precision != DAMAS_PREC_FP64 && precision != DAMAS_PREC_FP32 &&
@@ -500,7 +502,8 @@ extern "C" void damas_ctx_destroy(damas_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
-                      &ctx->E16, &ctx->A32, &ctx->coop_ws, &ctx->coop_tab})
+                      &ctx->E16, &ctx->A32, &ctx->Alo, &ctx->tsum, &ctx->cls, &ctx->coop_ws,
+                      &ctx->coop_tab})
         if (b->p)
             (void)hipFree(b->p);
     if (ctx->kc_pinned)
@@ -536,6 +539,20 @@ extern "C" int damas_ctx_last_workgroups(const damas_ctx *ctx, int32_t *workgrou
     if (!ctx || !workgroups)
         return fail(DAMAS_EINVAL, "NULL argument");
     *workgroups = ctx->last_workgroups;
+    return DAMAS_OK;
+}
+
+extern "C" int damas_ctx_classes(damas_ctx *ctx, int32_t n_bins, uint8_t *out)
+{
+    if (!ctx || !out || n_bins < 0)
+        return fail(DAMAS_EINVAL, "ctx and out must be non-NULL, n_bins >= 0");
+    if (n_bins == 0)
+        return DAMAS_OK;
+    if (!ctx->cls.p || ctx->cls.bytes < (size_t)n_bins)
+        return fail(DAMAS_EINVAL, "no classes of %d bins on this context", n_bins);
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    HIP_TRY(hipMemcpy(out, ctx->cls.p, (size_t)n_bins, hipMemcpyDeviceToHost), "read classes");
     return DAMAS_OK;
 }
 
@@ -617,6 +634,8 @@ struct SolvePlan {
     int32_t max_kept;
     std::vector<int32_t> st_host; // kept points per bin, where the host knows them
     int32_t bulk, refine;         // sweeps on the storage precision / FP32 copy
+    bool classes;                 // per-bin precision classes (DAMAS_POLICY_AUTO)
+    double rho_wide, rho_f32;     // their thresholds
     int64_t e_stride, e16_stride;
     int64_t a_elems;
     int nb_ws;                    // bins the workspace holds at once
@@ -641,6 +660,10 @@ int make_plan(int32_t M, int32_t N, int32_t n_bins, const damas_params *p, Solve
         return fail(DAMAS_EINVAL, "predictor = %d is not a DAMAS_PRED_* value", p->predictor);
     if (n_bins < 0 || p->iterations < 0)
         return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
+    if (p->policy != DAMAS_POLICY_AUTO && p->policy != DAMAS_POLICY_FIXED)
+        return fail(DAMAS_EINVAL, "policy = %d is not a DAMAS_POLICY_* value", p->policy);
+    if (!(p->rho_wide >= 0.0) || !(p->rho_f32 >= 0.0))
+        return fail(DAMAS_EINVAL, "rho_wide and rho_f32 must be >= 0 (0: defaults)");
     P.bf16 = p->precision == DAMAS_PREC_BF16;
     if (P.bf16 && (p->refine_sweeps < 0 || p->refine_sweeps > p->iterations))
         return fail(DAMAS_EINVAL, "refine_sweeps = %d outside [0, iterations = %d]",
@@ -688,7 +711,12 @@ int make_plan(int32_t M, int32_t N, int32_t n_bins, const damas_params *p, Solve
         P.a_elems = (int64_t)n_bins * ldm * ldm;
     }
     P.nb_ws = P.batched ? n_bins : 1;
-    P.need64 = !P.bf16 || P.refine > 0;
+    P.classes = p->policy == DAMAS_POLICY_AUTO && p->precision != DAMAS_PREC_FP64;
+    P.rho_wide = p->rho_wide > 0.0 ? p->rho_wide : DAMAS_RHO_WIDE_DEFAULT;
+    P.rho_f32 = p->rho_f32 > 0.0 ? p->rho_f32 : DAMAS_RHO_F32_DEFAULT;
+    // With classes a bf16 solve always builds the FP32 system: bins that
+    // skip the bf16 bulk run every sweep on it.
+    P.need64 = !P.bf16 || P.refine > 0 || P.classes;
     P.need16 = P.bf16 && P.bulk > 0;
     return DAMAS_OK;
 }
@@ -714,8 +742,11 @@ size_t plan_workspace_bytes(const SolvePlan &P, bool own_b, bool own_idx, bool o
         t += sizeof(uint16_t) * (size_t)P.e16_stride * P.nb_ws;
     if (P.need16 || !P.bf16)
         t += P.es * (size_t)P.a_elems;
-    if (P.bf16 && P.refine > 0)
+    if (P.bf16 && P.need64)
         t += sizeof(float) * (size_t)P.a_elems;
+    if (P.classes)
+        t += sizeof(uint16_t) * (size_t)P.a_elems +
+             sizeof(double) * (size_t)P.nb_ws * (size_t)psf_tiles(P.max_kept) + (size_t)P.nb_ws;
     return t;
 }
 
@@ -744,8 +775,15 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
     if ((P.need16 || !P.bf16) &&
         (rc = ensure(ctx, ctx->A, P.es * (size_t)P.a_elems, s, "A arena")))
         return rc;
-    if (P.bf16 && P.refine > 0 &&
+    if (P.bf16 && P.need64 &&
         (rc = ensure(ctx, ctx->A32, sizeof(float) * (size_t)P.a_elems, s, "FP32 A arena")))
+        return rc;
+    if (P.classes &&
+        ((rc = ensure(ctx, ctx->Alo, sizeof(uint16_t) * (size_t)P.a_elems, s, "lo arena")) ||
+         (rc = ensure(ctx, ctx->tsum,
+                      sizeof(double) * (size_t)P.nb_ws * (size_t)psf_tiles(P.max_kept), s,
+                      "tile sums")) ||
+         (rc = ensure(ctx, ctx->cls, (size_t)P.nb_ws, s, "bin classes"))))
         return rc;
     P.bm = b_map ? b_map : (double *)ctx->b.p;
     P.ix = idx ? idx : (int32_t *)ctx->idx.p;
@@ -809,9 +847,10 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
         return (double)((st + 63) / 64) * std::max(kFloor, rows);
     };
     const int nb = P.n_bins;
-    int cap = gs_coop_capacity(P.bf16 ? DAMAS_PREC_BF16 : P.p->precision, P.max_kept);
-    if (P.bf16 && P.refine > 0)
-        cap = std::min(cap, gs_coop_capacity(DAMAS_PREC_FP32, P.max_kept));
+    int cap = gs_coop_capacity(P.bf16 ? DAMAS_PREC_BF16 : P.p->precision, P.max_kept,
+                               P.classes && !P.bf16);
+    if (P.bf16 && P.need64)
+        cap = std::min(cap, gs_coop_capacity(DAMAS_PREC_FP32, P.max_kept, P.classes));
     const int G = ctx->coop_budget < 0 ? cap : std::min(ctx->coop_budget, cap);
     if (G < 1)
         return 0;
@@ -949,6 +988,19 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
             return rc;
         HIP_TRY(hipEventRecord(evb.first, s), "hipEventRecord");
     }
+    // Per-bin classes: chosen by the float PSF, read by the sweeps.
+    PsfClassArgs pc;
+    GsClassArgs gca;
+    if (P.classes) {
+        pc.lo = (uint16_t *)ctx->Alo.p;
+        pc.tsum = (double *)ctx->tsum.p;
+        pc.cls = (uint8_t *)ctx->cls.p;
+        pc.rho_wide = P.rho_wide;
+        pc.rho_f32 = bf16 ? P.rho_f32 : HUGE_VAL; // a float solve has no F32 class
+        pc.wide_cap = gs_wide_capacity();
+        gca.cls = pc.cls;
+        gca.lo = pc.lo;
+    }
     // Storage-precision system (bulk sweeps) and, for BF16, the FP32 copy.
     if (build && P.need64) {
         HIP_TRY(launch_steer(P.kg, nb, freq, ix, st, max_kept, (double *)ctx->E.p, P.e_stride,
@@ -956,7 +1008,7 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
                 "steer launch");
         HIP_TRY(launch_psf(P.M, nb, st, max_kept, bf16 ? DAMAS_PREC_FP32 : p->precision,
                            (const double *)ctx->E.p, P.e_stride, P.off,
-                           bf16 ? ctx->A32.p : ctx->A.p, P.fault, s),
+                           bf16 ? ctx->A32.p : ctx->A.p, P.fault, s, pc),
                 "psf launch");
     }
     if (build && P.need16) {
@@ -986,27 +1038,38 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
             return rc;
     }
     ctx->last_workgroups = n_wg > 0 ? n_wg : nb;
-    auto sweeps = [&](int prec, const void *Ap, int iters, const void *xi) -> hipError_t {
+    auto sweeps = [&](int prec, const void *Ap, int iters, const void *xi,
+                      const GsClassArgs &g) -> hipError_t {
         if (n_wg > 0)
             return launch_gs_coop(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi,
                                   x_map, P.fault, (const int32_t *)ctx->coop_tab.p, n_wg, gpw,
-                                  ctx->coop_ws.p, s);
+                                  ctx->coop_ws.p, g, s);
         return launch_gs(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi, x_map,
-                         P.fault, s);
+                         P.fault, s, g);
     };
     if (!bf16) {
-        HIP_TRY(sweeps(p->precision, ctx->A.p, p->iterations, x_init), "gs launch");
+        GsClassArgs g = gca;
+        g.iters_cls = p->iterations;
+        HIP_TRY(sweeps(p->precision, ctx->A.p, p->iterations, x_init, g), "gs launch");
     } else {
         // Bulk sweeps on bf16 A, then the refinement sweeps on the FP32
-        // copy, warm-started from the bulk result in place.
+        // copy, warm-started from the bulk result in place.  With classes,
+        // bins of class F32 or wide skip the bulk and run every sweep in
+        // the second launch.
         const void *xi = x_init;
-        if (P.bulk > 0 || P.refine == 0) {
-            HIP_TRY(sweeps(DAMAS_PREC_BF16, ctx->A.p, P.bulk, xi), "gs launch (bf16)");
+        if (P.bulk > 0 || (P.refine == 0 && !P.classes)) {
+            GsClassArgs g;
+            g.cls = gca.cls;
+            g.iters_cls = 0;
+            HIP_TRY(sweeps(DAMAS_PREC_BF16, ctx->A.p, P.bulk, xi, g), "gs launch (bf16)");
             xi = x_map;
         }
-        if (P.refine > 0)
-            HIP_TRY(sweeps(DAMAS_PREC_FP32, ctx->A32.p, P.refine, xi),
+        if (P.refine > 0 || P.classes) {
+            GsClassArgs g = gca;
+            g.iters_cls = p->iterations;
+            HIP_TRY(sweeps(DAMAS_PREC_FP32, ctx->A32.p, P.refine, xi, g),
                     "gs launch (fp32 refinement)");
+        }
     }
     if (ctx->timing) {
         HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
@@ -1169,7 +1232,8 @@ size_t damas::ctx_bytes(const damas_ctx *ctx)
 {
     size_t t = 0;
     for (const Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
-                            &ctx->E16, &ctx->A32, &ctx->coop_ws, &ctx->coop_tab})
+                            &ctx->E16, &ctx->A32, &ctx->Alo, &ctx->tsum, &ctx->cls,
+                            &ctx->coop_ws, &ctx->coop_tab})
         t += b->bytes;
     return t;
 }
@@ -1182,7 +1246,8 @@ int damas::ctx_trim(damas_ctx *ctx)
         return fail(DAMAS_EBUSY, "a graph captured on this context still uses its workspace");
     ctx->coop_tab_host.clear();
     for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->off, &ctx->E, &ctx->A, &ctx->E16,
-                      &ctx->A32, &ctx->coop_ws, &ctx->coop_tab}) {
+                      &ctx->A32, &ctx->Alo, &ctx->tsum, &ctx->cls, &ctx->coop_ws,
+                      &ctx->coop_tab}) {
         if (b->p)
             HIP_TRY(hipFree(b->p), "hipFree");
         b->p = nullptr;
@@ -1215,7 +1280,7 @@ bool damas::PsfCache::shrink_to(size_t room)
         lru.pop_back();
         if (it == map.end())
             continue;
-        for (Buffer *b : {&it->second.A, &it->second.A32})
+        for (Buffer *b : {&it->second.A, &it->second.A32, &it->second.Alo, &it->second.cls})
             if (b->p) {
                 (void)hipFree(b->p); // synchronises: no copy still reads it
                 used -= b->bytes;
@@ -1230,7 +1295,7 @@ bool damas::PsfCache::shrink_to(size_t room)
 void damas::PsfCache::clear()
 {
     for (auto &kv : map) {
-        for (Buffer *b : {&kv.second.A, &kv.second.A32})
+        for (Buffer *b : {&kv.second.A, &kv.second.A32, &kv.second.Alo, &kv.second.cls})
             if (b->p)
                 (void)hipFree(b->p);
         if (kv.second.ready)
@@ -1293,10 +1358,10 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
             "read freq");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     std::string key;
-    const int32_t hdr[5] = {g->M, g->N, p->precision, P.need64, P.need16};
-    const double box[6] = {g->x0, g->x1, g->y0, g->y1, g->z0, g->c};
-    append(key, hdr, 5);
-    append(key, box, 6);
+    const int32_t hdr[6] = {g->M, g->N, p->precision, P.need64, P.need16, P.classes};
+    const double box[8] = {g->x0, g->x1, g->y0, g->y1, g->z0, g->c, P.rho_wide, P.rho_f32};
+    append(key, hdr, 6);
+    append(key, box, P.classes ? 8 : 6);
     append(key, mic.data(), mic.size());
     append(key, fr.data(), fr.size());
     append(key, st.data(), st.size());
@@ -1317,7 +1382,9 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
         return fail(DAMAS_EINVAL, "packed systems (%lld elements) exceed the arena (%lld)",
                     (long long)packed, (long long)P.a_elems);
     const size_t a_bytes = (P.need16 || !P.bf16) ? P.es * (size_t)packed : 0;
-    const size_t a32_bytes = (P.bf16 && P.refine > 0) ? sizeof(float) * (size_t)packed : 0;
+    const size_t a32_bytes = (P.bf16 && P.need64) ? sizeof(float) * (size_t)packed : 0;
+    const size_t lo_bytes = P.classes ? sizeof(uint16_t) * (size_t)packed : 0;
+    const size_t cls_bytes = P.classes ? (size_t)n_bins : 0;
     {
         std::lock_guard<std::mutex> lk(cache->mu);
         auto it = cache->map.find(key);
@@ -1328,16 +1395,19 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
             it->second.lru = cache->lru.begin();
             // The entry may have been filled on another stream.
             HIP_TRY(hipStreamWaitEvent(s, it->second.ready, 0), "hipStreamWaitEvent");
-            if (it->second.A.bytes < a_bytes || it->second.A32.bytes < a32_bytes)
+            if (it->second.A.bytes < a_bytes || it->second.A32.bytes < a32_bytes ||
+                it->second.Alo.bytes < lo_bytes || it->second.cls.bytes < cls_bytes)
                 return fail(DAMAS_EINVAL, "cached systems smaller than their key states");
-            if (a_bytes)
-                HIP_TRY(hipMemcpyAsync(ctx->A.p, it->second.A.p, a_bytes,
-                                       hipMemcpyDeviceToDevice, s),
-                        "cached A");
-            if (a32_bytes)
-                HIP_TRY(hipMemcpyAsync(ctx->A32.p, it->second.A32.p, a32_bytes,
-                                       hipMemcpyDeviceToDevice, s),
-                        "cached FP32 A");
+            const std::pair<void *, std::pair<const Buffer *, size_t>> cp[] = {
+                {ctx->A.p, {&it->second.A, a_bytes}},
+                {ctx->A32.p, {&it->second.A32, a32_bytes}},
+                {ctx->Alo.p, {&it->second.Alo, lo_bytes}},
+                {ctx->cls.p, {&it->second.cls, cls_bytes}}};
+            for (const auto &c : cp)
+                if (c.second.second)
+                    HIP_TRY(hipMemcpyAsync(c.first, c.second.first->p, c.second.second,
+                                           hipMemcpyDeviceToDevice, s),
+                            "cached systems");
             // The copies must finish before the entry can be evicted.
             HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
             *hit = 1;
@@ -1352,19 +1422,23 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
         return DAMAS_OK;
     // Store a copy of the systems just built, if they fit the budget.
     std::lock_guard<std::mutex> lk(cache->mu);
-    if (cache->map.count(key) || !cache->make_room(a_bytes + a32_bytes))
+    const size_t all_bytes = a_bytes + a32_bytes + lo_bytes + cls_bytes;
+    if (cache->map.count(key) || !cache->make_room(all_bytes))
         return DAMAS_OK;
     PsfCache::Entry e;
     e.key = key;
     for (auto pr : {std::make_pair(&e.A, std::make_pair(ctx->A.p, a_bytes)),
-                    std::make_pair(&e.A32, std::make_pair(ctx->A32.p, a32_bytes))}) {
+                    std::make_pair(&e.A32, std::make_pair(ctx->A32.p, a32_bytes)),
+                    std::make_pair(&e.Alo, std::make_pair(ctx->Alo.p, lo_bytes)),
+                    std::make_pair(&e.cls, std::make_pair(ctx->cls.p, cls_bytes))}) {
         if (!pr.second.second)
             continue;
         if (hipMalloc(&pr.first->p, pr.second.second) != hipSuccess) {
             (void)hipGetLastError();
-            if (e.A.p)
-                (void)hipFree(e.A.p); // synchronises with its pending copy
-            return DAMAS_OK;          // no room on the device: skip caching
+            for (Buffer *b : {&e.A, &e.A32, &e.Alo, &e.cls})
+                if (b->p)
+                    (void)hipFree(b->p); // synchronises with its pending copy
+            return DAMAS_OK;             // no room on the device: skip caching
         }
         pr.first->bytes = pr.second.second;
         HIP_TRY(hipMemcpyAsync(pr.first->p, pr.second.first, pr.second.second,
@@ -1375,14 +1449,14 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
         hipEventRecord(e.ready, s) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(s);
-        for (Buffer *b : {&e.A, &e.A32})
+        for (Buffer *b : {&e.A, &e.A32, &e.Alo, &e.cls})
             if (b->p)
                 (void)hipFree(b->p);
         if (e.ready)
             (void)hipEventDestroy(e.ready);
         return DAMAS_OK;
     }
-    cache->used += a_bytes + a32_bytes;
+    cache->used += all_bytes;
     auto ins = cache->map.emplace(key, std::move(e));
     cache->lru.push_front(&ins.first->first);
     ins.first->second.lru = cache->lru.begin();

@@ -100,9 +100,27 @@ hipError_t launch_steer(const Geom &g, int n_bins, const double *freq,
                         int max_kept, double *E, int64_t e_stride, int *fault,
                         hipStream_t s);
 
+// Storage classes of a bin (see PsfClassArgs and GsClassArgs).
+constexpr int kClsF32 = 1, kClsWide = 2;
+
+// Per-bin storage classes chosen after a float PSF: lo (device, or null)
+// receives the bf16 residuals bf16(A - float(A)) of every bin; with cls
+// non-null, tsum (device, n_bins x psf_tiles(max_kept) doubles) receives
+// the tile sums of A and cls (device, n_bins bytes) the class of each bin
+// (kClsWide: mean row sum over the kept points above rho_wide and at most
+// wide_cap kept; else kClsF32 above rho_f32; else 0).
+struct PsfClassArgs {
+    uint16_t *lo = nullptr;
+    double *tsum = nullptr;
+    uint8_t *cls = nullptr;
+    double rho_wide = 0.0, rho_f32 = 0.0;
+    int wide_cap = 0;
+};
+int64_t psf_tiles(int max_kept);
 hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                       int precision, const double *E, int64_t e_stride,
-                      const int64_t *off, void *A, int *fault, hipStream_t s);
+                      const int64_t *off, void *A, int *fault, hipStream_t s,
+                      const PsfClassArgs &pc = PsfClassArgs());
 
 // bf16 steering rows (half-width MP = M rounded up to 16) and the PSF on the
 // bf16 matrix cores.
@@ -114,10 +132,25 @@ hipError_t launch_psf16(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                         const uint16_t *E, int64_t e_stride, const int64_t *off, uint16_t *A,
                         int *fault, hipStream_t s);
 
+// Per-bin storage classes of a sweep launch: cls (per bin, device, or
+// null: every bin of class 0) with kClsF32 = every sweep on the float
+// system, kClsWide = every sweep on float hi + bf16 lo; lo (device) the
+// bf16 residual arena of wide bins, at the float arena's offsets; iters_cls
+// the sweeps of a bin whose class is not 0.
+struct GsClassArgs {
+    const uint8_t *cls = nullptr;
+    const uint16_t *lo = nullptr;
+    int iters_cls = 0;
+};
+
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                      const int32_t *idx, const int64_t *off, int precision,
                      int unit_diagonal, const void *A, const double *b, int iterations,
-                     const void *x_init, void *x_map, int *fault, hipStream_t s);
+                     const void *x_init, void *x_map, int *fault, hipStream_t s,
+                     const GsClassArgs &gc = GsClassArgs());
+
+// Largest kept count of a wide bin (float hi + bf16 lo sweeps).
+int gs_wide_capacity();
 
 // Largest s_tilde the sweep kernel holds on chip for a precision.
 int gs_max_kept(int precision);
@@ -131,12 +164,14 @@ int gs_max_kept(int precision);
 size_t gs_coop_ws_bytes(int n_bins, int max_kept);
 int gs_max_ranks();
 int gs_groups_per_wave(int precision, int s_tilde, int ranks);
-// Workgroups of the cooperative kernel that can be resident at once.
-int gs_coop_capacity(int precision, int max_kept);
+// Workgroups of the cooperative kernel that can be resident at once (lo:
+// with wide bins possible).
+int gs_coop_capacity(int precision, int max_kept, bool lo = false);
 hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                           const int32_t *idx, const int64_t *off, int precision,
                           int unit_diagonal, const void *A, const double *b, int iterations,
                           const void *x_init, void *x_map, int *fault, const int32_t *tab,
-                          int n_wg, int groups_per_wave, void *ws, hipStream_t s);
+                          int n_wg, int groups_per_wave, void *ws, const GsClassArgs &gc,
+                          hipStream_t s);
 
 } // namespace damas

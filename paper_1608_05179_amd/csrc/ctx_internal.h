@@ -28,7 +28,7 @@ struct Buffer {
 struct PsfCache {
     struct Entry {
         std::string key;
-        Buffer A, A32;
+        Buffer A, A32, Alo, cls; // systems, lo residuals and bin classes
         hipEvent_t ready = nullptr; // recorded after the copies that fill A, A32
         std::list<const std::string *>::iterator lru;
     };
@@ -62,6 +62,9 @@ struct damas_ctx {
     // faults.
     int *fault = nullptr;
     damas::Buffer b, idx, st, kc, off, E, A, E16, A32;
+    // per-bin precision classes: bf16 residuals of the float arena (same
+    // offsets), tile sums of A, one class byte per bin
+    damas::Buffer Alo, tsum, cls;
     // keep counts last uploaded to kc (skip identical re-uploads)
     std::vector<int32_t> kc_host;
     int32_t *kc_pinned = nullptr;

@@ -53,6 +53,14 @@ constexpr int kGsTile = 64;
 constexpr int kGsMaxStreamWaves = 15;   // stream waves per workgroup, at most
 constexpr int kGsPre = 8;               // serial wave: LDS reads issued this many steps ahead
 constexpr int kGsSparseRows = 12;       // a tile with at most this many moving rows visits only them
+// LDS the sweep kernels may use (the 160 KB of a CU, less a margin).
+constexpr size_t kGsLdsLimit = 160 * 1024 - 512;
+// Storage classes of a bin (kClsF32, kClsWide) are chosen per bin on the
+// device before its system is built: a bf16 solve's bin that skips the
+// bf16 bulk sweeps, a float solve's ill-conditioned bin.
+// Stream-wave shape of wide bins (head groups, tail batch): the tail loop
+// covers strips of any length.
+constexpr int kGsLoNH = 4, kGsLoNB = 2;
 
 // 16 bytes of A per lane: CPL = 2 doubles, 4 floats or 8 bf16.
 template <typename TA> struct Vec16;
@@ -150,14 +158,27 @@ template <int M> __device__ __forceinline__ float lane_xor(float v)
 // stores each loaded 16-byte piece of a row as it is.  (Blocks widened to
 // double would spare the serial wave its conversions, but their LDS
 // traffic delays its reads by more: measured slower.)
-template <typename TA> struct alignas(16) TileBlocks {
+// A wide bin (LO) stores A as a float hi plus a bf16 lo = bf16(A - hi);
+// its blocks carry the lo parts beside the float ones, and the serial wave
+// widens hi + lo to double.  Clo and Ulo interleave the rows of each pair
+// (2p, 2p + 1): entry (i, l) sits at lo_at(i, l), so one 32-bit read gives
+// the serial wave the lo parts of two consecutive steps.
+__device__ __forceinline__ int lo_at(int i, int l) { return ((i >> 1) * kGsTile + l) * 2 + (i & 1); }
+template <bool LO> struct LoBlocks {
+    bf16s Clo[kGsTile * kGsTile];
+    bf16s Ulo[(kGsTile + kGsPre) * kGsTile];
+    bf16s dglo[kGsTile];
+};
+template <> struct LoBlocks<false> {};
+template <typename TA, bool LO = false> struct alignas(16) TileBlocks : LoBlocks<LO> {
     TA C[kGsTile * kGsTile];
     TA U[(kGsTile + kGsPre) * kGsTile];
     TA dg[kGsTile];
 };
 static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
-                  sizeof(bf16s) * kGsTile * kGsTile % 16 == 0,
-              "U starts 16-byte aligned after C");
+                  sizeof(bf16s) * kGsTile * kGsTile % 16 == 0 &&
+                  sizeof(LoBlocks<true>) % 16 == 0,
+              "U starts 16-byte aligned after C, C after the low blocks");
 
 // ---------------------------------------------------------------------------
 // Stream role: one of NW waves (sw = 0..).  A period computes
@@ -174,11 +195,17 @@ static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
 // NH: groups per wave loaded a whole tile ahead (the head), together with
 // the rows of the two hand-over blocks; NB: groups per tail batch, two
 // batches in flight.  DG: hand over the diagonal too (only sweeps that scale
-// by 1 / A_ii read it).
-template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave {
+// by 1 / A_ii read it).  LO (float A only): the bin is wide -- its A is the
+// float arena plus a bf16 arena of residuals lo = bf16(A - hi) at the same
+// offsets; each element is widened to hi + lo in double and the sums run in
+// FP64 (x~ is not rounded), so the strip sums carry A to about 2^-33.
+template <typename TA, int NW, int NH, int NB, bool DG = true, bool LO = false>
+struct StreamWave {
+    static_assert(!LO || std::is_same<TA, float>::value, "wide bins store a float hi");
     typedef Vec16<TA> VA;
     typedef typename VA::type VT;
-    typedef typename VA::acc AT;
+    typedef std::conditional_t<LO, double, typename VA::acc> AT;
+    typedef uint2 VL; // the lo parts of a 16-byte hi piece (4 bf16)
     static constexpr int CPL = VA::n;
     static constexpr int LPJ = kGsTile / CPL;
     static constexpr int GT = kGsTile / CPL;         // row groups per tile
@@ -197,6 +224,9 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     int xcap;         // last row group start with x on chip (ld - CPL)
     uint32_t gstride; // bytes per group
     VT head[NH], hu[NU], hc[NU];
+    __amdgpu_buffer_rsrc_t rlo;                 // LO: the bin's lo arena
+    VL hlo[LO ? NH : 1], hulo[LO ? NU : 1], hclo[LO ? NU : 1];
+    uint32_t ulomask[LO ? NU : 1][2];           // LO: U's triangle in lo words
     // With a float or bf16 A: per hand-over row, the bits of each 32-bit word
     // of the lane's 16-byte piece to keep for U's strict upper part (the
     // columns c > i); the same in every period.
@@ -204,7 +234,7 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     uint32_t umask[kMaskWords ? NU : 1][4];
 
     __device__ __forceinline__ void init(const TA *A, int64_t ld_, int St_, int sw_, int lane_,
-                                         int gsw_, int nwt_)
+                                         int gsw_, int nwt_, const bf16s *Alo = nullptr)
     {
         ld = ld_;
         St = St_;
@@ -221,6 +251,24 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
         rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<TA *>(A), (short)0,
                                                  (int)(ld * ld * (int64_t)sizeof(TA)),
                                                  0x00020000);
+        if constexpr (LO) {
+            rlo = __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16s *>(Alo), (short)0,
+                                                    (int)(ld * ld * (int64_t)sizeof(bf16s)),
+                                                    0x00020000);
+#pragma unroll
+            for (int m = 0; m < NU; ++m) {
+                const int i = (sw + NW * m) * CPL + jp;
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    uint32_t k = 0;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e)
+                        if (cl + d * 2 + e > i)
+                            k |= 0xffffu << (16 * e);
+                    ulomask[m][d] = k;
+                }
+            }
+        }
         if constexpr (kMaskWords) {
             constexpr int EPW = 4 / sizeof(TA); // elements per 32-bit word
 #pragma unroll
@@ -252,14 +300,25 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
             VT, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)vo, (int)(g * gstride), 0));
     }
 
+    // The lo parts of group g (LO): half the byte offsets of the float hi.
+    __device__ __forceinline__ VL load_lo(int g, uint32_t vo) const
+    {
+        return __builtin_bit_cast(
+            VL, __builtin_amdgcn_raw_buffer_load_b64(rlo, (int)(vo >> 1),
+                                                     (int)(g * (gstride >> 1)), 0));
+    }
+
     // The head of strip T0 and, with `hand`, the rows of its hand-over
     // blocks (columns of tile T0 for U, of tile TN0 for C).
     __device__ __forceinline__ void prefetch_head(int T0)
     {
         const uint32_t vo = voff(T0);
 #pragma unroll
-        for (int n = 0; n < NH; ++n)
+        for (int n = 0; n < NH; ++n) {
             head[n] = load(gsw + nwt * n, vo);
+            if constexpr (LO)
+                hlo[n] = load_lo(gsw + nwt * n, vo);
+        }
     }
     __device__ __forceinline__ void prefetch_hand(int T0, int TN0)
     {
@@ -268,6 +327,10 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
         for (int m = 0; m < NU; ++m) {
             hu[m] = load(T0 / CPL + sw + NW * m, vo);
             hc[m] = load(T0 / CPL + sw + NW * m, voff(TN0));
+            if constexpr (LO) {
+                hulo[m] = load_lo(T0 / CPL + sw + NW * m, vo);
+                hclo[m] = load_lo(T0 / CPL + sw + NW * m, voff(TN0));
+            }
         }
     }
     __device__ __forceinline__ void prefetch(int T0, int TN0, bool hand = true)
@@ -308,6 +371,36 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     // group, then single-rate FMAs; FP64 would cost a widening and a
     // half-rate FMA per element, which left the stream waves' SIMDs busy for
     // most of a period), FP64 for a double A.
+    // Element s of a lo piece, as a float (bf16 is the upper half).
+    __device__ static __forceinline__ float lo_elem(const VL &l, int s)
+    {
+        const uint32_t w = s < 2 ? l.x : l.y;
+        return __builtin_bit_cast(float, (s & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+
+    // LO: acc += (hi + lo) x in double over the groups in v / vl.
+    template <int n>
+    __device__ __forceinline__ void sum_lo(const VT (&v)[n], const VL (&vl)[n], int g0,
+                                           double (&acc)[CPL], const double *xs) const
+    {
+        constexpr int C = 4;
+#pragma unroll
+        for (int k0 = 0; k0 < n; k0 += C) {
+            double xj[C];
+#pragma unroll
+            for (int k = k0; k < k0 + C && k < n; ++k)
+                xj[k - k0] = xrow(g0 + nwt * k, xs)[jp];
+#pragma unroll
+            for (int k = k0; k < k0 + C && k < n; ++k)
+#pragma unroll
+                for (int s = 0; s < CPL; ++s) {
+                    const double a = (double)VA::raw(v[k], s) + (double)lo_elem(vl[k], s);
+                    acc[s] = fma(a, xj[k - k0], acc[s]);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
     template <int n>
     __device__ __forceinline__ void sum(const VT (&v)[n], int g0, AT (&acc)[CPL],
                                         const double *xs) const
@@ -331,7 +424,7 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     // Blocks of tile T for the serial wave: U and dg from hu (zero outside
     // S~), C from hc.
     __device__ __forceinline__ void handover(int T0, const bool (&colok)[CPL],
-                                             TileBlocks<TA> *blk) const
+                                             TileBlocks<TA, LO> *blk) const
     {
 #pragma unroll
         for (int m = 0; m < NU; ++m) {
@@ -341,10 +434,27 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
             if constexpr (DG) {
 #pragma unroll
                 for (int s = 0; s < CPL; ++s)
-                    if (cl + s == i)
+                    if (cl + s == i) {
                         blk->dg[i] = VA::raw(hu[m], s);
+                        if constexpr (LO) {
+                            const uint32_t w = s < 2 ? hulo[m].x : hulo[m].y;
+                            blk->dglo[i].u = (uint16_t)((s & 1) ? (w >> 16) : (w & 0xffffu));
+                        }
+                    }
             }
             *reinterpret_cast<VT *>(&blk->C[i * kGsTile + cl]) = hc[m];
+            if constexpr (LO) {
+                VL w = hulo[m];
+                w.x &= ulomask[m][0];
+                w.y &= ulomask[m][1];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t cw = e < 2 ? hclo[m].x : hclo[m].y;
+                    const uint32_t uw = e < 2 ? w.x : w.y;
+                    blk->Clo[lo_at(i, cl + e)].u = (uint16_t)((e & 1) ? (cw >> 16) : cw);
+                    blk->Ulo[lo_at(i, cl + e)].u = (uint16_t)((e & 1) ? (uw >> 16) : uw);
+                }
+            }
             if constexpr (kMaskWords) {
                 // Entries outside S~ are zero already (padding of A, or
                 // loads past its end), so only the triangle is masked.
@@ -372,7 +482,7 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
     // issuing them unconditionally keeps the head in the same registers
     // from one period to the next).
     __device__ __forceinline__ void period(const double *xs, int T0, int NT0, int NTN0,
-                                           double *part, TileBlocks<TA> *blk,
+                                           double *part, TileBlocks<TA, LO> *blk,
                                            bool hand = true)
     {
         AT acc[CPL];
@@ -393,7 +503,10 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
         // The next head is issued once the sums have read this one, ahead
         // of the hand-over, whose rows were issued a period ago: its loads
         // then stream while the hand-over is stored instead of after it.
-        sum(head, gsw, acc, xs);
+        if constexpr (LO)
+            sum_lo(head, hlo, gsw, acc, xs);
+        else
+            sum(head, gsw, acc, xs);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (kEarlyHead)
             prefetch_head(NT0);
@@ -421,31 +534,41 @@ template <typename TA, int NW, int NH, int NB, bool DG = true> struct StreamWave
             if (nk > NH) {
                 const uint32_t vo = voff(T0);
                 VT b0[NB], b1[NB];
-                auto fill = [&](VT(&dst)[NB], int k0) {
+                VL l0[LO ? NB : 1], l1[LO ? NB : 1];
+                auto fill = [&](VT(&dst)[NB], VL(&dlo)[LO ? NB : 1], int k0) {
 #pragma unroll
-                    for (int n = 0; n < NB; ++n)
+                    for (int n = 0; n < NB; ++n) {
                         dst[n] = load(gsw + nwt * (k0 + n), vo);
+                        if constexpr (LO)
+                            dlo[n] = load_lo(gsw + nwt * (k0 + n), vo);
+                    }
                 };
-                fill(b0, NH);
+                auto add = [&](const VT(&v)[NB], const VL(&vl)[LO ? NB : 1], int g0) {
+                    if constexpr (LO)
+                        sum_lo(v, vl, g0, acc, xs);
+                    else
+                        sum(v, g0, acc, xs);
+                };
+                fill(b0, l0, NH);
                 int k0 = NH;
                 for (; k0 + 2 * NB < nk; k0 += 2 * NB) {
-                    fill(b1, k0 + NB);
+                    fill(b1, l1, k0 + NB);
                     __builtin_amdgcn_sched_barrier(0);
-                    sum(b0, gsw + nwt * k0, acc, xs);
+                    add(b0, l0, gsw + nwt * k0);
                     __builtin_amdgcn_sched_barrier(0);
-                    fill(b0, k0 + 2 * NB);
+                    fill(b0, l0, k0 + 2 * NB);
                     __builtin_amdgcn_sched_barrier(0);
-                    sum(b1, gsw + nwt * (k0 + NB), acc, xs);
+                    add(b1, l1, gsw + nwt * (k0 + NB));
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 if (k0 + NB < nk) {
-                    fill(b1, k0 + NB);
+                    fill(b1, l1, k0 + NB);
                     __builtin_amdgcn_sched_barrier(0);
-                    sum(b0, gsw + nwt * k0, acc, xs);
+                    add(b0, l0, gsw + nwt * k0);
                     __builtin_amdgcn_sched_barrier(0);
-                    sum(b1, gsw + nwt * (k0 + NB), acc, xs);
+                    add(b1, l1, gsw + nwt * (k0 + NB));
                 } else {
-                    sum(b0, gsw + nwt * k0, acc, xs);
+                    add(b0, l0, gsw + nwt * k0);
                 }
             }
         }
@@ -624,9 +747,9 @@ struct OwnerLink {
     int *fault;
 };
 
-template <typename TA, int NW, bool UNIT>
+template <typename TA, int NW, bool UNIT, bool LO = false>
 __device__ __forceinline__ void serial_role(double *xs, const double *parts, double *xnew,
-                                            const TileBlocks<TA> *blks,
+                                            const TileBlocks<TA, LO> *blks,
                                             const int32_t *__restrict__ id,
                                             const double *__restrict__ bf, int St, int ntile,
                                             long long total, int lane,
@@ -635,6 +758,8 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
 {
     __builtin_amdgcn_s_setprio(3);
     auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
+    // A block entry in double: hi, or hi + lo for a wide bin.
+    auto wd = [](TA h, bf16s l) { return LO ? widen(h) + widen(l) : widen(h); };
     int t = 0;
     const int t1 = nxt(0), t2 = nxt(t1);
     double bt = lane < St ? bf[id[lane]] : 0.0;               // tile t
@@ -649,16 +774,33 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         const int rows = min(kGsTile, St - t0);
         const int steps = (rows + 7) & ~7;
         const bool mine = lane < rows;
-        const TileBlocks<TA> &bk = blks[q & 1];
+        const TileBlocks<TA, LO> &bk = blks[q & 1];
         const double *pt = parts + (q & 1) * NW * kGsTile;
         // The first block entries of the tile are read before the partial
         // sums, so their latency overlaps the sum.
         TA ur[kGsPre], cr[kGsPre];
+        // lo parts of a wide bin, two steps per word (step i in half i & 1)
+        uint32_t ul2[kGsPre / 2], cl2[kGsPre / 2];
 #pragma unroll
         for (int i = 0; i < kGsPre; ++i) {
             ur[i] = bk.U[i * kGsTile + lane];
             cr[i] = bk.C[i * kGsTile + lane];
         }
+#pragma unroll
+        for (int i = 0; i < kGsPre / 2; ++i) {
+            if constexpr (LO) {
+                ul2[i] = *reinterpret_cast<const uint32_t *>(&bk.Ulo[lo_at(2 * i, lane)]);
+                cl2[i] = *reinterpret_cast<const uint32_t *>(&bk.Clo[lo_at(2 * i, lane)]);
+            } else {
+                ul2[i] = cl2[i] = 0u;
+            }
+        }
+        // The lo part of step u (of the read-ahead window) from its word.
+        auto half = [](uint32_t w, int u) {
+            bf16s h;
+            h.u = (uint16_t)((u & 1) ? (w >> 16) : w);
+            return h;
+        };
         __builtin_amdgcn_sched_barrier(0);
         // The stream waves' partial sums, added as a tree (depth log2 NW).
         double pk[NW];
@@ -678,20 +820,35 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
             // round trips to memory rather than two per helper.
             if (!coop_wait_all(co.flags, co.ranks, (uint32_t)(q + 1), lane))
                 atomicOr(co.fault, 8);
-            double hs[kGsMaxRanks];
+            // (A wide bin's serial wave, which also holds the lo block
+            // entries, loads them in batches of 8 to stay within its
+            // registers; the additions keep the helper order.)
+            constexpr int HB = LO ? 8 : kGsMaxRanks;
             const double *slot = co.part + (q & 1) * kGsTile + lane;
 #pragma unroll
-            for (int h = 1; h < kGsMaxRanks; ++h)
-                if (h < co.ranks)
-                    hs[h] = coop_ld(slot + h * 2 * kGsTile);
+            for (int h0 = 0; h0 < kGsMaxRanks; h0 += HB) {
+                if (h0 >= co.ranks)
+                    break;
+                double hs[HB];
 #pragma unroll
-            for (int h = 1; h < kGsMaxRanks; ++h)
-                if (h < co.ranks)
-                    r += hs[h];
+                for (int h = h0; h < h0 + HB; ++h)
+                    if (h >= 1 && h < co.ranks)
+                        hs[h - h0] = coop_ld(slot + h * 2 * kGsTile);
+#pragma unroll
+                for (int h = h0; h < h0 + HB; ++h)
+                    if (h >= 1 && h < co.ranks)
+                        r += hs[h - h0];
+            }
         }
         double il = 1.0;
-        if (!UNIT)
-            il = mine ? 1.0 / widen(bk.dg[lane]) : 0.0;
+        if (!UNIT) {
+            bf16s dl;
+            if constexpr (LO)
+                dl = bk.dglo[lane];
+            else
+                dl.u = 0;
+            il = mine ? 1.0 / wd(bk.dg[lane], dl) : 0.0;
+        }
         // x~ holds the tile's latest values once the stream waves have
         // committed them, a period after they were formed; with a single
         // tile that is the period running now, so they come from registers.
@@ -739,17 +896,24 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                 const int j = __builtin_ctzll(nz); // wave-uniform
                 const TA uj = bk.U[j * kGsTile + lane];
                 const TA cj = bk.C[j * kGsTile + lane];
+                bf16s ujl, cjl;
+                if constexpr (LO) {
+                    ujl = bk.Ulo[lo_at(j, lane)];
+                    cjl = bk.Clo[lo_at(j, lane)];
+                } else {
+                    ujl.u = cjl.u = 0;
+                }
                 const double m = lane_bcast(mn, j);
-                double udj = widen(uj);
+                double udj = wd(uj, ujl);
                 if (!UNIT)
                     udj *= il;
                 rho -= udj * m;
-                rnext -= widen(cj) * m;
+                rnext -= wd(cj, cjl) * m;
                 pend = j >= 63 ? 0ull : (pend & (~0ull << (j + 1)));
             }
             rn = rnext;
         } else {
-            double ud = UNIT ? widen(ur[0]) : widen(ur[0]) * il;
+            double ud = UNIT ? wd(ur[0], half(ul2[0], 0)) : wd(ur[0], half(ul2[0], 0)) * il;
             double cdp = 0.0, mp = 0.0; // coupling of the previous step
             double rn4[4] = {0.0, 0.0, 0.0, 0.0};
             auto block = [&](int i0, auto reads) {
@@ -760,7 +924,8 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                     // min(rho, x) and the updates subtract.
                     const double mn = fmin(rho, xl);
                     __builtin_amdgcn_sched_barrier(0);
-                    double udn = widen(ur[(u + 1) % kGsPre]);
+                    const int un = (u + 1) % kGsPre;
+                    double udn = wd(ur[un], half(ul2[un / 2], un));
                     if (!UNIT)
                         udn *= il;
                     __builtin_amdgcn_sched_barrier(0);
@@ -771,12 +936,23 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
                     __builtin_amdgcn_sched_barrier(0);
                     rho -= ud * m;
                     __builtin_amdgcn_sched_barrier(0);
-                    cdp = widen(cr[u]);
+                    cdp = wd(cr[u], half(cl2[u / 2], u));
                     mp = m;
                     ud = udn;
                     if constexpr (decltype(reads)::value) {
                         ur[u] = bk.U[(i + kGsPre) * kGsTile + lane];
                         cr[u] = bk.C[(i + kGsPre) * kGsTile + lane];
+                        // A word holds steps u and u + 1 (u even): it is
+                        // replaced once both are used, after step u + 1,
+                        // with the next window's pair.
+                        if constexpr (LO) {
+                            if (u & 1) {
+                                ul2[u / 2] = *reinterpret_cast<const uint32_t *>(
+                                    &bk.Ulo[lo_at(i - 1 + kGsPre, lane)]);
+                                cl2[u / 2] = *reinterpret_cast<const uint32_t *>(
+                                    &bk.Clo[lo_at(i - 1 + kGsPre, lane)]);
+                            }
+                        }
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -841,20 +1017,21 @@ template <int NW, int WAVES> constexpr bool gs_spare_waves()
     return WAVES > 1 + NW;
 }
 
-template <typename TA, int NW, int WAVES, int NH, int NB, bool UNIT>
+template <typename TA, int NW, int WAVES, int NH, int NB, bool UNIT, bool LO = false>
 __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xnew,
-                                          TileBlocks<TA> *blks, const TA *A, int64_t ld, int St,
-                                          const int32_t *__restrict__ id,
+                                          TileBlocks<TA, LO> *blks, const TA *A, int64_t ld,
+                                          int St, const int32_t *__restrict__ id,
                                           const double *__restrict__ bf, long long total,
                                           int ntile, int w, int lane, int nwt,
                                           OwnerLink co = OwnerLink{nullptr, nullptr, nullptr, 1,
-                                                                   nullptr})
+                                                                   nullptr},
+                                          const bf16s *Alo = nullptr)
 {
     auto nxt = [&](int t) { return t + 1 == ntile ? 0 : t + 1; };
     constexpr bool spare = gs_spare_waves<NW, WAVES>();
     if (w == 0) {
         __syncthreads();
-        serial_role<TA, NW, UNIT>(xs, parts, xnew, blks, id, bf, St, ntile, total, lane,
+        serial_role<TA, NW, UNIT, LO>(xs, parts, xnew, blks, id, bf, St, ntile, total, lane,
                                       co);
     } else if (spare && (w & 3) == 0) {
         for (long long q = 0; q <= total; ++q)
@@ -877,8 +1054,8 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
         // it (unit diagonal): fewer instructions for the stream waves, which
         // set the period once most tiles skip their zero rows.
         constexpr bool dg = !UNIT;
-        StreamWave<TA, NW, NH, NB, dg> sw;
-        sw.init(A, ld, St, si, lane, si, nwt);
+        StreamWave<TA, NW, NH, NB, dg, LO> sw;
+        sw.init(A, ld, St, si, lane, si, nwt, Alo);
         const int t1 = nxt(0), t2 = nxt(t1);
         sw.prefetch(0, t1 * kGsTile);
         sw.period(xs, 0, t1 * kGsTile, t2 * kGsTile, parts, &blks[0]);
@@ -901,9 +1078,36 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
     __syncthreads();
 }
 
-template <typename TA, int NW> constexpr size_t gs_lds_fixed()
+template <typename TA, int NW, bool LO = false> constexpr size_t gs_lds_fixed()
 {
-    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TA>);
+    return sizeof(double) * (2 * NW * kGsTile + 2 * kGsTile) + 2 * sizeof(TileBlocks<TA, LO>);
+}
+
+// Unknowns a wide bin may hold: x~ beside the wide blocks of NW stream waves.
+template <int NW> constexpr int gs_lo_cap()
+{
+    return (int)(((kGsLdsLimit - gs_lds_fixed<float, NW, true>()) / sizeof(double)) & ~(size_t)7);
+}
+
+// Per-bin storage classes of a launch: cls (per bin, or null: every bin of
+// class 0), the lo arena of wide bins (same element offsets as the float
+// arena, or null), and the sweeps of a bin whose class is not 0.
+struct GsClasses {
+    const uint8_t *cls;
+    const bf16s *lo;
+    int iters_cls;
+};
+
+// Sweeps, class and width of bin f; St clamped as the kernels' checks do.
+template <typename TA, int NW>
+__device__ __forceinline__ void bin_class(const GsClasses &gc, int f, int St, int iters,
+                                          int *iters_f, bool *wide)
+{
+    const int c = gc.cls ? (int)gc.cls[f] : 0;
+    *iters_f = c ? gc.iters_cls : iters;
+    *wide = false;
+    if constexpr (std::is_same<TA, float>::value)
+        *wide = (c & kClsWide) && gc.lo != nullptr && St <= gs_lo_cap<NW>();
 }
 
 template <typename TA, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
@@ -911,16 +1115,12 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     int N, const int32_t *__restrict__ s_tilde, int max_kept,
     const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
     const TA *__restrict__ A_all, const double *__restrict__ b, int iters,
-    const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault)
+    const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault, GsClasses gc)
 {
     // LDS: x~ [ld_cap] | partial sums [2][NW][64] | staging [2][64] |
-    //      tile blocks [2]
+    //      tile blocks [2] (with their lo parts for a wide bin, whose x~
+    //      region is held to gs_lo_cap)
     extern __shared__ double xs[];
-    const int64_t ld_cap = ld_of(max_kept);
-    double *parts = xs + ld_cap;
-    double *xnew = parts + 2 * NW * kGsTile;
-    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xnew + 2 * kGsTile);
-
     const int f = blockIdx.x;
     const int S = N * N;
     int St = s_tilde[f];
@@ -929,14 +1129,22 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
             atomicOr(fault, 4);
         St = 0;
     }
-    if (NB == 0 && (St + Vec16<TA>::n - 1) / Vec16<TA>::n > NH * NW) {
+    int iters_f;
+    bool wide;
+    bin_class<TA, NW>(gc, f, St, iters, &iters_f, &wide);
+    if (!wide && NB == 0 && (St + Vec16<TA>::n - 1) / Vec16<TA>::n > NH * NW) {
         // A shape without tail must hold every row group in its head.
         if (threadIdx.x == 0)
             atomicOr(fault, 16);
         St = 0;
     }
+    const int64_t ld_cap = wide ? ld_of(min(max_kept, gs_lo_cap<NW>())) : ld_of(max_kept);
+    double *parts = xs + ld_cap;
+    double *xnew = parts + 2 * NW * kGsTile;
+    void *blk = xnew + 2 * kGsTile;
     const int64_t ld = ld_of(St);
-    const TA *A = A_all + (St > 0 ? off[f] : 0);
+    const int64_t a0 = St > 0 ? off[f] : 0;
+    const TA *A = A_all + a0;
     const int32_t *id = idx + (int64_t)f * S;
     const double *bf = b + (int64_t)f * S;
     const int tid = threadIdx.x;
@@ -947,17 +1155,32 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     for (int64_t i = tid; i < ld; i += nthr)
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     {
-        uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / 4); i += nthr)
+        const int nz = (int)((wide ? 2 * sizeof(TileBlocks<float, true>)
+                                   : 2 * sizeof(TileBlocks<TA>)) / 4);
+        uint32_t *z = reinterpret_cast<uint32_t *>(blk); // all-zero bits: 0 in every type
+        for (int i = tid; i < nz; i += nthr)
             z[i] = 0u;
     }
     __syncthreads();
 
     const int ntile = (St + kGsTile - 1) / kGsTile;
-    const long long total = (long long)iters * ntile;
-    if (total > 0)
-        sweep_bin<TA, NW, WAVES, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
-                                            ntile, w, lane, NW);
+    const long long total = (long long)iters_f * ntile;
+    if (total > 0) {
+        bool done = false;
+        if constexpr (std::is_same<TA, float>::value) {
+            if (wide) {
+                sweep_bin<float, NW, WAVES, kGsLoNH, kGsLoNB, UNIT, true>(
+                    xs, parts, xnew, reinterpret_cast<TileBlocks<float, true> *>(blk), A, ld, St,
+                    id, bf, total, ntile, w, lane, NW,
+                    OwnerLink{nullptr, nullptr, nullptr, 1, nullptr}, gc.lo + a0);
+                done = true;
+            }
+        }
+        if (!done)
+            sweep_bin<TA, NW, WAVES, NH, NB, UNIT>(xs, parts, xnew,
+                                                  reinterpret_cast<TileBlocks<TA> *>(blk), A, ld,
+                                                  St, id, bf, total, ntile, w, lane, NW);
+    }
 
     // Scatter: x_map[n] = x~_i at n = idx[i], 0 in the gaps between kept
     // points, so every grid point is written exactly once.
@@ -996,36 +1219,20 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
 // bin.
 // One job of the cooperative kernel: rank `rank` of the `ranks` workgroups
 // of bin f (ranks == 1: the bin alone, nothing exchanged).
-template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
-__device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
-                                         const int32_t *__restrict__ s_tilde, int max_kept,
-                                         const int32_t *__restrict__ idx,
-                                         const int64_t *__restrict__ off,
-                                         const TA *__restrict__ A_all,
-                                         const double *__restrict__ b, int iters,
-                                         const TX *__restrict__ x_init, TX *__restrict__ x_map,
-                                         int *fault, const GsCoop &co, double *xs)
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB, bool LO>
+__device__ __forceinline__ void coop_body(int f, int rank, int ranks, int N, int St,
+                                          int64_t ld_cap, const int32_t *__restrict__ idx,
+                                          const TA *__restrict__ A, const bf16s *Alo,
+                                          const double *__restrict__ b, int iters,
+                                          const TX *__restrict__ x_init, TX *__restrict__ x_map,
+                                          int *fault, const GsCoop &co, double *xs)
 {
-    const int64_t ld_cap = ld_of(max_kept);
     double *parts = xs + ld_cap;
     double *xnew = parts + 2 * NW * kGsTile;
-    TileBlocks<TA> *blks = reinterpret_cast<TileBlocks<TA> *>(xnew + 2 * kGsTile);
+    TileBlocks<TA, LO> *blks = reinterpret_cast<TileBlocks<TA, LO> *>(xnew + 2 * kGsTile);
 
     const int S = N * N;
-    int St = s_tilde[f];
-    if (St > max_kept) {
-        if (threadIdx.x == 0)
-            atomicOr(fault, 4);
-        St = 0;
-    }
-    if (NB == 0 && (St + Vec16<TA>::n - 1) / Vec16<TA>::n > NH * NW * ranks) {
-        // A shape without tail must hold every row group in its head.
-        if (threadIdx.x == 0)
-            atomicOr(fault, 16);
-        St = 0;
-    }
     const int64_t ld = ld_of(St);
-    const TA *A = A_all + (St > 0 ? off[f] : 0);
     const int32_t *id = idx + (int64_t)f * S;
     const double *bf = b + (int64_t)f * S;
     const int tid = threadIdx.x;
@@ -1040,7 +1247,7 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
         xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
     if (rank == 0) {
         uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
-        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA>) / 4); i += nthr)
+        for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA, LO>) / 4); i += nthr)
             z[i] = 0u;
     }
     __syncthreads();
@@ -1075,15 +1282,15 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
                 tc = nxt(tc);
             }
         } else {
-            StreamWave<TA, NW, NH, NB> sw;
-            sw.init(A, ld, St, w - 1, lane, rank * NW + w - 1, ranks * NW);
+            StreamWave<TA, NW, NH, NB, true, LO> sw;
+            sw.init(A, ld, St, w - 1, lane, rank * NW + w - 1, ranks * NW, Alo);
             sw.prefetch(0, 0, false);
             int tc = ntile - 1;
             for (long long p = -1; p + 1 < total; ++p) {
                 const int tn = nxt(tc), tnn = nxt(tn);
                 __syncthreads();
                 sw.period(xs, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, parts,
-                          (TileBlocks<TA> *)nullptr, false);
+                          (TileBlocks<TA, LO> *)nullptr, false);
                 __syncthreads();
                 tc = tn;
             }
@@ -1093,9 +1300,10 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
 
     // Owner.
     if (total > 0)
-        sweep_bin<TA, NW, 1 + NW, NH, NB, UNIT>(xs, parts, xnew, blks, A, ld, St, id, bf, total,
-                                            ntile, w, lane, ranks * NW,
-                                            OwnerLink{flags, part, xpub, ranks, fault});
+        sweep_bin<TA, NW, 1 + NW, NH, NB, UNIT, LO>(xs, parts, xnew, blks, A, ld, St, id, bf,
+                                                    total, ntile, w, lane, ranks * NW,
+                                                    OwnerLink{flags, part, xpub, ranks, fault},
+                                                    Alo);
 
     TX *xo = x_map + (int64_t)f * S;
     if (St == 0) {
@@ -1115,6 +1323,49 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
     }
 }
 
+// One job: the bin's kept count (with the capacity checks), its class and
+// sweeps, then the body for a wide or an ordinary bin.  Every rank of a bin
+// reaches the same decisions.
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
+__device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
+                                         const int32_t *__restrict__ s_tilde, int max_kept,
+                                         const int32_t *__restrict__ idx,
+                                         const int64_t *__restrict__ off,
+                                         const TA *__restrict__ A_all,
+                                         const double *__restrict__ b, int iters,
+                                         const TX *__restrict__ x_init, TX *__restrict__ x_map,
+                                         int *fault, const GsCoop &co, const GsClasses &gc,
+                                         double *xs)
+{
+    int St = s_tilde[f];
+    if (St > max_kept) {
+        if (threadIdx.x == 0)
+            atomicOr(fault, 4);
+        St = 0;
+    }
+    int iters_f;
+    bool wide;
+    bin_class<TA, NW>(gc, f, St, iters, &iters_f, &wide);
+    if (!wide && NB == 0 && (St + Vec16<TA>::n - 1) / Vec16<TA>::n > NH * NW * ranks) {
+        // A shape without tail must hold every row group in its head.
+        if (threadIdx.x == 0)
+            atomicOr(fault, 16);
+        St = 0;
+    }
+    const int64_t a0 = St > 0 ? off[f] : 0;
+    if constexpr (std::is_same<TA, float>::value) {
+        if (wide) {
+            coop_body<TA, TX, UNIT, NW, kGsLoNH, kGsLoNB, true>(
+                f, rank, ranks, N, St, ld_of(min(max_kept, gs_lo_cap<NW>())), idx, A_all + a0,
+                gc.lo + a0, b, iters_f, x_init, x_map, fault, co, xs);
+            return;
+        }
+    }
+    coop_body<TA, TX, UNIT, NW, NH, NB, false>(f, rank, ranks, N, St, ld_of(max_kept), idx,
+                                               A_all + a0, nullptr, b, iters_f, x_init, x_map,
+                                               fault, co, xs);
+}
+
 
 // The cooperative kernel: workgroup g runs jobs co.wg[2g] .. co.wg[2g+1]-1
 // of co.jobs (bin, rank, ranks) in order.  A bin with ranks > 1 is the first
@@ -1126,14 +1377,15 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
     int N, const int32_t *__restrict__ s_tilde, int max_kept,
     const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
     const TA *__restrict__ A_all, const double *__restrict__ b, int iters,
-    const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault, GsCoop co)
+    const TX *__restrict__ x_init, TX *__restrict__ x_map, int *fault, GsCoop co,
+    GsClasses gc)
 {
     extern __shared__ double xs[];
     const int j0 = co.wg[2 * blockIdx.x], j1 = co.wg[2 * blockIdx.x + 1];
     for (int j = j0; j < j1; ++j) {
         coop_job<TA, TX, UNIT, NW, NH, NB>(co.jobs[3 * j], co.jobs[3 * j + 1],
                                            co.jobs[3 * j + 2], N, s_tilde, max_kept, idx, off,
-                                           A_all, b, iters, x_init, x_map, fault, co, xs);
+                                           A_all, b, iters, x_init, x_map, fault, co, gc, xs);
         __syncthreads(); // the next job reuses LDS
     }
 }
@@ -1159,21 +1411,30 @@ template <> struct GsShapes<bf16s> {
     static constexpr int cnw = 11, c_short_nh = 12, c_short_nb = 0, c_long_nh = 6, c_long_nb = 4;
 };
 
-// Dynamic LDS of a launch: A's storage type TA, NW stream waves.
-template <typename TA, int NW> static size_t gs_lds_bytes_t(int max_kept)
+// Dynamic LDS of a launch: A's storage type TA, NW stream waves; with
+// wide bins possible (float A, a lo arena), also the wide layout.
+template <typename TA, int NW> static size_t gs_lds_bytes_t(int max_kept, bool lo = false)
 {
-    return gs_lds_fixed<TA, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
+    size_t n = gs_lds_fixed<TA, NW>() + sizeof(double) * (size_t)ld_of(max_kept);
+    if (lo && std::is_same<TA, float>::value)
+        n = std::max(n, gs_lds_fixed<float, NW, true>() +
+                            sizeof(double) * (size_t)ld_of(std::min(max_kept, gs_lo_cap<NW>())));
+    return n;
 }
 
-// LDS the sweep kernels may use (the 160 KB of a CU, less a margin).
-constexpr size_t kGsLdsLimit = 160 * 1024 - 512;
+static GsClasses to_dev(const GsClassArgs &a)
+{
+    return GsClasses{a.cls, reinterpret_cast<const bf16s *>(a.lo), a.iters_cls};
+}
+
+int gs_wide_capacity() { return std::min(gs_lo_cap<9>(), gs_lo_cap<11>()); }
 
 // Of the cooperative kernel (blocks in A's storage type).
-static size_t gs_coop_lds_bytes(int precision, int max_kept)
+static size_t gs_coop_lds_bytes(int precision, int max_kept, bool lo = false)
 {
     switch (precision) {
     case DAMAS_PREC_FP64: return gs_lds_bytes_t<double, GsShapes<double>::cnw>(max_kept);
-    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::cnw>(max_kept);
+    case DAMAS_PREC_FP32: return gs_lds_bytes_t<float, GsShapes<float>::cnw>(max_kept, lo);
     default: return gs_lds_bytes_t<bf16s, GsShapes<bf16s>::cnw>(max_kept);
     }
 }
@@ -1200,16 +1461,16 @@ template <typename TA, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB
 static hipError_t launch_gs_t(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                               const int32_t *idx, const int64_t *off, const void *A,
                               const double *b, int iterations, const void *x_init,
-                              void *x_map, int *fault, hipStream_t s)
+                              void *x_map, int *fault, const GsClassArgs &gc, hipStream_t s)
 {
     static const hipError_t attr =
         allow_big_lds((const void *)gs_kernel<TA, TX, UNIT, NW, WAVES, NH, NB>);
     if (attr != hipSuccess)
         return attr;
     hipLaunchKernelGGL((gs_kernel<TA, TX, UNIT, NW, WAVES, NH, NB>), dim3(n_bins),
-                       dim3(64 * WAVES), (gs_lds_bytes_t<TA, NW>(max_kept)), s, N, s_tilde,
-                       max_kept, idx, off, (const TA *)A, b, iterations, (const TX *)x_init,
-                       (TX *)x_map, fault);
+                       dim3(64 * WAVES), (gs_lds_bytes_t<TA, NW>(max_kept, gc.lo != nullptr)),
+                       s, N, s_tilde, max_kept, idx, off, (const TA *)A, b, iterations,
+                       (const TX *)x_init, (TX *)x_map, fault, to_dev(gc));
     return hipGetLastError();
 }
 
@@ -1217,7 +1478,8 @@ template <typename TA, typename TX>
 static hipError_t launch_gs_u(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                               const int32_t *idx, const int64_t *off, int unit_diagonal,
                               const void *A, const double *b, int iterations,
-                              const void *x_init, void *x_map, int *fault, hipStream_t s)
+                              const void *x_init, void *x_map, int *fault,
+                              const GsClassArgs &gc, hipStream_t s)
 {
     typedef GsShapes<TA> SH;
     // A strip fits the short shape's head when every wave's groups do.
@@ -1225,7 +1487,8 @@ static hipError_t launch_gs_u(int N, int n_bins, const int32_t *s_tilde, int max
         ld_of(max_kept) <= (int64_t)SH::short_nh * SH::nw * Vec16<TA>::n;
 #define DAMAS_GS_LAUNCH(U, NH, NB)                                                               \
     launch_gs_t<TA, TX, U, SH::nw, SH::waves, NH, NB>(N, n_bins, s_tilde, max_kept, idx, off,  \
-                                                      A, b, iterations, x_init, x_map, fault, s)
+                                                      A, b, iterations, x_init, x_map, fault,  \
+                                                      gc, s)
     if (unit_diagonal)
         return shrt ? DAMAS_GS_LAUNCH(true, SH::short_nh, SH::short_nb)
                     : DAMAS_GS_LAUNCH(true, SH::long_nh, SH::long_nb);
@@ -1305,7 +1568,7 @@ static const void *coop_pick(int precision, int unit, int groups_per_wave)
 #undef DAMAS_COOP_PICK
 }
 
-int gs_coop_capacity(int precision, int max_kept)
+int gs_coop_capacity(int precision, int max_kept, bool lo)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1315,7 +1578,7 @@ int gs_coop_capacity(int precision, int max_kept)
     const void *fn = coop_pick(precision, 1, 1 << 30);
     (void)allow_big_lds(fn);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * (1 + nw),
-                                                     gs_coop_lds_bytes(precision, max_kept)) !=
+                                                     gs_coop_lds_bytes(precision, max_kept, lo)) !=
         hipSuccess) {
         (void)hipGetLastError();
         return 0;
@@ -1327,7 +1590,8 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
                           const int32_t *idx, const int64_t *off, int precision,
                           int unit_diagonal, const void *A, const double *b, int iterations,
                           const void *x_init, void *x_map, int *fault, const int32_t *tab,
-                          int n_wg, int groups_per_wave, void *ws, hipStream_t s)
+                          int n_wg, int groups_per_wave, void *ws, const GsClassArgs &gca,
+                          hipStream_t s)
 {
     if (n_bins == 0 || n_wg == 0)
         return hipSuccess;
@@ -1350,10 +1614,11 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
     const void *fn = coop_pick(precision, unit_diagonal, groups_per_wave);
     (void)allow_big_lds(fn);
     const int nw = coop_stream_waves(precision);
-    size_t lds = gs_coop_lds_bytes(precision, max_kept);
+    size_t lds = gs_coop_lds_bytes(precision, max_kept, gca.lo != nullptr);
+    GsClasses gc = to_dev(gca);
     void *args[] = {&N,  (void *)&s_tilde, &max_kept, (void *)&idx, (void *)&off,
                     (void *)&A, (void *)&b, &iterations, (void *)&x_init, &x_map,
-                    &fault, &co};
+                    &fault, &co, &gc};
     return hipLaunchCooperativeKernel(fn, dim3(n_wg), dim3(64 * (1 + nw)), args,
                                       (unsigned)lds, s);
 }
@@ -1361,19 +1626,20 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,
                      const int32_t *idx, const int64_t *off, int precision,
                      int unit_diagonal, const void *A, const double *b, int iterations,
-                     const void *x_init, void *x_map, int *fault, hipStream_t s)
+                     const void *x_init, void *x_map, int *fault, hipStream_t s,
+                     const GsClassArgs &gc)
 {
     if (n_bins == 0)
         return hipSuccess;
     if (precision == DAMAS_PREC_FP64)
         return launch_gs_u<double, double>(N, n_bins, s_tilde, max_kept, idx, off,
                                            unit_diagonal, A, b, iterations, x_init, x_map,
-                                           fault, s);
+                                           fault, gc, s);
     if (precision == DAMAS_PREC_BF16)
         return launch_gs_u<bf16s, float>(N, n_bins, s_tilde, max_kept, idx, off, unit_diagonal,
-                                         A, b, iterations, x_init, x_map, fault, s);
+                                         A, b, iterations, x_init, x_map, fault, gc, s);
     return launch_gs_u<float, float>(N, n_bins, s_tilde, max_kept, idx, off, unit_diagonal,
-                                     A, b, iterations, x_init, x_map, fault, s);
+                                     A, b, iterations, x_init, x_map, fault, gc, s);
 }
 
 } // namespace damas

@@ -72,16 +72,35 @@ __device__ inline dacc4 mma64(double a, double b, dacc4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+__device__ inline uint16_t bf16_rne_f(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7fffu + ((u >> 16) & 1u); // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+// Optional outputs of the float PSF for the per-bin storage classes:
+//   lo    bf16 residuals lo = bf16(A - float(A)) at the arena's offsets,
+//   tsum  per bin and tile, the sum of the tile's entries of A over kept
+//         rows and columns, each off-diagonal value counted for (i,j) and
+//         (j,i) (tile index t of the launch grid, stride tstride per bin).
+struct PsfExtra {
+    uint16_t *lo;
+    double *tsum;
+    int64_t tstride;
+};
+
 template <typename TS>
 __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
     int M, const int32_t *__restrict__ s_tilde, int max_kept,
     const double *__restrict__ E, int64_t e_stride,
-    const int64_t *__restrict__ off, TS *__restrict__ A, int *fault)
+    const int64_t *__restrict__ off, TS *__restrict__ A, int *fault, PsfExtra ex)
 {
     __shared__ double erI[kPsfTile * kPsfPitch];
     __shared__ double eiI[kPsfTile * kPsfPitch];
     __shared__ double erJ[kPsfTile * kPsfPitch];
     __shared__ double eiJ[kPsfTile * kPsfPitch];
+    __shared__ double red[kPsfThreads / 64];
 
     const int f = blockIdx.y;
     const int St = s_tilde[f];
@@ -178,7 +197,9 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
     // Epilogue: A = (Re^2 + Im^2) / M^2 in double, rounded once to TS,
     // mirrored; unit diagonal.
     TS *Af = A + off[f];
+    uint16_t *Lf = ex.lo ? ex.lo + off[f] : nullptr;
     const double inv = 1.0 / ((double)M * (double)M);
+    double tacc = 0.0; // this thread's share of the tile's sum
     for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 2; ++c)
             for (int v = 0; v < 4; ++v) {
@@ -187,16 +208,73 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
                 if (row >= ld || colj >= ld)
                     continue;
                 const double x = re[a][c][v], y = im[a][c][v];
-                const TS val = (TS)((x * x + y * y) * inv);
+                const double vd = (x * x + y * y) * inv;
+                const TS val = (TS)vd;
                 // Tiles with I < J have every column beyond every row; on
                 // diagonal tiles the lower half is the mirror of the upper.
                 if (colj > row) {
                     Af[row * ld + colj] = val;
                     Af[colj * ld + row] = val;
+                    if (Lf) {
+                        const uint16_t l = bf16_rne_f((float)(vd - (double)val));
+                        Lf[row * ld + colj] = l;
+                        Lf[colj * ld + row] = l;
+                    }
+                    if (colj < St)
+                        tacc += 2.0 * vd;
                 } else if (colj == row) {
                     Af[row * ld + row] = row < St ? (TS)1 : (TS)0;
+                    if (Lf)
+                        Lf[row * ld + row] = 0;
+                    if (row < St)
+                        tacc += 1.0;
                 }
             }
+    if (ex.tsum) {
+        // Fixed-order reduction (lanes, then waves), so the sum and the
+        // classes chosen from it are the same in every run.
+        for (int o = 32; o >= 1; o >>= 1)
+            tacc += __shfl_xor(tacc, o, 64);
+        if (lane == 0)
+            red[w] = tacc;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            ex.tsum[(int64_t)f * ex.tstride + t] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// Storage class of each bin from the mean row sum of its A over the kept
+// points, rho = (1/S~) sum_ij A_ij: about the number of kept points inside
+// one main lobe, a measure of how strongly the unknowns overlap (the bins
+// whose iterates move most with A's rounding have the largest).  A bin
+// above rho_wide (and within the wide sweeps' capacity) is wide; in a bf16
+// solve a bin above rho_f32 runs every sweep on the float system.  One
+// wave per bin; the tile sums are added in a fixed order.
+__global__ __launch_bounds__(64) void class_kernel(const int32_t *__restrict__ s_tilde,
+                                                   int max_kept, const double *__restrict__ tsum,
+                                                   int64_t tstride, double rho_wide,
+                                                   double rho_f32, int wide_cap,
+                                                   uint8_t *__restrict__ cls)
+{
+    const int f = blockIdx.x;
+    const int St = s_tilde[f];
+    const int lane = threadIdx.x;
+    const int64_t nt = (ld_of(St) + kPsfTile - 1) / kPsfTile;
+    const int64_t ntiles = St > 0 && St <= max_kept ? nt * (nt + 1) / 2 : 0;
+    double acc = 0.0;
+    for (int64_t t = lane; t < ntiles; t += 64)
+        acc += tsum[(int64_t)f * tstride + t];
+    for (int o = 32; o >= 1; o >>= 1)
+        acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) {
+        const double rho = St > 0 ? acc / (double)St : 0.0;
+        uint8_t c = 0;
+        if (rho > rho_wide && St <= wide_cap && ntiles > 0)
+            c = kClsWide;
+        else if (rho > rho_f32 && ntiles > 0)
+            c = kClsF32;
+        cls[f] = c;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -424,20 +502,36 @@ hipError_t launch_steer(const Geom &g, int n_bins, const double *freq,
     return hipGetLastError();
 }
 
+int64_t psf_tiles(int max_kept)
+{
+    const int64_t nt = (ld_of(max_kept) + kPsfTile - 1) / kPsfTile;
+    return nt * (nt + 1) / 2;
+}
+
 hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                       int precision, const double *E, int64_t e_stride,
-                      const int64_t *off, void *A, int *fault, hipStream_t s)
+                      const int64_t *off, void *A, int *fault, hipStream_t s,
+                      const PsfClassArgs &pc)
 {
     if (n_bins == 0 || max_kept == 0)
         return hipSuccess;
-    const int64_t nt = (ld_of(max_kept) + kPsfTile - 1) / kPsfTile;
-    dim3 grid((unsigned)(nt * (nt + 1) / 2), n_bins);
-    if (precision == DAMAS_PREC_FP64)
+    const int64_t tiles = psf_tiles(max_kept);
+    dim3 grid((unsigned)tiles, n_bins);
+    PsfExtra ex{nullptr, nullptr, tiles};
+    if (precision == DAMAS_PREC_FP64) {
         hipLaunchKernelGGL(psf_kernel<double>, grid, dim3(kPsfThreads), 0, s, M,
-                           s_tilde, max_kept, E, e_stride, off, (double *)A, fault);
-    else
-        hipLaunchKernelGGL(psf_kernel<float>, grid, dim3(kPsfThreads), 0, s, M,
-                           s_tilde, max_kept, E, e_stride, off, (float *)A, fault);
+                           s_tilde, max_kept, E, e_stride, off, (double *)A, fault, ex);
+        return hipGetLastError();
+    }
+    ex.lo = pc.lo;
+    ex.tsum = pc.cls ? pc.tsum : nullptr;
+    hipLaunchKernelGGL(psf_kernel<float>, grid, dim3(kPsfThreads), 0, s, M,
+                       s_tilde, max_kept, E, e_stride, off, (float *)A, fault, ex);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !pc.cls)
+        return e;
+    hipLaunchKernelGGL(class_kernel, dim3(n_bins), dim3(64), 0, s, s_tilde, max_kept, pc.tsum,
+                       tiles, pc.rho_wide, pc.rho_f32, pc.wide_cap, pc.cls);
     return hipGetLastError();
 }
 

@@ -35,6 +35,12 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16 = 2
 
+POLICY_AUTO = 0
+POLICY_FIXED = 1
+CLASS_NARROW = 0
+CLASS_FP32 = 1
+CLASS_WIDE = 2
+
 # Element type of A by precision, and of the x maps.
 _DTYPE = {PREC_FP64: torch.float64, PREC_FP32: torch.float32, PREC_BF16: torch.bfloat16}
 _XTYPE = {PREC_FP64: torch.float64, PREC_FP32: torch.float32, PREC_BF16: torch.float32}
@@ -61,7 +67,8 @@ class Params(ctypes.Structure):
     _fields_ = [("select_mode", c_i32), ("eps", c_dbl),
                 ("keep_count", ctypes.POINTER(c_i32)), ("keep_count_all", c_i32),
                 ("iterations", c_i32), ("precision", c_i32), ("batched", c_i32),
-                ("max_kept", c_i32), ("refine_sweeps", c_i32), ("predictor", c_i32)]
+                ("max_kept", c_i32), ("refine_sweeps", c_i32), ("predictor", c_i32),
+                ("policy", c_i32), ("rho_wide", c_dbl), ("rho_f32", c_dbl)]
 
 
 def _sig(name, res, *args):
@@ -77,6 +84,7 @@ _sig("damas_ld", c_i64, c_i32)
 _sig("damas_coarse_count", c_i32, c_i32)
 _sig("damas_mp", c_i32, c_i32)
 _sig("damas_gs_capacity", c_i32, c_i32)
+_sig("damas_wide_capacity", c_i32)
 _G = ctypes.POINTER(Geometry)
 _sig("damas_csm", ctypes.c_int, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp)
 _sig("damas_das_map", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_vp)
@@ -93,6 +101,7 @@ _sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i
 _sig("damas_ctx_create", ctypes.c_int, c_i32, ctypes.POINTER(c_vp))
 _sig("damas_ctx_destroy", None, c_vp)
 _sig("damas_ctx_set_timing", ctypes.c_int, c_vp, c_i32)
+_sig("damas_ctx_classes", ctypes.c_int, c_vp, c_i32, c_vp)
 _sig("damas_ctx_set_coop", ctypes.c_int, c_vp, c_i32)
 _sig("damas_ctx_last_workgroups", ctypes.c_int, c_vp, ctypes.POINTER(c_i32))
 _sig("damas_ctx_gs_time", ctypes.c_int, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64))
@@ -191,6 +200,11 @@ def mp(M: int) -> int:
 def gs_capacity(precision: int) -> int:
     """Largest max_kept the sweeps accept at this precision (0 if unknown)."""
     return int(_lib.damas_gs_capacity(int(precision)))
+
+
+def wide_capacity() -> int:
+    """Largest kept count of a wide bin (float hi + bf16 lo sweeps)."""
+    return int(_lib.damas_wide_capacity())
 
 
 def _ptr(t, dtype=None, name="tensor"):
@@ -388,6 +402,12 @@ class Context:
     def set_timing(self, enabled: bool):
         _check(_lib.damas_ctx_set_timing(self._h, 1 if enabled else 0))
 
+    def classes(self, n_bins: int) -> np.ndarray:
+        """Storage class per bin of the last batched solve (CLASS_*)."""
+        out = np.zeros(n_bins, np.uint8)
+        _check(_lib.damas_ctx_classes(self._h, int(n_bins), out.ctypes.data))
+        return out
+
     def gs_time(self):
         """(milliseconds, launches) of the timed sweep launches since the
         last call."""
@@ -404,7 +424,8 @@ class Context:
     def solve(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
               keep_count=None, iterations=1000, precision=PREC_FP32, batched=True,
               max_kept=0, refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
-              s_tilde=None, predictor=0, stream=None):
+              s_tilde=None, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0,
+              stream=None):
         """Every step for every bin on the device; returns x_map.
 
         keep_count: an int, or a sequence of per-bin ints (host values)."""
@@ -414,7 +435,7 @@ class Context:
         if x_map is None:
             x_map = torch.empty(nb, S, dtype=_XTYPE[precision], device=freq.device)
         p, kc_arr = _params(nb, select_mode, eps, keep_count, iterations, precision, batched,
-                            max_kept, refine_sweeps, predictor)
+                            max_kept, refine_sweeps, predictor, policy, rho_wide, rho_f32)
         dt = _XTYPE[precision]
         _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
                                     _ptr(freq, torch.float64, "freq"),
@@ -430,13 +451,13 @@ class Context:
 
     def autotune(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                  keep_count=None, precision=PREC_FP32, max_kept=0, trial_sweeps=30,
-                 stream=None) -> dict:
+                 policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0, stream=None) -> dict:
         """Tune the cooperative sweep schedule on this problem (trial solves
         of trial_sweeps sweeps); the choice stays on the context."""
         csm = _as_interleaved(csm)
         nb = freq.numel()
         p, _kc = _params(nb, select_mode, eps, keep_count, trial_sweeps, precision, True,
-                         max_kept, 0)
+                         max_kept, 0, 0, policy, rho_wide, rho_f32)
         r = TuneResult()
         _check(_lib.damas_ctx_autotune(self._h, ctypes.byref(g), nb,
                                        _ptr(freq, torch.float64, "freq"),
@@ -447,7 +468,7 @@ class Context:
     def capture(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                 keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
                 refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
-                s_tilde=None):
+                s_tilde=None, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0):
         """Capture this batched solve into a Graph (csm must be float64
         interleaved (n_bins, M, M, 2) so that in-place updates reach the
         graph)."""
@@ -457,7 +478,7 @@ class Context:
         if x_map is None:
             x_map = torch.empty(nb, g.N * g.N, dtype=_XTYPE[precision], device=freq.device)
         p, kc = _params(nb, select_mode, eps, keep_count, iterations, precision, True,
-                        max_kept, refine_sweeps)
+                        max_kept, refine_sweeps, 0, policy, rho_wide, rho_f32)
         dt = _XTYPE[precision]
         h = c_vp()
         _check(_lib.damas_graph_capture(self._h, ctypes.byref(g), nb,
@@ -495,7 +516,7 @@ class Graph:
 
 
 def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, max_kept,
-            refine_sweeps, predictor=0):
+            refine_sweeps, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0):
     """Params struct and the ctypes array that keeps per-bin counts alive."""
     kc_arr = None
     kc_all = 0
@@ -510,16 +531,17 @@ def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, ma
     p = Params(int(select_mode), float(eps),
                ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
                int(kc_all), int(iterations), int(precision), 1 if batched else 0,
-               int(max_kept), int(refine_sweeps), int(predictor))
+               int(max_kept), int(refine_sweeps), int(predictor), int(policy),
+               float(rho_wide), float(rho_f32))
     return p, kc_arr
 
 
 def query_footprint(M: int, N: int, n_bins: int, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                     keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
-                    refine_sweeps=0) -> int:
+                    refine_sweeps=0, policy=POLICY_AUTO) -> int:
     """Device bytes of a whole-path solve of this shape (no device work)."""
     p, _kc = _params(n_bins, select_mode, eps, keep_count, iterations, precision, True,
-                     max_kept, refine_sweeps)
+                     max_kept, refine_sweeps, 0, policy)
     out = ctypes.c_uint64()
     _check(_lib.damas_query_footprint(int(M), int(N), int(n_bins), ctypes.byref(p),
                                       ctypes.byref(out)))
@@ -555,14 +577,14 @@ class Server:
 
     def submit(self, mic, N, extent, z0, freqs, csm, *, select_mode=SEL_KEEP_COUNT, eps=0.0,
                keep_count=None, iterations=1000, precision=PREC_FP32, refine_sweeps=0,
-               max_kept=0, c=343.0) -> int:
+               max_kept=0, c=343.0, policy=POLICY_AUTO) -> int:
         """Queue one solve; returns its ticket.  csm: complex (n_bins, M, M)."""
         mic = np.ascontiguousarray(mic, dtype=np.float64)
         freqs = np.ascontiguousarray(freqs, dtype=np.float64)
         nb = freqs.size
         csm = np.ascontiguousarray(np.asarray(csm, dtype=np.complex128).view(np.float64))
         p, kc = _params(nb, select_mode, eps, keep_count, iterations, precision, True,
-                        max_kept, refine_sweeps)
+                        max_kept, refine_sweeps, 0, policy)
         x = np.zeros((nb, N * N), np.float64 if precision == PREC_FP64 else np.float32)
         st = np.zeros(nb, np.int32)
         x0, x1, y0, y1 = extent

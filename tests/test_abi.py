@@ -143,6 +143,12 @@ def test_query_footprint_closed_form(lib):
     want2 += 8 * 2 * S + 4 * 2 * S + 4 * 2 + 8 * 3
     want2 += 8 * 2 * L2 * 2 * M + 4 * 2 * L2 * L2
     assert dm.query_footprint(M, N, 2, select_mode=dm.SEL_KEEP_COUNT, keep_count=100,
+                              iterations=10, policy=dm.POLICY_FIXED) == want2
+    # the per-bin precision classes (default policy) add the bf16 residual
+    # arena, the PSF's tile sums (ld 104: 2 x 2 tiles, 3 in the upper
+    # triangle) and one class byte per bin
+    want2 += 2 * 2 * L2 * L2 + 8 * 2 * 3 + 2
+    assert dm.query_footprint(M, N, 2, select_mode=dm.SEL_KEEP_COUNT, keep_count=100,
                               iterations=10) == want2
     # BF16 with refinement holds both arenas and both steering tables
     fb = dm.query_footprint(M, N, 1, precision=dm.PREC_BF16, refine_sweeps=5, iterations=10)
