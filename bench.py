@@ -1,34 +1,39 @@
 """Throughput of the wavelet-compressed DAMAS path on one MI355X.
 
-Headline workload (the benchmarked configuration): a 64-mic five-arm
-log-spiral array of radius 0.6 m, a 41 x 41 scan grid on a 2 x 2 m plane
-1.5 m away, 64 frequency bins over 1-8 kHz, 5 uncorrelated sources, CSMs
-averaged over 1024 complex-Gaussian snapshots at 20 dB SNR; each bin keeps
-the 20 % of grid points with the largest wavelet detail (S~ = 337) and runs
-1000 Gauss-Seidel sweeps with A stored in float.  A step is one whole solve
-of all 64 bins: DAS map, selection, layout, steering rows, PSF build and
-sweeps, all on the GPU, with inputs already resident in HBM.
+Headline workload (the benchmarked configuration, the metric's largest
+single-GPU band): 128 microphones uniform in a 0.6 m disc, a 101 x 101 scan
+grid on a 2 x 2 m plane 1.5 m away, 256 frequency bins over 0.5-12 kHz,
+10 uncorrelated sources, CSMs averaged over 2048 complex-Gaussian snapshots
+at 10 dB SNR; each bin keeps its K_f ~ U{300..4000} grid points of largest
+wavelet detail and runs 2000 Gauss-Seidel sweeps, A stored in float with
+the per-bin precision policy (bins whose kept points overlap most are
+widened to float + bf16 residuals).  A step is one whole batched solve of
+all 256 bins: DAS map, selection, layout, steering rows, PSF build with the
+class choice, and the sweeps, all on the GPU, with inputs resident in HBM.
 
 Prints one JSON line.  Beyond the throughput keys:
   latency_ms     p50 / p99 of the per-step solve time (HIP events)
-  plain          the same solve as one launch per step per bin
+  classes        bins per storage class chosen by the policy
+  plain          one launch per step per bin, on a spread of sampled bins
+                 (each solved alone), against the batched solve of the same
+                 bins, and the whole band's plain time interpolated from them
   roofline       the sweep kernel's algorithmic A bytes over its measured
                  launch time (HIP events recorded by the library on the
                  solve's stream), against HBM peak
-  cpu_baseline   the FP64 oracle on the host, on a bounded sample of bins,
-                 and the GPU result's relative L2 error against it
-  variants       the other workloads at their full sizes (plain FP64 on a
-                 21 x 21 grid; BF16 storage with FP32 refinement on 81 x 81,
-                 32 bins; uneven compressed grids over 256 bins), each with
-                 throughput, latency and the roofline of its sweeps and, for
-                 BF16, of the PSF build on the bf16 matrix cores; and the
-                 served workload (Poisson arrivals on the request server) with
-                 p50/p99 latency and updates/s at the specified and at a
-                 sustainable rate.
+  cpu_baseline   the FP64 oracle on the host's cores (one process per bin)
+                 on a bounded sample of bins, and the GPU result's relative
+                 L2 error against it per sampled bin
+  variants       the other workloads at their full sizes: the compressed
+                 41 x 41 band (latency-bound: ns per serial row step), plain
+                 FP64 on 21 x 21, the 81 x 81 precision band (policy, plus
+                 the fixed bf16 setting as the precision trade-off, each with
+                 its error against the oracle on sampled bins), the served
+                 workload, the CSM step and the PSF build alone.
 
---workload NAME measures one workload alone (compressed, plain, precision,
-batched, served) and prints its record as the line; --workload copy runs one
-1 GiB device-to-device copy, the calibration of the HBM byte counters.
+--workload NAME measures one workload alone (batched, compressed, plain,
+precision, served, csm, psf) and prints its record as the line; --workload
+copy runs one 1 GiB device-to-device copy, the calibration of the HBM byte
+counters.
 """
 import argparse
 import hashlib
@@ -45,28 +50,33 @@ METRIC = "DAMAS grid-point updates/s + p50/p99 solve latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_traffic.json")
+CLOCK_GHZ = 2.4
 GS_SOURCE = os.path.join(ROOT, "paper_1608_05179_amd", "csrc", "gs.hip")
 
 
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=2,
-                    help="per-bin (plain) solves timed for the comparison; 0 skips them")
-    ap.add_argument("--cpu-bins", type=int, default=64,
-                    help="bins of the workload the oracle solves for the CPU baseline")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-bins", type=int, default=8,
+                    help="bins of the band solved one launch per step (plain) for the "
+                         "comparison; 0 skips it")
+    ap.add_argument("--cpu-bins", type=int, default=16,
+                    help="bins of the band the oracle solves for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--workload", default=None,
-                    choices=["compressed", "plain", "precision", "batched", "served",
-                             "csm", "copy"])
+                    choices=["batched", "compressed", "plain", "precision", "served",
+                             "csm", "psf", "copy"])
     ap.add_argument("--refine", type=int, default=60,
                     help="FP32 refinement sweeps of the precision workload")
     ap.add_argument("--tune-sweeps", type=int, default=20,
-                    help="sweeps per autotuner trial before a variant is timed (0: no tuning)")
+                    help="sweeps per autotuner trial before a workload is timed (0: no tuning)")
+    ap.add_argument("--fixed", action="store_true",
+                    help="every bin at the workload's stated precision (no per-bin policy)")
+    ap.add_argument("--rho-wide", type=float, default=0.0,
+                    help="widening threshold of the per-bin policy (0: the library default)")
     return ap.parse_args()
 
 
@@ -75,12 +85,13 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
-def _traffic():
-    """HBM bytes per sweep launch from the committed counter summary, if it
-    was taken on the current sweep kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _traffic(workload):
+    """HBM bytes per sweep launch of a workload from its committed counter
+    summary, if that was taken on the current sweep kernel source."""
+    path = os.path.join(ROOT, "profiles", f"gs_traffic_{workload}.json")
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         t = json.load(fh)
     src = hashlib.sha256(open(GS_SOURCE, "rb").read()).hexdigest()
     if t.get("gs_source_sha256") != src:
@@ -88,8 +99,21 @@ def _traffic():
     return t.get("hbm_bytes_per_launch")
 
 
+_GENERATED = {}
+
+
 def _workload(name, refine):
-    """(synthetic workload, select mode, precision, refine sweeps, label)."""
+    """(synthetic workload, select mode, precision, refine sweeps, label);
+    each workload is generated once per process and handed out as a copy."""
+    import copy
+    key = (name, refine)
+    if key not in _GENERATED:
+        _GENERATED[key] = _make_workload(name, refine)
+    w, *rest = _GENERATED[key]
+    return (copy.copy(w), *rest)
+
+
+def _make_workload(name, refine):
     from paper_1608_05179_amd import damas as dm
     from paper_1608_05179_amd import synth
     if name == "compressed":
@@ -106,168 +130,270 @@ def _workload(name, refine):
         w = synth.precision_bf16(refine_sweeps=refine)
         return (w, dm.SEL_KEEP_ALL, dm.PREC_BF16, refine,
                 f"precision-bf16: M=64 spiral, 81x81 grid (S=6561), 32 bins 2-10 kHz, "
-                f"keep all, 1000 sweeps: {1000 - refine} on bf16 A + {refine} on f32 A")
+                f"keep all, 1000 sweeps, bf16 bulk + {refine} f32 refinement sweeps where "
+                f"the policy allows bf16")
     w = synth.batched_fp32()
     return (w, dm.SEL_KEEP_COUNT, dm.PREC_FP32, 0,
             "batched-fp32: M=128 disc, 101x101 grid, 256 bins 0.5-12 kHz, keep "
-            "U{300..4000} per bin, 2000 sweeps, A stored f32")
+            "U{300..4000} per bin, 2000 sweeps, A stored f32 (ill-conditioned bins "
+            "f32 + bf16 residual)")
 
 
-def measure(name, steps, warmup, plain_steps, refine=60, psf_kernel_time=False,
-            tune_sweeps=0):
-    """Time `steps` batched solves of a workload; returns its record."""
-    import numpy as np
+class _Problem:
+    """Device-resident inputs of a workload and a context solving it."""
+
+    def __init__(self, name, refine, fixed=False, bins=None, rho_wide=0.0):
+        import numpy as np
+        import torch
+
+        from paper_1608_05179_amd import damas as dm
+        w, mode, prec, R, label = _workload(name, refine)
+        if bins is not None:  # a subset of the band's bins
+            w.freqs, w.csm = w.freqs[bins].copy(), w.csm[bins].copy()
+            if w.keep_counts is not None:
+                w.keep_counts = w.keep_counts[bins].copy()
+        self.w, self.mode, self.prec, self.R, self.label = w, mode, prec, R, label
+        self.policy = dm.POLICY_FIXED if fixed else dm.POLICY_AUTO
+        self.rho_wide = rho_wide
+        dev = torch.device("cuda:0")
+        self.K = None
+        if mode == dm.SEL_KEEP_COUNT:
+            self.K = ([int(v) for v in w.keep_counts] if w.keep_counts is not None
+                      else int(w.keep_count))
+        self.mic = torch.tensor(w.mic, dtype=torch.float64, device=dev)
+        self.g = dm.geometry(self.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+        self.freq = torch.tensor(w.freqs, dtype=torch.float64, device=dev)
+        self.csm = torch.view_as_real(
+            torch.tensor(w.csm, dtype=torch.complex128)).contiguous().to(dev)
+        xt = torch.float64 if prec == dm.PREC_FP64 else torch.float32
+        self.x = torch.empty(w.n_bins, w.S, dtype=xt, device=dev)
+        self.st = torch.zeros(w.n_bins, dtype=torch.int32, device=dev)
+        self.idx = torch.zeros(w.n_bins, w.S, dtype=torch.int32, device=dev)
+        self.ctx = dm.Context(0)
+        self.np = np
+
+    def solve(self, batched=True):
+        self.ctx.solve(self.g, self.freq, self.csm, select_mode=self.mode, keep_count=self.K,
+                       iterations=self.w.iterations, precision=self.prec, batched=batched,
+                       refine_sweeps=self.R, x_map=self.x, s_tilde=self.st, idx=self.idx,
+                       policy=self.policy, rho_wide=self.rho_wide)
+
+    def tune(self, sweeps):
+        return self.ctx.autotune(self.g, self.freq, self.csm, select_mode=self.mode,
+                                 keep_count=self.K, precision=self.prec, trial_sweeps=sweeps,
+                                 policy=self.policy, rho_wide=self.rho_wide)
+
+    def close(self):
+        self.ctx.close()
+
+
+def _time_steps(pb, steps, warmup):
+    """Wall and HIP-event times of `steps` batched solves, with the
+    library's per-phase event times (recorded on the solve's stream)."""
     import torch
 
     from paper_1608_05179_amd import damas as dm
-
-    w, mode, prec, R, label = _workload(name, refine)
-    dev = torch.device("cuda:0")
-    I = w.iterations
-    K = None
-    if mode == dm.SEL_KEEP_COUNT:
-        K = [int(v) for v in w.keep_counts] if w.keep_counts is not None else int(w.keep_count)
-    mic = torch.tensor(w.mic, dtype=torch.float64, device=dev)
-    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
-    freq = torch.tensor(w.freqs, dtype=torch.float64, device=dev)
-    csm = torch.view_as_real(torch.tensor(w.csm, dtype=torch.complex128)).contiguous().to(dev)
-    xt = torch.float64 if prec == dm.PREC_FP64 else torch.float32
-    x = torch.empty(w.n_bins, w.S, dtype=xt, device=dev)
-    st = torch.zeros(w.n_bins, dtype=torch.int32, device=dev)
-    idx = torch.zeros(w.n_bins, w.S, dtype=torch.int32, device=dev)
-    ctx = dm.Context(0)
-    stream = torch.cuda.current_stream()
-
-    def step(batched=True):
-        ctx.solve(g, freq, csm, select_mode=mode, keep_count=K, iterations=I,
-                  precision=prec, batched=batched, refine_sweeps=R, x_map=x, s_tilde=st,
-                  idx=idx)
-
-    tune = None
-    if tune_sweeps > 0:
-        # Set-up, not timed: the schedule autotuner on this problem.
-        tune = ctx.autotune(g, freq, csm, select_mode=mode, keep_count=K, precision=prec,
-                            trial_sweeps=tune_sweeps)
     for _ in range(warmup):
-        step()
-    ctx.check()
-    s_tilde = st.cpu().numpy().astype(np.int64)
-    updates = int(s_tilde.sum()) * I
-
-    ctx.set_timing(True)
-    ctx.phase_time(dm.PHASE_SWEEPS)
-    ctx.phase_time(dm.PHASE_SYSTEM)
+        pb.solve()
+    pb.ctx.check()
+    stream = torch.cuda.current_stream()
+    pb.ctx.set_timing(True)
+    pb.ctx.phase_time(dm.PHASE_SWEEPS)
+    pb.ctx.phase_time(dm.PHASE_SYSTEM)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for e0, e1 in ev:
         e0.record(stream)
-        step()
+        pb.solve()
         e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ctx.check()
-    gs_ms, gs_n = ctx.phase_time(dm.PHASE_SWEEPS)
-    sys_ms, sys_n = ctx.phase_time(dm.PHASE_SYSTEM)
-    ctx.set_timing(False)
-    wg = ctx.last_workgroups()
+    pb.ctx.check()
+    gs_ms, gs_n = pb.ctx.phase_time(dm.PHASE_SWEEPS)
+    sys_ms, sys_n = pb.ctx.phase_time(dm.PHASE_SYSTEM)
+    pb.ctx.set_timing(False)
     lat = [e0.elapsed_time(e1) for e0, e1 in ev]
-    ms_step = wall * 1e3 / steps
+    return wall * 1e3 / steps, lat, gs_ms / max(gs_n, 1), sys_ms / max(sys_n, 1)
 
-    # Sweeps: S~^2 elements of A per sweep per bin, at the storage width
-    # (bf16 bulk sweeps and f32 refinement sweeps for the precision path).
-    sq = int((s_tilde * s_tilde).sum())
-    if prec == dm.PREC_FP64:
-        a_bytes, a_kind = sq * I * 8, "f64"
-    elif prec == dm.PREC_FP32:
-        a_bytes, a_kind = sq * I * 4, "f32"
-    else:
-        a_bytes, a_kind = sq * ((I - R) * 2 + R * 4), "bf16+f32"
-    gs_avg = gs_ms / max(gs_n, 1)
+
+def _sweep_bytes(pb, s_tilde, cls):
+    """Algorithmic A bytes of one solve's sweeps: S~_f^2 elements of A per
+    sweep of bin f, at the width its class stores them (f64 8 B; f32 4 B;
+    wide f32 + bf16 residual 6 B; bf16 bulk 2 B with the refinement sweeps
+    on f32)."""
+    from paper_1608_05179_amd import damas as dm
+    I, R = pb.w.iterations, pb.R
+    tot = 0
+    for f, v in enumerate(s_tilde):
+        sq = int(v) * int(v)
+        c = int(cls[f]) if cls is not None else 0
+        if pb.prec == dm.PREC_FP64:
+            tot += sq * I * 8
+        elif c == dm.CLASS_WIDE:
+            tot += sq * I * 6
+        elif pb.prec == dm.PREC_FP32 or c == dm.CLASS_FP32:
+            tot += sq * I * 4
+        else:
+            tot += sq * ((I - R) * 2 + R * 4)
+    return tot
+
+
+def measure(name, steps, warmup, refine=60, tune_sweeps=0, fixed=False, rho_wide=0.0):
+    """Time `steps` batched solves of a workload; returns (record, problem)."""
+    import numpy as np
+
+    from paper_1608_05179_amd import damas as dm
+    pb = _Problem(name, refine, fixed, rho_wide=rho_wide)
+    w = pb.w
+    tune = pb.tune(tune_sweeps) if tune_sweeps > 0 else None  # set-up, not timed
+    ms_step, lat, gs_avg, sys_avg = _time_steps(pb, steps, warmup)
+    s_tilde = pb.st.cpu().numpy().astype(np.int64)
+    cls = pb.ctx.classes(w.n_bins) if (pb.policy == dm.POLICY_AUTO and
+                                       pb.prec != dm.PREC_FP64) else None
+    updates = int(s_tilde.sum()) * w.iterations
+    a_bytes = _sweep_bytes(pb, s_tilde, cls)
     achieved = a_bytes / (gs_avg * 1e-3) / 1e9
     rec = {
-        "workload": label, "bins": w.n_bins, "iterations": I,
+        "workload": pb.label + (" [fixed precision]" if fixed else ""),
+        "bins": w.n_bins, "iterations": w.iterations,
         "s_tilde_min": int(s_tilde.min()), "s_tilde_max": int(s_tilde.max()),
         "updates_per_step": updates,
         "value": round(updates / (ms_step * 1e-3), 1), "unit": "grid-point updates/s",
         "ms_per_step": round(ms_step, 4),
         "latency_ms": {"p50": round(_pct(lat, 50), 4), "p99": round(_pct(lat, 99), 4)},
-        "sweeps_ms": round(gs_avg, 4), "system_build_ms": round(sys_ms / max(sys_n, 1), 4),
-        "sweep_workgroups": wg,
+        "sweeps_ms": round(gs_avg, 4), "system_build_ms": round(sys_avg, 4),
+        "sweep_workgroups": pb.ctx.last_workgroups(),
         "autotune": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "kernel": f"gs_kernel (A {a_kind})", "kernel_avg_ms": round(gs_avg, 4),
-                     "algorithmic_bytes": a_bytes},
+                     "kernel": "gs_coop_kernel / gs_kernel (the solve's sweep launches)",
+                     "kernel_avg_ms": round(gs_avg, 4), "algorithmic_bytes": a_bytes},
     }
+    if cls is not None:
+        rec["classes"] = {"narrow": int((cls == dm.CLASS_NARROW).sum()),
+                          "fp32": int((cls == dm.CLASS_FP32).sum()),
+                          "wide": int((cls == dm.CLASS_WIDE).sum())}
+    return rec, pb
 
-    if plain_steps > 0:
-        step(batched=False)
+
+def plain_sampled(name, nbins, warmup=1):
+    """One launch per step per bin ("plain") on a spread of the band's bins
+    (each solved alone, so its sweeps run on one workgroup), and the batched
+    solve of the same bins; the band's plain time is interpolated from the
+    per-bin times as a function of the kept count."""
+    import numpy as np
+    import torch
+
+    full, _, _, _, _ = _workload(name, 60)
+    n = full.n_bins
+    kc = np.asarray(full.keep_counts) if full.keep_counts is not None else np.full(n, 1)
+    order = np.argsort(kc, kind="stable")
+    bins = sorted(set(int(order[i]) for i in np.linspace(0, n - 1, nbins).round().astype(int)))
+    per = []
+    for f in bins:
+        pb = _Problem(name, 60, bins=[f])
+        for _ in range(warmup):
+            pb.solve(batched=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(plain_steps):
-            step(batched=False)
-        torch.cuda.synchronize()
-        plain_ms = (time.perf_counter() - t0) * 1e3 / plain_steps
-        ctx.check()
-        rec["plain"] = {"value": round(updates / (plain_ms * 1e-3), 1),
-                        "ms_per_step": round(plain_ms, 3),
-                        "batched_speedup": round(plain_ms / ms_step, 2)}
+        pb.solve(batched=False)
+        pb.ctx.check()
+        per.append((time.perf_counter() - t0) * 1e3)
+        pb.close()
+    pb = _Problem(name, 60, bins=bins)
+    pb.solve()
+    pb.ctx.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pb.solve()
+    pb.ctx.check()
+    batched_ms = (time.perf_counter() - t0) * 1e3
+    pb.close()
+    ks = kc[bins].astype(float)
+    band_ms = float(np.interp(kc.astype(float), ks, np.asarray(per)).sum())
+    return {"bins": bins, "kept": [int(v) for v in kc[bins]],
+            "ms_per_bin": [round(v, 2) for v in per],
+            "plain_ms_sampled_bins": round(sum(per), 2),
+            "batched_ms_same_bins": round(batched_ms, 2),
+            "batched_speedup_sampled": round(sum(per) / batched_ms, 2),
+            "plain_ms_band_interpolated": round(band_ms, 1)}
 
-    if psf_kernel_time and prec == dm.PREC_BF16:
-        # The bf16 PSF kernel alone (step-level call on the same kept sets),
-        # timed with events on the stream it is launched on.
-        mk = int(s_tilde.max())
-        E16 = dm.steer_bf16(g, freq, idx, st, mk)
-        off = dm.layout(st, mk)
-        A16 = dm.psf_bf16(w.M, st, mk, E16, off)
-        reps = 5
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            dm.psf_bf16(w.M, st, mk, E16, off, A=A16)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        psf_ms = e0.elapsed_time(e1) / reps
-        ent = int(sum(v * (v + 1) // 2 for v in s_tilde))   # distinct entries
-        flops = ent * 8 * w.M                                # 8M flops per entry
-        wbytes = sq * 2                                      # both triangles, bf16
-        tf = flops / (psf_ms * 1e-3) / 1e12
-        rec["psf_bf16"] = {"bound": "mfma", "achieved": round(tf, 2),
-                           "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4),
-                           "kernel_avg_ms": round(psf_ms, 4), "algorithmic_flops": flops,
-                           "write_GBs": round(wbytes / (psf_ms * 1e-3) / 1e9, 1),
-                           "write_frac_of_hbm": round(wbytes / (psf_ms * 1e-3) / 1e9
-                                                      / HBM_PEAK_GBS, 4)}
-        del A16, E16
-    elif psf_kernel_time:
-        # The PSF kernel of a float or double A alone (f64 MFMA on the
-        # steering rows), on the same kept sets, timed on its stream.
-        mk = int(s_tilde.max())
-        E = dm.steer(g, freq, idx, st, mk)
-        off = dm.layout(st, mk)
-        Ap = dm.psf(w.M, st, mk, prec, E, off)
-        reps = 5
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            dm.psf(w.M, st, mk, prec, E, off, A=Ap)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        psf_ms = e0.elapsed_time(e1) / reps
-        ent = int(sum(v * (v + 1) // 2 for v in s_tilde))   # distinct entries
-        flops = ent * 8 * w.M                                # 8M flops per entry
-        tf = flops / (psf_ms * 1e-3) / 1e12
-        rec["psf_f64_mfma"] = {"bound": "mfma", "achieved": round(tf, 2),
-                               "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                               "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
-                               "kernel": f"psf_kernel (A {a_kind})",
-                               "kernel_avg_ms": round(psf_ms, 4), "algorithmic_flops": flops}
-        del Ap, E
-    ctx.close()
-    return rec, w, x, st
+
+def _oracle_worker(args):
+    """One bin through the oracle (DAS map, Algorithm 1, PSF, sweeps)."""
+    import numpy as np
+
+    import oracle
+    mic, N, ext, z0, c, freq, csm, mode, K, iters = args
+    og = oracle.Geometry(mic, N, *ext, z0, c)
+    t0 = time.perf_counter()
+    r = oracle.solve_bin(og, freq, csm, mode, keep_count=K, iters=iters)
+    return r["x"], len(r["idx"]), time.perf_counter() - t0, np.float64(r["margin"])
+
+
+def _host_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def oracle_check(pb, bins, cores=None, extra_maps=()):
+    """The oracle on `bins` of a solved problem, one process per bin on up
+    to `cores` host cores.  Returns (per-bin relative L2 of the GPU map
+    against the oracle, oracle updates, wall seconds, cores used), and the
+    same errors for each further GPU map of the same problem in
+    `extra_maps`."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    w = pb.w
+    cores = min(cores or _host_cores(), len(bins))
+    xg = pb.x.double().cpu().numpy()
+    jobs = []
+    for f in bins:
+        K = pb.K[f] if isinstance(pb.K, list) else (pb.K or 0)
+        jobs.append((w.mic, w.N, (w.x0, w.x1, w.y0, w.y1), w.z0, w.c, float(w.freqs[f]),
+                     w.csm[f], pb.mode, int(K), w.iterations))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    def errors(x):
+        return {int(f): float(f"{np.linalg.norm(x[f] - xr) / np.linalg.norm(xr):.3e}")
+                for f, (xr, _, _, _) in zip(bins, res)}
+    upd = sum(n for _, n, _, _ in res) * w.iterations
+    if extra_maps:
+        return errors(xg), upd, wall, cores, [errors(x) for x in extra_maps]
+    return errors(xg), upd, wall, cores
+
+
+def measure_latency_bound(name, steps, warmup, tune_sweeps):
+    """A band whose systems stay in cache (the compressed workload: 64 bins
+    of 337 kept, 29 MB of A): each bin's sweeps are a chain of S~ I serial
+    row steps on one workgroup, so the sweeps are reported as ns per row
+    step against the step chain's floor, not against HBM."""
+    rec, pb = measure(name, steps, warmup, tune_sweeps=tune_sweeps)
+    w = pb.w
+    steps_chain = int(rec["s_tilde_max"]) * w.iterations
+    ns = rec["sweeps_ms"] * 1e6 / steps_chain
+    rec["roofline"] = {"bound": "latency", "achieved": round(ns, 2),
+                       "unit": "ns per serial row step",
+                       "floor": round(29 / CLOCK_GHZ, 2),
+                       "floor_basis": "bare min -> broadcast -> fma chain, about 29 cycles "
+                                      "at 2.4 GHz",
+                       "frac": round((29 / CLOCK_GHZ) / ns, 4),
+                       "algorithmic_GBs": rec["roofline"]["achieved"],
+                       "kernel_avg_ms": rec["sweeps_ms"]}
+    pb.close()
+    return rec
 
 
 def measure_served(n_pool=24, n_trace=40, rate=200.0, n_sustained=16, slots=4):
@@ -315,13 +441,15 @@ def measure_served(n_pool=24, n_trace=40, rate=200.0, n_sustained=16, slots=4):
                 "latency_ms": {"p50": round(_pct(lat, 50), 1), "p99": round(_pct(lat, 99), 1)},
                 "cache_hits": hits, "wall_s": round(wall, 2)}
 
-    # one warm request so library set-up is not in the first latency
-    srv.wait(submit(pool[0]))
-    spec = trace(rate, n_trace, 0)
-    lam_s = max(0.6 * spec["completed_req_s"], 0.05)
-    sus = trace(lam_s, n_sustained, 1)
-    stats = srv.stats()
-    srv.close()
+    try:
+        # one warm request so library set-up is not in the first latency
+        srv.wait(submit(pool[0]))
+        spec = trace(rate, n_trace, 0)
+        lam_s = max(0.6 * spec["completed_req_s"], 0.05)
+        sus = trace(lam_s, n_sustained, 1)
+        stats = srv.stats()
+    finally:
+        srv.close()
     return {"workload": f"served: Poisson arrivals, pool of {n_pool} requests (M=64 spiral, "
                         "N 41-101, 1-64 bins of the 1-8 kHz table, K 200-6000, 1000 sweeps, "
                         f"f32), {slots} stream slots",
@@ -368,6 +496,88 @@ def measure_csm(steps=5, warmup=1):
                          "input_GBs": round(nb * K * M * 16 / (ms * 1e-3) / 1e9, 1)}}
 
 
+def measure_psf(reps=5):
+    """The PSF build alone, step-level calls on the kept sets of two bands:
+    the batched band's float A on the f64 matrix cores, and the precision
+    band's bf16 A on the bf16 matrix cores (8 M flops per distinct entry;
+    2 or 4 bytes stored per entry, both triangles)."""
+    import numpy as np
+    import torch
+
+    from paper_1608_05179_amd import damas as dm
+    out = {}
+    for name, kind in (("batched", "f64"), ("precision", "bf16")):
+        pb = _Problem(name, 60)
+        w = pb.w
+        dm.das_map(pb.g, pb.freq, pb.csm)  # warm
+        b = dm.das_map(pb.g, pb.freq, pb.csm)
+        if pb.mode == dm.SEL_KEEP_COUNT:
+            kc = torch.tensor(pb.K, dtype=torch.int32, device="cuda:0")
+            idx, st = dm.select(w.N, b, pb.mode, keep_count=kc)
+        else:
+            idx, st = dm.select(w.N, b, pb.mode)
+        s_tilde = st.cpu().numpy().astype(np.int64)
+        mk = int(s_tilde.max())
+        stream = torch.cuda.current_stream()
+        if kind == "bf16":
+            E = dm.steer_bf16(pb.g, pb.freq, idx, st, mk)
+            off = dm.layout(st, mk)
+            A = dm.psf_bf16(w.M, st, mk, E, off)
+            call = lambda: dm.psf_bf16(w.M, st, mk, E, off, A=A)  # noqa: E731
+            peak, es = BF16_MFMA_PEAK_TFLOPS, 2
+        else:
+            E = dm.steer(pb.g, pb.freq, idx, st, mk)
+            off = dm.layout(st, mk)
+            A = dm.psf(w.M, st, mk, dm.PREC_FP32, E, off)
+            call = lambda: dm.psf(w.M, st, mk, dm.PREC_FP32, E, off, A=A)  # noqa: E731
+            peak, es = FP64_MFMA_PEAK_TFLOPS, 4
+        call()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ent = int(sum(v * (v + 1) // 2 for v in s_tilde))
+        flops = ent * 8 * w.M
+        wbytes = int((s_tilde * s_tilde).sum()) * es
+        tf = flops / (ms * 1e-3) / 1e12
+        out[f"{name}_{kind}"] = {
+            "workload": f"PSF of the {name} band's kept sets ({w.n_bins} bins, S~ "
+                        f"{int(s_tilde.min())}-{mk}, M={w.M}), A stored {kind if kind == 'bf16' else 'f32'}",
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": peak,
+                         "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                         "kernel": "psf16_kernel" if kind == "bf16" else "psf_kernel<float>",
+                         "kernel_avg_ms": round(ms, 4), "algorithmic_flops": flops},
+            "write_GBs": round(wbytes / (ms * 1e-3) / 1e9, 1),
+            "write_frac_of_hbm": round(wbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del A, E, off, idx, st, b
+        pb.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def measure_precision(steps, warmup, refine, tune_sweeps, check_bins=(0, 31)):
+    """The precision band under the policy and with the bf16 setting fixed
+    (the precision trade-off), each with its error against the oracle on
+    sampled bins (the oracle needs about a minute per 6561-unknown bin)."""
+    rec_f, pb_f = measure("precision", steps, warmup, refine=refine,
+                          tune_sweeps=tune_sweeps, fixed=True)
+    x_fixed = pb_f.x.double().cpu().numpy()
+    pb_f.close()
+    rec, pb = measure("precision", steps, warmup, refine=refine, tune_sweeps=tune_sweeps)
+    errs, _, wall, cores, (errs_f,) = oracle_check(pb, list(check_bins),
+                                                    extra_maps=(x_fixed,))
+    pb.close()
+    note = f"bins {list(check_bins)}, {wall:.0f} s on {cores} cores"
+    for r, e in ((rec, errs), (rec_f, errs_f)):
+        r["oracle_rel_l2"] = e
+        r["oracle_max_rel_l2"] = max(e.values())
+        r["oracle_check"] = note
+    return {"policy": rec, "bf16_fixed": rec_f}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -377,7 +587,7 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch  # noqa: F401
+    import torch
 
     if args.workload == "copy":
         # Counter calibration: one device-to-device copy of 1 GiB (a plain
@@ -395,67 +605,93 @@ def main():
     if args.workload == "csm":
         print(json.dumps(measure_csm()), flush=True)
         return
+    if args.workload == "psf":
+        print(json.dumps(measure_psf()), flush=True)
+        torch.cuda.synchronize()
+        return
+    if args.workload == "compressed":
+        print(json.dumps(measure_latency_bound("compressed", args.steps, args.warmup,
+                                               args.tune_sweeps)), flush=True)
+        return
     if args.workload is not None:
-        rec, _, _, _ = measure(args.workload, args.steps, args.warmup, args.plain_steps,
-                               refine=args.refine, psf_kernel_time=True,
-                               tune_sweeps=args.tune_sweeps)
+        rec, pb = measure(args.workload, args.steps, args.warmup, refine=args.refine,
+                          tune_sweeps=args.tune_sweeps, fixed=args.fixed,
+                          rho_wide=args.rho_wide)
+        pb.close()
+        torch.cuda.synchronize()
         print(json.dumps(rec), flush=True)
         return
 
-    rec, w, x, st = measure("compressed", args.steps, args.warmup, args.plain_steps,
-                            psf_kernel_time=True)
-    rec["roofline"]["traffic"] = _traffic()
+    # ---- headline: the batched band --------------------------------------
+    rec, pb = measure("batched", args.steps, args.warmup, tune_sweeps=args.tune_sweeps,
+                      fixed=args.fixed, rho_wide=args.rho_wide)
+    rec["roofline"]["traffic"] = _traffic("batched")
     out = {
         "metric": METRIC, "value": rec["value"], "unit": rec["unit"],
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "dtype_detail": "A stored f32, partial strip sums f32; residuals, x and row updates f64",
+        "dtype_detail": "A stored f32 (wide bins: f32 + bf16 residual, FP64 strip sums); "
+                        "narrow bins' partial strip sums f32; residuals, x and row "
+                        "updates f64",
         "config": {"workload": rec["workload"], "bins": rec["bins"],
-                   "s_tilde": rec["s_tilde_max"], "iterations": rec["iterations"],
-                   "a_storage": "f32", "updates_per_step": rec["updates_per_step"]},
+                   "s_tilde_min": rec["s_tilde_min"], "s_tilde_max": rec["s_tilde_max"],
+                   "iterations": rec["iterations"], "updates_per_step": rec["updates_per_step"],
+                   "policy": "fixed" if args.fixed else "auto"},
         "latency_ms": rec["latency_ms"],
+        "classes": rec.get("classes"),
+        "sweeps_ms": rec["sweeps_ms"], "system_build_ms": rec["system_build_ms"],
+        "sweep_workgroups": rec["sweep_workgroups"], "autotune": rec["autotune"],
         "roofline": rec["roofline"],
     }
-    if "plain" in rec:
-        out["plain"] = rec["plain"]
-    if "psf_f64_mfma" in rec:
-        out["psf_f64_mfma"] = rec["psf_f64_mfma"]
-
-    # ---- CPU baseline: the oracle on a bounded sample of bins ------------
+    w = pb.w
+    # ---- CPU baseline and per-bin error: the oracle on sampled bins ------
     if not args.no_cpu:
-        import oracle
-        oracle.build()
-        og = oracle.Geometry(w.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+        s_tilde = pb.st.cpu().numpy()
         nb = min(args.cpu_bins, w.n_bins)
-        bins = np.linspace(0, w.n_bins - 1, nb).round().astype(int)
-        xg = x.double().cpu().numpy()
-        worst = 0.0
-        t0 = time.perf_counter()
-        refs = []
-        for f in bins:
-            refs.append(oracle.solve_bin(og, w.freqs[f], w.csm[f], oracle.SEL_KEEP_COUNT,
-                                         keep_count=w.keep_count, iters=w.iterations))
-        cpu_t = time.perf_counter() - t0
-        for f, r in zip(bins, refs):
-            worst = max(worst, float(np.linalg.norm(xg[f] - r["x"]) / np.linalg.norm(r["x"])))
-        cpu_updates = sum(len(r["idx"]) for r in refs) * w.iterations
-        out["cpu_baseline"] = {"value": round(cpu_updates / cpu_t, 1),
-                               "unit": "grid-point updates/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{nb} of {w.n_bins} bins, whole path per bin, "
-                                         f"{cpu_t:.1f} s single-threaded FP64 C",
-                               "gpu_max_rel_l2_vs_oracle": float(f"{worst:.3e}")}
+        bins = sorted(set(np.linspace(0, w.n_bins - 1, nb).round().astype(int).tolist())
+                      | {0, 1, 2})
+        errs, upd, wall, cores = oracle_check(pb, bins)
+        lscpu = ""
+        try:
+            import subprocess
+            r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+            for line in r.stdout.splitlines():
+                if line.startswith("Model name"):
+                    lscpu = line.split(":", 1)[1].strip()
+        except Exception:
+            pass
+        out["cpu_baseline"] = {
+            "value": round(upd / wall, 1), "unit": "grid-point updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{len(bins)} of {w.n_bins} bins (0, 1, 2 and a spread; "
+                      f"{int(sum(s_tilde[b] for b in bins))} kept in all), whole path per "
+                      f"bin at 2000 sweeps, FP64 C, one process per bin on {cores} cores, "
+                      f"{wall:.1f} s wall",
+            "host_cpu": lscpu, "host_cores_visible": os.cpu_count()}
+        out["oracle_rel_l2"] = errs
+        out["oracle_max_rel_l2"] = max(errs.values())
+    pb.close()
+    torch.cuda.empty_cache()
+    if args.plain_bins > 0:
+        out["plain"] = plain_sampled("batched", args.plain_bins)
+        torch.cuda.empty_cache()
 
     # ---- the other workloads at full size ---------------------------------
     if not args.no_variants:
-        out["variants"] = {}
-        for name, steps in (("plain", 5), ("precision", 2), ("batched", 2)):
-            v, _, _, _ = measure(name, steps, 1, 0, refine=args.refine,
-                                 psf_kernel_time=True, tune_sweeps=args.tune_sweeps)
-            out["variants"][name] = v
-            torch.cuda.empty_cache()
-        out["variants"]["served"] = measure_served()
-        out["variants"]["csm"] = measure_csm()
+        v = {}
+        v["compressed"] = measure_latency_bound("compressed", 10, 2, args.tune_sweeps)
+        r, p2 = measure("plain", 5, 1)
+        p2.close()
+        v["plain"] = r
+        torch.cuda.empty_cache()
+        v["precision"] = measure_precision(2, 1, args.refine, args.tune_sweeps)
+        torch.cuda.empty_cache()
+        v["served"] = measure_served()
+        v["csm"] = measure_csm()
+        v["psf"] = measure_psf()
+        out["variants"] = v
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -357,6 +357,9 @@ typedef struct {
                                     tile: max(floor, rows it sums), so that
                                     short bins, bound by the row chain, are
                                     not under-weighted; 0: rows alone     */
+    double wide_cost;            /* cost per element of a wide bin relative
+                                    to a narrow one in the schedule
+                                    (DAMAS_POLICY_AUTO)                    */
 } damas_tune_result;
 
 struct damas_params {
@@ -428,10 +431,13 @@ int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins, const d
 
 /* Autotuner of the cooperative sweep schedule: times trial solves of this
  * problem (batched, trial_sweeps sweeps each, into a scratch map; for BF16
- * all sweeps on the bf16 system) for one workgroup per bin and for a grid
- * of schedule knobs (minimum rows per rank, split threshold, rank cost),
+ * the bulk sweeps on the bf16 system) for one workgroup per bin and for a
+ * grid of schedule knobs (minimum rows per rank, split threshold, rank
+ * cost; with wide bins under DAMAS_POLICY_AUTO, then their cost factor),
  * timing each distinct schedule once, keeps the fastest on the context for
- * its later solves and reports it.  Inputs as for damas_solve_dev;
+ * its later solves and reports it.  Under the policy, cooperative batched
+ * solves read the bins' classes back before planning (one synchronisation
+ * of the solve's stream) so the schedule weighs wide bins by that factor.  Inputs as for damas_solve_dev;
  * synchronises on `stream`. */
 int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
                        const double *freq, const double *csm, const damas_params *p,

@@ -510,6 +510,8 @@ extern "C" void damas_ctx_destroy(damas_ctx *ctx)
         (void)hipHostFree(ctx->kc_pinned);
     if (ctx->coop_pinned)
         (void)hipHostFree(ctx->coop_pinned);
+    if (ctx->cls_pinned)
+        (void)hipHostFree(ctx->cls_pinned);
     if (ctx->kc_done)
         (void)hipEventDestroy(ctx->kc_done);
     if (ctx->coop_done)
@@ -832,7 +834,8 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
 // used only if its estimated makespan (ranks cost kCoopOverhead more per
 // element than a bin alone) beats one workgroup per bin by 10 %.
 // tab = [first, end) job per workgroup, then (bin, rank, ranks) per job.
-int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int *gpw)
+int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int *gpw,
+              const uint8_t *cls = nullptr)
 {
     if (ctx->coop_budget == 0 || !ctx->tune.coop || ctx->capturing || !P.batched ||
         P.st_host.empty())
@@ -846,7 +849,12 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
     auto cost = [&](int st, double rows) {
         return (double)((st + 63) / 64) * std::max(kFloor, rows);
     };
+    // A wide bin's elements cost more (6 bytes, FP64 products): its work is
+    // scaled by the context's wide_cost when the classes are known.
     const int nb = P.n_bins;
+    auto scale = [&](int f) {
+        return cls && cls[f] == kClsWide ? ctx->tune.wide_cost : 1.0;
+    };
     int cap = gs_coop_capacity(P.bf16 ? DAMAS_PREC_BF16 : P.p->precision, P.max_kept,
                                P.classes && !P.bf16);
     if (P.bf16 && P.need64)
@@ -858,7 +866,7 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
     double total = 0.0, plain_span = 0.0;
     for (int f = 0; f < nb; ++f) {
         const double l = (double)ld_of(P.st_host[f]);
-        work[f] = kFloor > 0.0 ? cost(P.st_host[f], l) : l * l;
+        work[f] = (kFloor > 0.0 ? cost(P.st_host[f], l) : l * l) * scale(f);
         total += work[f];
         plain_span = std::max(plain_span, work[f]);
     }
@@ -903,7 +911,8 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
             for (int h = 0; h < ranks[f]; ++h, ++g) {
                 wg_jobs[g] = {f, h, ranks[f]};
                 load[g] = kCoopOverhead *
-                          (kFloor > 0.0 ? cost(P.st_host[f], (double)ld_of(P.st_host[f]) / ranks[f])
+                          (kFloor > 0.0 ? cost(P.st_host[f],
+                                               (double)ld_of(P.st_host[f]) / ranks[f]) * scale(f)
                                         : work[f] / ranks[f]);
             }
     std::vector<int> solo;
@@ -1027,10 +1036,31 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
             return rc;
         HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
     }
-    // Cooperative schedule (batched solves of host-known kept counts).
+    // Cooperative schedule (batched solves of host-known kept counts).  With
+    // per-bin classes the schedule weighs wide bins by their cost, so the
+    // classes the PSF chose come to the host first (one synchronisation of
+    // the solve's stream, before the sweeps; not under graph capture, which
+    // schedules no cooperation).
     std::vector<int32_t> tab;
     int gpw = 0;
-    const int n_wg = nb == P.n_bins ? plan_coop(ctx, P, tab, &gpw) : 0;
+    const uint8_t *cls_host = nullptr;
+    if (P.classes && nb == P.n_bins && ctx->coop_budget != 0 && ctx->tune.coop &&
+        !ctx->capturing && P.batched && !P.st_host.empty()) {
+        if (ctx->cls_pinned_n < (size_t)nb) {
+            if (ctx->cls_pinned)
+                HIP_TRY(hipHostFree(ctx->cls_pinned), "hipHostFree");
+            ctx->cls_pinned = nullptr;
+            ctx->cls_pinned_n = 0;
+            HIP_TRY(hipHostMalloc((void **)&ctx->cls_pinned, (size_t)nb), "hipHostMalloc");
+            ctx->cls_pinned_n = nb;
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->cls_pinned, ctx->cls.p, (size_t)nb, hipMemcpyDeviceToHost,
+                               s),
+                "read classes");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        cls_host = ctx->cls_pinned;
+    }
+    const int n_wg = nb == P.n_bins ? plan_coop(ctx, P, tab, &gpw, cls_host) : 0;
     if (n_wg > 0) {
         if ((rc = upload_tab(ctx, tab, s)) ||
             (rc = ensure(ctx, ctx->coop_ws, gs_coop_ws_bytes(nb, max_kept), s,
@@ -1503,56 +1533,105 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
         int min_rows;
         double split, overhead;
         int floor_rows;
+        double wide_cost;
     };
-    std::vector<Cand> cands = {{false, 320, 1.25, 1.3, 0}, {true, 320, 1.25, 1.3, 0}};
+    const double wc0 = saved.wide_cost;
+    std::vector<Cand> cands = {{false, 320, 1.25, 1.3, 0, wc0}, {true, 320, 1.25, 1.3, 0, wc0}};
     for (int fl : {0, 640, 1280})
         for (int mr : {256, 320, 512, 1024})
             for (double sp : {1.0, 1.25, 2.0})
                 for (double ov : {1.1, 1.3, 1.6})
-                    cands.push_back({true, mr, sp, ov, fl});
+                    cands.push_back({true, mr, sp, ov, fl, wc0});
+    // One trial solve first: it warms up and, under the per-bin policy,
+    // gives the classes the schedules are planned with.
+    ctx->timing = true;
+    rc = damas_solve_dev(ctx, g, n_bins, freq, csm, &tp, nullptr, xm, nullptr, nullptr,
+                         nullptr, s);
+    if (rc == DAMAS_OK)
+        rc = damas_check(ctx, s);
+    std::vector<uint8_t> cls;
+    bool any_wide = false;
+    if (rc == DAMAS_OK && P.classes) {
+        cls.resize(n_bins);
+        if (hipMemcpy(cls.data(), ctx->cls.p, (size_t)n_bins, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            rc = fail(DAMAS_EDEVICE, "read classes");
+        for (uint8_t c : cls)
+            any_wide = any_wide || c == kClsWide;
+    }
+    {
+        double t = 0.0;
+        int64_t n = 0;
+        (void)damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, &t, &n);
+    }
     // Candidates that produce the same schedule are timed once.
     std::map<std::vector<int32_t>, double> timed;
-    double best = 1e300, dflt = 0.0;
-    size_t bi = 0;
     int ran = 0;
-    ctx->timing = true;
-    for (size_t c = 0; c < cands.size() && rc == DAMAS_OK; ++c) {
-        ctx->tune.coop = cands[c].coop;
-        ctx->tune.min_rows = cands[c].min_rows;
-        ctx->tune.split = cands[c].split;
-        ctx->tune.overhead = cands[c].overhead;
-        ctx->tune.floor_rows = cands[c].floor_rows;
+    auto apply = [&](const Cand &c) {
+        ctx->tune.coop = c.coop;
+        ctx->tune.min_rows = c.min_rows;
+        ctx->tune.split = c.split;
+        ctx->tune.overhead = c.overhead;
+        ctx->tune.floor_rows = c.floor_rows;
+        ctx->tune.wide_cost = c.wide_cost;
+    };
+    auto time_cand = [&](const Cand &c, double *ms) -> int {
+        apply(c);
         std::vector<int32_t> tab;
         int gpw = 0;
-        if (plan_coop(ctx, P, tab, &gpw) == 0)
+        if (plan_coop(ctx, P, tab, &gpw, cls.empty() ? nullptr : cls.data()) == 0)
             tab.clear(); // one workgroup per bin
-        double ms;
         auto it = timed.find(tab);
         if (it != timed.end()) {
-            ms = it->second;
-        } else {
-            ms = 0.0;
-            int64_t n = 0;
-            for (int rep = 0; rep < 2 && rc == DAMAS_OK; ++rep) {
-                double t = 0.0;
-                (void)damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, &t, &n);
-                rc = damas_solve_dev(ctx, g, n_bins, freq, csm, &tp, nullptr, xm, nullptr,
-                                     nullptr, nullptr, s);
-                if (rc == DAMAS_OK)
-                    rc = damas_check(ctx, s);
-                if (rc == DAMAS_OK)
-                    rc = damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, &ms, &n);
-            }
-            if (rc)
-                break;
-            timed[tab] = ms;
+            *ms = it->second;
+            return DAMAS_OK;
+        }
+        int r = DAMAS_OK;
+        int64_t n = 0;
+        for (int rep = 0; rep < 2 && r == DAMAS_OK; ++rep) {
+            double t = 0.0;
+            (void)damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, &t, &n);
+            r = damas_solve_dev(ctx, g, n_bins, freq, csm, &tp, nullptr, xm, nullptr, nullptr,
+                                nullptr, s);
+            if (r == DAMAS_OK)
+                r = damas_check(ctx, s);
+            if (r == DAMAS_OK)
+                r = damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, ms, &n);
+        }
+        if (r == DAMAS_OK) {
+            timed[tab] = *ms;
             ++ran;
         }
+        return r;
+    };
+    double best = 1e300, dflt = 0.0;
+    size_t bi = 0;
+    for (size_t c = 0; c < cands.size() && rc == DAMAS_OK; ++c) {
+        double ms = 0.0;
+        if ((rc = time_cand(cands[c], &ms)))
+            break;
         if (c == 1)
             dflt = ms; // the untuned knobs
         if (ms < best) {
             best = ms;
             bi = c;
+        }
+    }
+    // With wide bins, the cost of their elements in the schedule, around
+    // the best knobs.
+    if (rc == DAMAS_OK && any_wide && cands[bi].coop) {
+        const Cand base = cands[bi];
+        for (double wcost : {1.0, 1.35, 2.1, 2.6}) {
+            Cand c = base;
+            c.wide_cost = wcost;
+            double ms = 0.0;
+            if ((rc = time_cand(c, &ms)))
+                break;
+            cands.push_back(c);
+            if (ms < best) {
+                best = ms;
+                bi = cands.size() - 1;
+            }
         }
     }
     double t = 0.0;
@@ -1564,11 +1643,7 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
         ctx->tune = saved;
         return rc;
     }
-    ctx->tune.coop = cands[bi].coop;
-    ctx->tune.min_rows = cands[bi].min_rows;
-    ctx->tune.split = cands[bi].split;
-    ctx->tune.overhead = cands[bi].overhead;
-    ctx->tune.floor_rows = cands[bi].floor_rows;
+    apply(cands[bi]);
     out->coop = cands[bi].coop;
     out->coop_min_rows = cands[bi].min_rows;
     out->coop_split = cands[bi].split;
@@ -1577,6 +1652,7 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
     out->default_ms_per_sweep = dflt / trial_sweeps;
     out->candidates_timed = ran;
     out->coop_floor_rows = cands[bi].floor_rows;
+    out->wide_cost = cands[bi].wide_cost;
     return DAMAS_OK;
 }
 

@@ -65,6 +65,8 @@ struct damas_ctx {
     // per-bin precision classes: bf16 residuals of the float arena (same
     // offsets), tile sums of A, one class byte per bin
     damas::Buffer Alo, tsum, cls;
+    uint8_t *cls_pinned = nullptr; // classes read back for the schedule
+    size_t cls_pinned_n = 0;
     // keep counts last uploaded to kc (skip identical re-uploads)
     std::vector<int32_t> kc_host;
     int32_t *kc_pinned = nullptr;
@@ -82,6 +84,7 @@ struct damas_ctx {
         double split = 1.25;   // bins above split x the mean work per workgroup get ranks
         double overhead = 1.3; // cost per element of a rank relative to a bin alone
         int floor_rows = 0;    // cost model: a tile costs max(floor_rows, ld) (0: ld)
+        double wide_cost = 1.7; // cost per element of a wide bin relative to a narrow one
     } tune;
     // graph capture: `capturing` turns cooperation off (cooperative launches
     // are not captured), for the sizing solve too; `in_capture` refuses

@@ -197,8 +197,10 @@ static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
 // batches in flight.  DG: hand over the diagonal too (only sweeps that scale
 // by 1 / A_ii read it).  LO (float A only): the bin is wide -- its A is the
 // float arena plus a bf16 arena of residuals lo = bf16(A - hi) at the same
-// offsets; each element is widened to hi + lo in double and the sums run in
-// FP64 (x~ is not rounded), so the strip sums carry A to about 2^-33.
+// offsets; hi x_j is formed and summed in FP64 (exact products, so the sums
+// carry A's float part exactly), lo x_j in FP32 (a term 2^-24 of the first,
+// so its rounding is negligible), and the strip sums carry A to about
+// 2^-33.
 template <typename TA, int NW, int NH, int NB, bool DG = true, bool LO = false>
 struct StreamWave {
     static_assert(!LO || std::is_same<TA, float>::value, "wide bins store a float hi");
@@ -378,10 +380,12 @@ struct StreamWave {
         return __builtin_bit_cast(float, (s & 1) ? (w & 0xffff0000u) : (w << 16));
     }
 
-    // LO: acc += (hi + lo) x in double over the groups in v / vl.
+    // LO: acc += hi x in double, acl += lo x in float, over the groups in
+    // v / vl (one FP64 fma and one FP32 fma per element).
     template <int n>
     __device__ __forceinline__ void sum_lo(const VT (&v)[n], const VL (&vl)[n], int g0,
-                                           double (&acc)[CPL], const double *xs) const
+                                           double (&acc)[CPL], float (&acl)[CPL],
+                                           const double *xs) const
     {
         constexpr int C = 4;
 #pragma unroll
@@ -391,12 +395,14 @@ struct StreamWave {
             for (int k = k0; k < k0 + C && k < n; ++k)
                 xj[k - k0] = xrow(g0 + nwt * k, xs)[jp];
 #pragma unroll
-            for (int k = k0; k < k0 + C && k < n; ++k)
+            for (int k = k0; k < k0 + C && k < n; ++k) {
+                const float xf = (float)xj[k - k0];
 #pragma unroll
                 for (int s = 0; s < CPL; ++s) {
-                    const double a = (double)VA::raw(v[k], s) + (double)lo_elem(vl[k], s);
-                    acc[s] = fma(a, xj[k - k0], acc[s]);
+                    acc[s] = fma((double)VA::raw(v[k], s), xj[k - k0], acc[s]);
+                    acl[s] = fmaf(lo_elem(vl[k], s), xf, acl[s]);
                 }
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -486,10 +492,12 @@ struct StreamWave {
                                            bool hand = true)
     {
         AT acc[CPL];
+        float acl[CPL]; // LO: the lo terms
         bool colok[CPL];
 #pragma unroll
         for (int s = 0; s < CPL; ++s) {
             acc[s] = AT(0);
+            acl[s] = 0.0f;
             colok[s] = T0 + cl + s < St;
         }
         // Per-period copies of the loop-invariant strides keep the compiler
@@ -504,7 +512,7 @@ struct StreamWave {
         // of the hand-over, whose rows were issued a period ago: its loads
         // then stream while the hand-over is stored instead of after it.
         if constexpr (LO)
-            sum_lo(head, hlo, gsw, acc, xs);
+            sum_lo(head, hlo, gsw, acc, acl, xs);
         else
             sum(head, gsw, acc, xs);
         __builtin_amdgcn_sched_barrier(0);
@@ -545,7 +553,7 @@ struct StreamWave {
                 };
                 auto add = [&](const VT(&v)[NB], const VL(&vl)[LO ? NB : 1], int g0) {
                     if constexpr (LO)
-                        sum_lo(v, vl, g0, acc, xs);
+                        sum_lo(v, vl, g0, acc, acl, xs);
                     else
                         sum(v, g0, acc, xs);
                 };
@@ -571,6 +579,12 @@ struct StreamWave {
                     add(b0, l0, gsw + nwt * k0);
                 }
             }
+        }
+
+        if constexpr (LO) {
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+                acc[s] += (double)acl[s];
         }
 
         // Sum the CPL row groups (lanes l, l + LPJ, ...) of each column.

@@ -120,7 +120,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("coop", c_i32), ("coop_min_rows", c_i32), ("coop_split", c_dbl),
                 ("coop_overhead", c_dbl), ("best_ms_per_sweep", c_dbl),
                 ("default_ms_per_sweep", c_dbl), ("candidates_timed", c_i32),
-                ("coop_floor_rows", c_i32)]
+                ("coop_floor_rows", c_i32), ("wide_cost", c_dbl)]
 
 
 _sig("damas_ctx_autotune", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
