@@ -429,6 +429,35 @@ int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins, const d
                 const double *csm, const damas_params *p, const void *x_init, void *x_map,
                 double *b_map, int32_t *idx, int32_t *s_tilde);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * batched whole-path solve of damas_solve_dev with no context, its whole
+ * workspace (b, kept indices, offsets, steering rows, the A arena and, under
+ * DAMAS_POLICY_AUTO, the lo residuals, tile sums and classes, plus a fault
+ * word) carved from one static device array per GPU of
+ * damas_static_scratch_bytes() bytes (96 MiB), held by the library for the
+ * process's lifetime.  The call allocates nothing (no hipMalloc, hipFree or
+ * pinned staging) and only enqueues kernels on `stream`, the fault word
+ * included (cleared by a kernel, not a memset).
+ *   g, freq, csm, x_init, x_map, b_map, idx, s_tilde  as for damas_solve_dev
+ *   p           precision DAMAS_PREC_FP64 or DAMAS_PREC_FP32; p->batched,
+ *               p->keep_count, p->keep_count_all and refine_sweeps are
+ *               ignored; p->max_kept bounds the kept points per bin for
+ *               EPS_REL and KEEP_COUNT (0: N*N) and sizes the workspace
+ *   keep_count  DEVICE, n_bins int32 (KEEP_COUNT; may be NULL otherwise)
+ * Sweeps run one workgroup per bin (no cooperative schedule).  A solve whose
+ * workspace exceeds the array fails with DAMAS_EINVAL before any launch
+ * (supply b_map, idx and s_tilde, or a smaller max_kept, to shrink it).
+ * Device-side faults are reported by damas_check(NULL, stream).  Every call
+ * on a device shares that device's array: calls that overlap on one device
+ * (concurrent streams or threads) race, and must be serialised by the
+ * caller. */
+int damas_solve_static(const damas_geometry *g, int32_t n_bins, const double *freq,
+                       const double *csm, const damas_params *p, const int32_t *keep_count,
+                       const void *x_init, void *x_map, double *b_map, int32_t *idx,
+                       int32_t *s_tilde, void *stream);
+int64_t damas_static_scratch_bytes(void);
+
 /* Autotuner of the cooperative sweep schedule: times trial solves of this
  * problem (batched, trial_sweeps sweeps each, into a scratch map; for BF16
  * the bulk sweeps on the bf16 system) for one workgroup per bin and for a

@@ -595,20 +595,35 @@ extern "C" int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches)
     return damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, ms, launches);
 }
 
+namespace {
+int static_fault(int **out);
+}
+
 extern "C" int damas_check(damas_ctx *ctx, void *stream)
 {
     if (ctx)
         HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
-    // A context's own word, or the step-level calls' word of the device.
+    // A context's own word, or the step-level calls' word of the device
+    // and, once damas_solve_static has run on it, the static solve's word.
     int *fault = ctx ? ctx->fault : nullptr;
+    int *sfault = nullptr;
     if (!fault) {
         int rc = fault_word(&fault);
+        if (!rc)
+            rc = static_fault(&sfault);
         if (rc)
             return rc;
     }
     int v = 0;
     HIP_TRY(hipMemcpy(&v, fault, sizeof v, hipMemcpyDeviceToHost), "read fault word");
+    if (sfault) {
+        int w = 0;
+        HIP_TRY(hipMemcpy(&w, sfault, sizeof w, hipMemcpyDeviceToHost), "read fault word");
+        if (w)
+            HIP_TRY(hipMemset(sfault, 0, sizeof(int)), "clear fault word");
+        v |= w;
+    }
     if (v) {
         HIP_TRY(hipMemset(fault, 0, sizeof(int)), "clear fault word");
         // Bits: 4 a bin kept more points than max_kept; 8 a cooperative
@@ -1744,4 +1759,183 @@ extern "C" void damas_graph_destroy(damas_graph *gr)
         (void)hipGraphDestroy(gr->graph);
     --gr->ctx->graphs;
     delete gr;
+}
+
+// ---------------------------------------------------------------------------
+// whole-path solve without allocation: the workspace in a static device
+// array
+
+namespace {
+
+// Workspace of damas_solve_static: one array per device, held for the
+// process's lifetime.  Host code never passes the array's name to a kernel
+// or copy (it is a host-side stand-in there); it uses the device address
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t kStaticScratchBytes = (size_t)96 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, unsigned char *> g_scratch;
+
+// Device address of the current device's array, looked up once per
+// device; *out is null (and DAMAS_OK returned) when `create` is false and
+// no static solve has run on this device yet.
+int scratch_addr(unsigned char **out, bool create = true)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return DAMAS_OK;
+    }
+    *out = nullptr;
+    if (!create)
+        return DAMAS_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(DAMAS_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch[dev] = (unsigned char *)p;
+    *out = (unsigned char *)p;
+    return DAMAS_OK;
+}
+
+// The static solve's fault word: the first 4 bytes of the array.
+int static_fault(int **out)
+{
+    unsigned char *base = nullptr;
+    int rc = scratch_addr(&base, false);
+    *out = base ? (int *)base : nullptr;
+    return rc;
+}
+
+// Clears n words (a kernel, not a memset node, so a captured graph replays
+// it faithfully).
+__global__ void static_fill_zero(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Bump allocation of 256-byte aligned regions from the array.
+struct Carve {
+    unsigned char *base;
+    size_t used = 256; // bytes 0..255: the fault word
+    void *take(size_t bytes)
+    {
+        void *p = base + used;
+        used += (bytes + 255) & ~(size_t)255;
+        return p;
+    }
+};
+
+} // namespace
+
+extern "C" int64_t damas_static_scratch_bytes(void) { return (int64_t)kStaticScratchBytes; }
+
+extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const double *freq,
+                                  const double *csm, const damas_params *p,
+                                  const int32_t *keep_count, const void *x_init, void *x_map,
+                                  double *b_map, int32_t *idx, int32_t *s_tilde, void *stream)
+{
+    int rc = check_geometry(g);
+    if (rc)
+        return rc;
+    if (!p)
+        return fail(DAMAS_EINVAL, "params are NULL");
+    if (p->precision != DAMAS_PREC_FP64 && p->precision != DAMAS_PREC_FP32)
+        return fail(DAMAS_EINVAL, "damas_solve_static solves at FP64 or FP32 (precision %d)",
+                    p->precision);
+    if ((rc = check_mode(p->select_mode, p->eps)))
+        return rc;
+    if (p->predictor != DAMAS_PRED_HAAR && p->predictor != DAMAS_PRED_LINEAR)
+        return fail(DAMAS_EINVAL, "predictor = %d is not a DAMAS_PRED_* value", p->predictor);
+    if (p->policy != DAMAS_POLICY_AUTO && p->policy != DAMAS_POLICY_FIXED)
+        return fail(DAMAS_EINVAL, "policy = %d is not a DAMAS_POLICY_* value", p->policy);
+    if (!(p->rho_wide >= 0.0))
+        return fail(DAMAS_EINVAL, "rho_wide must be >= 0 (0: default)");
+    if (n_bins < 0 || p->iterations < 0)
+        return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
+    if (n_bins == 0)
+        return DAMAS_OK;
+    if (!freq || !csm || !x_map)
+        return fail(DAMAS_EINVAL, "freq, csm and x_map must be non-NULL");
+    if (p->select_mode == DAMAS_SEL_KEEP_COUNT && !keep_count)
+        return fail(DAMAS_EINVAL, "KEEP_COUNT needs keep_count (device, n_bins int32)");
+    const int32_t S = g->N * g->N, M = g->M;
+    const int32_t max_kept = p->select_mode == DAMAS_SEL_KEEP_ALL
+                                 ? S
+                                 : (p->max_kept > 0 ? std::min(p->max_kept, S) : S);
+    if ((rc = check_kept(max_kept, S, p->precision)))
+        return rc;
+
+    // Sizes of the workspace, all in the array.
+    const bool classes = p->policy == DAMAS_POLICY_AUTO && p->precision == DAMAS_PREC_FP32;
+    const size_t nb = (size_t)n_bins, es = elem_size(p->precision);
+    const int64_t ldm = ld_of(max_kept);
+    const int64_t e_stride = ldm * 2 * M;
+    const int64_t a_elems = (int64_t)n_bins * ldm * ldm;
+    const int64_t tiles = psf_tiles(max_kept);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t need = 256;
+    need += b_map ? 0 : al(sizeof(double) * nb * S);
+    need += idx ? 0 : al(sizeof(int32_t) * nb * S);
+    need += s_tilde ? 0 : al(sizeof(int32_t) * nb);
+    need += al(sizeof(int64_t) * (nb + 1)) + al(sizeof(double) * nb * e_stride) +
+            al(es * (size_t)a_elems);
+    if (classes)
+        need += al(sizeof(uint16_t) * (size_t)a_elems) + al(sizeof(double) * nb * tiles) +
+                al(nb);
+    if (need > kStaticScratchBytes)
+        return fail(DAMAS_EINVAL,
+                    "this solve needs %zu bytes of workspace; damas_solve_static holds %zu "
+                    "(fewer bins, a smaller max_kept, or caller-supplied b_map/idx/s_tilde)",
+                    need, kStaticScratchBytes);
+
+    unsigned char *base = nullptr;
+    if ((rc = scratch_addr(&base)))
+        return rc;
+    Carve c{base};
+    int *fault = (int *)base;
+    double *bm = b_map ? b_map : (double *)c.take(sizeof(double) * nb * S);
+    int32_t *ix = idx ? idx : (int32_t *)c.take(sizeof(int32_t) * nb * S);
+    int32_t *st = s_tilde ? s_tilde : (int32_t *)c.take(sizeof(int32_t) * nb);
+    int64_t *off = (int64_t *)c.take(sizeof(int64_t) * (nb + 1));
+    double *E = (double *)c.take(sizeof(double) * nb * e_stride);
+    void *A = c.take(es * (size_t)a_elems);
+    PsfClassArgs pc;
+    GsClassArgs gca;
+    if (classes) {
+        pc.lo = (uint16_t *)c.take(sizeof(uint16_t) * (size_t)a_elems);
+        pc.tsum = (double *)c.take(sizeof(double) * nb * tiles);
+        pc.cls = (uint8_t *)c.take(nb);
+        pc.rho_wide = p->rho_wide > 0.0 ? p->rho_wide : DAMAS_RHO_WIDE_DEFAULT;
+        pc.rho_f32 = HUGE_VAL;
+        pc.wide_cap = gs_wide_capacity();
+        gca.cls = pc.cls;
+        gca.lo = pc.lo;
+        gca.iters_cls = p->iterations;
+    }
+
+    hipStream_t s = (hipStream_t)stream;
+    const Geom kg = make_geom(*g);
+    hipLaunchKernelGGL(static_fill_zero, dim3(1), dim3(64), 0, s, (uint32_t *)fault, (int64_t)1);
+    HIP_TRY(hipGetLastError(), "fault word clear");
+    HIP_TRY(launch_das(kg, n_bins, freq, csm, bm, s), "das launch");
+    HIP_TRY(launch_select(g->N, n_bins, bm, p->select_mode, p->eps, p->predictor,
+                          p->select_mode == DAMAS_SEL_KEEP_COUNT ? keep_count : nullptr, ix, st,
+                          s),
+            "select launch");
+    HIP_TRY(launch_layout(n_bins, st, max_kept, a_elems, off, fault, s), "layout launch");
+    HIP_TRY(launch_steer(kg, n_bins, freq, ix, st, max_kept, E, e_stride, fault, s),
+            "steer launch");
+    HIP_TRY(launch_psf(M, n_bins, st, max_kept, p->precision, E, e_stride, off, A, fault, s, pc),
+            "psf launch");
+    HIP_TRY(launch_gs(g->N, n_bins, st, max_kept, ix, off, p->precision, 1, A, bm,
+                      p->iterations, x_init, x_map, fault, s, gca),
+            "gs launch");
+    return DAMAS_OK;
 }

@@ -112,6 +112,9 @@ PHASE_SYSTEM = 1
 _sig("damas_solve_dev", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
      c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
 _sig("damas_check", ctypes.c_int, c_vp, c_vp)
+_sig("damas_solve_static", ctypes.c_int, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params), c_vp,
+     c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
+_sig("damas_static_scratch_bytes", c_i64)
 _sig("damas_query_footprint", ctypes.c_int, c_i32, c_i32, c_i32, ctypes.POINTER(Params),
      ctypes.POINTER(ctypes.c_uint64))
 
@@ -367,6 +370,34 @@ def check(ctx=None, stream=None):
 
 
 # ---- the whole path ----------------------------------------------------------
+
+def static_scratch_bytes() -> int:
+    """Bytes of the static device workspace of solve_static."""
+    return int(_lib.damas_static_scratch_bytes())
+
+
+def solve_static(g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
+                 keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
+                 x_init=None, x_map=None, b_map=None, idx=None, s_tilde=None, predictor=0,
+                 policy=POLICY_AUTO, rho_wide=0.0, stream=None):
+    """The whole-path solve with no allocation by the library (damas_solve_static):
+    keep_count is a device int32 tensor of n_bins (KEEP_COUNT).  Faults are
+    reported by check(None)."""
+    csm = _as_interleaved(csm)
+    nb = freq.numel()
+    if x_map is None:
+        x_map = torch.empty(nb, g.N * g.N, dtype=_XTYPE[precision], device=freq.device)
+    p, _kc = _params(nb, select_mode, eps, None, iterations, precision, True, max_kept, 0,
+                     predictor, policy, rho_wide, 0.0)
+    dt = _XTYPE[precision]
+    _check(_lib.damas_solve_static(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
+                                   _ptr(csm, torch.float64, "csm"), ctypes.byref(p),
+                                   _ptr(keep_count, torch.int32, "keep_count"),
+                                   _ptr(x_init, dt, "x_init"), _ptr(x_map, dt, "x_map"),
+                                   _ptr(b_map, torch.float64, "b_map"),
+                                   _ptr(idx, torch.int32, "idx"),
+                                   _ptr(s_tilde, torch.int32, "s_tilde"), _stream(stream)))
+    return x_map
 
 class Context:
     """damas_ctx: the device workspace of whole-path solves."""
