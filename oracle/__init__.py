@@ -24,6 +24,9 @@ _SRC = os.path.join(_HERE, "damas_oracle.c")
 _HDR = os.path.join(_HERE, "damas_oracle.h")
 _LIB = os.path.join(_HERE, "libdamas_oracle.so")
 
+STEER_UNIT = 0
+STEER_PAPER = 1
+
 SEL_KEEP_ALL = 0
 SEL_EPS_REL = 1
 SEL_KEEP_COUNT = 2
@@ -72,6 +75,12 @@ def _load():
         lib.orc_solve_bin.argtypes = [P(_Geom), d, pd, i, d, i, i, pd, pd, pi,
                                       pd, pd]
         lib.orc_solve_bin.restype = i
+        lib.orc_steering_form.argtypes = [P(_Geom), d, i, i, pi, pd, pd]
+        lib.orc_das_map_ex.argtypes = [P(_Geom), d, pd, i, i, pd]
+        lib.orc_psf_ex.argtypes = [i, i, pd, pd, i, pd]
+        lib.orc_solve_bin_ex.argtypes = [P(_Geom), d, pd, i, i, i, d, i, i, pd, pd, pi,
+                                         pd, pd]
+        lib.orc_solve_bin_ex.restype = i
         _lib = lib
     return _lib
 
@@ -226,3 +235,70 @@ def _interleave(csm):
         return np.ascontiguousarray(np.stack([csm.real, csm.imag], axis=-1),
                                     dtype=np.float64)
     return np.ascontiguousarray(csm, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Options beside the default readings: the paper's steering pair and CSM
+# diagonal removal.
+
+def steering_form(geom: Geometry, freq: float, pts, form: int = STEER_UNIT):
+    """(v, w): beamformer vectors v_m(r) and propagation vectors (the paper's
+    g_m(r)) of the listed points, complex128 (len(pts), M) each.  The unit
+    form gives v = w = exp(-i k |r - r_m|) ("Beamforming"); the paper's pair
+    weights them by |r - r_m| / |r| and |r| / |r - r_m| ("Beamforming",
+    "DAMAS")."""
+    g, keep = geom._c()
+    pts = np.ascontiguousarray(pts, dtype=np.int32)
+    M = geom.mic.shape[0]
+    v = np.zeros((len(pts), M, 2))
+    w = np.zeros((len(pts), M, 2))
+    _load().orc_steering_form(ctypes.byref(g), float(freq), int(form), len(pts), _pi(pts),
+                              _pd(v), _pd(w))
+    return v[..., 0] + 1j * v[..., 1], w[..., 0] + 1j * w[..., 1]
+
+
+def das_map_ex(geom: Geometry, freq: float, csm: np.ndarray, form: int = STEER_UNIT,
+               diag_removal: bool = False) -> np.ndarray:
+    """Delay-and-sum map with a steering form and optional CSM diagonal
+    removal: b = (v^H C v - diag sum_m |v_m|^2 C_mm) / (M^2 - diag M)."""
+    g, keep = geom._c()
+    c = _interleave(csm)
+    b = np.zeros(geom.N * geom.N)
+    _load().orc_das_map_ex(ctypes.byref(g), float(freq), _pd(c), int(form),
+                           1 if diag_removal else 0, _pd(b))
+    return b
+
+
+def psf_ex(v: np.ndarray, w: np.ndarray, diag_removal: bool = False) -> np.ndarray:
+    """A[i][j] = (|v_i^H w_j|^2 - diag sum_m |v_im|^2 |w_jm|^2) / (M^2 - diag M):
+    row i the beamformer point, column j the source point."""
+    v = np.ascontiguousarray(v, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.complex128)
+    st, M = v.shape
+    vi = np.ascontiguousarray(np.stack([v.real, v.imag], axis=-1))
+    wi = np.ascontiguousarray(np.stack([w.real, w.imag], axis=-1))
+    A = np.zeros((st, st))
+    _load().orc_psf_ex(int(M), int(st), _pd(vi), _pd(wi), 1 if diag_removal else 0, _pd(A))
+    return A
+
+
+def solve_bin_ex(geom: Geometry, freq: float, csm: np.ndarray, mode: int,
+                 form: int = STEER_UNIT, diag_removal: bool = False, eps: float = 0.0,
+                 keep_count: int = 0, iters: int = 1000, x_init=None):
+    """One bin end to end with a steering form and diagonal removal."""
+    g, keep = geom._c()
+    S = geom.N * geom.N
+    c = _interleave(csm)
+    b = np.zeros(S)
+    idx = np.zeros(S, dtype=np.int32)
+    x = np.zeros(S)
+    xi = None if x_init is None else np.ascontiguousarray(x_init, dtype=np.float64)
+    mg = ctypes.c_double()
+    st = _load().orc_solve_bin_ex(ctypes.byref(g), float(freq), _pd(c), int(form),
+                                  1 if diag_removal else 0, int(mode), float(eps),
+                                  int(keep_count), int(iters),
+                                  None if xi is None else _pd(xi), _pd(b), _pi(idx), _pd(x),
+                                  ctypes.byref(mg))
+    if st < 0:
+        raise MemoryError("oracle allocation failed")
+    return {"b": b, "idx": idx[:st].copy(), "x": x, "margin": mg.value}

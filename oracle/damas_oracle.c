@@ -389,3 +389,130 @@ int orc_solve_bin(const orc_geom *g, double freq, const double *csm,
     free(b); free(e); free(A); free(bt); free(xt);
     return St;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Steering forms and CSM diagonal removal.                               */
+
+void orc_steering_form(const orc_geom *g, double freq, int form, int n_pts, const int *pts,
+                       double *v, double *w)
+{
+    double k = wavenumber(g, freq);
+    for (int p = 0; p < n_pts; ++p) {
+        double r[3];
+        orc_grid_point(g, pts[p], r);
+        /* |r|: distance from the point to the array centre (the origin). */
+        double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        for (int m = 0; m < g->M; ++m) {
+            double ddx = r[0] - g->mic[3 * m + 0];
+            double ddy = r[1] - g->mic[3 * m + 1];
+            double ddz = r[2] - g->mic[3 * m + 2];
+            double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            double c = cos(k * d), s = -sin(k * d);
+            /* v_m = (d / |r|) e_m, g_m = (|r| / d) e_m (paper); both e_m
+             * in the unit form */
+            double av = form == ORC_STEER_PAPER ? d / rn : 1.0;
+            double ag = form == ORC_STEER_PAPER ? rn / d : 1.0;
+            size_t o = (size_t)2 * ((size_t)p * g->M + m);
+            if (v) {
+                v[o] = av * c;
+                v[o + 1] = av * s;
+            }
+            if (w) {
+                w[o] = ag * c;
+                w[o + 1] = ag * s;
+            }
+        }
+    }
+}
+
+void orc_das_map_ex(const orc_geom *g, double freq, const double *csm, int form, int diag,
+                    double *b)
+{
+    int M = g->M;
+    int S = g->N * g->N;
+    double *v = (double *)malloc(sizeof(double) * 2 * (size_t)M);
+    double norm = (double)M * (double)M - (diag ? (double)M : 0.0);
+    for (int n = 0; n < S; ++n) {
+        orc_steering_form(g, freq, form, 1, &n, v, NULL);
+        /* sum_m sum_m' conj(v_m) C_mm' v_m', real part, without the m = m'
+         * terms when the diagonal is removed */
+        double acc = 0.0;
+        for (int m = 0; m < M; ++m) {
+            double ar = v[2 * m], ai = -v[2 * m + 1]; /* conj(v_m) */
+            for (int mp = 0; mp < M; ++mp) {
+                if (diag && mp == m)
+                    continue;
+                const double *c = csm + 2 * ((size_t)m * M + mp);
+                double tr = ar * c[0] - ai * c[1];
+                double ti = ar * c[1] + ai * c[0];
+                acc += tr * v[2 * mp] - ti * v[2 * mp + 1];
+            }
+        }
+        b[n] = acc / norm;
+    }
+    free(v);
+}
+
+void orc_psf_ex(int M, int St, const double *v, const double *w, int diag, double *A)
+{
+    /* the reciprocal, as orc_psf scales by 1 / M^2 */
+    double inv = 1.0 / ((double)M * (double)M - (diag ? (double)M : 0.0));
+    for (int i = 0; i < St; ++i) {
+        const double *vi = v + (size_t)2 * M * i;
+        for (int j = 0; j < St; ++j) {
+            const double *wj = w + (size_t)2 * M * j;
+            double re = 0.0, im = 0.0, dd = 0.0;
+            for (int m = 0; m < M; ++m) {
+                /* conj(v_im) * w_jm */
+                double ar = vi[2 * m], ai = -vi[2 * m + 1];
+                double br = wj[2 * m], bi = wj[2 * m + 1];
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+                /* |v_im|^2 |w_jm|^2: the m = m' term of |v_i^H w_j|^2 */
+                dd += (ar * ar + ai * ai) * (br * br + bi * bi);
+            }
+            A[(size_t)i * St + j] = (re * re + im * im - (diag ? dd : 0.0)) * inv;
+        }
+    }
+}
+
+int orc_solve_bin_ex(const orc_geom *g, double freq, const double *csm, int form, int diag,
+                     int mode, double eps, int keep_count, int iters, const double *x_init,
+                     double *b_map, int *idx, double *x_map, double *margin)
+{
+    int S = g->N * g->N;
+    int M = g->M;
+    double *b = (double *)malloc(sizeof(double) * (size_t)S);
+    if (!b)
+        return -1;
+    orc_das_map_ex(g, freq, csm, form, diag, b);
+    int St = orc_select(g->N, b, mode, eps, keep_count, idx, NULL, margin);
+
+    double *v = (double *)malloc(sizeof(double) * 2 * (size_t)M * (size_t)St);
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)M * (size_t)St);
+    double *A = (double *)malloc(sizeof(double) * (size_t)St * (size_t)St);
+    double *bt = (double *)malloc(sizeof(double) * (size_t)St);
+    double *xt = (double *)malloc(sizeof(double) * (size_t)St);
+    if (St && (!v || !w || !A || !bt || !xt)) {
+        free(b); free(v); free(w); free(A); free(bt); free(xt);
+        return -1;
+    }
+    orc_steering_form(g, freq, form, St, idx, v, w);
+    orc_psf_ex(M, St, v, w, diag, A);
+    for (int i = 0; i < St; ++i) {
+        bt[i] = b[idx[i]];
+        xt[i] = x_init ? x_init[idx[i]] : 0.0;
+    }
+    orc_gs(St, A, bt, iters, xt);
+
+    if (b_map)
+        memcpy(b_map, b, sizeof(double) * (size_t)S);
+    if (x_map) {
+        for (int n = 0; n < S; ++n)
+            x_map[n] = 0.0;
+        for (int i = 0; i < St; ++i)
+            x_map[idx[i]] = xt[i];
+    }
+    free(b); free(v); free(w); free(A); free(bt); free(xt);
+    return St;
+}

@@ -95,6 +95,41 @@ void orc_psf(int M, int St, const double *e, double *A);
  * rows 0..St-1 of A x = b, starting from the values in x, updated in place. */
 void orc_gs(int St, const double *A, const double *b, int iters, double *x);
 
+/* ---- options beside the default readings --------------------------- */
+
+/* Steering forms (section "Beamforming", the beamformer vector v, and
+ * section "DAMAS", the propagation vector g):
+ *  ORC_STEER_UNIT   v_m(r) = g_m(r) = exp(-i k |r - r_m|)  (the default);
+ *  ORC_STEER_PAPER  v_m(r) = (|r - r_m| / |r|) exp(-i k |r - r_m|),
+ *                   g_m(r) = (|r| / |r - r_m|) exp(-i k |r - r_m|),
+ *                   |r| the distance from the point to the array centre. */
+enum { ORC_STEER_UNIT = 0, ORC_STEER_PAPER = 1 };
+
+/* Beamformer vectors v (n_pts x M) and propagation vectors w (the paper's
+ * g, n_pts x M) of the listed points, complex interleaved; either output
+ * may be NULL. */
+void orc_steering_form(const orc_geom *g, double freq, int form, int n_pts, const int *pts,
+                       double *v, double *w);
+
+/* Delay-and-sum map with a steering form and optional removal of the CSM
+ * diagonal (section "Beamforming": diagonal removal is usually applied):
+ *   b_n = (v_n^H C v_n - diag * sum_m |v_nm|^2 C_mm) / (M^2 - diag * M). */
+void orc_das_map_ex(const orc_geom *g, double freq, const double *csm, int form, int diag,
+                    double *b);
+
+/* Point-spread matrix of beamformer vectors v and propagation vectors w
+ * (St x M each): A[i][j] = PSF(r_i | r_j), the map at point i of a unit
+ * source at point j, with the same diagonal removal as the map:
+ *   A[i][j] = (|v_i^H w_j|^2 - diag * sum_m |v_im|^2 |w_jm|^2) / (M^2 - diag M).
+ * Every entry is computed on its own (A is not symmetric for the paper's
+ * pair). */
+void orc_psf_ex(int M, int St, const double *v, const double *w, int diag, double *A);
+
+/* orc_solve_bin with a steering form and diagonal removal. */
+int orc_solve_bin_ex(const orc_geom *g, double freq, const double *csm, int form, int diag,
+                     int mode, double eps, int keep_count, int iters, const double *x_init,
+                     double *b_map, int *idx, double *x_map, double *margin);
+
 /* The whole path for one frequency bin: DAS map, selection, compressed
  * system, sweeps.  x_init (nullable) is a full N*N map whose kept entries
  * start the sweeps (zero otherwise).  Outputs (all nullable except idx):

@@ -82,26 +82,34 @@ def grid_xyz(N: int, x0: float, x1: float, y0: float, y1: float, z0: float,
 
 
 def monopole_field(mic: np.ndarray, src_xyz: np.ndarray, freq: float,
-                   c: float = SPEED_OF_SOUND) -> np.ndarray:
-    """Free-field pressure at each mic from unit monopoles: M x K complex."""
+                   c: float = SPEED_OF_SOUND, model: str = "unit") -> np.ndarray:
+    """Free-field pressure at each mic from monopoles: M x K complex.
+    model "unit": unit magnitude exp(-i k d) at every mic; model "spherical":
+    the 1/d spreading of a monopole normalised to the pressure at the array
+    centre, (|r_s| / d) exp(-i k d), d = |r_s - r_m|."""
     dist = np.linalg.norm(mic[:, None, :] - src_xyz[None, :, :], axis=-1)
-    return np.exp(-1j * (2.0 * np.pi * freq / c) * dist)
+    p = np.exp(-1j * (2.0 * np.pi * freq / c) * dist)
+    if model == "spherical":
+        p = p * (np.linalg.norm(src_xyz, axis=-1)[None, :] / dist)
+    elif model != "unit":
+        raise ValueError(f"unknown source model {model!r}")
+    return p
 
 
-def exact_csm(mic, src_xyz, powers, freq, c=SPEED_OF_SOUND) -> np.ndarray:
+def exact_csm(mic, src_xyz, powers, freq, c=SPEED_OF_SOUND, model="unit") -> np.ndarray:
     """C = sum_k q_k g_k g_k^H: the expectation of Eq. (1) for uncorrelated
     sources without noise."""
-    g = monopole_field(mic, src_xyz, freq, c)
+    g = monopole_field(mic, src_xyz, freq, c, model)
     C = (g * powers[None, :]) @ g.conj().T
     return 0.5 * (C + C.conj().T)
 
 
 def snapshot_csm(mic, src_xyz, powers, freq, n_snap, snr_db, seed_key,
-                 c=SPEED_OF_SOUND) -> np.ndarray:
+                 c=SPEED_OF_SOUND, model="unit") -> np.ndarray:
     """Eq. (1): average of p_i p_i^H over n_snap complex-Gaussian snapshots
     with white noise at the given per-microphone SNR."""
     rng = _rng(*seed_key, _SNAPSHOTS)
-    g = monopole_field(mic, src_xyz, freq, c)
+    g = monopole_field(mic, src_xyz, freq, c, model)
     K = len(powers)
     M = mic.shape[0]
     s = (rng.standard_normal((K, n_snap)) + 1j * rng.standard_normal((K, n_snap)))
@@ -294,7 +302,7 @@ def served_request(seed: int, table_bins: int = 64) -> Workload:
 
 def custom(mic, N, extent, z0, freqs, src_pts, powers, *, snapshots=None,
            snr_db=None, seed=99, select_mode=SEL_KEEP_ALL, eps=0.0,
-           keep_count=0, iterations=100, precision="fp32") -> Workload:
+           keep_count=0, iterations=100, precision="fp32", model="unit") -> Workload:
     """A small workload for tests: exact CSM when ``snapshots`` is None."""
     x0, x1, y0, y1 = extent
     src_pts = np.asarray(src_pts)
@@ -302,10 +310,10 @@ def custom(mic, N, extent, z0, freqs, src_pts, powers, *, snapshots=None,
     xyz = grid_xyz(N, x0, x1, y0, y1, z0, src_pts)
     freqs = np.asarray(freqs, dtype=np.float64)
     if snapshots is None:
-        csm = np.stack([exact_csm(mic, xyz, powers, f) for f in freqs])
+        csm = np.stack([exact_csm(mic, xyz, powers, f, model=model) for f in freqs])
     else:
         csm = np.stack([snapshot_csm(mic, xyz, powers, f, snapshots, snr_db,
-                                     (seed, b)) for b, f in enumerate(freqs)])
+                                     (seed, b), model=model) for b, f in enumerate(freqs)])
     return Workload("custom", np.asarray(mic, dtype=np.float64), N, x0, x1, y0,
                     y1, z0, freqs, csm, select_mode, eps=eps,
                     keep_count=keep_count, iterations=iterations,
