@@ -89,6 +89,16 @@ extern "C" {
                              the sweep state and row residuals stay
                              double, partial sums FP32 as above            */
 
+/* ---- steering forms (section "Beamforming" v_m, section "DAMAS" g_m) ---- */
+#define DAMAS_STEER_UNIT 0  /* v_m(r) = g_m(r) = exp(-i k |r - r_m|): A is
+                               symmetric with A_nn = 1 (the default)        */
+#define DAMAS_STEER_PAPER 1 /* the paper's pair: beamformer
+                               v_m(r) = (|r - r_m| / |r|) exp(-i k |r - r_m|),
+                               source model
+                               g_m(r) = (|r| / |r - r_m|) exp(-i k |r - r_m|),
+                               |r| the distance to the array centre; A is
+                               not symmetric, A_nn = 1                      */
+
 /* ---- per-bin precision policy of a whole-path solve ------------------ */
 #define DAMAS_POLICY_AUTO 0  /* per bin, the storage of A that keeps the
                                 iterate within about 1e-4 of the FP64
@@ -229,6 +239,39 @@ int damas_layout(int32_t n_bins, int32_t *s_tilde, int32_t max_kept,
 int damas_steer(const damas_geometry *g, int32_t n_bins, const double *freq,
                 const int32_t *idx, const int32_t *s_tilde, int32_t max_kept,
                 double *E, int64_t e_stride, void *stream);
+
+/* damas_das_map with a steering form (DAMAS_STEER_*) and, with
+ * diag_removal = 1, the CSM diagonal removed (section "Beamforming": the
+ * m = m' terms dropped, the map normalised by M^2 - M):
+ *   b[f*S + n] = Re(v_n^H C_f v_n - diag * sum_m |v_nm|^2 C_f,mm) /
+ *                (M^2 - diag * M),
+ * v_n the unit steering vector or the paper's beamformer vector.  Same
+ * arguments and errors as damas_das_map otherwise. */
+int damas_das_map_ex(const damas_geometry *g, int32_t n_bins, const double *freq,
+                     const double *csm, int32_t steering, int32_t diag_removal, double *b,
+                     void *stream);
+
+/* damas_steer with a steering form: DAMAS_STEER_UNIT as damas_steer;
+ * DAMAS_STEER_PAPER writes two row sets per bin, rows [0, ld) the
+ * beamformer vectors v = (|r - r_m| / |r|) e and rows [ld, 2 ld) the
+ * propagation vectors g = (|r| / |r - r_m|) e (ld = damas_ld(s_tilde[f]);
+ * e_stride >= 2 damas_ld(max_kept) 2M when n_bins > 1). */
+int damas_steer_ex(const damas_geometry *g, int32_t n_bins, const double *freq,
+                   const int32_t *idx, const int32_t *s_tilde, int32_t max_kept,
+                   int32_t steering, double *E, int64_t e_stride, void *stream);
+
+/* damas_psf with a steering form and diagonal removal, from the rows of
+ * damas_steer_ex.  DAMAS_STEER_UNIT: A as damas_psf, symmetric.
+ * DAMAS_STEER_PAPER: A is not symmetric and the arena holds it TRANSPOSED,
+ * row r = source point, column c = beam point:
+ *   A_f[r*ld + c] = PSF(r_c | r_r) = |v_c^H g_r|^2 / M^2,
+ * which is the layout damas_gs reads (a strip of 64 columns holds the
+ * coefficients of 64 rows of A x).  diag_removal = 1: every entry becomes
+ * (|.|^2 - sum_m |v_m|^2 |g_m|^2) / (M^2 - M) (M for unit steering), the
+ * diagonal stays 1 exactly and padding 0. */
+int damas_psf_ex(int32_t M, int32_t n_bins, const int32_t *s_tilde, int32_t max_kept,
+                 int32_t precision, int32_t steering, int32_t diag_removal, const double *E,
+                 int64_t e_stride, const int64_t *off, void *A, void *stream);
 
 /* Half-width of a bf16 steering row: M rounded up to 16. */
 int32_t damas_mp(int32_t M);
@@ -384,6 +427,13 @@ struct damas_params {
     double rho_wide;           /* AUTO: widening threshold (0: default)     */
     double rho_f32;            /* AUTO, BF16: bf16 bulk only at rho <= this
                                   (0: default)                              */
+    int32_t steering;          /* DAMAS_STEER_* (0 = UNIT); PAPER needs
+                                  FP64 or FP32 precision                    */
+    int32_t diag_removal;      /* 1: remove the CSM diagonal from the map
+                                  (section "Beamforming") and use the
+                                  matching PSF, A = (|v^H g|^2 -
+                                  sum_m |v_m|^2 |g_m|^2) / (M^2 - M); the
+                                  map may then be negative                  */
 };
 
 /* Storage class of each bin in the context's last batched solve under

@@ -104,6 +104,19 @@ int check_psf_precision(int32_t p)
     return DAMAS_OK;
 }
 
+// Steering form and diagonal removal of a solve (the paper's pair needs the
+// double steering rows of the f64 PSF: FP64 or FP32 storage).
+int check_form(int32_t steering, int32_t diag, int32_t precision)
+{
+    if (steering != DAMAS_STEER_UNIT && steering != DAMAS_STEER_PAPER)
+        return fail(DAMAS_EINVAL, "steering = %d is not a DAMAS_STEER_* value", steering);
+    if (diag != 0 && diag != 1)
+        return fail(DAMAS_EINVAL, "diag_removal must be 0 or 1");
+    if (steering == DAMAS_STEER_PAPER && precision == DAMAS_PREC_BF16)
+        return fail(DAMAS_EINVAL, "the paper's steering pair is built at FP64 or FP32");
+    return DAMAS_OK;
+}
+
 int check_mode(int32_t mode, double eps)
 {
     if (mode != DAMAS_SEL_KEEP_ALL && mode != DAMAS_SEL_EPS_REL &&
@@ -341,6 +354,75 @@ extern "C" int damas_psf(int32_t M, int32_t n_bins, const int32_t *s_tilde,
         return rc;
     HIP_TRY(launch_psf(M, n_bins, s_tilde, max_kept, precision, E, e_stride, off,
                        A, fault, (hipStream_t)stream),
+            "psf launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_das_map_ex(const damas_geometry *g, int32_t n_bins, const double *freq,
+                                const double *csm, int32_t steering, int32_t diag_removal,
+                                double *b, void *stream)
+{
+    int rc = check_geometry(g);
+    if (rc || (rc = check_form(steering, diag_removal, DAMAS_PREC_FP64)))
+        return rc;
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    if (n_bins > 0 && (!freq || !csm || !b))
+        return fail(DAMAS_EINVAL, "freq, csm and b must be non-NULL");
+    HIP_TRY(launch_das(make_geom(*g), n_bins, freq, csm, b, (hipStream_t)stream, steering,
+                       diag_removal),
+            "das launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_steer_ex(const damas_geometry *g, int32_t n_bins, const double *freq,
+                              const int32_t *idx, const int32_t *s_tilde, int32_t max_kept,
+                              int32_t steering, double *E, int64_t e_stride, void *stream)
+{
+    int rc = check_geometry(g);
+    if (rc || (rc = check_form(steering, 0, DAMAS_PREC_FP64)))
+        return rc;
+    const int32_t S = g->N * g->N;
+    if (n_bins < 0)
+        return fail(DAMAS_EINVAL, "n_bins < 0");
+    if (max_kept < 0 || max_kept > S)
+        return fail(DAMAS_EINVAL, "max_kept = %d outside [0, N*N]", max_kept);
+    if (n_bins > 0 && (!freq || !idx || !s_tilde || !E))
+        return fail(DAMAS_EINVAL, "freq, idx, s_tilde and E must be non-NULL");
+    const int64_t rows = ld_of(max_kept) * (steering == DAMAS_STEER_PAPER ? 2 : 1);
+    if (n_bins > 1 && e_stride < rows * 2 * g->M)
+        return fail(DAMAS_EINVAL, "e_stride < rows * 2M (two row sets for the paper's pair)");
+    int *fault;
+    if ((rc = fault_word(&fault)))
+        return rc;
+    HIP_TRY(launch_steer(make_geom(*g), n_bins, freq, idx, s_tilde, max_kept, E, e_stride,
+                         fault, (hipStream_t)stream, steering),
+            "steer launch");
+    return DAMAS_OK;
+}
+
+extern "C" int damas_psf_ex(int32_t M, int32_t n_bins, const int32_t *s_tilde,
+                            int32_t max_kept, int32_t precision, int32_t steering,
+                            int32_t diag_removal, const double *E, int64_t e_stride,
+                            const int64_t *off, void *A, void *stream)
+{
+    int rc = check_psf_precision(precision);
+    if (rc || (rc = check_form(steering, diag_removal, precision)))
+        return rc;
+    if (M < 1 || M > 128)
+        return fail(DAMAS_EINVAL, "M = %d outside [1, 128]", M);
+    if (n_bins < 0 || max_kept < 0)
+        return fail(DAMAS_EINVAL, "n_bins and max_kept must be >= 0");
+    if (n_bins > 0 && (!s_tilde || !E || !off || !A))
+        return fail(DAMAS_EINVAL, "s_tilde, E, off and A must be non-NULL");
+    const int64_t rows = ld_of(max_kept) * (steering == DAMAS_STEER_PAPER ? 2 : 1);
+    if (n_bins > 1 && e_stride < rows * 2 * M)
+        return fail(DAMAS_EINVAL, "e_stride < rows * 2M (two row sets for the paper's pair)");
+    int *fault;
+    if ((rc = fault_word(&fault)))
+        return rc;
+    HIP_TRY(launch_psf(M, n_bins, s_tilde, max_kept, precision, E, e_stride, off, A, fault,
+                       (hipStream_t)stream, PsfClassArgs(), steering, diag_removal),
             "psf launch");
     return DAMAS_OK;
 }
@@ -652,6 +734,7 @@ struct SolvePlan {
     std::vector<int32_t> st_host; // kept points per bin, where the host knows them
     int32_t bulk, refine;         // sweeps on the storage precision / FP32 copy
     bool classes;                 // per-bin precision classes (DAMAS_POLICY_AUTO)
+    int steering, diag;           // steering form, CSM diagonal removal
     double rho_wide, rho_f32;     // their thresholds
     int64_t e_stride, e16_stride;
     int64_t a_elems;
@@ -681,6 +764,8 @@ int make_plan(int32_t M, int32_t N, int32_t n_bins, const damas_params *p, Solve
         return fail(DAMAS_EINVAL, "policy = %d is not a DAMAS_POLICY_* value", p->policy);
     if (!(p->rho_wide >= 0.0) || !(p->rho_f32 >= 0.0))
         return fail(DAMAS_EINVAL, "rho_wide and rho_f32 must be >= 0 (0: defaults)");
+    if ((rc = check_form(p->steering, p->diag_removal, p->precision)))
+        return rc;
     P.bf16 = p->precision == DAMAS_PREC_BF16;
     if (P.bf16 && (p->refine_sweeps < 0 || p->refine_sweeps > p->iterations))
         return fail(DAMAS_EINVAL, "refine_sweeps = %d outside [0, iterations = %d]",
@@ -716,7 +801,10 @@ int make_plan(int32_t M, int32_t N, int32_t n_bins, const damas_params *p, Solve
     const int64_t ldm = ld_of(P.max_kept);
     P.refine = P.bf16 ? p->refine_sweeps : 0;
     P.bulk = p->iterations - P.refine;
-    P.e_stride = ldm * 2 * M;
+    P.steering = p->steering;
+    P.diag = p->diag_removal;
+    // the paper's pair keeps two row sets (beamformer, propagation) per bin
+    P.e_stride = ldm * 2 * M * (P.steering == DAMAS_STEER_PAPER ? 2 : 1);
     P.e16_stride = ldm * 2 * mp_of(M);
     if (!P.batched) {
         P.a_elems = ldm * ldm;
@@ -763,7 +851,8 @@ size_t plan_workspace_bytes(const SolvePlan &P, bool own_b, bool own_idx, bool o
         t += sizeof(float) * (size_t)P.a_elems;
     if (P.classes)
         t += sizeof(uint16_t) * (size_t)P.a_elems +
-             sizeof(double) * (size_t)P.nb_ws * (size_t)psf_tiles(P.max_kept) + (size_t)P.nb_ws;
+             sizeof(double) * (size_t)P.nb_ws * (size_t)psf_tiles(P.max_kept, P.steering) +
+             (size_t)P.nb_ws;
     return t;
 }
 
@@ -798,8 +887,9 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
     if (P.classes &&
         ((rc = ensure(ctx, ctx->Alo, sizeof(uint16_t) * (size_t)P.a_elems, s, "lo arena")) ||
          (rc = ensure(ctx, ctx->tsum,
-                      sizeof(double) * (size_t)P.nb_ws * (size_t)psf_tiles(P.max_kept), s,
-                      "tile sums")) ||
+                      sizeof(double) * (size_t)P.nb_ws *
+                          (size_t)psf_tiles(P.max_kept, P.steering),
+                      s, "tile sums")) ||
          (rc = ensure(ctx, ctx->cls, (size_t)P.nb_ws, s, "bin classes"))))
         return rc;
     P.bm = b_map ? b_map : (double *)ctx->b.p;
@@ -1028,11 +1118,11 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
     // Storage-precision system (bulk sweeps) and, for BF16, the FP32 copy.
     if (build && P.need64) {
         HIP_TRY(launch_steer(P.kg, nb, freq, ix, st, max_kept, (double *)ctx->E.p, P.e_stride,
-                             P.fault, s),
+                             P.fault, s, P.steering),
                 "steer launch");
         HIP_TRY(launch_psf(P.M, nb, st, max_kept, bf16 ? DAMAS_PREC_FP32 : p->precision,
                            (const double *)ctx->E.p, P.e_stride, P.off,
-                           bf16 ? ctx->A32.p : ctx->A.p, P.fault, s, pc),
+                           bf16 ? ctx->A32.p : ctx->A.p, P.fault, s, pc, P.steering, P.diag),
                 "psf launch");
     }
     if (build && P.need16) {
@@ -1040,7 +1130,7 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
                                P.e16_stride, P.fault, s),
                 "steer16 launch");
         HIP_TRY(launch_psf16(P.M, nb, st, max_kept, (const uint16_t *)ctx->E16.p,
-                             P.e16_stride, P.off, (uint16_t *)ctx->A.p, P.fault, s),
+                             P.e16_stride, P.off, (uint16_t *)ctx->A.p, P.fault, s, P.diag),
                 "psf16 launch");
     }
     std::pair<hipEvent_t, hipEvent_t> ev{};
@@ -1174,7 +1264,7 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
     const int32_t S = P.S, M = P.M;
 
     if (P.batched) {
-        HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s), "das launch");
+        HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s, P.steering, P.diag), "das launch");
         HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, p->predictor, P.kc, P.ix,
                               P.st, s),
                 "select launch");
@@ -1189,7 +1279,8 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
         const size_t fS = (size_t)f * S;
         const char *xi = x_init ? (const char *)x_init + P.xs * fS : nullptr;
         char *xm = (char *)x_map + P.xs * fS;
-        HIP_TRY(launch_das(P.kg, 1, freq + f, csm + (size_t)f * M * M * 2, P.bm + fS, s),
+        HIP_TRY(launch_das(P.kg, 1, freq + f, csm + (size_t)f * M * M * 2, P.bm + fS, s,
+                           P.steering, P.diag),
                 "das launch");
         HIP_TRY(launch_select(P.N, 1, P.bm + fS, p->select_mode, p->eps, p->predictor,
                               P.kc ? P.kc + f : nullptr, P.ix + fS, P.st + f, s),
@@ -1379,7 +1470,7 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
     P.kg = make_geom(*g);
     if ((rc = prepare(ctx, P, nullptr, nullptr, s_tilde, s)))
         return rc;
-    HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s), "das launch");
+    HIP_TRY(launch_das(P.kg, n_bins, freq, csm, P.bm, s, P.steering, P.diag), "das launch");
     HIP_TRY(launch_select(P.N, n_bins, P.bm, p->select_mode, p->eps, p->predictor, P.kc, P.ix,
                               P.st, s),
             "select launch");
@@ -1403,9 +1494,10 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
             "read freq");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     std::string key;
-    const int32_t hdr[6] = {g->M, g->N, p->precision, P.need64, P.need16, P.classes};
+    const int32_t hdr[8] = {g->M,      g->N,      p->precision, P.need64,
+                            P.need16,  P.classes, P.steering,   P.diag};
     const double box[8] = {g->x0, g->x1, g->y0, g->y1, g->z0, g->c, P.rho_wide, P.rho_f32};
-    append(key, hdr, 6);
+    append(key, hdr, 8);
     append(key, box, P.classes ? 8 : 6);
     append(key, mic.data(), mic.size());
     append(key, fr.data(), fr.size());
@@ -1857,6 +1949,8 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
         return fail(DAMAS_EINVAL, "policy = %d is not a DAMAS_POLICY_* value", p->policy);
     if (!(p->rho_wide >= 0.0))
         return fail(DAMAS_EINVAL, "rho_wide must be >= 0 (0: default)");
+    if ((rc = check_form(p->steering, p->diag_removal, p->precision)))
+        return rc;
     if (n_bins < 0 || p->iterations < 0)
         return fail(DAMAS_EINVAL, "n_bins and iterations must be >= 0");
     if (n_bins == 0)
@@ -1876,9 +1970,9 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
     const bool classes = p->policy == DAMAS_POLICY_AUTO && p->precision == DAMAS_PREC_FP32;
     const size_t nb = (size_t)n_bins, es = elem_size(p->precision);
     const int64_t ldm = ld_of(max_kept);
-    const int64_t e_stride = ldm * 2 * M;
+    const int64_t e_stride = ldm * 2 * M * (p->steering == DAMAS_STEER_PAPER ? 2 : 1);
     const int64_t a_elems = (int64_t)n_bins * ldm * ldm;
-    const int64_t tiles = psf_tiles(max_kept);
+    const int64_t tiles = psf_tiles(max_kept, p->steering);
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     size_t need = 256;
     need += b_map ? 0 : al(sizeof(double) * nb * S);
@@ -1924,15 +2018,18 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
     const Geom kg = make_geom(*g);
     hipLaunchKernelGGL(static_fill_zero, dim3(1), dim3(64), 0, s, (uint32_t *)fault, (int64_t)1);
     HIP_TRY(hipGetLastError(), "fault word clear");
-    HIP_TRY(launch_das(kg, n_bins, freq, csm, bm, s), "das launch");
+    HIP_TRY(launch_das(kg, n_bins, freq, csm, bm, s, p->steering, p->diag_removal),
+            "das launch");
     HIP_TRY(launch_select(g->N, n_bins, bm, p->select_mode, p->eps, p->predictor,
                           p->select_mode == DAMAS_SEL_KEEP_COUNT ? keep_count : nullptr, ix, st,
                           s),
             "select launch");
     HIP_TRY(launch_layout(n_bins, st, max_kept, a_elems, off, fault, s), "layout launch");
-    HIP_TRY(launch_steer(kg, n_bins, freq, ix, st, max_kept, E, e_stride, fault, s),
+    HIP_TRY(launch_steer(kg, n_bins, freq, ix, st, max_kept, E, e_stride, fault, s,
+                         p->steering),
             "steer launch");
-    HIP_TRY(launch_psf(M, n_bins, st, max_kept, p->precision, E, e_stride, off, A, fault, s, pc),
+    HIP_TRY(launch_psf(M, n_bins, st, max_kept, p->precision, E, e_stride, off, A, fault, s, pc,
+                       p->steering, p->diag_removal),
             "psf launch");
     HIP_TRY(launch_gs(g->N, n_bins, st, max_kept, ix, off, p->precision, 1, A, bm,
                       p->iterations, x_init, x_map, fault, s, gca),

@@ -60,6 +60,15 @@ __device__ inline double point_mic_dist(const Geom &g, int n, int m)
     return sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
 }
 
+// Distance from grid point n to the array centre (the origin), in double.
+__device__ inline double point_origin_dist(const Geom &g, int n)
+{
+    int ix = n % g.N, iy = n / g.N;
+    double px = g.x0 + (double)ix * g.dx;
+    double py = g.y0 + (double)iy * g.dy;
+    return sqrt(px * px + py * py + g.z0 * g.z0);
+}
+
 // Lane-uniform broadcast of lane `src` (wave64); src must be uniform.
 __device__ inline float lane_bcast(float v, int src)
 {
@@ -80,8 +89,11 @@ hipError_t launch_csm(int M, int K, int n_bins, const double *snap, double *csm,
                       hipStream_t s);
 int csm_upper_blocks(int M);
 
+// steering: DAMAS_STEER_UNIT or DAMAS_STEER_PAPER; diag: remove the CSM
+// diagonal.
 hipError_t launch_das(const Geom &g, int n_bins, const double *freq,
-                      const double *csm, double *b, hipStream_t s);
+                      const double *csm, double *b, hipStream_t s,
+                      int steering = DAMAS_STEER_UNIT, int diag = 0);
 
 hipError_t launch_select(int N, int n_bins, const double *b, int mode,
                          double eps, int predictor, const int32_t *keep_count, int32_t *idx,
@@ -95,10 +107,12 @@ hipError_t launch_layout(int n_bins, int32_t *s_tilde, int max_kept,
 // (once per kernel).
 hipError_t allow_big_lds(const void *kernel);
 
+// steering DAMAS_STEER_PAPER writes two row sets per bin: the beamformer
+// vectors in rows [0, ld), the propagation vectors in rows [ld, 2 ld).
 hipError_t launch_steer(const Geom &g, int n_bins, const double *freq,
                         const int32_t *idx, const int32_t *s_tilde,
                         int max_kept, double *E, int64_t e_stride, int *fault,
-                        hipStream_t s);
+                        hipStream_t s, int steering = DAMAS_STEER_UNIT);
 
 // Storage classes of a bin (see PsfClassArgs and GsClassArgs).
 constexpr int kClsF32 = 1, kClsWide = 2;
@@ -116,11 +130,16 @@ struct PsfClassArgs {
     double rho_wide = 0.0, rho_f32 = 0.0;
     int wide_cap = 0;
 };
-int64_t psf_tiles(int max_kept);
+// Tiles of a bin's PSF launch grid: the upper triangle, or every tile for
+// the paper's (non-symmetric) pair.
+int64_t psf_tiles(int max_kept, int steering = DAMAS_STEER_UNIT);
+// steering: the paper's pair stores A transposed (see psf.hip); diag: the
+// CSM diagonal removed, A = (|G|^2 - sum |v|^2 |g|^2) / (M^2 - M).
 hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                       int precision, const double *E, int64_t e_stride,
                       const int64_t *off, void *A, int *fault, hipStream_t s,
-                      const PsfClassArgs &pc = PsfClassArgs());
+                      const PsfClassArgs &pc = PsfClassArgs(),
+                      int steering = DAMAS_STEER_UNIT, int diag = 0);
 
 // bf16 steering rows (half-width MP = M rounded up to 16) and the PSF on the
 // bf16 matrix cores.
@@ -130,7 +149,7 @@ hipError_t launch_steer16(const Geom &g, int n_bins, const double *freq, const i
                           int *fault, hipStream_t s);
 hipError_t launch_psf16(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                         const uint16_t *E, int64_t e_stride, const int64_t *off, uint16_t *A,
-                        int *fault, hipStream_t s);
+                        int *fault, hipStream_t s, int diag = 0);
 
 // Per-bin storage classes of a sweep launch: cls (per bin, device, or
 // null: every bin of class 0) with kClsF32 = every sweep on the float

@@ -1,5 +1,9 @@
 // Delay-and-sum beamforming map (section "Beamforming", Eq. dirty_map_1):
-// b_n = Re(e_n^H C e_n) / M^2 at every grid point of every bin, in double.
+// b_n = Re(v_n^H C v_n) / M^2 at every grid point of every bin, in double,
+// with v the unit-magnitude steering vector e_n or (the paper's beamformer
+// vector) v_nm = (|r_n - r_m| / |r_n|) e_nm; with the CSM diagonal removed
+// (the paper notes it is usually applied) the m = m' terms are dropped and
+// the map is normalised by M^2 - M instead.
 //
 // One workgroup = one bin x 64 grid points; lane = grid point.  The 64
 // steering vectors of the tile are built once into LDS (M x 64 complex
@@ -13,11 +17,12 @@ namespace damas {
 constexpr int kDasPts = 64;
 constexpr int kDasThreads = 256;
 
+template <bool PAPER, bool DIAG>
 __global__ __launch_bounds__(kDasThreads) void das_kernel(
     Geom g, int S, const double *__restrict__ freq,
     const double *__restrict__ csm, double *__restrict__ b)
 {
-    extern __shared__ double2 sh_e[]; // [M][64]: (cos, -sin) of k d
+    extern __shared__ double2 sh_e[]; // [M][64]: a (cos, -sin) of k d, a = 1 or d / |r|
     __shared__ double part[kDasThreads / 64][kDasPts];
 
     const int f = blockIdx.y;
@@ -31,8 +36,10 @@ __global__ __launch_bounds__(kDasThreads) void das_kernel(
         double2 e = make_double2(0.0, 0.0);
         if (n < S) {
             double s, c;
-            sincos(k * point_mic_dist(g, n, m), &s, &c);
-            e = make_double2(c, -s);
+            const double d = point_mic_dist(g, n, m);
+            sincos(k * d, &s, &c);
+            const double a = PAPER ? d / point_origin_dist(g, n) : 1.0;
+            e = make_double2(a * c, -a * s);
         }
         sh_e[m * kDasPts + p] = e;
     }
@@ -66,31 +73,51 @@ __global__ __launch_bounds__(kDasThreads) void das_kernel(
             acc += e1.x * y1r + e1.y * y1i;
         }
     }
+    if (DIAG) {
+        // The m = m' terms, |v_m|^2 C_mm (C_mm real), of this wave's rows.
+        double dsum = 0.0;
+        for (int m = w; m < M; m += 4) {
+            const double2 e = sh_e[m * kDasPts + lane];
+            dsum += (e.x * e.x + e.y * e.y) * C[((size_t)m * M + m) * 2];
+        }
+        acc -= dsum;
+    }
     part[w][lane] = acc;
     __syncthreads();
     if (threadIdx.x < kDasPts) {
         int n = p0 + lane;
         if (n < S) {
             double s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-            b[(size_t)f * S + n] = s / ((double)M * (double)M);
+            b[(size_t)f * S + n] = s / ((double)M * (double)M - (DIAG ? (double)M : 0.0));
         }
     }
 }
 
-hipError_t launch_das(const Geom &g, int n_bins, const double *freq,
-                      const double *csm, double *b, hipStream_t s)
+template <bool PAPER, bool DIAG>
+static hipError_t launch_das_t(const Geom &g, int n_bins, const double *freq,
+                               const double *csm, double *b, hipStream_t s)
 {
     const int S = g.N * g.N;
-    if (n_bins == 0 || S == 0)
-        return hipSuccess;
     dim3 grid((S + kDasPts - 1) / kDasPts, n_bins);
     size_t lds = sizeof(double2) * (size_t)g.M * kDasPts;
-    static const hipError_t attr = allow_big_lds((const void *)das_kernel);
+    static const hipError_t attr = allow_big_lds((const void *)das_kernel<PAPER, DIAG>);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL(das_kernel, grid, dim3(kDasThreads), lds, s, g, S, freq,
+    hipLaunchKernelGGL((das_kernel<PAPER, DIAG>), grid, dim3(kDasThreads), lds, s, g, S, freq,
                        csm, b);
     return hipGetLastError();
+}
+
+hipError_t launch_das(const Geom &g, int n_bins, const double *freq,
+                      const double *csm, double *b, hipStream_t s, int steering, int diag)
+{
+    if (n_bins == 0 || g.N == 0)
+        return hipSuccess;
+    if (steering == DAMAS_STEER_PAPER)
+        return diag ? launch_das_t<true, true>(g, n_bins, freq, csm, b, s)
+                    : launch_das_t<true, false>(g, n_bins, freq, csm, b, s);
+    return diag ? launch_das_t<false, true>(g, n_bins, freq, csm, b, s)
+                : launch_das_t<false, false>(g, n_bins, freq, csm, b, s);
 }
 
 } // namespace damas

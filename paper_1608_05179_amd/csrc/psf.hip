@@ -9,6 +9,15 @@
 // cores (16x16x4 f64 MFMA); A is formed in double and rounded once to its
 // storage type.  A is symmetric, so only tiles I <= J are computed and each
 // value is written to (i,j) and (j,i).
+//
+// With the paper's pair (beamformer v, propagation g of different
+// magnitudes) A is not symmetric: every tile is computed, and the arena
+// holds A transposed, row r = source point, column c = beam point,
+// arena[r][c] = A[c][r] = |g_r^H v_c|^2 / M^2, so that a 64-column strip of
+// the arena holds the coefficients of 64 rows of A x, as the sweeps read it.
+// With the CSM diagonal removed, A = (|G|^2 - sum_m |v_m|^2 |g_m|^2) /
+// (M^2 - M): the sum is M for unit steering and one more real product (of
+// squared magnitudes) on the matrix cores for the paper's pair.
 #include "common.h"
 
 namespace damas {
@@ -17,6 +26,10 @@ namespace damas {
 // Steering rows (double): E[f][i] = [cos(k d_0..M-1), -sin(k d_0..M-1)] for
 // the kept points i < s_tilde, zero for the padding rows up to ld.
 
+// With the paper's pair (PAPER) two row sets per bin: rows [0, ld) hold the
+// beamformer vectors v = (d / |r|) e, rows [ld, 2 ld) the propagation
+// vectors g = (|r| / d) e.
+template <bool PAPER>
 __global__ __launch_bounds__(256) void steer_kernel(
     Geom g, const double *__restrict__ freq, const int32_t *__restrict__ idx,
     const int32_t *__restrict__ s_tilde, int max_kept, double *__restrict__ E,
@@ -37,17 +50,32 @@ __global__ __launch_bounds__(256) void steer_kernel(
     if (i >= ld)
         return;
     double *row = E + (int64_t)f * e_stride + i * 2 * M;
+    double *row_g = row + ld * 2 * M; // PAPER: the propagation vectors
     if (i < St) {
         const int S = g.N * g.N;
         const int n = idx[(int64_t)f * S + i];
         const double k = kTwoPi * freq[f] / g.c;
         double s, c;
-        sincos(k * point_mic_dist(g, n, m), &s, &c);
-        row[m] = c;
-        row[M + m] = -s;
+        const double d = point_mic_dist(g, n, m);
+        sincos(k * d, &s, &c);
+        if (PAPER) {
+            const double rn = point_origin_dist(g, n);
+            const double av = d / rn, ag = rn / d;
+            row[m] = av * c;
+            row[M + m] = -av * s;
+            row_g[m] = ag * c;
+            row_g[M + m] = -ag * s;
+        } else {
+            row[m] = c;
+            row[M + m] = -s;
+        }
     } else {
         row[m] = 0.0;
         row[M + m] = 0.0;
+        if (PAPER) {
+            row_g[m] = 0.0;
+            row_g[M + m] = 0.0;
+        }
     }
 }
 
@@ -90,7 +118,7 @@ struct PsfExtra {
     int64_t tstride;
 };
 
-template <typename TS>
+template <typename TS, bool PAIR, bool DIAG>
 __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
     int M, const int32_t *__restrict__ s_tilde, int max_kept,
     const double *__restrict__ E, int64_t e_stride,
@@ -112,28 +140,42 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
     const int64_t ld = ld_of(St);
     const int nt = (int)((ld + kPsfTile - 1) / kPsfTile);
     const int t = blockIdx.x;
-    if (t >= nt * (nt + 1) / 2)
-        return;
-    // Upper-triangle tile (I <= J), J-major numbering t = J(J+1)/2 + I.
-    int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (J * (J + 1) / 2 > t)
-        --J;
-    while ((J + 1) * (J + 2) / 2 <= t)
-        ++J;
-    const int I = t - J * (J + 1) / 2;
+    int I, J;
+    if (PAIR) {
+        // Every tile, I (arena rows, sources) fastest.
+        if (t >= nt * nt)
+            return;
+        I = t % nt;
+        J = t / nt;
+    } else {
+        if (t >= nt * (nt + 1) / 2)
+            return;
+        // Upper-triangle tile (I <= J), J-major numbering t = J(J+1)/2 + I.
+        J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while (J * (J + 1) / 2 > t)
+            --J;
+        while ((J + 1) * (J + 2) / 2 <= t)
+            ++J;
+        I = t - J * (J + 1) / 2;
+    }
     const int64_t I0 = (int64_t)I * kPsfTile, J0 = (int64_t)J * kPsfTile;
 
     const double *Ef = E + (int64_t)f * e_stride;
+    // Row operands: tile I from the propagation rows (the pair) or the
+    // steering rows, tile J from the (beamformer) steering rows.
+    const double *EfI = PAIR ? Ef + ld * 2 * M : Ef;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int wr = w >> 1, wc = w & 1; // 32 x 32 quadrant of the tile
     const int lr = lane & 15, lg = lane >> 4;
 
-    dacc4 re[2][2], im[2][2];
+    dacc4 re[2][2], im[2][2], dd[PAIR && DIAG ? 2 : 1][PAIR && DIAG ? 2 : 1];
     for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 2; ++c) {
             re[a][c] = dacc4{0, 0, 0, 0};
             im[a][c] = dacc4{0, 0, 0, 0};
+            if constexpr (PAIR && DIAG)
+                dd[a][c] = dacc4{0, 0, 0, 0};
         }
 
     for (int mc = 0; mc < M; mc += kPsfChunk) {
@@ -143,7 +185,7 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
             double vrI = 0, viI = 0, vrJ = 0, viJ = 0;
             if (m < M) {
                 if (I0 + r < ld) {
-                    const double *row = Ef + (I0 + r) * 2 * M;
+                    const double *row = EfI + (I0 + r) * 2 * M;
                     vrI = row[m];
                     viI = row[M + m];
                 }
@@ -188,6 +230,8 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
                         re[a][c] = mma64(xi, yi, re[a][c]);
                         im[a][c] = mma64(xr, yi, im[a][c]);
                         im[a][c] = mma64(-xi, yr, im[a][c]);
+                        if constexpr (PAIR && DIAG)
+                            dd[a][c] = mma64(xr * xr + xi * xi, yr * yr + yi * yi, dd[a][c]);
                     }
                 }
             }
@@ -198,7 +242,7 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
     // mirrored; unit diagonal.
     TS *Af = A + off[f];
     uint16_t *Lf = ex.lo ? ex.lo + off[f] : nullptr;
-    const double inv = 1.0 / ((double)M * (double)M);
+    const double inv = 1.0 / ((double)M * (double)M - (DIAG ? (double)M : 0.0));
     double tacc = 0.0; // this thread's share of the tile's sum
     for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 2; ++c)
@@ -208,8 +252,27 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
                 if (row >= ld || colj >= ld)
                     continue;
                 const double x = re[a][c][v], y = im[a][c][v];
-                const double vd = (x * x + y * y) * inv;
+                // The m = m' terms removed with the diagonal (M for unit
+                // steering, on kept rows and columns only: padding stays 0).
+                double dterm = 0.0;
+                if constexpr (DIAG)
+                    dterm = PAIR ? dd[PAIR && DIAG ? a : 0][PAIR && DIAG ? c : 0][v]
+                                 : (row < St && colj < St ? (double)M : 0.0);
+                const double vd = (x * x + y * y - dterm) * inv;
                 const TS val = (TS)vd;
+                if constexpr (PAIR) {
+                    // Every entry on its own (arena[row][colj] = A[colj][row]);
+                    // the same point's entry is A_ii = 1.
+                    const bool same = colj == row;
+                    const TS sv = same ? (row < St ? (TS)1 : (TS)0) : val;
+                    Af[row * ld + colj] = sv;
+                    if (Lf)
+                        Lf[row * ld + colj] =
+                            same ? (uint16_t)0 : bf16_rne_f((float)(vd - (double)val));
+                    if (row < St && colj < St)
+                        tacc += same ? 1.0 : vd;
+                    continue;
+                }
                 // Tiles with I < J have every column beyond every row; on
                 // diagonal tiles the lower half is the mirror of the upper.
                 if (colj > row) {
@@ -253,14 +316,15 @@ __global__ __launch_bounds__(kPsfThreads) void psf_kernel(
 __global__ __launch_bounds__(64) void class_kernel(const int32_t *__restrict__ s_tilde,
                                                    int max_kept, const double *__restrict__ tsum,
                                                    int64_t tstride, double rho_wide,
-                                                   double rho_f32, int wide_cap,
+                                                   double rho_f32, int wide_cap, int pair,
                                                    uint8_t *__restrict__ cls)
 {
     const int f = blockIdx.x;
     const int St = s_tilde[f];
     const int lane = threadIdx.x;
     const int64_t nt = (ld_of(St) + kPsfTile - 1) / kPsfTile;
-    const int64_t ntiles = St > 0 && St <= max_kept ? nt * (nt + 1) / 2 : 0;
+    const int64_t ntiles =
+        St > 0 && St <= max_kept ? (pair ? nt * nt : nt * (nt + 1) / 2) : 0;
     double acc = 0.0;
     for (int64_t t = lane; t < ntiles; t += 64)
         acc += tsum[(int64_t)f * tstride + t];
@@ -342,6 +406,7 @@ constexpr int kPsf16Pitch = kPsfTile + 8; // bf16 per LDS row of the staged tile
 // MFMA operand layout: lane l holds row l % 16 of its block, k = 8 (l / 16)
 // .. +7 of the current 32-wide k step (16 contiguous bytes of a row); the
 // accumulator element v of lane l is D[4 (l / 16) + v][l % 16].
+template <bool DIAG>
 __global__ __launch_bounds__(kPsfThreads) void psf16_kernel(
     int M, const int32_t *__restrict__ s_tilde, int max_kept,
     const uint16_t *__restrict__ E, int64_t e_stride, const int64_t *__restrict__ off,
@@ -416,14 +481,18 @@ __global__ __launch_bounds__(kPsfThreads) void psf16_kernel(
             }
     }
 
-    // A = (Re^2 + Im^2) / M^2 in FP32, rounded once to bf16, staged in LDS.
-    const float inv = 1.0f / ((float)M * (float)M);
+    // A = (Re^2 + Im^2) / M^2 in FP32 (with the diagonal removed:
+    // (Re^2 + Im^2 - M) / (M^2 - M) on kept entries), rounded once to bf16,
+    // staged in LDS.
+    const float inv = 1.0f / ((float)M * (float)M - (DIAG ? (float)M : 0.0f));
     for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 2; ++c)
             for (int v = 0; v < 4; ++v) {
                 const int r = wr * 32 + a * 16 + 4 * lg + v, col = wc * 32 + c * 16 + lr;
                 const float x = re[a][c][v], y = im[a][c][v];
-                T[r * kPsf16Pitch + col] = f32_to_bf16_rne((x * x + y * y) * inv);
+                const float dterm =
+                    DIAG && I0 + r < St && J0 + col < St ? (float)M : 0.0f;
+                T[r * kPsf16Pitch + col] = f32_to_bf16_rne((x * x + y * y - dterm) * inv);
             }
     __syncthreads();
 
@@ -477,61 +546,91 @@ hipError_t launch_steer16(const Geom &g, int n_bins, const double *freq, const i
 
 hipError_t launch_psf16(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                         const uint16_t *E, int64_t e_stride, const int64_t *off, uint16_t *A,
-                        int *fault, hipStream_t s)
+                        int *fault, hipStream_t s, int diag)
 {
     if (n_bins == 0 || max_kept == 0)
         return hipSuccess;
     const int64_t nt = (ld_of(max_kept) + kPsfTile - 1) / kPsfTile;
     dim3 grid((unsigned)(nt * (nt + 1) / 2), n_bins);
-    hipLaunchKernelGGL(psf16_kernel, grid, dim3(kPsfThreads), 0, s, M, s_tilde, max_kept, E,
-                       e_stride, off, A, fault);
+    if (diag)
+        hipLaunchKernelGGL(psf16_kernel<true>, grid, dim3(kPsfThreads), 0, s, M, s_tilde,
+                           max_kept, E, e_stride, off, A, fault);
+    else
+        hipLaunchKernelGGL(psf16_kernel<false>, grid, dim3(kPsfThreads), 0, s, M, s_tilde,
+                           max_kept, E, e_stride, off, A, fault);
     return hipGetLastError();
 }
 
 hipError_t launch_steer(const Geom &g, int n_bins, const double *freq,
                         const int32_t *idx, const int32_t *s_tilde,
                         int max_kept, double *E, int64_t e_stride, int *fault,
-                        hipStream_t s)
+                        hipStream_t s, int steering)
 {
     if (n_bins == 0 || max_kept == 0)
         return hipSuccess;
     const int64_t work = ld_of(max_kept) * g.M;
     dim3 grid((unsigned)((work + 255) / 256), n_bins);
-    hipLaunchKernelGGL(steer_kernel, grid, dim3(256), 0, s, g, freq, idx, s_tilde,
-                       max_kept, E, e_stride, fault);
+    if (steering == DAMAS_STEER_PAPER)
+        hipLaunchKernelGGL(steer_kernel<true>, grid, dim3(256), 0, s, g, freq, idx, s_tilde,
+                           max_kept, E, e_stride, fault);
+    else
+        hipLaunchKernelGGL(steer_kernel<false>, grid, dim3(256), 0, s, g, freq, idx, s_tilde,
+                           max_kept, E, e_stride, fault);
     return hipGetLastError();
 }
 
-int64_t psf_tiles(int max_kept)
+int64_t psf_tiles(int max_kept, int steering)
 {
     const int64_t nt = (ld_of(max_kept) + kPsfTile - 1) / kPsfTile;
-    return nt * (nt + 1) / 2;
+    return steering == DAMAS_STEER_PAPER ? nt * nt : nt * (nt + 1) / 2;
+}
+
+template <typename TS>
+static hipError_t launch_psf_t(dim3 grid, hipStream_t s, int steering, int diag, int M,
+                               const int32_t *s_tilde, int max_kept, const double *E,
+                               int64_t e_stride, const int64_t *off, TS *A, int *fault,
+                               PsfExtra ex)
+{
+#define DAMAS_PSF_LAUNCH(P, D)                                                                 \
+    hipLaunchKernelGGL((psf_kernel<TS, P, D>), grid, dim3(kPsfThreads), 0, s, M, s_tilde,      \
+                       max_kept, E, e_stride, off, A, fault, ex)
+    if (steering == DAMAS_STEER_PAPER) {
+        if (diag)
+            DAMAS_PSF_LAUNCH(true, true);
+        else
+            DAMAS_PSF_LAUNCH(true, false);
+    } else {
+        if (diag)
+            DAMAS_PSF_LAUNCH(false, true);
+        else
+            DAMAS_PSF_LAUNCH(false, false);
+    }
+#undef DAMAS_PSF_LAUNCH
+    return hipGetLastError();
 }
 
 hipError_t launch_psf(int M, int n_bins, const int32_t *s_tilde, int max_kept,
                       int precision, const double *E, int64_t e_stride,
                       const int64_t *off, void *A, int *fault, hipStream_t s,
-                      const PsfClassArgs &pc)
+                      const PsfClassArgs &pc, int steering, int diag)
 {
     if (n_bins == 0 || max_kept == 0)
         return hipSuccess;
-    const int64_t tiles = psf_tiles(max_kept);
+    const int64_t tiles = psf_tiles(max_kept, steering);
     dim3 grid((unsigned)tiles, n_bins);
     PsfExtra ex{nullptr, nullptr, tiles};
-    if (precision == DAMAS_PREC_FP64) {
-        hipLaunchKernelGGL(psf_kernel<double>, grid, dim3(kPsfThreads), 0, s, M,
-                           s_tilde, max_kept, E, e_stride, off, (double *)A, fault, ex);
-        return hipGetLastError();
-    }
+    if (precision == DAMAS_PREC_FP64)
+        return launch_psf_t<double>(grid, s, steering, diag, M, s_tilde, max_kept, E, e_stride,
+                                    off, (double *)A, fault, ex);
     ex.lo = pc.lo;
     ex.tsum = pc.cls ? pc.tsum : nullptr;
-    hipLaunchKernelGGL(psf_kernel<float>, grid, dim3(kPsfThreads), 0, s, M,
-                       s_tilde, max_kept, E, e_stride, off, (float *)A, fault, ex);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_psf_t<float>(grid, s, steering, diag, M, s_tilde, max_kept, E,
+                                       e_stride, off, (float *)A, fault, ex);
     if (e != hipSuccess || !pc.cls)
         return e;
     hipLaunchKernelGGL(class_kernel, dim3(n_bins), dim3(64), 0, s, s_tilde, max_kept, pc.tsum,
-                       tiles, pc.rho_wide, pc.rho_f32, pc.wide_cap, pc.cls);
+                       tiles, pc.rho_wide, pc.rho_f32, pc.wide_cap,
+                       steering == DAMAS_STEER_PAPER ? 1 : 0, pc.cls);
     return hipGetLastError();
 }
 

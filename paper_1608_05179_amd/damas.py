@@ -35,6 +35,9 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16 = 2
 
+STEER_UNIT = 0
+STEER_PAPER = 1
+
 POLICY_AUTO = 0
 POLICY_FIXED = 1
 CLASS_NARROW = 0
@@ -68,7 +71,8 @@ class Params(ctypes.Structure):
                 ("keep_count", ctypes.POINTER(c_i32)), ("keep_count_all", c_i32),
                 ("iterations", c_i32), ("precision", c_i32), ("batched", c_i32),
                 ("max_kept", c_i32), ("refine_sweeps", c_i32), ("predictor", c_i32),
-                ("policy", c_i32), ("rho_wide", c_dbl), ("rho_f32", c_dbl)]
+                ("policy", c_i32), ("rho_wide", c_dbl), ("rho_f32", c_dbl),
+                ("steering", c_i32), ("diag_removal", c_i32)]
 
 
 def _sig(name, res, *args):
@@ -95,6 +99,10 @@ _sig("damas_layout", ctypes.c_int, c_i32, c_vp, c_i32, c_i64, c_vp, c_vp)
 _sig("damas_steer", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i64, c_vp)
 _sig("damas_psf", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp)
 _sig("damas_steer_bf16", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_i64, c_vp)
+_sig("damas_das_map_ex", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp)
+_sig("damas_steer_ex", ctypes.c_int, _G, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_i64, c_vp)
+_sig("damas_psf_ex", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_i64,
+     c_vp, c_vp, c_vp)
 _sig("damas_psf_bf16", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp)
 _sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp,
      c_vp, c_i32, c_vp, c_vp, c_vp)
@@ -268,6 +276,52 @@ def das_map(g: Geometry, freq, csm, b=None, stream=None):
     return b
 
 
+def das_map_ex(g: Geometry, freq, csm, steering=STEER_UNIT, diag_removal=False, b=None,
+               stream=None):
+    """das_map with a steering form and optional CSM diagonal removal."""
+    csm = _as_interleaved(csm)
+    nb = freq.numel()
+    if b is None:
+        b = torch.empty(nb, g.N * g.N, dtype=torch.float64, device=freq.device)
+    _check(_lib.damas_das_map_ex(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
+                                 _ptr(csm, torch.float64, "csm"), int(steering),
+                                 1 if diag_removal else 0, _ptr(b, torch.float64, "b"),
+                                 _stream(stream)))
+    return b
+
+
+def steer_ex(g: Geometry, freq, idx, s_tilde, max_kept: int, steering=STEER_UNIT,
+             stream=None):
+    """Steering rows (n_bins, rows, 2M) double; the paper's pair has 2 ld rows
+    per bin (beamformer rows first, then propagation rows)."""
+    nb = freq.numel()
+    L = ld(max_kept) * (2 if steering == STEER_PAPER else 1)
+    E = torch.zeros(nb, L, 2 * g.M, dtype=torch.float64, device=freq.device)
+    _check(_lib.damas_steer_ex(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
+                               _ptr(idx, torch.int32, "idx"),
+                               _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
+                               int(steering), _ptr(E, torch.float64, "E"), L * 2 * g.M,
+                               _stream(stream)))
+    return E
+
+
+def psf_ex(M: int, s_tilde, max_kept: int, precision: int, E, off, steering=STEER_UNIT,
+           diag_removal=False, A=None, stream=None):
+    """Packed A arena (flat) with a steering form and diagonal removal; the
+    paper's pair stores A transposed (row = source point)."""
+    nb = s_tilde.numel()
+    if A is None:
+        total = int(off[-1].item())
+        A = torch.full((max(total, 1),), float("nan"), dtype=_DTYPE[precision],
+                       device=off.device)
+    _check(_lib.damas_psf_ex(int(M), nb, _ptr(s_tilde, torch.int32, "s_tilde"), int(max_kept),
+                             int(precision), int(steering), 1 if diag_removal else 0,
+                             _ptr(E, torch.float64, "E"), E.shape[1] * E.shape[2],
+                             _ptr(off, torch.int64, "off"), _ptr(A, _DTYPE[precision], "A"),
+                             _stream(stream)))
+    return A
+
+
 def select(N: int, b, mode: int, eps: float = 0.0, keep_count=None, predictor=0,
            stream=None):
     """Algorithm 1 with predictor PRED_HAAR or PRED_LINEAR: returns
@@ -379,7 +433,8 @@ def static_scratch_bytes() -> int:
 def solve_static(g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                  keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
                  x_init=None, x_map=None, b_map=None, idx=None, s_tilde=None, predictor=0,
-                 policy=POLICY_AUTO, rho_wide=0.0, stream=None):
+                 policy=POLICY_AUTO, rho_wide=0.0, steering=STEER_UNIT, diag_removal=False,
+                 stream=None):
     """The whole-path solve with no allocation by the library (damas_solve_static):
     keep_count is a device int32 tensor of n_bins (KEEP_COUNT).  Faults are
     reported by check(None)."""
@@ -388,7 +443,7 @@ def solve_static(g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
     if x_map is None:
         x_map = torch.empty(nb, g.N * g.N, dtype=_XTYPE[precision], device=freq.device)
     p, _kc = _params(nb, select_mode, eps, None, iterations, precision, True, max_kept, 0,
-                     predictor, policy, rho_wide, 0.0)
+                     predictor, policy, rho_wide, 0.0, steering, diag_removal)
     dt = _XTYPE[precision]
     _check(_lib.damas_solve_static(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
                                    _ptr(csm, torch.float64, "csm"), ctypes.byref(p),
@@ -456,7 +511,7 @@ class Context:
               keep_count=None, iterations=1000, precision=PREC_FP32, batched=True,
               max_kept=0, refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
               s_tilde=None, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0,
-              stream=None):
+              steering=STEER_UNIT, diag_removal=False, stream=None):
         """Every step for every bin on the device; returns x_map.
 
         keep_count: an int, or a sequence of per-bin ints (host values)."""
@@ -466,7 +521,8 @@ class Context:
         if x_map is None:
             x_map = torch.empty(nb, S, dtype=_XTYPE[precision], device=freq.device)
         p, kc_arr = _params(nb, select_mode, eps, keep_count, iterations, precision, batched,
-                            max_kept, refine_sweeps, predictor, policy, rho_wide, rho_f32)
+                            max_kept, refine_sweeps, predictor, policy, rho_wide, rho_f32,
+                            steering, diag_removal)
         dt = _XTYPE[precision]
         _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
                                     _ptr(freq, torch.float64, "freq"),
@@ -547,7 +603,8 @@ class Graph:
 
 
 def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, max_kept,
-            refine_sweeps, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0):
+            refine_sweeps, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0,
+            steering=STEER_UNIT, diag_removal=False):
     """Params struct and the ctypes array that keeps per-bin counts alive."""
     kc_arr = None
     kc_all = 0
@@ -563,7 +620,7 @@ def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, ma
                ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
                int(kc_all), int(iterations), int(precision), 1 if batched else 0,
                int(max_kept), int(refine_sweeps), int(predictor), int(policy),
-               float(rho_wide), float(rho_f32))
+               float(rho_wide), float(rho_f32), int(steering), 1 if diag_removal else 0)
     return p, kc_arr
 
 
