@@ -434,6 +434,13 @@ struct damas_params {
                                   matching PSF, A = (|v^H g|^2 -
                                   sum_m |v_m|^2 |g_m|^2) / (M^2 - M); the
                                   map may then be negative                  */
+    double *power;             /* optional output, n_bins doubles: each
+                                  bin's integrated power sum_n x_n (the
+                                  paper's Table 1 quantity P), summed in
+                                  double from the sweep state in a fixed
+                                  order; DEVICE memory for damas_solve_dev
+                                  and damas_solve_static, HOST memory for
+                                  damas_solve; ignored by the server      */
 };
 
 /* Storage class of each bin in the context's last batched solve under

@@ -1090,7 +1090,7 @@ int upload_tab(damas_ctx *ctx, const std::vector<int32_t> &tab, hipStream_t s)
 int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
                               int32_t max_kept, const double *freq, double *bm,
                               int32_t *ix, int32_t *st, const void *x_init, void *x_map,
-                              hipStream_t s, bool build = true)
+                              hipStream_t s, bool build = true, double *power = nullptr)
 {
     const damas_params *p = P.p;
     HIP_TRY(launch_layout(nb, st, max_kept, P.a_elems, P.off, P.fault, s), "layout launch");
@@ -1182,9 +1182,11 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
         return launch_gs(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi, x_map,
                          P.fault, s, g);
     };
+    // The last sweep launch of a bin writes its integrated power.
     if (!bf16) {
         GsClassArgs g = gca;
         g.iters_cls = p->iterations;
+        g.power = power;
         HIP_TRY(sweeps(p->precision, ctx->A.p, p->iterations, x_init, g), "gs launch");
     } else {
         // Bulk sweeps on bf16 A, then the refinement sweeps on the FP32
@@ -1192,16 +1194,19 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
         // bins of class F32 or wide skip the bulk and run every sweep in
         // the second launch.
         const void *xi = x_init;
+        const bool second = P.refine > 0 || P.classes;
         if (P.bulk > 0 || (P.refine == 0 && !P.classes)) {
             GsClassArgs g;
             g.cls = gca.cls;
             g.iters_cls = 0;
+            g.power = second ? nullptr : power;
             HIP_TRY(sweeps(DAMAS_PREC_BF16, ctx->A.p, P.bulk, xi, g), "gs launch (bf16)");
             xi = x_map;
         }
-        if (P.refine > 0 || P.classes) {
+        if (second) {
             GsClassArgs g = gca;
             g.iters_cls = p->iterations;
+            g.power = power;
             HIP_TRY(sweeps(DAMAS_PREC_FP32, ctx->A32.p, P.refine, xi, g),
                     "gs launch (fp32 refinement)");
         }
@@ -1269,7 +1274,7 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
                               P.st, s),
                 "select launch");
         return enqueue_system_and_sweeps(ctx, P, n_bins, P.max_kept, freq, P.bm, P.ix, P.st,
-                                         x_init, x_map, s);
+                                         x_init, x_map, s, true, p->power);
     }
 
     // Plain: each bin on its own, one launch per step; A, E and the layout
@@ -1286,7 +1291,8 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
                               P.kc ? P.kc + f : nullptr, P.ix + fS, P.st + f, s),
                 "select launch");
         if ((rc = enqueue_system_and_sweeps(ctx, P, 1, mk, freq + f, P.bm + fS, P.ix + fS,
-                                            P.st + f, xi, xm, s)))
+                                            P.st + f, xi, xm, s, true,
+                                            p->power ? p->power + f : nullptr)))
             return rc;
     }
     return DAMAS_OK;
@@ -1319,7 +1325,7 @@ extern "C" int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bi
     struct Buf {
         void *p = nullptr;
         ~Buf() { if (p) (void)hipFree(p); }
-    } dmic, dfreq, dcsm, dxi, dx, db, didx, dst;
+    } dmic, dfreq, dcsm, dxi, dx, db, didx, dst, dpow;
     auto alloc = [](Buf &b, size_t n) { return hipMalloc(&b.p, n ? n : 1); };
     HIP_TRY(alloc(dmic, M * 3 * sizeof(double)), "hipMalloc");
     HIP_TRY(alloc(dfreq, nb * sizeof(double)), "hipMalloc");
@@ -1333,6 +1339,8 @@ extern "C" int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bi
         HIP_TRY(alloc(didx, nb * S * sizeof(int32_t)), "hipMalloc");
     if (s_tilde)
         HIP_TRY(alloc(dst, nb * sizeof(int32_t)), "hipMalloc");
+    if (p->power)
+        HIP_TRY(alloc(dpow, nb * sizeof(double)), "hipMalloc");
     HIP_TRY(hipMemcpy(dmic.p, g->mic, M * 3 * sizeof(double), hipMemcpyHostToDevice), "copy");
     HIP_TRY(hipMemcpy(dfreq.p, freq, nb * sizeof(double), hipMemcpyHostToDevice), "copy");
     HIP_TRY(hipMemcpy(dcsm.p, csm, nb * M * M * 2 * sizeof(double), hipMemcpyHostToDevice),
@@ -1344,7 +1352,9 @@ extern "C" int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bi
         HIP_TRY(hipMemcpy(didx.p, idx, nb * S * sizeof(int32_t), hipMemcpyHostToDevice), "copy");
     damas_geometry gd = *g;
     gd.mic = (const double *)dmic.p;
-    rc = damas_solve_dev(ctx, &gd, n_bins, (const double *)dfreq.p, (const double *)dcsm.p, p,
+    damas_params pd = *p;
+    pd.power = (double *)dpow.p; // the host array is filled after the solve
+    rc = damas_solve_dev(ctx, &gd, n_bins, (const double *)dfreq.p, (const double *)dcsm.p, &pd,
                          dxi.p, dx.p, (double *)db.p, (int32_t *)didx.p, (int32_t *)dst.p,
                          nullptr);
     if (rc)
@@ -1358,6 +1368,8 @@ extern "C" int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bi
         HIP_TRY(hipMemcpy(idx, didx.p, nb * S * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
     if (s_tilde)
         HIP_TRY(hipMemcpy(s_tilde, dst.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+    if (p->power)
+        HIP_TRY(hipMemcpy(p->power, dpow.p, nb * sizeof(double), hipMemcpyDeviceToHost), "copy");
     return DAMAS_OK;
 }
 
@@ -2013,6 +2025,7 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
         gca.lo = pc.lo;
         gca.iters_cls = p->iterations;
     }
+    gca.power = p->power;
 
     hipStream_t s = (hipStream_t)stream;
     const Geom kg = make_geom(*g);

@@ -160,6 +160,7 @@ struct GsClassArgs {
     const uint8_t *cls = nullptr;
     const uint16_t *lo = nullptr;
     int iters_cls = 0;
+    double *power = nullptr; // device, per bin: sum of x over the bin (output)
 };
 
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,

@@ -1110,7 +1110,53 @@ struct GsClasses {
     const uint8_t *cls;
     const bf16s *lo;
     int iters_cls;
+    double *power; // per bin, sum of x~ over the kept points (or null)
 };
+
+// Scatter of a bin's x~ onto the full grid: x_map[n] = x~_i at n = idx[i],
+// 0 in the gaps between kept points, so every grid point is written exactly
+// once; and, with `power`, the bin's integrated power sum_i x~_i (in double,
+// from the sweep state) by a fixed-order reduction: each thread's strided
+// share, then the wave's lanes by xor steps, then the waves in order
+// (`red`: LDS for one double per wave, free once the sweeps are done).
+template <typename TX, int NTHR>
+__device__ __forceinline__ void scatter_bin(const double *xs, const int32_t *__restrict__ id,
+                                            int St, int S, TX *__restrict__ xo, double *power,
+                                            double *red)
+{
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    if (St == 0) {
+        for (int n = tid; n < S; n += NTHR)
+            xo[n] = (TX)0;
+    } else {
+        for (int i = tid; i < St; i += NTHR) {
+            const int n = id[i];
+            const int prev = i == 0 ? -1 : id[i - 1];
+            for (int q = prev + 1; q < n; ++q)
+                xo[q] = (TX)0;
+            xo[n] = (TX)xs[i];
+            acc += xs[i];
+            if (i == St - 1)
+                for (int q = n + 1; q < S; ++q)
+                    xo[q] = (TX)0;
+        }
+    }
+    if (!power) // uniform: a kernel argument
+        return;
+    for (int o = 32; o >= 1; o >>= 1)
+        acc += __shfl_xor(acc, o, 64);
+    __syncthreads(); // every wave is past its last read of `red`'s region
+    if ((tid & 63) == 0)
+        red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int k = 0; k < NTHR / 64; ++k)
+            t += red[k];
+        *power = t;
+    }
+}
 
 // Sweeps, class and width of bin f; St clamped as the kernels' checks do.
 template <typename TA, int NW>
@@ -1196,24 +1242,8 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
                                                   St, id, bf, total, ntile, w, lane, NW);
     }
 
-    // Scatter: x_map[n] = x~_i at n = idx[i], 0 in the gaps between kept
-    // points, so every grid point is written exactly once.
-    TX *xo = x_map + (int64_t)f * S;
-    if (St == 0) {
-        for (int n = tid; n < S; n += nthr)
-            xo[n] = (TX)0;
-        return;
-    }
-    for (int i = tid; i < St; i += nthr) {
-        const int n = id[i];
-        const int prev = i == 0 ? -1 : id[i - 1];
-        for (int q = prev + 1; q < n; ++q)
-            xo[q] = (TX)0;
-        xo[n] = (TX)xs[i];
-        if (i == St - 1)
-            for (int q = n + 1; q < S; ++q)
-                xo[q] = (TX)0;
-    }
+    scatter_bin<TX, nthr>(xs, id, St, S, x_map + (int64_t)f * S, gc.power ? gc.power + f : nullptr,
+                          parts);
 }
 
 // ---------------------------------------------------------------------------
@@ -1239,7 +1269,8 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int N, int
                                           const TA *__restrict__ A, const bf16s *Alo,
                                           const double *__restrict__ b, int iters,
                                           const TX *__restrict__ x_init, TX *__restrict__ x_map,
-                                          int *fault, const GsCoop &co, double *xs)
+                                          int *fault, const GsCoop &co, double *xs,
+                                          double *power)
 {
     double *parts = xs + ld_cap;
     double *xnew = parts + 2 * NW * kGsTile;
@@ -1319,22 +1350,7 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int N, int
                                                     OwnerLink{flags, part, xpub, ranks, fault},
                                                     Alo);
 
-    TX *xo = x_map + (int64_t)f * S;
-    if (St == 0) {
-        for (int n = tid; n < S; n += nthr)
-            xo[n] = (TX)0;
-        return;
-    }
-    for (int i = tid; i < St; i += nthr) {
-        const int n = id[i];
-        const int prev = i == 0 ? -1 : id[i - 1];
-        for (int q = prev + 1; q < n; ++q)
-            xo[q] = (TX)0;
-        xo[n] = (TX)xs[i];
-        if (i == St - 1)
-            for (int q = n + 1; q < S; ++q)
-                xo[q] = (TX)0;
-    }
+    scatter_bin<TX, nthr>(xs, id, St, S, x_map + (int64_t)f * S, power, parts);
 }
 
 // One job: the bin's kept count (with the capacity checks), its class and
@@ -1371,13 +1387,14 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
         if (wide) {
             coop_body<TA, TX, UNIT, NW, kGsLoNH, kGsLoNB, true>(
                 f, rank, ranks, N, St, ld_of(min(max_kept, gs_lo_cap<NW>())), idx, A_all + a0,
-                gc.lo + a0, b, iters_f, x_init, x_map, fault, co, xs);
+                gc.lo + a0, b, iters_f, x_init, x_map, fault, co, xs,
+                gc.power ? gc.power + f : nullptr);
             return;
         }
     }
     coop_body<TA, TX, UNIT, NW, NH, NB, false>(f, rank, ranks, N, St, ld_of(max_kept), idx,
                                                A_all + a0, nullptr, b, iters_f, x_init, x_map,
-                                               fault, co, xs);
+                                               fault, co, xs, gc.power ? gc.power + f : nullptr);
 }
 
 
@@ -1438,7 +1455,7 @@ template <typename TA, int NW> static size_t gs_lds_bytes_t(int max_kept, bool l
 
 static GsClasses to_dev(const GsClassArgs &a)
 {
-    return GsClasses{a.cls, reinterpret_cast<const bf16s *>(a.lo), a.iters_cls};
+    return GsClasses{a.cls, reinterpret_cast<const bf16s *>(a.lo), a.iters_cls, a.power};
 }
 
 int gs_wide_capacity() { return std::min(gs_lo_cap<9>(), gs_lo_cap<11>()); }

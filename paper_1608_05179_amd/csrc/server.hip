@@ -213,6 +213,7 @@ int damas_server::run(Slot &sl, Req *r)
     g.c = r->c;
     damas_params p = r->params;
     p.batched = 1;
+    p.power = nullptr; // a request's params are host memory; its power is not kept
     p.keep_count = r->keep_count.empty() ? nullptr : r->keep_count.data();
     int hit = 0;
     rc = solve_cached(sl.ctx, &g, r->n_bins, (const double *)sl.freq.p,
@@ -347,6 +348,7 @@ extern "C" int damas_submit(damas_server *srv, const damas_request *q, uint64_t 
     r->freq.assign(q->freq, q->freq + q->n_bins);
     r->csm.assign(q->csm, q->csm + (size_t)q->n_bins * q->M * q->M * 2);
     r->params = q->params;
+    r->params.power = nullptr;
     if (q->params.keep_count)
         r->keep_count.assign(q->params.keep_count, q->params.keep_count + q->n_bins);
     r->params.keep_count = nullptr;

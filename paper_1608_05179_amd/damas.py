@@ -72,7 +72,7 @@ class Params(ctypes.Structure):
                 ("iterations", c_i32), ("precision", c_i32), ("batched", c_i32),
                 ("max_kept", c_i32), ("refine_sweeps", c_i32), ("predictor", c_i32),
                 ("policy", c_i32), ("rho_wide", c_dbl), ("rho_f32", c_dbl),
-                ("steering", c_i32), ("diag_removal", c_i32)]
+                ("steering", c_i32), ("diag_removal", c_i32), ("power", c_vp)]
 
 
 def _sig(name, res, *args):
@@ -511,8 +511,10 @@ class Context:
               keep_count=None, iterations=1000, precision=PREC_FP32, batched=True,
               max_kept=0, refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
               s_tilde=None, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0,
-              steering=STEER_UNIT, diag_removal=False, stream=None):
-        """Every step for every bin on the device; returns x_map.
+              steering=STEER_UNIT, diag_removal=False, power=None, stream=None):
+        """Every step for every bin on the device; returns x_map.  power (a
+        device float64 tensor of n_bins, optional) receives each bin's
+        integrated power.
 
         keep_count: an int, or a sequence of per-bin ints (host values)."""
         csm = _as_interleaved(csm)
@@ -523,6 +525,7 @@ class Context:
         p, kc_arr = _params(nb, select_mode, eps, keep_count, iterations, precision, batched,
                             max_kept, refine_sweeps, predictor, policy, rho_wide, rho_f32,
                             steering, diag_removal)
+        p.power = _ptr(power, torch.float64, "power")
         dt = _XTYPE[precision]
         _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
                                     _ptr(freq, torch.float64, "freq"),
