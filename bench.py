@@ -178,6 +178,15 @@ class _Problem:
                        refine_sweeps=self.R, x_map=self.x, s_tilde=self.st, idx=self.idx,
                        policy=self.policy, rho_wide=self.rho_wide)
 
+    def capture(self):
+        """The same batched solve captured into a graph on this context (its
+        cooperative schedule included); replays write self.x."""
+        return self.ctx.capture(self.g, self.freq, self.csm, select_mode=self.mode,
+                                keep_count=self.K, iterations=self.w.iterations,
+                                precision=self.prec, refine_sweeps=self.R, x_map=self.x,
+                                s_tilde=self.st, idx=self.idx, policy=self.policy,
+                                rho_wide=self.rho_wide)
+
     def tune(self, sweeps):
         return self.ctx.autotune(self.g, self.freq, self.csm, select_mode=self.mode,
                                  keep_count=self.K, precision=self.prec, trial_sweeps=sweeps,
@@ -218,6 +227,33 @@ def _time_steps(pb, steps, warmup):
     return wall * 1e3 / steps, lat, gs_ms / max(gs_n, 1), sys_ms / max(sys_n, 1)
 
 
+def _time_graph(pb, steps, warmup):
+    """The solve captured once (set-up, not timed), then `steps` replays:
+    wall time per replay, HIP-event latencies, and the graph's sweep
+    workgroups.  Each replay is the whole path on the resident inputs."""
+    import torch
+    graph = pb.capture()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    pb.ctx.check()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        graph.launch(stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pb.ctx.check()
+    lat = [e0.elapsed_time(e1) for e0, e1 in ev]
+    wg = graph.workgroups()
+    graph.close()
+    return wall * 1e3 / steps, lat, wg
+
+
 def _sweep_bytes(pb, s_tilde, cls):
     """Algorithmic A bytes of one solve's sweeps: S~_f^2 elements of A per
     sweep of bin f, at the width its class stores them (f64 8 B; f32 4 B;
@@ -240,8 +276,10 @@ def _sweep_bytes(pb, s_tilde, cls):
     return tot
 
 
-def measure(name, steps, warmup, refine=60, tune_sweeps=0, fixed=False, rho_wide=0.0):
-    """Time `steps` batched solves of a workload; returns (record, problem)."""
+def measure(name, steps, warmup, refine=60, tune_sweeps=0, fixed=False, rho_wide=0.0,
+            graph=True):
+    """Time `steps` batched solves of a workload, eager and (graph) as
+    replays of one captured graph; returns (record, problem)."""
     import numpy as np
 
     from paper_1608_05179_amd import damas as dm
@@ -271,6 +309,13 @@ def measure(name, steps, warmup, refine=60, tune_sweeps=0, fixed=False, rho_wide
                      "kernel": "gs_coop_kernel / gs_kernel (the solve's sweep launches)",
                      "kernel_avg_ms": round(gs_avg, 4), "algorithmic_bytes": a_bytes},
     }
+    if graph:
+        g_ms, g_lat, g_wg = _time_graph(pb, steps, warmup)
+        rec["graph"] = {"ms_per_step": round(g_ms, 4),
+                        "value": round(updates / (g_ms * 1e-3), 1),
+                        "latency_ms": {"p50": round(_pct(g_lat, 50), 4),
+                                       "p99": round(_pct(g_lat, 99), 4)},
+                        "sweep_workgroups": g_wg}
     if cls is not None:
         rec["classes"] = {"narrow": int((cls == dm.CLASS_NARROW).sum()),
                           "fp32": int((cls == dm.CLASS_FP32).sum()),

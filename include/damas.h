@@ -63,6 +63,12 @@ extern "C" {
 #define DAMAS_SEL_KEEP_COUNT 2 /* keep level-0 points plus the points of
                                   largest |d| (ties: lower grid index first)
                                   up to keep_count points in total          */
+#define DAMAS_SEL_KEEP_FRAC 3  /* the KEEP_COUNT rule with the same count for
+                                  every bin, ceil(keep_frac * N*N) (the
+                                  ceiling of that double product; level-0
+                                  points included); whole-path solves and
+                                  the server only, the step-level
+                                  damas_select takes counts                */
 
 /* ---- predictors of Algorithm 1's interpolating wavelet ------------- */
 #define DAMAS_PRED_HAAR 0   /* order 0: the lower-left neighbour on G^j     */
@@ -142,8 +148,9 @@ const char *damas_strerror(int code);
 const char *damas_last_error(void);
 
 /* Leading dimension (row stride, in elements) of a compressed system with
- * s_tilde unknowns: s_tilde rounded up to a multiple of 8.  Rows and the
- * columns j >= s_tilde of the padding are zero. */
+ * s_tilde unknowns: s_tilde rounded up to a multiple of 32 (so float rows
+ * start on whole 128-byte lines).  Rows and the columns j >= s_tilde of the
+ * padding are zero. */
 int64_t damas_ld(int32_t s_tilde);
 
 /* The largest max_kept the sweeps accept at `precision` (DAMAS_PREC_*):
@@ -441,6 +448,8 @@ struct damas_params {
                                   order; DEVICE memory for damas_solve_dev
                                   and damas_solve_static, HOST memory for
                                   damas_solve; ignored by the server      */
+    double keep_frac;          /* KEEP_FRAC: fraction of the N*N grid
+                                  points to keep, in (0, 1]               */
 };
 
 /* Storage class of each bin in the context's last batched solve under
@@ -535,16 +544,27 @@ int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
  * a HIP graph (after one eager solve that sizes the workspace).  Every
  * replay runs the same launches on the same buffers, so it reads the
  * current contents of freq, csm and x_init: a new CSM in place gives a new
- * solve.  Captured solves use one workgroup per bin (cooperative launches
- * are not captured).  While a graph exists its context refuses solves that
- * would grow the workspace (DAMAS_EBUSY).  The launch sequence holds no
- * memset nodes. */
+ * solve.  The sweeps replay the schedule the eager solve chose: cooperative
+ * (several workgroups per long bin, one launch for the band) when it was,
+ * from a copy of the schedule table the graph owns, as kernel nodes carrying
+ * the cooperative launch attribute; with per-bin classes the
+ * schedule weighs the classes of that eager solve, and a replay whose
+ * classes differ (a new CSM that changes the kept sets) is still exact, only
+ * balanced for the old ones.  While a graph exists its context refuses
+ * solves that would grow the workspace (DAMAS_EBUSY).  The launch sequence
+ * holds no memset nodes.  A replay must not run concurrently with other
+ * work on the context, nor, when cooperative, with work that would keep its
+ * workgroups from being resident together (its bounded waits would then
+ * report fault bit 8 through damas_check). */
 typedef struct damas_graph damas_graph;
 int damas_graph_capture(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
                         const double *freq, const double *csm, const damas_params *p,
                         const void *x_init, void *x_map, double *b_map, int32_t *idx,
                         int32_t *s_tilde, damas_graph **out);
 int damas_graph_launch(damas_graph *gr, void *stream);
+/* Workgroups of the graph's sweep launches (n_bins when one per bin); 0 for
+ * NULL. */
+int32_t damas_graph_workgroups(const damas_graph *gr);
 void damas_graph_destroy(damas_graph *gr);
 
 /* Device bytes a whole-path solve of this shape holds (host only, no device

@@ -127,6 +127,30 @@ int check_mode(int32_t mode, double eps)
     return DAMAS_OK;
 }
 
+} // namespace
+
+// KEEP_FRAC is KEEP_COUNT with one count for every bin, ceil(keep_frac *
+// N^2): *q becomes `tmp`, a copy of *p in that form, or stays p for the
+// other modes.
+int damas::resolve_frac(const damas_params *p, int32_t N, damas_params &tmp,
+                        const damas_params **q)
+{
+    *q = p;
+    if (!p || p->select_mode != DAMAS_SEL_KEEP_FRAC)
+        return DAMAS_OK;
+    const double f = p->keep_frac;
+    if (!(f > 0.0 && f <= 1.0))
+        return fail(DAMAS_EINVAL, "keep_frac = %g outside (0, 1]", f);
+    tmp = *p;
+    tmp.select_mode = DAMAS_SEL_KEEP_COUNT;
+    tmp.keep_count = nullptr;
+    tmp.keep_count_all = (int32_t)std::ceil(f * (double)N * (double)N);
+    *q = &tmp;
+    return DAMAS_OK;
+}
+
+namespace {
+
 int check_kept(int32_t max_kept, int32_t S, int32_t precision)
 {
     if (max_kept < 0 || max_kept > S)
@@ -1144,8 +1168,8 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
     // Cooperative schedule (batched solves of host-known kept counts).  With
     // per-bin classes the schedule weighs wide bins by their cost, so the
     // classes the PSF chose come to the host first (one synchronisation of
-    // the solve's stream, before the sweeps; not under graph capture, which
-    // schedules no cooperation).
+    // the solve's stream, before the sweeps).  A captured solve neither
+    // synchronises nor plans: it runs the schedule its graph holds.
     std::vector<int32_t> tab;
     int gpw = 0;
     const uint8_t *cls_host = nullptr;
@@ -1165,20 +1189,33 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         cls_host = ctx->cls_pinned;
     }
-    const int n_wg = nb == P.n_bins ? plan_coop(ctx, P, tab, &gpw, cls_host) : 0;
-    if (n_wg > 0) {
-        if ((rc = upload_tab(ctx, tab, s)) ||
-            (rc = ensure(ctx, ctx->coop_ws, gs_coop_ws_bytes(nb, max_kept), s,
-                         "coop exchange")))
+    int n_wg;
+    const int32_t *tab_dev = nullptr;
+    if (ctx->capturing) {
+        n_wg = nb == P.n_bins && ctx->cap_tab ? ctx->cap_nwg : 0;
+        gpw = ctx->cap_gpw;
+        tab_dev = ctx->cap_tab;
+        if (n_wg > 0 && (rc = ensure(ctx, ctx->coop_ws, gs_coop_ws_bytes(nb, max_kept), s,
+                                     "coop exchange")))
             return rc;
+    } else {
+        n_wg = nb == P.n_bins ? plan_coop(ctx, P, tab, &gpw, cls_host) : 0;
+        if (n_wg > 0) {
+            if ((rc = upload_tab(ctx, tab, s)) ||
+                (rc = ensure(ctx, ctx->coop_ws, gs_coop_ws_bytes(nb, max_kept), s,
+                             "coop exchange")))
+                return rc;
+            tab_dev = (const int32_t *)ctx->coop_tab.p;
+        }
     }
     ctx->last_workgroups = n_wg > 0 ? n_wg : nb;
+    ctx->last_coop = n_wg > 0;
+    ctx->last_gpw = gpw;
     auto sweeps = [&](int prec, const void *Ap, int iters, const void *xi,
                       const GsClassArgs &g) -> hipError_t {
         if (n_wg > 0)
             return launch_gs_coop(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi,
-                                  x_map, P.fault, (const int32_t *)ctx->coop_tab.p, n_wg, gpw,
-                                  ctx->coop_ws.p, g, s);
+                                  x_map, P.fault, tab_dev, n_wg, gpw, ctx->coop_ws.p, g, s);
         return launch_gs(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi, x_map,
                          P.fault, s, g);
     };
@@ -1229,8 +1266,12 @@ extern "C" int damas_query_footprint(int32_t M, int32_t N, int32_t n_bins,
         return fail(DAMAS_EINVAL, "M = %d outside [1, 128]", M);
     if (N < 1 || N > 46340)
         return fail(DAMAS_EINVAL, "N = %d outside [1, 46340]", N);
+    damas_params pn;
+    int rc = resolve_frac(p, N, pn, &p);
+    if (rc)
+        return rc;
     SolvePlan P;
-    int rc = make_plan(M, N, n_bins, p, P);
+    rc = make_plan(M, N, n_bins, p, P);
     if (rc)
         return rc;
     const size_t nb = (size_t)n_bins, S = (size_t)P.S;
@@ -1253,6 +1294,9 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
         return fail(DAMAS_EINVAL, "ctx is NULL");
     int rc = check_geometry(g);
     if (rc)
+        return rc;
+    damas_params pn;
+    if ((rc = resolve_frac(p, g->N, pn, &p)))
         return rc;
     SolvePlan P;
     if ((rc = make_plan(g->M, g->N, n_bins, p, P)))
@@ -1626,6 +1670,9 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
     int rc = check_geometry(g);
     if (rc)
         return rc;
+    damas_params pn;
+    if ((rc = resolve_frac(p, g->N, pn, &p)))
+        return rc;
     SolvePlan P;
     if ((rc = make_plan(g->M, g->N, n_bins, p, P)))
         return rc;
@@ -1782,7 +1829,40 @@ struct damas_graph {
     damas_ctx *ctx = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int32_t *tab = nullptr; // the cooperative schedule the graph replays (or null)
+    int workgroups = 0;     // of its sweep launches
 };
+
+// Set the cooperative attribute on the graph's sweep kernel nodes.
+static int mark_coop_nodes(hipGraph_t graph)
+{
+    size_t n = 0;
+    if (hipGraphGetNodes(graph, nullptr, &n) != hipSuccess)
+        return 1;
+    std::vector<hipGraphNode_t> nodes(n);
+    if (n && hipGraphGetNodes(graph, nodes.data(), &n) != hipSuccess)
+        return 1;
+    int marked = 0;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(nd, &t) != hipSuccess)
+            return 1;
+        if (t != hipGraphNodeTypeKernel)
+            continue;
+        hipKernelNodeParams kp{};
+        if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess)
+            return 1;
+        if (!gs_is_coop_kernel(kp.func))
+            continue;
+        hipKernelNodeAttrValue v{};
+        v.cooperative = 1;
+        if (hipGraphKernelNodeSetAttribute(nd, hipKernelNodeAttributeCooperative, &v) !=
+            hipSuccess)
+            return 1;
+        ++marked;
+    }
+    return marked > 0 ? 0 : 1;
+}
 
 extern "C" int damas_graph_capture(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
                                    const double *freq, const double *csm,
@@ -1797,49 +1877,81 @@ extern "C" int damas_graph_capture(damas_ctx *ctx, const damas_geometry *g, int3
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
-    // One eager solve sizes every buffer and uploads the keep counts; the
-    // captured launches then find the workspace ready.
-    ctx->capturing = true; // the same (one-workgroup) launches as the capture
+    // One eager solve sizes every buffer, uploads the keep counts and, for a
+    // batched solve of host-known kept counts, chooses the cooperative
+    // schedule.  The graph keeps its own copy of that table, so later solves
+    // on the context cannot change what it replays.
     int rc = damas_solve_dev(ctx, g, n_bins, freq, csm, p, x_init, x_map, b_map, idx, s_tilde,
                              s);
-    ctx->capturing = false;
     if (rc == DAMAS_OK)
         rc = damas_check(ctx, s);
+    int32_t *tab = nullptr;
+    int nwg = 0, gpw = 0;
+    if (rc == DAMAS_OK && ctx->last_coop) {
+        const size_t bytes = sizeof(int32_t) * ctx->coop_tab_host.size();
+        if (hipMalloc((void **)&tab, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            tab = nullptr;
+            rc = fail(DAMAS_ENOMEM, "graph schedule table (%zu bytes)", bytes);
+        } else if (hipMemcpy(tab, ctx->coop_tab_host.data(), bytes, hipMemcpyHostToDevice) !=
+                   hipSuccess) {
+            rc = fail(DAMAS_EDEVICE, "graph schedule table upload");
+        }
+        nwg = ctx->last_workgroups;
+        gpw = ctx->last_gpw;
+    }
     hipGraph_t graph = nullptr;
     if (rc == DAMAS_OK) {
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = fail(DAMAS_EDEVICE, "hipStreamBeginCapture");
         } else {
             ctx->capturing = ctx->in_capture = true;
+            ctx->cap_tab = tab;
+            ctx->cap_nwg = nwg;
+            ctx->cap_gpw = gpw;
             rc = damas_solve_dev(ctx, g, n_bins, freq, csm, p, x_init, x_map, b_map, idx,
                                  s_tilde, s);
             ctx->capturing = ctx->in_capture = false;
+            ctx->cap_tab = nullptr;
             const hipError_t e = hipStreamEndCapture(s, &graph);
             if (rc == DAMAS_OK && e != hipSuccess)
                 rc = fail(DAMAS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
         }
     }
+    // Capture records a cooperative launch as a plain kernel node; the
+    // sweep nodes get the cooperative attribute back, so a replay launches
+    // them as the eager solve does (all workgroups resident together).
+    if (rc == DAMAS_OK && tab && (rc = mark_coop_nodes(graph)))
+        rc = fail(DAMAS_EDEVICE, "marking the cooperative sweep nodes");
     (void)hipStreamDestroy(s);
-    if (rc) {
+    auto drop = [&](int code) {
         if (graph)
             (void)hipGraphDestroy(graph);
-        return rc;
-    }
+        if (tab)
+            (void)hipFree(tab);
+        return code;
+    };
+    if (rc)
+        return drop(rc);
     damas_graph *gr = new (std::nothrow) damas_graph();
-    if (!gr) {
-        (void)hipGraphDestroy(graph);
-        return fail(DAMAS_ENOMEM, "graph allocation");
-    }
+    if (!gr)
+        return drop(fail(DAMAS_ENOMEM, "graph allocation"));
     if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(graph);
         delete gr;
-        return fail(DAMAS_EDEVICE, "hipGraphInstantiate");
+        return drop(fail(DAMAS_EDEVICE, "hipGraphInstantiate"));
     }
     gr->graph = graph;
     gr->ctx = ctx;
+    gr->tab = tab;
+    gr->workgroups = tab ? nwg : ctx->last_workgroups;
     ++ctx->graphs;
     *out = gr;
     return DAMAS_OK;
+}
+
+extern "C" int32_t damas_graph_workgroups(const damas_graph *gr)
+{
+    return gr ? gr->workgroups : 0;
 }
 
 extern "C" int damas_graph_launch(damas_graph *gr, void *stream)
@@ -1861,6 +1973,8 @@ extern "C" void damas_graph_destroy(damas_graph *gr)
         (void)hipGraphExecDestroy(gr->exec);
     if (gr->graph)
         (void)hipGraphDestroy(gr->graph);
+    if (gr->tab)
+        (void)hipFree(gr->tab);
     --gr->ctx->graphs;
     delete gr;
 }
@@ -1924,6 +2038,14 @@ __global__ void static_fill_zero(uint32_t *p, int64_t n)
         p[i] = 0u;
 }
 
+// Sets n words to v.
+__global__ void static_fill_value(uint32_t *p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // Bump allocation of 256-byte aligned regions from the array.
 struct Carve {
     unsigned char *base;
@@ -1950,6 +2072,12 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
         return rc;
     if (!p)
         return fail(DAMAS_EINVAL, "params are NULL");
+    // KEEP_FRAC: the host knows the count, so it also bounds max_kept; the
+    // counts go to the device from the array.
+    const bool frac = p->select_mode == DAMAS_SEL_KEEP_FRAC;
+    damas_params pn;
+    if ((rc = resolve_frac(p, g->N, pn, &p)))
+        return rc;
     if (p->precision != DAMAS_PREC_FP64 && p->precision != DAMAS_PREC_FP32)
         return fail(DAMAS_EINVAL, "damas_solve_static solves at FP64 or FP32 (precision %d)",
                     p->precision);
@@ -1969,12 +2097,14 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
         return DAMAS_OK;
     if (!freq || !csm || !x_map)
         return fail(DAMAS_EINVAL, "freq, csm and x_map must be non-NULL");
-    if (p->select_mode == DAMAS_SEL_KEEP_COUNT && !keep_count)
+    if (p->select_mode == DAMAS_SEL_KEEP_COUNT && !keep_count && !frac)
         return fail(DAMAS_EINVAL, "KEEP_COUNT needs keep_count (device, n_bins int32)");
     const int32_t S = g->N * g->N, M = g->M;
-    const int32_t max_kept = p->select_mode == DAMAS_SEL_KEEP_ALL
-                                 ? S
-                                 : (p->max_kept > 0 ? std::min(p->max_kept, S) : S);
+    const int32_t frac_kept =
+        frac ? std::min(std::max(p->keep_count_all, coarse_count(g->N)), S) : 0;
+    const int32_t max_kept = p->select_mode == DAMAS_SEL_KEEP_ALL ? S
+                             : frac ? frac_kept
+                                    : (p->max_kept > 0 ? std::min(p->max_kept, S) : S);
     if ((rc = check_kept(max_kept, S, p->precision)))
         return rc;
 
@@ -1992,6 +2122,8 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
     need += s_tilde ? 0 : al(sizeof(int32_t) * nb);
     need += al(sizeof(int64_t) * (nb + 1)) + al(sizeof(double) * nb * e_stride) +
             al(es * (size_t)a_elems);
+    if (frac)
+        need += al(sizeof(int32_t) * nb);
     if (classes)
         need += al(sizeof(uint16_t) * (size_t)a_elems) + al(sizeof(double) * nb * tiles) +
                 al(nb);
@@ -2012,6 +2144,7 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
     int64_t *off = (int64_t *)c.take(sizeof(int64_t) * (nb + 1));
     double *E = (double *)c.take(sizeof(double) * nb * e_stride);
     void *A = c.take(es * (size_t)a_elems);
+    int32_t *kc = frac ? (int32_t *)c.take(sizeof(int32_t) * nb) : nullptr;
     PsfClassArgs pc;
     GsClassArgs gca;
     if (classes) {
@@ -2031,6 +2164,12 @@ extern "C" int damas_solve_static(const damas_geometry *g, int32_t n_bins, const
     const Geom kg = make_geom(*g);
     hipLaunchKernelGGL(static_fill_zero, dim3(1), dim3(64), 0, s, (uint32_t *)fault, (int64_t)1);
     HIP_TRY(hipGetLastError(), "fault word clear");
+    if (frac) {
+        hipLaunchKernelGGL(static_fill_value, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
+                           (uint32_t *)kc, (int64_t)nb, (uint32_t)frac_kept);
+        HIP_TRY(hipGetLastError(), "keep counts fill");
+        keep_count = kc;
+    }
     HIP_TRY(launch_das(kg, n_bins, freq, csm, bm, s, p->steering, p->diag_removal),
             "das launch");
     HIP_TRY(launch_select(g->N, n_bins, bm, p->select_mode, p->eps, p->predictor,

@@ -45,8 +45,21 @@ __host__ __device__ inline float bf16_to_float(bf16s v)
     return __builtin_bit_cast(float, (uint32_t)v.u << 16);
 }
 
-// Row stride of a compressed system: s_tilde rounded up to 8 elements.
-__host__ __device__ inline int64_t ld_of(int32_t st) { return ((int64_t)st + 7) & ~(int64_t)7; }
+// Row stride of a compressed system: s_tilde rounded up to 32 elements.
+// Arenas start on 256-byte boundaries and the per-bin offsets are sums of
+// ld^2, so every row of a float or double arena starts on a 128-byte line
+// and the 64-column piece of a row that a sweep strip reads covers whole
+// lines: no line is fetched for a neighbouring strip (with 8-element rows
+// three lines in four straddled, and the streamed bands fetched 1.35-1.4
+// times their algorithmic bytes).  bf16 rows start on 64-byte halves; 64
+// elements would align them too but pad the small cache-resident systems
+// out of L2 (measured: no faster on the bf16 sweeps, 11 % slower on 337-row
+// bins).
+constexpr int kLdAlign = 32;
+__host__ __device__ inline int64_t ld_of(int32_t st)
+{
+    return ((int64_t)st + kLdAlign - 1) & ~(int64_t)(kLdAlign - 1);
+}
 
 // Distance from grid point n to microphone m, in double.
 __device__ inline double point_mic_dist(const Geom &g, int n, int m)
@@ -193,5 +206,8 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
                           const void *x_init, void *x_map, int *fault, const int32_t *tab,
                           int n_wg, int groups_per_wave, void *ws, const GsClassArgs &gc,
                           hipStream_t s);
+// Whether fn is one of the cooperative kernel's instances (graph capture
+// turns their cooperative launches into plain kernel nodes).
+bool gs_is_coop_kernel(const void *fn);
 
 } // namespace damas

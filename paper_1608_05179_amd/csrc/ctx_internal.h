@@ -86,11 +86,19 @@ struct damas_ctx {
         int floor_rows = 0;    // cost model: a tile costs max(floor_rows, ld) (0: ld)
         double wide_cost = 1.7; // cost per element of a wide bin relative to a narrow one
     } tune;
-    // graph capture: `capturing` turns cooperation off (cooperative launches
-    // are not captured), for the sizing solve too; `in_capture` refuses
+    // graph capture: `capturing` marks the captured solve, which makes no
+    // host synchronisation and plans no schedule: its sweeps run the
+    // schedule the sizing solve before it chose, from the graph's own copy
+    // of the table (cap_tab, cap_nwg workgroups, cap_gpw groups per wave),
+    // or one workgroup per bin when cap_tab is null; `in_capture` refuses
     // workspace growth inside the captured solve
     bool capturing = false, in_capture = false;
+    const int32_t *cap_tab = nullptr;
+    int cap_nwg = 0, cap_gpw = 0;
     int graphs = 0;
+    // the last sweep launch's schedule: cooperative or not, groups per wave
+    bool last_coop = false;
+    int last_gpw = 0;
     std::vector<int32_t> coop_tab_host; // last uploaded schedule
     damas::Buffer coop_ws, coop_tab;
     int32_t *coop_pinned = nullptr;
@@ -101,6 +109,10 @@ struct damas_ctx {
 };
 
 namespace damas {
+
+// KEEP_FRAC params in their KEEP_COUNT form (*q = &tmp), or p itself (*q =
+// p) for the other modes; an invalid keep_frac fails with DAMAS_EINVAL.
+int resolve_frac(const damas_params *p, int32_t N, damas_params &tmp, const damas_params **q);
 
 // Device bytes a context currently holds, and release of its workspace.
 size_t ctx_bytes(const damas_ctx *ctx);

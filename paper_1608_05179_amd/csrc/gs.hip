@@ -1100,7 +1100,8 @@ template <typename TA, int NW, bool LO = false> constexpr size_t gs_lds_fixed()
 // Unknowns a wide bin may hold: x~ beside the wide blocks of NW stream waves.
 template <int NW> constexpr int gs_lo_cap()
 {
-    return (int)(((kGsLdsLimit - gs_lds_fixed<float, NW, true>()) / sizeof(double)) & ~(size_t)7);
+    return (int)(((kGsLdsLimit - gs_lds_fixed<float, NW, true>()) / sizeof(double)) &
+                 ~(size_t)(kLdAlign - 1));
 }
 
 // Per-bin storage classes of a launch: cls (per bin, or null: every bin of
@@ -1485,7 +1486,7 @@ int gs_max_kept(int precision)
     // Everything in the 160 KB of LDS of one CU, less a margin, for both
     // kernels.
     const size_t fixed = std::max(gs_plain_lds_bytes(precision, 0), gs_coop_lds_bytes(precision, 0));
-    return (int)(((kGsLdsLimit - fixed) / sizeof(double)) & ~(size_t)7);
+    return (int)(((kGsLdsLimit - fixed) / sizeof(double)) & ~(size_t)(kLdAlign - 1));
 }
 
 template <typename TA, typename TX, bool UNIT, int NW, int WAVES, int NH, int NB>
@@ -1597,6 +1598,16 @@ static const void *coop_pick(int precision, int unit, int groups_per_wave)
         DAMAS_COOP_PICK(bf16s, float)
     DAMAS_COOP_PICK(float, float)
 #undef DAMAS_COOP_PICK
+}
+
+bool gs_is_coop_kernel(const void *fn)
+{
+    for (int prec : {DAMAS_PREC_FP64, DAMAS_PREC_FP32, DAMAS_PREC_BF16})
+        for (int unit : {0, 1})
+            for (int gpw : {1, 1 << 30}) // the short and the long shape
+                if (fn == coop_pick(prec, unit, gpw))
+                    return true;
+    return false;
 }
 
 int gs_coop_capacity(int precision, int max_kept, bool lo)

@@ -324,6 +324,10 @@ extern "C" int damas_submit(damas_server *srv, const damas_request *q, uint64_t 
         return set_error(DAMAS_EINVAL, "mic, freq, csm and x_map must be non-NULL");
     uint64_t fp = 0;
     int rc = damas_query_footprint(q->M, q->N, q->n_bins, &q->params, &fp);
+    damas_params pn;
+    const damas_params *qp = &q->params;
+    if (rc == DAMAS_OK)
+        rc = resolve_frac(&q->params, q->N, pn, &qp);
     if (rc)
         return rc;
     if (fp > srv->o.hbm_budget) {
@@ -347,10 +351,10 @@ extern "C" int damas_submit(damas_server *srv, const damas_request *q, uint64_t 
     r->mic.assign(q->mic, q->mic + 3 * (size_t)q->M);
     r->freq.assign(q->freq, q->freq + q->n_bins);
     r->csm.assign(q->csm, q->csm + (size_t)q->n_bins * q->M * q->M * 2);
-    r->params = q->params;
+    r->params = *qp;
     r->params.power = nullptr;
-    if (q->params.keep_count)
-        r->keep_count.assign(q->params.keep_count, q->params.keep_count + q->n_bins);
+    if (qp->keep_count)
+        r->keep_count.assign(qp->keep_count, qp->keep_count + q->n_bins);
     r->params.keep_count = nullptr;
     r->x_map = q->x_map;
     r->s_tilde = q->s_tilde;

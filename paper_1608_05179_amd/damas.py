@@ -28,6 +28,7 @@ ECAPACITY = -7
 SEL_KEEP_ALL = 0
 SEL_EPS_REL = 1
 SEL_KEEP_COUNT = 2
+SEL_KEEP_FRAC = 3
 PRED_HAAR = 0
 PRED_LINEAR = 1
 
@@ -72,7 +73,8 @@ class Params(ctypes.Structure):
                 ("iterations", c_i32), ("precision", c_i32), ("batched", c_i32),
                 ("max_kept", c_i32), ("refine_sweeps", c_i32), ("predictor", c_i32),
                 ("policy", c_i32), ("rho_wide", c_dbl), ("rho_f32", c_dbl),
-                ("steering", c_i32), ("diag_removal", c_i32), ("power", c_vp)]
+                ("steering", c_i32), ("diag_removal", c_i32), ("power", c_vp),
+                ("keep_frac", c_dbl)]
 
 
 def _sig(name, res, *args):
@@ -139,6 +141,7 @@ _sig("damas_ctx_autotune", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POI
 _sig("damas_graph_capture", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
      c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_vp))
 _sig("damas_graph_launch", ctypes.c_int, c_vp, c_vp)
+_sig("damas_graph_workgroups", c_i32, c_vp)
 _sig("damas_graph_destroy", None, c_vp)
 
 
@@ -434,16 +437,17 @@ def solve_static(g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                  keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
                  x_init=None, x_map=None, b_map=None, idx=None, s_tilde=None, predictor=0,
                  policy=POLICY_AUTO, rho_wide=0.0, steering=STEER_UNIT, diag_removal=False,
-                 stream=None):
+                 keep_frac=0.0, stream=None):
     """The whole-path solve with no allocation by the library (damas_solve_static):
-    keep_count is a device int32 tensor of n_bins (KEEP_COUNT).  Faults are
+    keep_count is a device int32 tensor of n_bins (KEEP_COUNT; KEEP_FRAC takes
+    keep_frac instead).  Faults are
     reported by check(None)."""
     csm = _as_interleaved(csm)
     nb = freq.numel()
     if x_map is None:
         x_map = torch.empty(nb, g.N * g.N, dtype=_XTYPE[precision], device=freq.device)
     p, _kc = _params(nb, select_mode, eps, None, iterations, precision, True, max_kept, 0,
-                     predictor, policy, rho_wide, 0.0, steering, diag_removal)
+                     predictor, policy, rho_wide, 0.0, steering, diag_removal, keep_frac)
     dt = _XTYPE[precision]
     _check(_lib.damas_solve_static(ctypes.byref(g), nb, _ptr(freq, torch.float64, "freq"),
                                    _ptr(csm, torch.float64, "csm"), ctypes.byref(p),
@@ -511,7 +515,8 @@ class Context:
               keep_count=None, iterations=1000, precision=PREC_FP32, batched=True,
               max_kept=0, refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
               s_tilde=None, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0,
-              steering=STEER_UNIT, diag_removal=False, power=None, stream=None):
+              steering=STEER_UNIT, diag_removal=False, power=None, keep_frac=0.0,
+              stream=None):
         """Every step for every bin on the device; returns x_map.  power (a
         device float64 tensor of n_bins, optional) receives each bin's
         integrated power.
@@ -524,7 +529,7 @@ class Context:
             x_map = torch.empty(nb, S, dtype=_XTYPE[precision], device=freq.device)
         p, kc_arr = _params(nb, select_mode, eps, keep_count, iterations, precision, batched,
                             max_kept, refine_sweeps, predictor, policy, rho_wide, rho_f32,
-                            steering, diag_removal)
+                            steering, diag_removal, keep_frac)
         p.power = _ptr(power, torch.float64, "power")
         dt = _XTYPE[precision]
         _check(_lib.damas_solve_dev(self._h, ctypes.byref(g), nb,
@@ -541,13 +546,14 @@ class Context:
 
     def autotune(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                  keep_count=None, precision=PREC_FP32, max_kept=0, trial_sweeps=30,
-                 policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0, stream=None) -> dict:
+                 policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0, keep_frac=0.0,
+                 stream=None) -> dict:
         """Tune the cooperative sweep schedule on this problem (trial solves
         of trial_sweeps sweeps); the choice stays on the context."""
         csm = _as_interleaved(csm)
         nb = freq.numel()
         p, _kc = _params(nb, select_mode, eps, keep_count, trial_sweeps, precision, True,
-                         max_kept, 0, 0, policy, rho_wide, rho_f32)
+                         max_kept, 0, 0, policy, rho_wide, rho_f32, keep_frac=keep_frac)
         r = TuneResult()
         _check(_lib.damas_ctx_autotune(self._h, ctypes.byref(g), nb,
                                        _ptr(freq, torch.float64, "freq"),
@@ -558,7 +564,8 @@ class Context:
     def capture(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                 keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
                 refine_sweeps=0, x_init=None, x_map=None, b_map=None, idx=None,
-                s_tilde=None, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0):
+                s_tilde=None, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0,
+                steering=STEER_UNIT, diag_removal=False, power=None, keep_frac=0.0):
         """Capture this batched solve into a Graph (csm must be float64
         interleaved (n_bins, M, M, 2) so that in-place updates reach the
         graph)."""
@@ -568,7 +575,9 @@ class Context:
         if x_map is None:
             x_map = torch.empty(nb, g.N * g.N, dtype=_XTYPE[precision], device=freq.device)
         p, kc = _params(nb, select_mode, eps, keep_count, iterations, precision, True,
-                        max_kept, refine_sweeps, 0, policy, rho_wide, rho_f32)
+                        max_kept, refine_sweeps, predictor, policy, rho_wide, rho_f32,
+                        steering, diag_removal, keep_frac)
+        p.power = _ptr(power, torch.float64, "power")
         dt = _XTYPE[precision]
         h = c_vp()
         _check(_lib.damas_graph_capture(self._h, ctypes.byref(g), nb,
@@ -593,6 +602,10 @@ class Graph:
         _check(_lib.damas_graph_launch(self._h, _stream(stream)))
         return self.x_map
 
+    def workgroups(self) -> int:
+        """Workgroups of the captured sweep launches (n_bins: one per bin)."""
+        return int(_lib.damas_graph_workgroups(self._h))
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.damas_graph_destroy(self._h)
@@ -607,7 +620,7 @@ class Graph:
 
 def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, max_kept,
             refine_sweeps, predictor=0, policy=POLICY_AUTO, rho_wide=0.0, rho_f32=0.0,
-            steering=STEER_UNIT, diag_removal=False):
+            steering=STEER_UNIT, diag_removal=False, keep_frac=0.0):
     """Params struct and the ctypes array that keeps per-bin counts alive."""
     kc_arr = None
     kc_all = 0
@@ -623,16 +636,17 @@ def _params(nb, select_mode, eps, keep_count, iterations, precision, batched, ma
                ctypes.cast(kc_arr, ctypes.POINTER(c_i32)) if kc_arr is not None else None,
                int(kc_all), int(iterations), int(precision), 1 if batched else 0,
                int(max_kept), int(refine_sweeps), int(predictor), int(policy),
-               float(rho_wide), float(rho_f32), int(steering), 1 if diag_removal else 0)
+               float(rho_wide), float(rho_f32), int(steering), 1 if diag_removal else 0,
+               None, float(keep_frac))
     return p, kc_arr
 
 
 def query_footprint(M: int, N: int, n_bins: int, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                     keep_count=None, iterations=1000, precision=PREC_FP32, max_kept=0,
-                    refine_sweeps=0, policy=POLICY_AUTO) -> int:
+                    refine_sweeps=0, policy=POLICY_AUTO, keep_frac=0.0) -> int:
     """Device bytes of a whole-path solve of this shape (no device work)."""
     p, _kc = _params(n_bins, select_mode, eps, keep_count, iterations, precision, True,
-                     max_kept, refine_sweeps, 0, policy)
+                     max_kept, refine_sweeps, 0, policy, keep_frac=keep_frac)
     out = ctypes.c_uint64()
     _check(_lib.damas_query_footprint(int(M), int(N), int(n_bins), ctypes.byref(p),
                                       ctypes.byref(out)))
@@ -668,14 +682,14 @@ class Server:
 
     def submit(self, mic, N, extent, z0, freqs, csm, *, select_mode=SEL_KEEP_COUNT, eps=0.0,
                keep_count=None, iterations=1000, precision=PREC_FP32, refine_sweeps=0,
-               max_kept=0, c=343.0, policy=POLICY_AUTO) -> int:
+               max_kept=0, c=343.0, policy=POLICY_AUTO, keep_frac=0.0) -> int:
         """Queue one solve; returns its ticket.  csm: complex (n_bins, M, M)."""
         mic = np.ascontiguousarray(mic, dtype=np.float64)
         freqs = np.ascontiguousarray(freqs, dtype=np.float64)
         nb = freqs.size
         csm = np.ascontiguousarray(np.asarray(csm, dtype=np.complex128).view(np.float64))
         p, kc = _params(nb, select_mode, eps, keep_count, iterations, precision, True,
-                        max_kept, refine_sweeps, 0, policy)
+                        max_kept, refine_sweeps, 0, policy, keep_frac=keep_frac)
         x = np.zeros((nb, N * N), np.float64 if precision == PREC_FP64 else np.float32)
         st = np.zeros(nb, np.int32)
         x0, x1, y0, y1 = extent

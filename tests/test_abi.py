@@ -43,7 +43,8 @@ def test_status_strings(lib):
 
 def test_layout_helpers(lib):
     lib.damas_ld.restype = ctypes.c_int64
-    assert [lib.damas_ld(v) for v in (0, 1, 8, 9, 337)] == [0, 8, 8, 16, 344]
+    # rows rounded up to 32 elements: float rows start on whole 128-byte lines
+    assert [lib.damas_ld(v) for v in (0, 1, 8, 9, 32, 33, 337)] == [0, 32, 32, 32, 32, 64, 352]
     # |G^0| = 4 unless N is a power of two (then only index 0 of each axis)
     assert [lib.damas_coarse_count(n) for n in (1, 2, 3, 4, 5, 16, 17, 21, 41, 101)] == \
         [1, 1, 4, 1, 4, 1, 4, 4, 4, 4]
@@ -55,14 +56,15 @@ def test_gs_capacity(lib):
     # One sweep workgroup's LDS (160 KB less a margin) beside the partial sums
     # and the two hand-over blocks of the larger (cooperative) kernel: x~ of
     # 1,856 unknowns with double A, 10,112 with float A; bf16 sweeps would
-    # hold 14,496 but a bf16 solve ends with FP32 sweeps.
+    # hold 14,496 but a bf16 solve ends with FP32 sweeps.  Capacities are
+    # multiples of the row alignment (32), so damas_ld(cap) == cap.
     assert [lib.damas_gs_capacity(p) for p in (dm.PREC_FP64, dm.PREC_FP32, dm.PREC_BF16)] == \
         [1856, 10112, 10112]
     assert lib.damas_gs_capacity(9) == 0 and lib.damas_gs_capacity(-1) == 0
     fake = ctypes.c_void_p(0x1000)
     for p in (dm.PREC_FP64, dm.PREC_FP32, dm.PREC_BF16):
         cap = lib.damas_gs_capacity(p)
-        assert dm._lib.damas_gs(101, 1, fake, cap + 8, fake, fake, p, 1, fake, fake, 1,
+        assert dm._lib.damas_gs(101, 1, fake, cap + 1, fake, fake, p, 1, fake, fake, 1,
                                 None, fake, None) == dm.EINVAL
 
 
@@ -190,3 +192,31 @@ def test_host_solve_validates_on_the_host(lib):
     f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 8
     p = ctypes.c_void_p(16)  # never dereferenced: the call fails validation
     assert f(None, p, 1, p, p, p, None, p, None, None, None) == -1
+
+
+def test_keep_frac_is_keep_count_of_its_ceiling(lib):
+    # KEEP_FRAC keeps ceil(p N^2) points in every bin (level-0 points
+    # included): p = 0.1, 0.2, 0.3 on a 41 x 41 grid keep 169, 337, 505.
+    import math
+    from paper_1608_05179_amd import damas as dm
+    M, N = 64, 41
+    for p, K in ((0.1, 169), (0.2, 337), (0.3, 505)):
+        assert math.ceil(p * N * N) == K
+        for prec in (dm.PREC_FP32, dm.PREC_FP64):
+            assert dm.query_footprint(M, N, 3, select_mode=dm.SEL_KEEP_FRAC, keep_frac=p,
+                                      precision=prec, iterations=10) == \
+                dm.query_footprint(M, N, 3, select_mode=dm.SEL_KEEP_COUNT, keep_count=K,
+                                   precision=prec, iterations=10)
+    # the whole grid, and a fraction below one point: clamped like KEEP_COUNT
+    assert dm.query_footprint(M, N, 1, select_mode=dm.SEL_KEEP_FRAC, keep_frac=1.0) == \
+        dm.query_footprint(M, N, 1, select_mode=dm.SEL_KEEP_COUNT, keep_count=N * N)
+    assert dm.query_footprint(M, N, 1, select_mode=dm.SEL_KEEP_FRAC, keep_frac=1e-9) == \
+        dm.query_footprint(M, N, 1, select_mode=dm.SEL_KEEP_COUNT, keep_count=1)
+    for bad in (0.0, -0.1, 1.5, float("nan"), float("inf")):
+        with pytest.raises(dm.DamasError) as ei:
+            dm.query_footprint(M, N, 1, select_mode=dm.SEL_KEEP_FRAC, keep_frac=bad)
+        assert ei.value.code == dm.EINVAL
+    # the step-level selection takes counts, not fractions
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.damas_select(N, 1, fake, dm.SEL_KEEP_FRAC, ctypes.c_double(0.0), fake, fake,
+                            fake, None) == dm.EINVAL

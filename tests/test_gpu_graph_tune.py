@@ -1,7 +1,8 @@
 """Graph capture and the schedule autotuner.
 
 A captured solve replays bitwise like the eager solve it captured (one
-workgroup per bin), on every replay, with eager work and synchronisations
+workgroup per bin, or the cooperative schedule of a batched band), on every
+replay, with eager work and synchronisations
 in between; a CSM changed in place gives the eager solve of the new CSM.
 The autotuner's choice stays on the context and its solves still match the
 oracle."""
@@ -65,6 +66,47 @@ def test_graph_replays_match_eager(dm, dev):
     graph.close()
     ctx.close()
     eager_ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_graph_cooperative_replays_match_eager(dm, dev, prec):
+    # Uneven kept counts: the long bins get helper workgroups, so the graph
+    # holds the cooperative sweep launches (one for FP32; bf16 bulk and FP32
+    # refinement for BF16).  Every replay equals, bitwise, the eager solve
+    # of a context that plans the same schedule, with eager work and
+    # synchronisations between replays; the power output is captured too.
+    import torch
+    if prec == "fp32":
+        w = synth.compressed_fp32(n_bins=4, N=61, iterations=120)
+        kw = dict(select_mode=dm.SEL_KEEP_COUNT, keep_count=[2400, 700, 3600, 150],
+                  iterations=w.iterations, precision=dm.PREC_FP32)
+    else:
+        w = synth.precision_bf16(n_bins=3, N=61, iterations=120)
+        kw = dict(select_mode=dm.SEL_KEEP_ALL, iterations=w.iterations,
+                  precision=dm.PREC_BF16, refine_sweeps=30)
+    mic, g, freq, csm = _setup(dm, dev, w)
+    eager = dm.Context(0)
+    p_ref = torch.zeros(w.n_bins, dtype=torch.float64, device=dev)
+    ref = eager.solve(g, freq, csm, power=p_ref, **kw).clone()
+    eager.check()
+    assert eager.last_workgroups() > w.n_bins
+    ctx = dm.Context(0)
+    p_out = torch.zeros(w.n_bins, dtype=torch.float64, device=dev)
+    graph = ctx.capture(g, freq, csm, power=p_out, **kw)
+    assert graph.workgroups() == eager.last_workgroups()
+    for _ in range(3):
+        graph.x_map.fill_(-1.0)
+        p_out.fill_(-1.0)
+        out = graph.launch()
+        torch.cuda.synchronize()
+        ctx.check()
+        assert torch.equal(out, ref)
+        assert torch.equal(p_out, p_ref)
+        eager.solve(g, freq, csm, **dict(kw, iterations=40))
+        torch.cuda.synchronize()
+    graph.close()
+    ctx.close()
+    eager.close()
 
 
 def test_autotune_keeps_a_valid_choice(orc, dm, dev):
