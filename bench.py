@@ -51,7 +51,7 @@ HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 CLOCK_GHZ = 2.4
-GS_SOURCE = os.path.join(ROOT, "paper_1608_05179_amd", "csrc", "gs.hip")
+CSRC = os.path.join(ROOT, "paper_1608_05179_amd", "csrc")
 
 
 def _parse():
@@ -85,16 +85,27 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
+def sources_sha256():
+    """One digest over the library's HIP sources (file names and contents,
+    in name order): counters taken on other sources no longer apply."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
 def _traffic(workload):
     """HBM bytes per sweep launch of a workload from its committed counter
-    summary, if that was taken on the current sweep kernel source."""
+    summary, if that was taken on the current library sources."""
     path = os.path.join(ROOT, "profiles", f"gs_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    src = hashlib.sha256(open(GS_SOURCE, "rb").read()).hexdigest()
-    if t.get("gs_source_sha256") != src:
+    if t.get("sources_sha256") != sources_sha256():
         return None
     return t.get("hbm_bytes_per_launch")
 
