@@ -80,6 +80,15 @@ def _parse():
     return ap.parse_args()
 
 
+_T0 = time.perf_counter()
+
+
+def _progress(msg):
+    """One line per finished phase on stderr (stdout carries only the
+    result line)."""
+    print(f"bench.py: {msg} ({time.perf_counter() - _T0:.0f} s)", file=sys.stderr, flush=True)
+
+
 def _pct(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v), q))
@@ -433,9 +442,10 @@ def oracle_check(pb, bins, cores=None, extra_maps=()):
 
 def measure_latency_bound(name, steps, warmup, tune_sweeps):
     """A band whose systems stay in cache (the compressed workload: 64 bins
-    of 337 kept, 29 MB of A): each bin's sweeps are a chain of S~ I serial
-    row steps on one workgroup, so the sweeps are reported as ns per row
-    step against the step chain's floor, not against HBM."""
+    of 337 kept, 29 MB of A; the plain workload: one bin of 441, 1.6 MB):
+    each bin's sweeps are a chain of S~ I serial row steps on one
+    workgroup, so the sweeps are reported as ns per row step against the
+    step chain's floor, not against HBM."""
     rec, pb = measure(name, steps, warmup, tune_sweeps=tune_sweeps)
     w = pb.w
     steps_chain = int(rec["s_tilde_max"]) * w.iterations
@@ -665,8 +675,8 @@ def main():
         print(json.dumps(measure_psf()), flush=True)
         torch.cuda.synchronize()
         return
-    if args.workload == "compressed":
-        print(json.dumps(measure_latency_bound("compressed", args.steps, args.warmup,
+    if args.workload in ("compressed", "plain"):
+        print(json.dumps(measure_latency_bound(args.workload, args.steps, args.warmup,
                                                args.tune_sweeps)), flush=True)
         return
     if args.workload is not None:
@@ -681,6 +691,7 @@ def main():
     # ---- headline: the batched band --------------------------------------
     rec, pb = measure("batched", args.steps, args.warmup, tune_sweeps=args.tune_sweeps,
                       fixed=args.fixed, rho_wide=args.rho_wide)
+    _progress("batched band timed")
     rec["roofline"]["traffic"] = _traffic("batched")
     out = {
         "metric": METRIC, "value": rec["value"], "unit": rec["unit"],
@@ -698,6 +709,7 @@ def main():
         "classes": rec.get("classes"),
         "sweeps_ms": rec["sweeps_ms"], "system_build_ms": rec["system_build_ms"],
         "sweep_workgroups": rec["sweep_workgroups"], "autotune": rec["autotune"],
+        "graph": rec.get("graph"),
         "roofline": rec["roofline"],
     }
     w = pb.w
@@ -727,25 +739,30 @@ def main():
             "host_cpu": lscpu, "host_cores_visible": os.cpu_count()}
         out["oracle_rel_l2"] = errs
         out["oracle_max_rel_l2"] = max(errs.values())
+        _progress("oracle on sampled bins done")
     pb.close()
     torch.cuda.empty_cache()
     if args.plain_bins > 0:
         out["plain"] = plain_sampled("batched", args.plain_bins)
         torch.cuda.empty_cache()
+        _progress("plain per-bin launches timed")
 
     # ---- the other workloads at full size ---------------------------------
     if not args.no_variants:
         v = {}
         v["compressed"] = measure_latency_bound("compressed", 10, 2, args.tune_sweeps)
-        r, p2 = measure("plain", 5, 1)
-        p2.close()
-        v["plain"] = r
+        _progress("compressed variant")
+        v["plain"] = measure_latency_bound("plain", 5, 1, 0)
         torch.cuda.empty_cache()
+        _progress("plain variant")
         v["precision"] = measure_precision(2, 1, args.refine, args.tune_sweeps)
         torch.cuda.empty_cache()
+        _progress("precision variant")
         v["served"] = measure_served()
+        _progress("served variant")
         v["csm"] = measure_csm()
         v["psf"] = measure_psf()
+        _progress("csm and psf variants")
         out["variants"] = v
     torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
