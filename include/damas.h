@@ -354,9 +354,38 @@ typedef struct damas_ctx damas_ctx;
 
 /* A context owns the device workspace (kept points, steering rows, the
  * packed A arena), grown on demand and reused across calls, for one device.
- * Not thread-safe. */
+ * Not thread-safe.  damas_ctx_create(device, out) is damas_ctx_create_ex
+ * with every option at its default. */
 int damas_ctx_create(int32_t device, damas_ctx **out);
 void damas_ctx_destroy(damas_ctx *ctx);
+
+/* Options of a context (damas_ctx_create_ex; host memory, read during the
+ * call; tune_cache is copied). */
+typedef struct {
+    int32_t device;          /* HIP device ordinal                          */
+    uint64_t hbm_budget;     /* bytes the context's workspace may hold; a
+                                solve that would grow it beyond fails with
+                                DAMAS_EADMIT, its outputs undefined (0: no
+                                limit; damas_query_footprint bounds a
+                                solve's need)                              */
+    const char *tune_cache;  /* path of a text file of autotune choices, or
+                                NULL: damas_ctx_autotune first looks its
+                                problem up there (and applies the stored
+                                choice without trial solves), else tunes
+                                and appends the choice; the file is read
+                                at creation                                */
+    int32_t deterministic;   /* 1: sweeps run one workgroup per bin (no
+                                cooperative schedule), so results depend
+                                only on the inputs, not on tuning or on
+                                the device's compute-unit count;
+                                damas_ctx_set_coop then accepts only 0     */
+} damas_ctx_opts;
+int damas_ctx_create_ex(const damas_ctx_opts *opts, damas_ctx **out);
+
+/* Description of the last failure of a call made on this context, from any
+ * thread ("" if none; NULL ctx: ""); the text is copied to storage of the
+ * calling thread, valid until that thread's next call to this function. */
+const char *damas_ctx_last_error(const damas_ctx *ctx);
 
 /* Timing of the phases of a solve: when enabled, each damas_solve_dev
  * records HIP events on the solve's stream around

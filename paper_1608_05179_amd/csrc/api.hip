@@ -21,6 +21,16 @@ using namespace damas;
 namespace {
 
 thread_local std::string g_err;
+thread_local damas_ctx *g_ctx_cur = nullptr; // see CtxScope
+
+void record(const char *msg)
+{
+    g_err = msg;
+    if (g_ctx_cur) {
+        std::lock_guard<std::mutex> lk(g_ctx_cur->err_mu);
+        g_ctx_cur->err = msg;
+    }
+}
 
 int fail(int code, const char *fmt, ...)
 {
@@ -29,7 +39,7 @@ int fail(int code, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_err = buf;
+    record(buf);
     return code;
 }
 
@@ -537,6 +547,14 @@ int ensure(damas_ctx *ctx, Buffer &buf, size_t bytes, hipStream_t s, const char 
     if (ctx->graphs > 0 || ctx->in_capture)
         return fail(DAMAS_EBUSY,
                     "%s would grow while a graph captured on this context exists", what);
+    if (ctx->hbm_budget) {
+        const size_t after = ctx_bytes(ctx) - buf.bytes + std::max(bytes, (size_t)256);
+        if (after > ctx->hbm_budget)
+            return fail(DAMAS_EADMIT,
+                        "%s would take the context's workspace to %zu bytes, beyond its "
+                        "budget of %llu",
+                        what, after, (unsigned long long)ctx->hbm_budget);
+    }
     if (buf.p) {
         // Work already enqueued may still read the old buffer.
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -570,10 +588,50 @@ int pop_events(damas_ctx *ctx, std::pair<hipEvent_t, hipEvent_t> *ev)
 
 } // namespace
 
+namespace {
+
+// Autotune cache lines: key, then the knobs and the timed ms per sweep.
+void load_tune_cache(damas_ctx *c)
+{
+    FILE *fh = fopen(c->tune_cache.c_str(), "r");
+    if (!fh)
+        return; // a missing file is an empty cache
+    char line[1024];
+    while (fgets(line, sizeof line, fh)) {
+        char key[512];
+        int coop = 0, mr = 0, fl = 0;
+        double sp = 0, ov = 0, wc = 0, ms = 0;
+        if (sscanf(line, "%511s %d %d %lf %lf %d %lf %lf", key, &coop, &mr, &sp, &ov, &fl, &wc,
+                   &ms) == 8) {
+            TuneKnobs k;
+            k.coop = coop != 0;
+            k.min_rows = mr;
+            k.split = sp;
+            k.overhead = ov;
+            k.floor_rows = fl;
+            k.wide_cost = wc;
+            c->tune_entries[key] = {k, ms};
+        }
+    }
+    fclose(fh);
+}
+
+} // namespace
+
 extern "C" int damas_ctx_create(int32_t device, damas_ctx **out)
 {
-    if (!out)
-        return fail(DAMAS_EINVAL, "out is NULL");
+    damas_ctx_opts o{};
+    o.device = device;
+    return damas_ctx_create_ex(&o, out);
+}
+
+extern "C" int damas_ctx_create_ex(const damas_ctx_opts *opts, damas_ctx **out)
+{
+    if (!out || !opts)
+        return fail(DAMAS_EINVAL, "opts and out must be non-NULL");
+    if (opts->deterministic != 0 && opts->deterministic != 1)
+        return fail(DAMAS_EINVAL, "deterministic must be 0 or 1");
+    const int32_t device = opts->device;
     int n = 0;
     HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
     if (device < 0 || device >= n)
@@ -597,8 +655,26 @@ extern "C" int damas_ctx_create(int32_t device, damas_ctx **out)
         delete c;
         return fail(DAMAS_EDEVICE, "context set-up (events, fault word)");
     }
+    c->hbm_budget = opts->hbm_budget;
+    c->deterministic = opts->deterministic == 1;
+    if (c->deterministic)
+        c->coop_budget = 0;
+    if (opts->tune_cache && opts->tune_cache[0]) {
+        c->tune_cache = opts->tune_cache;
+        load_tune_cache(c);
+    }
     *out = c;
     return DAMAS_OK;
+}
+
+extern "C" const char *damas_ctx_last_error(const damas_ctx *ctx)
+{
+    thread_local std::string copy;
+    if (!ctx)
+        return "";
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    copy = ctx->err;
+    return copy.c_str();
 }
 
 extern "C" void damas_ctx_destroy(damas_ctx *ctx)
@@ -636,14 +712,18 @@ extern "C" int damas_ctx_set_coop(damas_ctx *ctx, int32_t max_workgroups)
 {
     if (!ctx)
         return fail(DAMAS_EINVAL, "ctx is NULL");
+    CtxScope scope(ctx);
     if (max_workgroups < -1)
         return fail(DAMAS_EINVAL, "max_workgroups must be >= -1");
+    if (ctx->deterministic && max_workgroups != 0)
+        return fail(DAMAS_EINVAL, "a deterministic context runs one workgroup per bin");
     ctx->coop_budget = max_workgroups;
     return DAMAS_OK;
 }
 
 extern "C" int damas_ctx_last_workgroups(const damas_ctx *ctx, int32_t *workgroups)
 {
+    CtxScope scope(const_cast<damas_ctx *>(ctx));
     if (!ctx || !workgroups)
         return fail(DAMAS_EINVAL, "NULL argument");
     *workgroups = ctx->last_workgroups;
@@ -652,6 +732,7 @@ extern "C" int damas_ctx_last_workgroups(const damas_ctx *ctx, int32_t *workgrou
 
 extern "C" int damas_ctx_classes(damas_ctx *ctx, int32_t n_bins, uint8_t *out)
 {
+    CtxScope scope(ctx);
     if (!ctx || !out || n_bins < 0)
         return fail(DAMAS_EINVAL, "ctx and out must be non-NULL, n_bins >= 0");
     if (n_bins == 0)
@@ -666,6 +747,7 @@ extern "C" int damas_ctx_classes(damas_ctx *ctx, int32_t n_bins, uint8_t *out)
 
 extern "C" int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled)
 {
+    CtxScope scope(ctx);
     if (!ctx)
         return fail(DAMAS_EINVAL, "ctx is NULL");
     ctx->timing = enabled != 0;
@@ -675,6 +757,7 @@ extern "C" int damas_ctx_set_timing(damas_ctx *ctx, int32_t enabled)
 extern "C" int damas_ctx_phase_time(damas_ctx *ctx, int32_t phase, double *ms,
                                     int64_t *launches)
 {
+    CtxScope scope(ctx);
     if (!ctx || !ms || !launches)
         return fail(DAMAS_EINVAL, "NULL argument");
     if (phase < 0 || phase >= DAMAS_PHASES)
@@ -698,6 +781,7 @@ extern "C" int damas_ctx_phase_time(damas_ctx *ctx, int32_t phase, double *ms,
 
 extern "C" int damas_ctx_gs_time(damas_ctx *ctx, double *ms, int64_t *launches)
 {
+    CtxScope scope(ctx);
     return damas_ctx_phase_time(ctx, DAMAS_PHASE_SWEEPS, ms, launches);
 }
 
@@ -707,6 +791,7 @@ int static_fault(int **out);
 
 extern "C" int damas_check(damas_ctx *ctx, void *stream)
 {
+    CtxScope scope(ctx);
     if (ctx)
         HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
@@ -1290,6 +1375,7 @@ extern "C" int damas_solve_dev(damas_ctx *ctx, const damas_geometry *g,
                                const void *x_init, void *x_map, double *b_map,
                                int32_t *idx, int32_t *s_tilde, void *stream)
 {
+    CtxScope scope(ctx);
     if (!ctx)
         return fail(DAMAS_EINVAL, "ctx is NULL");
     int rc = check_geometry(g);
@@ -1350,6 +1436,7 @@ extern "C" int damas_solve(damas_ctx *ctx, const damas_geometry *g, int32_t n_bi
                            const void *x_init, void *x_map, double *b_map, int32_t *idx,
                            int32_t *s_tilde)
 {
+    CtxScope scope(ctx);
     if (!ctx || !g || !p)
         return fail(DAMAS_EINVAL, "ctx, g and p must be non-NULL");
     if (n_bins < 0)
@@ -1455,8 +1542,15 @@ int damas::set_error(int code, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_err = buf;
+    record(buf);
     return code;
+}
+
+damas_ctx *damas::ctx_scope_swap(damas_ctx *ctx)
+{
+    damas_ctx *prev = g_ctx_cur;
+    g_ctx_cur = ctx;
+    return prev;
 }
 
 bool damas::PsfCache::make_room(size_t need)
@@ -1659,10 +1753,40 @@ int damas::solve_cached(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
 // ---------------------------------------------------------------------------
 // autotuner: the cooperative schedule's knobs, by timing trial solves
 
+namespace {
+
+// Key of a problem in the autotune cache: what the schedule is a function
+// of (shape, precision and policy, the device's compute units, and the kept
+// counts, hashed FNV-1a, or the bound on them when the host does not know
+// them).
+std::string tune_key(const damas_ctx *ctx, const SolvePlan &P)
+{
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint32_t v) {
+        for (int b = 0; b < 4; ++b) {
+            h ^= (v >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    if (P.st_host.empty())
+        mix((uint32_t)P.max_kept);
+    for (int32_t v : P.st_host)
+        mix((uint32_t)v);
+    char buf[160];
+    snprintf(buf, sizeof buf, "M%d:N%d:B%d:P%d:A%d:R%d:cu%d:st%016llx", P.M, P.N, P.n_bins,
+             P.p->precision, P.classes ? 1 : 0, P.refine, cus, (unsigned long long)h);
+    return buf;
+}
+
+} // namespace
+
 extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
                                   const double *freq, const double *csm, const damas_params *p,
                                   int32_t trial_sweeps, void *stream, damas_tune_result *out)
 {
+    CtxScope scope(ctx);
     if (!ctx || !out || !p)
         return fail(DAMAS_EINVAL, "ctx, params and out must be non-NULL");
     if (trial_sweeps < 1)
@@ -1680,6 +1804,28 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
         return fail(DAMAS_EINVAL, "nothing to tune (n_bins, freq, csm)");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    auto report = [&](const TuneKnobs &k) {
+        out->coop = k.coop;
+        out->coop_min_rows = k.min_rows;
+        out->coop_split = k.split;
+        out->coop_overhead = k.overhead;
+        out->coop_floor_rows = k.floor_rows;
+        out->wide_cost = k.wide_cost;
+    };
+    // A problem the cache file holds takes its stored choice, untimed.
+    std::string key;
+    if (!ctx->tune_cache.empty()) {
+        key = tune_key(ctx, P);
+        auto it = ctx->tune_entries.find(key);
+        if (it != ctx->tune_entries.end()) {
+            ctx->tune = it->second.first;
+            report(ctx->tune);
+            out->best_ms_per_sweep = it->second.second;
+            out->default_ms_per_sweep = 0.0;
+            out->candidates_timed = 0;
+            return DAMAS_OK;
+        }
+    }
     // Trials: the caller's solve, batched, with trial_sweeps sweeps (for
     // BF16, all on the storage precision), into a scratch map.
     damas_params tp = *p;
@@ -1810,15 +1956,26 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
         return rc;
     }
     apply(cands[bi]);
-    out->coop = cands[bi].coop;
-    out->coop_min_rows = cands[bi].min_rows;
-    out->coop_split = cands[bi].split;
-    out->coop_overhead = cands[bi].overhead;
+    report(ctx->tune);
     out->best_ms_per_sweep = best / trial_sweeps;
     out->default_ms_per_sweep = dflt / trial_sweeps;
     out->candidates_timed = ran;
-    out->coop_floor_rows = cands[bi].floor_rows;
-    out->wide_cost = cands[bi].wide_cost;
+    if (!key.empty()) {
+        ctx->tune_entries[key] = {ctx->tune, out->best_ms_per_sweep};
+        const TuneKnobs &k = ctx->tune;
+        bool ok = false;
+        if (FILE *fh = fopen(ctx->tune_cache.c_str(), "a")) {
+            ok = fprintf(fh, "%s %d %d %.17g %.17g %d %.17g %.17g\n", key.c_str(),
+                         k.coop ? 1 : 0, k.min_rows, k.split, k.overhead, k.floor_rows,
+                         k.wide_cost, out->best_ms_per_sweep) >= 0;
+            ok = fclose(fh) == 0 && ok;
+        }
+        if (!ok)
+            return fail(DAMAS_EINVAL,
+                        "the tuned choice is applied, but the autotune cache %s could not be "
+                        "written",
+                        ctx->tune_cache.c_str());
+    }
     return DAMAS_OK;
 }
 
@@ -1870,6 +2027,7 @@ extern "C" int damas_graph_capture(damas_ctx *ctx, const damas_geometry *g, int3
                                    double *b_map, int32_t *idx, int32_t *s_tilde,
                                    damas_graph **out)
 {
+    CtxScope scope(ctx);
     if (!ctx || !out)
         return fail(DAMAS_EINVAL, "ctx and out must be non-NULL");
     if (ctx->timing)
@@ -1956,6 +2114,7 @@ extern "C" int32_t damas_graph_workgroups(const damas_graph *gr)
 
 extern "C" int damas_graph_launch(damas_graph *gr, void *stream)
 {
+    CtxScope scope(gr ? gr->ctx : nullptr);
     if (!gr)
         return fail(DAMAS_EINVAL, "graph is NULL");
     HIP_TRY(hipSetDevice(gr->ctx->device), "hipSetDevice");

@@ -48,9 +48,31 @@ struct PsfCache {
     void clear();
 };
 
-// Record a failure for damas_last_error() of the calling thread; returns
-// `code`.
+// Record a failure for damas_last_error() of the calling thread (and for
+// damas_ctx_last_error() of the context the thread is working on, see
+// CtxScope); returns `code`.
 int set_error(int code, const char *fmt, ...);
+
+// The context a thread's library calls are working on while a CtxScope
+// lives: failures recorded meanwhile are also kept on that context.
+damas_ctx *ctx_scope_swap(damas_ctx *ctx);
+struct CtxScope {
+    damas_ctx *prev;
+    explicit CtxScope(damas_ctx *ctx) : prev(ctx_scope_swap(ctx)) {}
+    ~CtxScope() { (void)ctx_scope_swap(prev); }
+    CtxScope(const CtxScope &) = delete;
+    CtxScope &operator=(const CtxScope &) = delete;
+};
+
+// One autotune choice (the cooperative schedule's knobs).
+struct TuneKnobs {
+    bool coop = true;
+    int min_rows = 320;     // rows per rank at least
+    double split = 1.25;    // bins above split x the mean work per workgroup get ranks
+    double overhead = 1.3;  // cost per element of a rank relative to a bin alone
+    int floor_rows = 0;     // cost model: a tile costs max(floor_rows, ld) (0: ld)
+    double wide_cost = 1.7; // cost per element of a wide bin relative to a narrow one
+};
 
 } // namespace damas
 
@@ -78,14 +100,17 @@ struct damas_ctx {
     int coop_budget = -1;
     int last_workgroups = 0; // of the last sweep launch (one per bin alone)
     // schedule knobs of the cooperative sweeps (set by damas_ctx_autotune)
-    struct {
-        bool coop = true;
-        int min_rows = 320;    // rows per rank at least
-        double split = 1.25;   // bins above split x the mean work per workgroup get ranks
-        double overhead = 1.3; // cost per element of a rank relative to a bin alone
-        int floor_rows = 0;    // cost model: a tile costs max(floor_rows, ld) (0: ld)
-        double wide_cost = 1.7; // cost per element of a wide bin relative to a narrow one
-    } tune;
+    damas::TuneKnobs tune;
+    // options (damas_ctx_create_ex): workspace budget (0: none), autotune
+    // cache file and its entries (problem key -> knobs, timed sweep ms),
+    // one workgroup per bin
+    uint64_t hbm_budget = 0;
+    std::string tune_cache;
+    std::unordered_map<std::string, std::pair<damas::TuneKnobs, double>> tune_entries;
+    bool deterministic = false;
+    // last failure of a call made on this context (damas_ctx_last_error)
+    mutable std::mutex err_mu;
+    std::string err;
     // graph capture: `capturing` marks the captured solve, which makes no
     // host synchronisation and plans no schedule: its sweeps run the
     // schedule the sizing solve before it chose, from the graph's own copy

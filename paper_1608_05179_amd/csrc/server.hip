@@ -185,6 +185,7 @@ void damas_server::work(int k)
 
 int damas_server::run(Slot &sl, Req *r)
 {
+    CtxScope scope(sl.ctx); // failures are also the slot context's last error
     const size_t S = (size_t)r->N * r->N, nb = (size_t)r->n_bins;
     const size_t xs = r->params.precision == DAMAS_PREC_FP64 ? sizeof(double) : sizeof(float);
     int rc;

@@ -109,6 +109,15 @@ _sig("damas_psf_bf16", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_i64, c_v
 _sig("damas_gs", ctypes.c_int, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp,
      c_vp, c_i32, c_vp, c_vp, c_vp)
 _sig("damas_ctx_create", ctypes.c_int, c_i32, ctypes.POINTER(c_vp))
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("device", c_i32), ("hbm_budget", ctypes.c_uint64),
+                ("tune_cache", ctypes.c_char_p), ("deterministic", c_i32)]
+
+
+_sig("damas_ctx_create_ex", ctypes.c_int, ctypes.POINTER(CtxOpts), ctypes.POINTER(c_vp))
+_sig("damas_ctx_last_error", ctypes.c_char_p, c_vp)
 _sig("damas_ctx_destroy", None, c_vp)
 _sig("damas_ctx_set_timing", ctypes.c_int, c_vp, c_i32)
 _sig("damas_ctx_classes", ctypes.c_int, c_vp, c_i32, c_vp)
@@ -461,11 +470,22 @@ def solve_static(g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
 class Context:
     """damas_ctx: the device workspace of whole-path solves."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, *, hbm_budget: int = 0, tune_cache=None,
+                 deterministic: bool = False):
+        """hbm_budget: bytes the workspace may hold (0: no limit);
+        tune_cache: path of the autotune cache file; deterministic: one
+        workgroup per bin, results independent of tuning."""
+        o = CtxOpts(int(device), int(hbm_budget),
+                    None if tune_cache is None else str(tune_cache).encode(),
+                    1 if deterministic else 0)
         h = c_vp()
-        _check(_lib.damas_ctx_create(int(device), ctypes.byref(h)))
+        _check(_lib.damas_ctx_create_ex(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self.device = device
+
+    def last_error(self) -> str:
+        """The last failure of a call made on this context, from any thread."""
+        return _lib.damas_ctx_last_error(self._h).decode()
 
     def close(self):
         if getattr(self, "_h", None):

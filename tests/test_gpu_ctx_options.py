@@ -1,0 +1,123 @@
+"""Context options and per-context errors (damas_ctx_create_ex,
+damas_ctx_last_error): a workspace budget refused with DAMAS_EADMIT, a
+deterministic context equal bitwise to one-workgroup-per-bin solves, an
+autotune cache file whose stored choice a second context applies without
+trials (and whose solves then equal the first context's bitwise), and the
+last failure of each context kept apart from the others and from the
+thread that made it."""
+import threading
+
+import numpy as np
+import pytest
+
+from paper_1608_05179_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KS = [2400, 700, 3600, 150]
+
+
+def _setup(dm, dev, w):
+    import torch
+    mic = torch.as_tensor(w.mic, dtype=torch.float64).to(dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    freq = torch.as_tensor(w.freqs, dtype=torch.float64).to(dev)
+    csm = torch.as_tensor(w.csm, dtype=torch.complex128).to(dev)
+    return mic, g, freq, csm
+
+
+def test_last_error_is_per_context(dm, dev):
+    w = synth.compressed_fp32(n_bins=2, N=41, iterations=20)
+    mic, g, freq, csm = _setup(dm, dev, w)
+    a, b = dm.Context(0), dm.Context(0)
+    assert a.last_error() == "" and b.last_error() == ""
+    with pytest.raises(dm.DamasError) as ei:
+        a.solve(g, freq, csm, iterations=20, precision=dm.PREC_BF16, refine_sweeps=50)
+    assert ei.value.code == dm.EINVAL
+    assert "refine_sweeps" in a.last_error() and b.last_error() == ""
+    b.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=337, iterations=20)
+    b.check()
+    assert b.last_error() == "" and "refine_sweeps" in a.last_error()
+
+    # a failure on b in another thread is b's, read from this thread
+    def bad():
+        try:
+            b.set_coop(-5)
+        except dm.DamasError:
+            pass
+    t = threading.Thread(target=bad)
+    t.start()
+    t.join()
+    assert "max_workgroups" in b.last_error() and "refine_sweeps" in a.last_error()
+    a.close()
+    b.close()
+
+
+def test_hbm_budget(dm, dev):
+    w = synth.compressed_fp32(n_bins=4, N=61, iterations=20)
+    mic, g, freq, csm = _setup(dm, dev, w)
+    small = dm.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(dm.DamasError) as ei:
+        small.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=KS, iterations=20)
+    assert ei.value.code == dm.EADMIT and "budget" in small.last_error()
+    need = dm.query_footprint(w.mic.shape[0], w.N, w.n_bins, select_mode=dm.SEL_KEEP_COUNT,
+                              keep_count=KS, iterations=20)
+    ok = dm.Context(0, hbm_budget=2 * need)
+    ok.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=KS, iterations=20)
+    ok.check()
+    small.close()
+    ok.close()
+
+
+def test_deterministic_is_one_workgroup_per_bin(dm, dev):
+    w = synth.compressed_fp32(n_bins=4, N=61, iterations=80)
+    mic, g, freq, csm = _setup(dm, dev, w)
+    d = dm.Context(0, deterministic=True)
+    x = d.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=KS,
+                iterations=w.iterations).clone()
+    d.check()
+    assert d.last_workgroups() == w.n_bins
+    with pytest.raises(dm.DamasError) as ei:
+        d.set_coop(-1)
+    assert ei.value.code == dm.EINVAL
+    d.set_coop(0)
+    ref = dm.Context(0)
+    ref.set_coop(0)
+    y = ref.solve(g, freq, csm, select_mode=dm.SEL_KEEP_COUNT, keep_count=KS,
+                  iterations=w.iterations)
+    ref.check()
+    import torch
+    assert torch.equal(x, y)
+    d.close()
+    ref.close()
+
+
+def test_tune_cache_is_reused(dm, dev, tmp_path):
+    import torch
+    path = tmp_path / "tune.txt"
+    w = synth.compressed_fp32(n_bins=4, N=61, iterations=100)
+    mic, g, freq, csm = _setup(dm, dev, w)
+    kw = dict(select_mode=dm.SEL_KEEP_COUNT, keep_count=KS)
+    c1 = dm.Context(0, tune_cache=path)
+    r1 = c1.autotune(g, freq, csm, trial_sweeps=5, **kw)
+    assert r1["candidates_timed"] >= 2
+    assert len(path.read_text().splitlines()) == 1
+    c2 = dm.Context(0, tune_cache=path)
+    r2 = c2.autotune(g, freq, csm, trial_sweeps=5, **kw)
+    assert r2["candidates_timed"] == 0
+    for k in ("coop", "coop_min_rows", "coop_split", "coop_overhead", "coop_floor_rows",
+              "wide_cost"):
+        assert r2[k] == r1[k], k
+    x1 = c1.solve(g, freq, csm, iterations=w.iterations, **kw).clone()
+    x2 = c2.solve(g, freq, csm, iterations=w.iterations, **kw)
+    c1.check()
+    c2.check()
+    assert c1.last_workgroups() == c2.last_workgroups()
+    assert torch.equal(x1, x2)
+    # another problem is tuned and appended
+    r3 = c2.autotune(g, freq, csm, trial_sweeps=5, select_mode=dm.SEL_KEEP_COUNT,
+                     keep_count=[3000, 3000, 200, 200])
+    assert r3["candidates_timed"] >= 1
+    assert len(path.read_text().splitlines()) == 2
+    c1.close()
+    c2.close()
