@@ -616,7 +616,18 @@ int damas_query_footprint(int32_t M, int32_t N, int32_t n_bins, const damas_para
  * frequencies, precision and the kept points of every bin, so a repeated
  * scene skips its steering and PSF launches (the key needs the kept points
  * on the host: one stream synchronisation per cached request).  Batched
- * solves only.  The server is thread-safe. */
+ * solves only.  The server is thread-safe.
+ *
+ * Batch former (max_batch > 1): a worker that takes a request whose kept
+ * counts the host knows (KEEP_ALL, KEEP_COUNT, KEEP_FRAC) also takes up to
+ * max_batch - 1 later queued requests with the same precision, sweep counts
+ * and policy, whatever their array, grid size or kept counts, while their
+ * summed footprints fit the budget, and runs them as one batch: each
+ * request's DAS map, selection and system build on its own grid, then one
+ * sweep launch over every bin of the batch (cooperative job lists), so small
+ * requests share the chip instead of queueing behind each other.  Merged
+ * requests bypass the PSF cache, finish together, and share one fault
+ * word: a device fault fails every request of its batch. */
 typedef struct damas_server damas_server;
 
 typedef struct {
@@ -626,6 +637,8 @@ typedef struct {
     uint64_t cache_budget; /* bytes of the PSF cache (0 disables it)         */
     int32_t slots;         /* concurrent requests (streams), >= 1            */
     int32_t max_queue;     /* waiting requests at most (DAMAS_EBUSY beyond)  */
+    int32_t max_batch;     /* requests merged into one batch at most (0 or 1:
+                              every request runs alone)                      */
 } damas_server_opts;
 
 /* One solve request; every pointer is HOST memory.  Inputs are copied at
@@ -660,6 +673,8 @@ typedef struct {
     uint64_t held_bytes;  /* workspaces and inputs held by the slots       */
     uint64_t cache_bytes; /* bytes in the PSF cache                       */
     int32_t queued, running;
+    uint64_t batches;     /* batches run (a request alone is one batch)     */
+    uint64_t merged;      /* requests that ran in a batch of two or more    */
 } damas_server_stats;
 
 int damas_server_create(const damas_server_opts *o, damas_server **out);

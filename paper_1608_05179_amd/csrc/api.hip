@@ -685,11 +685,13 @@ extern "C" void damas_ctx_destroy(damas_ctx *ctx)
     (void)hipDeviceSynchronize();
     for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
                       &ctx->E16, &ctx->A32, &ctx->Alo, &ctx->tsum, &ctx->cls, &ctx->coop_ws,
-                      &ctx->coop_tab})
+                      &ctx->coop_tab, &ctx->mapt})
         if (b->p)
             (void)hipFree(b->p);
     if (ctx->kc_pinned)
         (void)hipHostFree(ctx->kc_pinned);
+    if (ctx->mapt_pinned)
+        (void)hipHostFree(ctx->mapt_pinned);
     if (ctx->coop_pinned)
         (void)hipHostFree(ctx->coop_pinned);
     if (ctx->cls_pinned)
@@ -1193,62 +1195,64 @@ int upload_tab(damas_ctx *ctx, const std::vector<int32_t> &tab, hipStream_t s)
     return DAMAS_OK;
 }
 
-// Everything after the DAS map and the selection for bins [f0, f0 + nb)
-// (arrays offset by the caller): layout, steering and PSF(s) when `build`,
-// then the sweeps.
-int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
-                              int32_t max_kept, const double *freq, double *bm,
-                              int32_t *ix, int32_t *st, const void *x_init, void *x_map,
-                              hipStream_t s, bool build = true, double *power = nullptr)
+// Class arguments of a solve's PSF launches: the lo arena, tile sums and
+// class bytes of the context (offset by the caller for a part of a batch).
+PsfClassArgs psf_classes(damas_ctx *ctx, const SolvePlan &P)
 {
-    const damas_params *p = P.p;
-    HIP_TRY(launch_layout(nb, st, max_kept, P.a_elems, P.off, P.fault, s), "layout launch");
-    const bool bf16 = P.bf16;
-    int rc;
-    std::pair<hipEvent_t, hipEvent_t> evb{};
-    if (ctx->timing) {
-        if ((rc = pop_events(ctx, &evb)))
-            return rc;
-        HIP_TRY(hipEventRecord(evb.first, s), "hipEventRecord");
-    }
-    // Per-bin classes: chosen by the float PSF, read by the sweeps.
     PsfClassArgs pc;
-    GsClassArgs gca;
     if (P.classes) {
         pc.lo = (uint16_t *)ctx->Alo.p;
         pc.tsum = (double *)ctx->tsum.p;
         pc.cls = (uint8_t *)ctx->cls.p;
         pc.rho_wide = P.rho_wide;
-        pc.rho_f32 = bf16 ? P.rho_f32 : HUGE_VAL; // a float solve has no F32 class
+        pc.rho_f32 = P.bf16 ? P.rho_f32 : HUGE_VAL; // a float solve has no F32 class
         pc.wide_cap = gs_wide_capacity();
-        gca.cls = pc.cls;
-        gca.lo = pc.lo;
     }
-    // Storage-precision system (bulk sweeps) and, for BF16, the FP32 copy.
-    if (build && P.need64) {
-        HIP_TRY(launch_steer(P.kg, nb, freq, ix, st, max_kept, (double *)ctx->E.p, P.e_stride,
-                             P.fault, s, P.steering),
+    return pc;
+}
+
+// Steering and PSF(s) of bins [0, nb) (arrays, offsets `off`, steering rows
+// E / E16 and the class arguments offset by the caller): the
+// storage-precision system and, for BF16, the FP32 copy.
+int enqueue_system(const SolvePlan &P, int32_t nb, int32_t max_kept, const double *freq,
+                   const int32_t *ix, int32_t *st, const int64_t *off, double *E,
+                   uint16_t *E16, void *A, void *A32, const PsfClassArgs &pc, hipStream_t s)
+{
+    if (P.need64) {
+        HIP_TRY(launch_steer(P.kg, nb, freq, ix, st, max_kept, E, P.e_stride, P.fault, s,
+                             P.steering),
                 "steer launch");
-        HIP_TRY(launch_psf(P.M, nb, st, max_kept, bf16 ? DAMAS_PREC_FP32 : p->precision,
-                           (const double *)ctx->E.p, P.e_stride, P.off,
-                           bf16 ? ctx->A32.p : ctx->A.p, P.fault, s, pc, P.steering, P.diag),
+        HIP_TRY(launch_psf(P.M, nb, st, max_kept, P.bf16 ? DAMAS_PREC_FP32 : P.p->precision, E,
+                           P.e_stride, off, P.bf16 ? A32 : A, P.fault, s, pc, P.steering,
+                           P.diag),
                 "psf launch");
     }
-    if (build && P.need16) {
-        HIP_TRY(launch_steer16(P.kg, nb, freq, ix, st, max_kept, (uint16_t *)ctx->E16.p,
-                               P.e16_stride, P.fault, s),
+    if (P.need16) {
+        HIP_TRY(launch_steer16(P.kg, nb, freq, ix, st, max_kept, E16, P.e16_stride, P.fault, s),
                 "steer16 launch");
-        HIP_TRY(launch_psf16(P.M, nb, st, max_kept, (const uint16_t *)ctx->E16.p,
-                             P.e16_stride, P.off, (uint16_t *)ctx->A.p, P.fault, s, P.diag),
+        HIP_TRY(launch_psf16(P.M, nb, st, max_kept, E16, P.e16_stride, off, (uint16_t *)A,
+                             P.fault, s, P.diag),
                 "psf16 launch");
     }
-    std::pair<hipEvent_t, hipEvent_t> ev{};
-    if (ctx->timing) {
-        HIP_TRY(hipEventRecord(evb.second, s), "hipEventRecord");
-        ctx->phase_events[DAMAS_PHASE_SYSTEM].push_back(evb);
-        if ((rc = pop_events(ctx, &ev)))
-            return rc;
-        HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
+    return DAMAS_OK;
+}
+
+// Schedule and sweeps of bins [0, nb) after their systems are built:
+// cooperative job lists for a batched solve whose kept counts the host
+// knows (P.st_host), else one workgroup per bin; `map` (device, or null)
+// places bins of different grids.
+int enqueue_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb, int32_t max_kept,
+                   const double *bm, const int32_t *ix, const int32_t *st, const void *x_init,
+                   void *x_map, hipStream_t s, double *power, const int64_t *map)
+{
+    const damas_params *p = P.p;
+    const bool bf16 = P.bf16;
+    int rc;
+    GsClassArgs gca;
+    gca.map = map;
+    if (P.classes) {
+        gca.cls = (const uint8_t *)ctx->cls.p;
+        gca.lo = (const uint16_t *)ctx->Alo.p;
     }
     // Cooperative schedule (batched solves of host-known kept counts).  With
     // per-bin classes the schedule weighs wide bins by their cost, so the
@@ -1320,6 +1324,7 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
         if (P.bulk > 0 || (P.refine == 0 && !P.classes)) {
             GsClassArgs g;
             g.cls = gca.cls;
+            g.map = map;
             g.iters_cls = 0;
             g.power = second ? nullptr : power;
             HIP_TRY(sweeps(DAMAS_PREC_BF16, ctx->A.p, P.bulk, xi, g), "gs launch (bf16)");
@@ -1333,14 +1338,254 @@ int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
                     "gs launch (fp32 refinement)");
         }
     }
-    if (ctx->timing) {
-        HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
-        ctx->phase_events[DAMAS_PHASE_SWEEPS].push_back(ev);
+    return DAMAS_OK;
+}
+
+// Timed phases of a solve: events around each (when the context times).
+struct PhaseTimer {
+    damas_ctx *ctx;
+    hipStream_t s;
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    int begin()
+    {
+        if (!ctx->timing)
+            return DAMAS_OK;
+        int rc = pop_events(ctx, &ev);
+        if (rc)
+            return rc;
+        HIP_TRY(hipEventRecord(ev.first, s), "hipEventRecord");
+        return DAMAS_OK;
     }
+    int end(int phase)
+    {
+        if (!ctx->timing)
+            return DAMAS_OK;
+        HIP_TRY(hipEventRecord(ev.second, s), "hipEventRecord");
+        ctx->phase_events[phase].push_back(ev);
+        return DAMAS_OK;
+    }
+};
+
+// Everything after the DAS map and the selection for bins [f0, f0 + nb)
+// (arrays offset by the caller): layout, steering and PSF(s) when `build`,
+// then the sweeps.
+int enqueue_system_and_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb,
+                              int32_t max_kept, const double *freq, double *bm,
+                              int32_t *ix, int32_t *st, const void *x_init, void *x_map,
+                              hipStream_t s, bool build = true, double *power = nullptr)
+{
+    HIP_TRY(launch_layout(nb, st, max_kept, P.a_elems, P.off, P.fault, s), "layout launch");
+    int rc;
+    PhaseTimer sys{ctx, s}, sw{ctx, s};
+    if ((rc = sys.begin()))
+        return rc;
+    // Per-bin classes: chosen by the float PSF, read by the sweeps.
+    if (build && (rc = enqueue_system(P, nb, max_kept, freq, ix, st, P.off, (double *)ctx->E.p,
+                                      (uint16_t *)ctx->E16.p, ctx->A.p, ctx->A32.p,
+                                      psf_classes(ctx, P), s)))
+        return rc;
+    if ((rc = sys.end(DAMAS_PHASE_SYSTEM)) || (rc = sw.begin()) ||
+        (rc = enqueue_sweeps(ctx, P, nb, max_kept, bm, ix, st, x_init, x_map, s, power,
+                             nullptr)))
+        return rc;
+    return sw.end(DAMAS_PHASE_SWEEPS);
+}
+
+// Copy n elements of T from host `src` to device `dst` through a pinned
+// staging buffer that the previous upload (event `done`) no longer reads.
+template <typename T>
+int upload_pinned(T *&pinned, size_t &pinned_n, hipEvent_t done, void *dst, const T *src,
+                  size_t n, hipStream_t s, const char *what)
+{
+    HIP_TRY(hipEventSynchronize(done), "hipEventSynchronize");
+    if (pinned_n < n) {
+        if (pinned)
+            HIP_TRY(hipHostFree(pinned), "hipHostFree");
+        pinned = nullptr;
+        pinned_n = 0;
+        HIP_TRY(hipHostMalloc((void **)&pinned, sizeof(T) * n), "hipHostMalloc");
+        pinned_n = n;
+    }
+    memcpy(pinned, src, sizeof(T) * n);
+    HIP_TRY(hipMemcpyAsync(dst, pinned, sizeof(T) * n, hipMemcpyHostToDevice, s), what);
+    HIP_TRY(hipEventRecord(done, s), "hipEventRecord");
     return DAMAS_OK;
 }
 
 } // namespace
+
+bool damas::merge_compatible(const damas_params &a, const damas_params &b)
+{
+    auto known = [](const damas_params &q) {
+        return q.select_mode == DAMAS_SEL_KEEP_ALL || q.select_mode == DAMAS_SEL_KEEP_COUNT;
+    };
+    return known(a) && known(b) && a.precision == b.precision && a.iterations == b.iterations &&
+           (a.precision != DAMAS_PREC_BF16 || a.refine_sweeps == b.refine_sweeps) &&
+           a.policy == b.policy && a.rho_wide == b.rho_wide && a.rho_f32 == b.rho_f32;
+}
+
+int damas::merged_sizes(const std::vector<MergedPart> &parts, int64_t *map_elems, int64_t *bins)
+{
+    int64_t m = 0, b = 0;
+    for (const MergedPart &q : parts) {
+        m += (int64_t)q.n_bins * q.g.N * q.g.N;
+        b += q.n_bins;
+    }
+    *map_elems = m;
+    *bins = b;
+    return DAMAS_OK;
+}
+
+int damas::solve_merged(damas_ctx *ctx, const std::vector<MergedPart> &parts, void *x_all,
+                        int32_t *st_all, std::vector<int64_t> *bin0_out,
+                        std::vector<int64_t> *map0_out, hipStream_t s)
+{
+    CtxScope scope(ctx);
+    const int R = (int)parts.size();
+    if (R == 0)
+        return DAMAS_OK;
+    if (!x_all)
+        return fail(DAMAS_EINVAL, "x_all is NULL");
+    std::vector<damas_params> pp(R);
+    std::vector<SolvePlan> Ps(R);
+    int rc;
+    for (int r = 0; r < R; ++r) {
+        const MergedPart &q = parts[r];
+        pp[r] = q.p;
+        pp[r].batched = 1;
+        pp[r].power = nullptr;
+        pp[r].keep_count = q.keep_count.empty() ? nullptr : q.keep_count.data();
+        if ((rc = check_geometry(&q.g)) || (rc = make_plan(q.g.M, q.g.N, q.n_bins, &pp[r], Ps[r])))
+            return rc;
+        if (!q.freq || !q.csm || q.n_bins < 1)
+            return fail(DAMAS_EINVAL, "part %d: freq, csm and n_bins >= 1 needed", r);
+        if (!merge_compatible(pp[0], pp[r]))
+            return fail(DAMAS_EINVAL, "part %d's sweep settings or selection mode cannot join "
+                                      "the batch", r);
+        Ps[r].kg = make_geom(q.g);
+        Ps[r].fault = ctx->fault;
+    }
+    // Bins, maps, steering rows, arena elements and tile sums of each part.
+    std::vector<int64_t> bin0(R), map0(R), e0(R), e16_0(R), tile0(R);
+    int64_t B = 0, maps = 0, et = 0, e16t = 0, at = 0, tt = 0;
+    int32_t max_kept = 0, Nmax = 0;
+    std::vector<int32_t> st_all_host, kc_all;
+    std::vector<int64_t> table;
+    for (int r = 0; r < R; ++r) {
+        const SolvePlan &P = Ps[r];
+        bin0[r] = B;
+        map0[r] = maps;
+        e0[r] = et;
+        e16_0[r] = e16t;
+        tile0[r] = tt;
+        for (int f = 0; f < P.n_bins; ++f) {
+            table.push_back(maps + (int64_t)f * P.S);
+            table.push_back(P.S);
+            kc_all.push_back(pp[r].keep_count ? pp[r].keep_count[f] : pp[r].keep_count_all);
+        }
+        st_all_host.insert(st_all_host.end(), P.st_host.begin(), P.st_host.end());
+        B += P.n_bins;
+        maps += (int64_t)P.n_bins * P.S;
+        if (P.need64)
+            et += P.e_stride * P.n_bins;
+        if (P.need16)
+            e16t += P.e16_stride * P.n_bins;
+        at += P.a_elems;
+        if (P.classes)
+            tt += (int64_t)P.n_bins * psf_tiles(P.max_kept, P.steering);
+        max_kept = std::max(max_kept, P.max_kept);
+        Nmax = std::max(Nmax, P.N);
+    }
+    if (B > (int64_t)1 << 24 || maps > ((int64_t)1 << 40))
+        return fail(DAMAS_EINVAL, "merged batch too large (%lld bins)", (long long)B);
+    // The batch as one plan: part 0's sweep settings, every bin's count.
+    SolvePlan Pm = Ps[0];
+    Pm.n_bins = (int32_t)B;
+    Pm.nb_ws = (int32_t)B;
+    Pm.st_host = st_all_host;
+    Pm.max_kept = max_kept;
+    Pm.a_elems = at;
+    Pm.N = Nmax;
+    Pm.S = Nmax * Nmax;
+    const SolvePlan &P0 = Ps[0];
+    if ((rc = ensure(ctx, ctx->b, sizeof(double) * (size_t)maps, s, "b")) ||
+        (rc = ensure(ctx, ctx->idx, sizeof(int32_t) * (size_t)maps, s, "idx")) ||
+        (!st_all && (rc = ensure(ctx, ctx->st, sizeof(int32_t) * (size_t)B, s, "s_tilde"))) ||
+        (rc = ensure(ctx, ctx->kc, sizeof(int32_t) * (size_t)B, s, "keep counts")) ||
+        (rc = ensure(ctx, ctx->off, sizeof(int64_t) * (size_t)(B + 1), s, "offsets")) ||
+        (rc = ensure(ctx, ctx->mapt, sizeof(int64_t) * (size_t)(2 * B), s, "map table")) ||
+        (P0.need64 &&
+         (rc = ensure(ctx, ctx->E, sizeof(double) * (size_t)et, s, "steering rows"))) ||
+        (P0.need16 &&
+         (rc = ensure(ctx, ctx->E16, sizeof(uint16_t) * (size_t)e16t, s, "bf16 steering rows"))) ||
+        ((P0.need16 || !P0.bf16) &&
+         (rc = ensure(ctx, ctx->A, P0.es * (size_t)at, s, "A arena"))) ||
+        (P0.bf16 && P0.need64 &&
+         (rc = ensure(ctx, ctx->A32, sizeof(float) * (size_t)at, s, "FP32 A arena"))))
+        return rc;
+    if (P0.classes &&
+        ((rc = ensure(ctx, ctx->Alo, sizeof(uint16_t) * (size_t)at, s, "lo arena")) ||
+         (rc = ensure(ctx, ctx->tsum, sizeof(double) * (size_t)tt, s, "tile sums")) ||
+         (rc = ensure(ctx, ctx->cls, (size_t)B, s, "bin classes"))))
+        return rc;
+    // Keep counts and the map table (pinned staging; the kept-count cache
+    // of single solves no longer describes ctx->kc).
+    ctx->kc_host.clear();
+    if ((rc = upload_pinned(ctx->kc_pinned, ctx->kc_pinned_n, ctx->kc_done, ctx->kc.p,
+                            kc_all.data(), kc_all.size(), s, "upload keep counts")) ||
+        (rc = upload_pinned(ctx->mapt_pinned, ctx->mapt_pinned_n, ctx->kc_done, ctx->mapt.p,
+                            table.data(), table.size(), s, "upload map table")))
+        return rc;
+    double *bm = (double *)ctx->b.p;
+    int32_t *ix = (int32_t *)ctx->idx.p;
+    int32_t *st = st_all ? st_all : (int32_t *)ctx->st.p;
+    int64_t *off = (int64_t *)ctx->off.p;
+    const int32_t *kc = (const int32_t *)ctx->kc.p;
+    for (int r = 0; r < R; ++r) {
+        const SolvePlan &P = Ps[r];
+        const MergedPart &q = parts[r];
+        HIP_TRY(launch_das(P.kg, P.n_bins, q.freq, q.csm, bm + map0[r], s, P.steering, P.diag),
+                "das launch");
+        HIP_TRY(launch_select(P.N, P.n_bins, bm + map0[r], pp[r].select_mode, pp[r].eps,
+                              pp[r].predictor,
+                              pp[r].select_mode == DAMAS_SEL_KEEP_COUNT ? kc + bin0[r] : nullptr,
+                              ix + map0[r], st + bin0[r], s),
+                "select launch");
+    }
+    HIP_TRY(launch_layout((int)B, st, max_kept, at, off, ctx->fault, s), "layout launch");
+    PhaseTimer sys{ctx, s}, sw{ctx, s};
+    if ((rc = sys.begin()))
+        return rc;
+    for (int r = 0; r < R; ++r) {
+        const SolvePlan &P = Ps[r];
+        PsfClassArgs pc = psf_classes(ctx, P);
+        if (P.classes) {
+            pc.tsum += tile0[r];
+            pc.cls += bin0[r];
+        }
+        if ((rc = enqueue_system(P, P.n_bins, P.max_kept, parts[r].freq, ix + map0[r],
+                                 st + bin0[r], off + bin0[r], (double *)ctx->E.p + e0[r],
+                                 (uint16_t *)ctx->E16.p + e16_0[r], ctx->A.p, ctx->A32.p, pc,
+                                 s)))
+            return rc;
+    }
+    Pm.bm = bm;
+    Pm.ix = ix;
+    Pm.st = st;
+    Pm.off = off;
+    Pm.kc = kc;
+    Pm.fault = ctx->fault;
+    if ((rc = sys.end(DAMAS_PHASE_SYSTEM)) || (rc = sw.begin()) ||
+        (rc = enqueue_sweeps(ctx, Pm, (int32_t)B, max_kept, bm, ix, st, nullptr, x_all, s,
+                             nullptr, (const int64_t *)ctx->mapt.p)) ||
+        (rc = sw.end(DAMAS_PHASE_SWEEPS)))
+        return rc;
+    if (bin0_out)
+        *bin0_out = bin0;
+    if (map0_out)
+        *map0_out = map0;
+    return DAMAS_OK;
+}
 
 extern "C" int damas_query_footprint(int32_t M, int32_t N, int32_t n_bins,
                                      const damas_params *p, uint64_t *bytes)
@@ -1512,7 +1757,7 @@ size_t damas::ctx_bytes(const damas_ctx *ctx)
     size_t t = 0;
     for (const Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->kc, &ctx->off, &ctx->E, &ctx->A,
                             &ctx->E16, &ctx->A32, &ctx->Alo, &ctx->tsum, &ctx->cls,
-                            &ctx->coop_ws, &ctx->coop_tab})
+                            &ctx->coop_ws, &ctx->coop_tab, &ctx->mapt})
         t += b->bytes;
     return t;
 }
@@ -1526,7 +1771,7 @@ int damas::ctx_trim(damas_ctx *ctx)
     ctx->coop_tab_host.clear();
     for (Buffer *b : {&ctx->b, &ctx->idx, &ctx->st, &ctx->off, &ctx->E, &ctx->A, &ctx->E16,
                       &ctx->A32, &ctx->Alo, &ctx->tsum, &ctx->cls, &ctx->coop_ws,
-                      &ctx->coop_tab}) {
+                      &ctx->coop_tab, &ctx->mapt}) {
         if (b->p)
             HIP_TRY(hipFree(b->p), "hipFree");
         b->p = nullptr;

@@ -174,6 +174,10 @@ struct GsClassArgs {
     const uint16_t *lo = nullptr;
     int iters_cls = 0;
     double *power = nullptr; // device, per bin: sum of x over the bin (output)
+    // device, per bin (base, S): where bin f's maps (idx, b, x_init, x_map)
+    // start and how many grid points they hold, for a batch of different
+    // grids; null: f N^2 and N^2
+    const int64_t *map = nullptr;
 };
 
 hipError_t launch_gs(int N, int n_bins, const int32_t *s_tilde, int max_kept,

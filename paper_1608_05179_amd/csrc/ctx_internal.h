@@ -87,6 +87,10 @@ struct damas_ctx {
     // per-bin precision classes: bf16 residuals of the float arena (same
     // offsets), tile sums of A, one class byte per bin
     damas::Buffer Alo, tsum, cls;
+    // merged batches: per bin (map base, grid points), and its staging
+    damas::Buffer mapt;
+    int64_t *mapt_pinned = nullptr;
+    size_t mapt_pinned_n = 0;
     uint8_t *cls_pinned = nullptr; // classes read back for the schedule
     size_t cls_pinned_n = 0;
     // keep counts last uploaded to kc (skip identical re-uploads)
@@ -138,6 +142,32 @@ namespace damas {
 // KEEP_FRAC params in their KEEP_COUNT form (*q = &tmp), or p itself (*q =
 // p) for the other modes; an invalid keep_frac fails with DAMAS_EINVAL.
 int resolve_frac(const damas_params *p, int32_t N, damas_params &tmp, const damas_params **q);
+
+// One request of a merged batch (the request server's batch former): its
+// geometry (device mic), bins, device freq and csm, and params (host; the
+// kept counts, KEEP_ALL or KEEP_COUNT, in keep_count or keep_count_all).
+struct MergedPart {
+    damas_geometry g;
+    int32_t n_bins = 0;
+    const double *freq = nullptr, *csm = nullptr;
+    damas_params p{};
+    std::vector<int32_t> keep_count;
+};
+// Whether two requests' sweeps can share one launch: the same precision,
+// sweep counts and policy, and kept counts the host knows.
+bool merge_compatible(const damas_params &a, const damas_params &b);
+// The whole path for several requests on different grids at once: each
+// part's DAS map, selection and system build on its own grid, then one
+// sweep launch (cooperative job lists over every bin of the batch).  Part
+// r's bins are bins bin0[r].. of the batch and its maps start at element
+// map0[r] of x_all (n_bins x N^2 each, x of the batch's precision) and of
+// st_all (device, one count per bin).  No PSF cache.  Filled bin0/map0 on
+// success.
+int solve_merged(damas_ctx *ctx, const std::vector<MergedPart> &parts, void *x_all,
+                 int32_t *st_all, std::vector<int64_t> *bin0, std::vector<int64_t> *map0,
+                 hipStream_t s);
+// Host-side sizes of a merged batch: x_all elements and bins.
+int merged_sizes(const std::vector<MergedPart> &parts, int64_t *map_elems, int64_t *bins);
 
 // Device bytes a context currently holds, and release of its workspace.
 size_t ctx_bytes(const damas_ctx *ctx);

@@ -1111,8 +1111,23 @@ struct GsClasses {
     const uint8_t *cls;
     const bf16s *lo;
     int iters_cls;
-    double *power; // per bin, sum of x~ over the kept points (or null)
+    double *power;      // per bin, sum of x~ over the kept points (or null)
+    const int64_t *map; // per bin (base, S) of its maps, or null: (f N^2, N^2)
 };
+
+// Element offset and grid-point count of bin f's maps (kept indices, b~,
+// x_init, x_map): f N^2 and N^2 for a band on one grid, from the table for
+// a batch of requests on different grids.
+__device__ __forceinline__ void bin_map(const GsClasses &gc, int f, int N, int64_t *base, int *S)
+{
+    if (gc.map) {
+        *base = gc.map[2 * f];
+        *S = (int)gc.map[2 * f + 1];
+    } else {
+        *S = N * N;
+        *base = (int64_t)f * *S;
+    }
+}
 
 // Scatter of a bin's x~ onto the full grid: x_map[n] = x~_i at n = idx[i],
 // 0 in the gaps between kept points, so every grid point is written exactly
@@ -1183,7 +1198,9 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     //      region is held to gs_lo_cap)
     extern __shared__ double xs[];
     const int f = blockIdx.x;
-    const int S = N * N;
+    int64_t mb;
+    int S;
+    bin_map(gc, f, N, &mb, &S);
     int St = s_tilde[f];
     if (St > max_kept) {
         if (threadIdx.x == 0)
@@ -1206,15 +1223,15 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
     const int64_t ld = ld_of(St);
     const int64_t a0 = St > 0 ? off[f] : 0;
     const TA *A = A_all + a0;
-    const int32_t *id = idx + (int64_t)f * S;
-    const double *bf = b + (int64_t)f * S;
+    const int32_t *id = idx + mb;
+    const double *bf = b + mb;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     constexpr int nthr = 64 * WAVES;
     for (int64_t i = tid; i < ld; i += nthr)
-        xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
+        xs[i] = (i < St && x_init) ? (double)x_init[mb + id[i]] : 0.0;
     {
         const int nz = (int)((wide ? 2 * sizeof(TileBlocks<float, true>)
                                    : 2 * sizeof(TileBlocks<TA>)) / 4);
@@ -1243,8 +1260,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
                                                   St, id, bf, total, ntile, w, lane, NW);
     }
 
-    scatter_bin<TX, nthr>(xs, id, St, S, x_map + (int64_t)f * S, gc.power ? gc.power + f : nullptr,
-                          parts);
+    scatter_bin<TX, nthr>(xs, id, St, S, x_map + mb, gc.power ? gc.power + f : nullptr, parts);
 }
 
 // ---------------------------------------------------------------------------
@@ -1265,7 +1281,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
 // One job of the cooperative kernel: rank `rank` of the `ranks` workgroups
 // of bin f (ranks == 1: the bin alone, nothing exchanged).
 template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB, bool LO>
-__device__ __forceinline__ void coop_body(int f, int rank, int ranks, int N, int St,
+__device__ __forceinline__ void coop_body(int f, int rank, int ranks, int64_t mb, int S, int St,
                                           int64_t ld_cap, const int32_t *__restrict__ idx,
                                           const TA *__restrict__ A, const bf16s *Alo,
                                           const double *__restrict__ b, int iters,
@@ -1277,10 +1293,9 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int N, int
     double *xnew = parts + 2 * NW * kGsTile;
     TileBlocks<TA, LO> *blks = reinterpret_cast<TileBlocks<TA, LO> *>(xnew + 2 * kGsTile);
 
-    const int S = N * N;
     const int64_t ld = ld_of(St);
-    const int32_t *id = idx + (int64_t)f * S;
-    const double *bf = b + (int64_t)f * S;
+    const int32_t *id = idx + mb;
+    const double *bf = b + mb;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1290,7 +1305,7 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int N, int
     double *xpub = co.xpub + (int64_t)f * co.xstride;
 
     for (int64_t i = tid; i < ld; i += nthr)
-        xs[i] = (i < St && x_init) ? (double)x_init[(int64_t)f * S + id[i]] : 0.0;
+        xs[i] = (i < St && x_init) ? (double)x_init[mb + id[i]] : 0.0;
     if (rank == 0) {
         uint32_t *z = reinterpret_cast<uint32_t *>(blks); // all-zero bits: 0 in every type
         for (int i = tid; i < (int)(2 * sizeof(TileBlocks<TA, LO>) / 4); i += nthr)
@@ -1351,7 +1366,7 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int N, int
                                                     OwnerLink{flags, part, xpub, ranks, fault},
                                                     Alo);
 
-    scatter_bin<TX, nthr>(xs, id, St, S, x_map + (int64_t)f * S, power, parts);
+    scatter_bin<TX, nthr>(xs, id, St, S, x_map + mb, power, parts);
 }
 
 // One job: the bin's kept count (with the capacity checks), its class and
@@ -1384,16 +1399,19 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
         St = 0;
     }
     const int64_t a0 = St > 0 ? off[f] : 0;
+    int64_t mb;
+    int S;
+    bin_map(gc, f, N, &mb, &S);
     if constexpr (std::is_same<TA, float>::value) {
         if (wide) {
             coop_body<TA, TX, UNIT, NW, kGsLoNH, kGsLoNB, true>(
-                f, rank, ranks, N, St, ld_of(min(max_kept, gs_lo_cap<NW>())), idx, A_all + a0,
+                f, rank, ranks, mb, S, St, ld_of(min(max_kept, gs_lo_cap<NW>())), idx, A_all + a0,
                 gc.lo + a0, b, iters_f, x_init, x_map, fault, co, xs,
                 gc.power ? gc.power + f : nullptr);
             return;
         }
     }
-    coop_body<TA, TX, UNIT, NW, NH, NB, false>(f, rank, ranks, N, St, ld_of(max_kept), idx,
+    coop_body<TA, TX, UNIT, NW, NH, NB, false>(f, rank, ranks, mb, S, St, ld_of(max_kept), idx,
                                                A_all + a0, nullptr, b, iters_f, x_init, x_map,
                                                fault, co, xs, gc.power ? gc.power + f : nullptr);
 }
@@ -1456,7 +1474,7 @@ template <typename TA, int NW> static size_t gs_lds_bytes_t(int max_kept, bool l
 
 static GsClasses to_dev(const GsClassArgs &a)
 {
-    return GsClasses{a.cls, reinterpret_cast<const bf16s *>(a.lo), a.iters_cls, a.power};
+    return GsClasses{a.cls, reinterpret_cast<const bf16s *>(a.lo), a.iters_cls, a.power, a.map};
 }
 
 int gs_wide_capacity() { return std::min(gs_lo_cap<9>(), gs_lo_cap<11>()); }

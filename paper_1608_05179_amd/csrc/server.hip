@@ -94,7 +94,7 @@ struct damas_server {
     uint64_t next = 1;
     std::vector<Slot> slots;
     bool stop = false;
-    uint64_t submitted = 0, completed = 0, rejected = 0;
+    uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, merged = 0;
     int running = 0;
 
     size_t slot_bytes(const Slot &sl) const
@@ -113,7 +113,15 @@ struct damas_server {
     }
     void work(int k);
     int run(Slot &sl, Req *r);
+    int run_batch(Slot &sl, const std::vector<Req *> &batch);
 };
+
+// A request the batch former may merge: kept counts known on the host.
+static bool mergeable(const Req *r)
+{
+    return r->params.select_mode == DAMAS_SEL_KEEP_ALL ||
+           r->params.select_mode == DAMAS_SEL_KEEP_COUNT;
+}
 
 // Release an idle slot's device memory (caller holds mu; the slot's
 // worker is waiting on it, so nothing of it is in flight).
@@ -137,50 +145,154 @@ void damas_server::work(int k)
             cv_work.wait(lk);
             continue;
         }
-        Req *r = queue.front();
+        // The batch: the front request and, when it can merge, later
+        // compatible ones (arrival order) up to max_batch.
+        std::vector<size_t> pick{0};
+        size_t fp = queue.front()->footprint;
+        const size_t budget = o.hbm_budget;
         // Admission: this slot reuses what it holds and the other slots
         // keep theirs; the cache gives up entries, then idle slots release
         // their workspaces, to make room.
-        const size_t budget = o.hbm_budget, fp = r->footprint;
-        auto fits = [&] {
-            const size_t mine = std::max(fp, me.held), others = held_total() - me.held;
+        auto fits_fp = [&](size_t need) {
+            const size_t mine = std::max(need, me.held), others = held_total() - me.held;
             if (others + mine > budget)
                 return false;
             std::lock_guard<std::mutex> ck(cache.mu);
             return cache.shrink_to(budget - others - mine);
         };
-        if (!fits()) {
+        if (!fits_fp(fp)) {
             for (Slot &sl : slots)
                 if (&sl != &me && !sl.busy && sl.held > 0)
                     trim_slot(sl);
             if (me.held > fp)
                 trim_slot(me);
-            if (!fits()) {
+            if (!fits_fp(fp)) {
                 // Wait for a running request to finish and release.
                 cv_work.wait(lk);
                 continue;
             }
         }
-        queue.pop_front();
+        const Req *head = queue.front();
+        if (o.max_batch > 1 && mergeable(head)) {
+            for (size_t i = 1; i < queue.size() && (int)pick.size() < o.max_batch; ++i) {
+                const Req *q = queue[i];
+                if (!mergeable(q) || !merge_compatible(head->params, q->params))
+                    continue;
+                const size_t more = fp + q->footprint;
+                const size_t mine = std::max(more, me.held), others = held_total() - me.held;
+                if (others + mine > budget)
+                    break;
+                fp = more;
+                pick.push_back(i);
+            }
+            if (pick.size() > 1 && !fits_fp(fp)) {
+                pick.resize(1);
+                fp = head->footprint;
+            }
+        }
+        std::vector<Req *> batch;
+        for (size_t i : pick)
+            batch.push_back(queue[i]);
+        for (size_t j = pick.size(); j-- > 0;)
+            queue.erase(queue.begin() + (std::ptrdiff_t)pick[j]);
         me.busy = true;
-        ++running;
-        me.held = std::max(me.held, (size_t)r->footprint); // reserve
-        r->t_start = Clock::now();
+        running += (int)batch.size();
+        me.held = std::max(me.held, fp); // reserve
+        const auto t_start = Clock::now();
+        for (Req *r : batch)
+            r->t_start = t_start;
         lk.unlock();
-        const int rc = run(me, r);
+        const int rc = batch.size() == 1 ? run(me, batch[0]) : run_batch(me, batch);
+        const std::string err = rc ? std::string(damas_last_error()) : std::string();
         lk.lock();
-        r->t_end = Clock::now();
-        r->status = rc;
-        if (rc)
-            r->err = damas_last_error();
-        r->done = true;
+        const auto t_end = Clock::now();
+        for (Req *r : batch) {
+            r->t_end = t_end;
+            r->status = rc;
+            r->err = err;
+            r->done = true;
+        }
         me.busy = false;
         me.held = slot_bytes(me);
-        --running;
-        ++completed;
+        running -= (int)batch.size();
+        completed += batch.size();
+        ++batches;
+        if (batch.size() > 1)
+            merged += batch.size();
         cv_done.notify_all();
         cv_work.notify_all();
     }
+}
+
+// A batch of two or more requests: inputs staged side by side in the
+// slot's buffers, one merged solve, each request's results copied back
+// from its own slice.
+int damas_server::run_batch(Slot &sl, const std::vector<Req *> &batch)
+{
+    CtxScope scope(sl.ctx); // failures are also the slot context's last error
+    size_t n_mic = 0, n_freq = 0, n_csm = 0, n_x = 0;
+    for (const Req *r : batch) {
+        n_mic += r->mic.size();
+        n_freq += r->freq.size();
+        n_csm += r->csm.size();
+        n_x += (size_t)r->n_bins * r->N * r->N;
+    }
+    const int prec = batch[0]->params.precision;
+    const size_t xs = prec == DAMAS_PREC_FP64 ? sizeof(double) : sizeof(float);
+    int rc;
+    if ((rc = grow(sl.mic, sizeof(double) * n_mic)) || (rc = grow(sl.freq, sizeof(double) * n_freq)) ||
+        (rc = grow(sl.csm, sizeof(double) * n_csm)) || (rc = grow(sl.x, xs * n_x)) ||
+        (rc = grow(sl.st, sizeof(int32_t) * n_freq)))
+        return rc;
+    hipStream_t s = sl.stream;
+    std::vector<MergedPart> parts(batch.size());
+    size_t om = 0, of = 0, oc = 0;
+    for (size_t i = 0; i < batch.size(); ++i) {
+        const Req *r = batch[i];
+        double *mic = (double *)sl.mic.p + om, *freq = (double *)sl.freq.p + of,
+               *csm = (double *)sl.csm.p + oc;
+        if (hipMemcpyAsync(mic, r->mic.data(), sizeof(double) * r->mic.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(freq, r->freq.data(), sizeof(double) * r->freq.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(csm, r->csm.data(), sizeof(double) * r->csm.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return set_error(DAMAS_EDEVICE, "upload of a batched request's inputs");
+        MergedPart &q = parts[i];
+        q.g.M = r->M;
+        q.g.mic = mic;
+        q.g.N = r->N;
+        q.g.x0 = r->x0;
+        q.g.x1 = r->x1;
+        q.g.y0 = r->y0;
+        q.g.y1 = r->y1;
+        q.g.z0 = r->z0;
+        q.g.c = r->c;
+        q.n_bins = r->n_bins;
+        q.freq = freq;
+        q.csm = csm;
+        q.p = r->params;
+        q.keep_count = r->keep_count;
+        om += r->mic.size();
+        of += r->freq.size();
+        oc += r->csm.size();
+    }
+    std::vector<int64_t> bin0, map0;
+    if ((rc = solve_merged(sl.ctx, parts, sl.x.p, (int32_t *)sl.st.p, &bin0, &map0, s)))
+        return rc;
+    for (size_t i = 0; i < batch.size(); ++i) {
+        Req *r = batch[i];
+        r->cache_hit = 0;
+        const size_t nx = (size_t)r->n_bins * r->N * r->N;
+        if (hipMemcpyAsync(r->x_map, (char *)sl.x.p + xs * (size_t)map0[i], xs * nx,
+                           hipMemcpyDeviceToHost, s) != hipSuccess ||
+            (r->s_tilde &&
+             hipMemcpyAsync(r->s_tilde, (int32_t *)sl.st.p + bin0[i],
+                            sizeof(int32_t) * r->n_bins, hipMemcpyDeviceToHost,
+                            s) != hipSuccess))
+            return set_error(DAMAS_EDEVICE, "download of a batched request's results");
+    }
+    return damas_check(sl.ctx, s); // synchronises; reports device faults
 }
 
 int damas_server::run(Slot &sl, Req *r)
@@ -238,6 +350,8 @@ extern "C" int damas_server_create(const damas_server_opts *o, damas_server **ou
         return set_error(DAMAS_EINVAL, "slots = %d outside [1, 16]", o->slots);
     if (o->max_queue < 1)
         return set_error(DAMAS_EINVAL, "max_queue must be >= 1");
+    if (o->max_batch < 0 || o->max_batch > 4096)
+        return set_error(DAMAS_EINVAL, "max_batch = %d outside [0, 4096]", o->max_batch);
     if (o->cache_budget > o->hbm_budget)
         return set_error(DAMAS_EINVAL, "cache_budget exceeds hbm_budget");
     int n = 0;
@@ -438,5 +552,7 @@ extern "C" int damas_server_get_stats(damas_server *srv, damas_server_stats *out
     out->cache_hits = srv->cache.hits;
     out->cache_misses = srv->cache.misses;
     out->cache_bytes = srv->cache.used;
+    out->batches = srv->batches;
+    out->merged = srv->merged;
     return DAMAS_OK;
 }

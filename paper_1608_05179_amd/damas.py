@@ -156,7 +156,8 @@ _sig("damas_graph_destroy", None, c_vp)
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("device", c_i32), ("hbm_budget", ctypes.c_uint64),
-                ("cache_budget", ctypes.c_uint64), ("slots", c_i32), ("max_queue", c_i32)]
+                ("cache_budget", ctypes.c_uint64), ("slots", c_i32), ("max_queue", c_i32),
+                ("max_batch", c_i32)]
 
 
 class Request(ctypes.Structure):
@@ -175,7 +176,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64),
                 ("cache_misses", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64),
-                ("cache_bytes", ctypes.c_uint64), ("queued", c_i32), ("running", c_i32)]
+                ("cache_bytes", ctypes.c_uint64), ("queued", c_i32), ("running", c_i32),
+                ("batches", ctypes.c_uint64), ("merged", ctypes.c_uint64)]
 
 
 _sig("damas_server_create", ctypes.c_int, ctypes.POINTER(ServerOpts), ctypes.POINTER(c_vp))
@@ -680,9 +682,11 @@ class Server:
     numpy arrays from wait()."""
 
     def __init__(self, device=0, hbm_budget=64 << 30, cache_budget=8 << 30, slots=2,
-                 max_queue=256):
+                 max_queue=256, max_batch=1):
+        """max_batch > 1: compatible queued requests (any grid) run as one
+        batch, their sweeps in one launch."""
         o = ServerOpts(int(device), int(hbm_budget), int(cache_budget), int(slots),
-                       int(max_queue))
+                       int(max_queue), int(max_batch))
         h = c_vp()
         _check(_lib.damas_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
