@@ -616,7 +616,10 @@ int damas_query_footprint(int32_t M, int32_t N, int32_t n_bins, const damas_para
  * frequencies, precision and the kept points of every bin, so a repeated
  * scene skips its steering and PSF launches (the key needs the kept points
  * on the host: one stream synchronisation per cached request).  Batched
- * solves only.  The server is thread-safe.
+ * solves only.  The server is thread-safe.  The slots' sweep launches pass
+ * a gate one at a time (each waits on the device for the previous ones), so
+ * every cooperative sweep grid has the whole device, while the uploads,
+ * system builds and downloads of the other slots overlap it.
  *
  * Batch former (max_batch > 1): a worker that takes a request whose kept
  * counts the host knows (KEEP_ALL, KEEP_COUNT, KEEP_FRAC) also takes up to

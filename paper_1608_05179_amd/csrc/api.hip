@@ -1300,6 +1300,12 @@ int enqueue_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb, int32_t max_k
     ctx->last_workgroups = n_wg > 0 ? n_wg : nb;
     ctx->last_coop = n_wg > 0;
     ctx->last_gpw = gpw;
+    // Gated contexts queue their sweeps behind the previous gated ones.
+    std::unique_lock<std::mutex> gate;
+    if (ctx->sweep_gate) {
+        gate = std::unique_lock<std::mutex>(*ctx->sweep_gate_mu);
+        HIP_TRY(hipStreamWaitEvent(s, *ctx->sweep_gate, 0), "hipStreamWaitEvent");
+    }
     auto sweeps = [&](int prec, const void *Ap, int iters, const void *xi,
                       const GsClassArgs &g) -> hipError_t {
         if (n_wg > 0)
@@ -1338,6 +1344,8 @@ int enqueue_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb, int32_t max_k
                     "gs launch (fp32 refinement)");
         }
     }
+    if (ctx->sweep_gate)
+        HIP_TRY(hipEventRecord(*ctx->sweep_gate, s), "hipEventRecord");
     return DAMAS_OK;
 }
 

@@ -115,6 +115,11 @@ struct damas_ctx {
     // last failure of a call made on this context (damas_ctx_last_error)
     mutable std::mutex err_mu;
     std::string err;
+    // sweep gate (set by the request server for its slots): every sweep
+    // launch of a context with a gate waits on the device for the previous
+    // gated sweeps, so one cooperative grid at a time holds the whole chip
+    hipEvent_t *sweep_gate = nullptr;
+    std::mutex *sweep_gate_mu = nullptr;
     // graph capture: `capturing` marks the captured solve, which makes no
     // host synchronisation and plans no schedule: its sweeps run the
     // schedule the sizing solve before it chose, from the graph's own copy

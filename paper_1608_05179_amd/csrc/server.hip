@@ -96,6 +96,11 @@ struct damas_server {
     bool stop = false;
     uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, merged = 0;
     int running = 0;
+    // the slots' sweep gate: their sweep launches run one after another,
+    // each with the whole device's cooperative budget, while uploads,
+    // system builds and downloads of other slots overlap them
+    hipEvent_t sweep_gate = nullptr;
+    std::mutex sweep_mu;
 
     size_t slot_bytes(const Slot &sl) const
     {
@@ -365,15 +370,19 @@ extern "C" int damas_server_create(const damas_server_opts *o, damas_server **ou
     srv->o = *o;
     srv->cache.budget = o->cache_budget;
     srv->slots.resize(o->slots);
-    // Cooperative sweeps of concurrent requests share the device: each slot
-    // launches at most its share of the compute units, so every launched
-    // workgroup can be resident at once.
-    int cus = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o->device);
+    // The slots' sweeps pass a gate in turn (each waits on the device for
+    // the previous ones), so every cooperative grid has the whole device.
+    if (hipEventCreateWithFlags(&srv->sweep_gate, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete srv;
+        return set_error(DAMAS_EDEVICE, "sweep gate event");
+    }
     for (Slot &sl : srv->slots) {
         int rc = damas_ctx_create(o->device, &sl.ctx);
-        if (rc == DAMAS_OK)
-            rc = damas_ctx_set_coop(sl.ctx, cus / o->slots);
+        if (rc == DAMAS_OK) {
+            sl.ctx->sweep_gate = &srv->sweep_gate;
+            sl.ctx->sweep_gate_mu = &srv->sweep_mu;
+        }
         if (rc == DAMAS_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
             rc = set_error(DAMAS_EDEVICE, "hipStreamCreate");
         if (rc) {
@@ -383,6 +392,7 @@ extern "C" int damas_server_create(const damas_server_opts *o, damas_server **ou
                 if (t.stream)
                     (void)hipStreamDestroy(t.stream);
             }
+            (void)hipEventDestroy(srv->sweep_gate);
             delete srv;
             return rc;
         }
@@ -420,6 +430,7 @@ extern "C" void damas_server_destroy(damas_server *srv)
         damas_ctx_destroy(sl.ctx);
         (void)hipStreamDestroy(sl.stream);
     }
+    (void)hipEventDestroy(srv->sweep_gate);
     {
         std::lock_guard<std::mutex> ck(srv->cache.mu);
         srv->cache.clear();
