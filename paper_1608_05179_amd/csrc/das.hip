@@ -7,15 +7,20 @@
 //
 // One workgroup = one bin x 64 grid points; lane = grid point.  The 64
 // steering vectors of the tile are built once into LDS (M x 64 complex
-// doubles, mic-major so a wave reads 64 consecutive points).  Wave w takes
-// CSM rows m = w, w+4, ...; a CSM row is wave-uniform, so its entries come
-// through the scalar cache while LDS feeds the per-lane steering values.
+// doubles, mic-major so a wave reads 64 consecutive points).  Wave w of the
+// workgroup takes the CSM rows m = w (mod waves); a CSM row is wave-uniform,
+// so its entries come through the scalar cache while LDS feeds the per-lane
+// steering values.  The tile's steering takes most of a CU's LDS, so one
+// workgroup runs per CU and its waves hide each other's scalar-load
+// latency.
 #include "common.h"
 
 namespace damas {
 
 constexpr int kDasPts = 64;
-constexpr int kDasThreads = 256;
+constexpr int kDasThreads = 1024;
+constexpr int kDasWaves = kDasThreads / 64;
+constexpr int kDasRows = 4; // CSM rows per pass of a wave
 
 template <bool PAPER, bool DIAG>
 __global__ __launch_bounds__(kDasThreads) void das_kernel(
@@ -49,34 +54,40 @@ __global__ __launch_bounds__(kDasThreads) void das_kernel(
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double *C = csm + (size_t)f * M * M * 2;
     double acc = 0.0;
-    // Two CSM rows per pass so each steering value read from LDS feeds
-    // eight multiply-adds.
-    for (int m = w; m < M; m += 8) {
-        const bool two = m + 4 < M;
-        const double *c0 = C + (size_t)m * M * 2;
-        const double *c1 = C + (size_t)(two ? m + 4 : m) * M * 2;
-        double y0r = 0.0, y0i = 0.0, y1r = 0.0, y1i = 0.0;
+    // Wave w takes CSM rows m = w (mod kDasWaves), kDasRows of them per
+    // pass, so each steering value read from LDS feeds 4 kDasRows
+    // multiply-adds; the rows' terms are added to the point's sum in row
+    // order whatever kDasRows is.
+    for (int m = w; m < M; m += kDasWaves * kDasRows) {
+        const double *cr[kDasRows];
+#pragma unroll
+        for (int q = 0; q < kDasRows; ++q)
+            cr[q] = C + (size_t)(m + kDasWaves * q < M ? m + kDasWaves * q : m) * M * 2;
+        double yr[kDasRows], yi[kDasRows];
+#pragma unroll
+        for (int q = 0; q < kDasRows; ++q)
+            yr[q] = yi[q] = 0.0;
         for (int mp = 0; mp < M; ++mp) {
-            double2 e = sh_e[mp * kDasPts + lane];
-            double ar = c0[2 * mp], ai = c0[2 * mp + 1];
-            double br = c1[2 * mp], bi = c1[2 * mp + 1];
-            y0r += ar * e.x - ai * e.y;
-            y0i += ar * e.y + ai * e.x;
-            y1r += br * e.x - bi * e.y;
-            y1i += br * e.y + bi * e.x;
+            const double2 e = sh_e[mp * kDasPts + lane];
+#pragma unroll
+            for (int q = 0; q < kDasRows; ++q) {
+                const double ar = cr[q][2 * mp], ai = cr[q][2 * mp + 1];
+                yr[q] += ar * e.x - ai * e.y;
+                yi[q] += ar * e.y + ai * e.x;
+            }
         }
         // Re(conj(e_m) y_m) = er*yr + ei*yi
-        double2 e0 = sh_e[m * kDasPts + lane];
-        acc += e0.x * y0r + e0.y * y0i;
-        if (two) {
-            double2 e1 = sh_e[(m + 4) * kDasPts + lane];
-            acc += e1.x * y1r + e1.y * y1i;
-        }
+#pragma unroll
+        for (int q = 0; q < kDasRows; ++q)
+            if (m + kDasWaves * q < M) {
+                const double2 e0 = sh_e[(m + kDasWaves * q) * kDasPts + lane];
+                acc += e0.x * yr[q] + e0.y * yi[q];
+            }
     }
     if (DIAG) {
         // The m = m' terms, |v_m|^2 C_mm (C_mm real), of this wave's rows.
         double dsum = 0.0;
-        for (int m = w; m < M; m += 4) {
+        for (int m = w; m < M; m += kDasWaves) {
             const double2 e = sh_e[m * kDasPts + lane];
             dsum += (e.x * e.x + e.y * e.y) * C[((size_t)m * M + m) * 2];
         }
@@ -87,7 +98,10 @@ __global__ __launch_bounds__(kDasThreads) void das_kernel(
     if (threadIdx.x < kDasPts) {
         int n = p0 + lane;
         if (n < S) {
-            double s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < kDasWaves; ++v)
+                s += part[v][lane];
             b[(size_t)f * S + n] = s / ((double)M * (double)M - (DIAG ? (double)M : 0.0));
         }
     }
