@@ -69,7 +69,7 @@ def _parse():
     ap.add_argument("--requests", type=int, default=40,
                     help="served workload: requests in the specified-rate trace")
     ap.add_argument("--workload", default=None,
-                    choices=["batched", "compressed", "plain", "precision", "served",
+                    choices=["batched", "compressed", "plain", "precision", "served", "stream",
                              "csm", "psf", "copy"])
     ap.add_argument("--refine", type=int, default=60,
                     help="FP32 refinement sweeps of the precision workload")
@@ -728,6 +728,24 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"workload": "copy", "bytes": src.numel() * 4}), flush=True)
+        return
+    if args.workload == "stream":
+        # Achievable read bandwidth: torch's sum over 8 GiB of float32 (a
+        # read stream; median of 5 HIP-event timed launches).
+        x = torch.ones(1 << 31, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            x.sum()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts[1:])[2]
+        print(json.dumps({"workload": "stream: torch.sum over 8 GiB of float32",
+                          "ms": round(ms, 3), "read_GBs": round(x.numel() * 4 / ms / 1e6, 1)}),
+              flush=True)
         return
     if args.workload == "served":
         # the one-request-per-launch comparison only on short traces
