@@ -567,6 +567,13 @@ int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32_t n_bins,
                        const double *freq, const double *csm, const damas_params *p,
                        int32_t trial_sweeps, void *stream, damas_tune_result *out);
 
+/* Apply schedule knobs (the coop .. wide_cost fields of a
+ * damas_tune_result, as damas_ctx_autotune reports them; the timing fields
+ * are ignored) to the context's later solves, without trial solves.
+ * DAMAS_EINVAL for knobs out of range (coop not 0/1, coop_min_rows < 64,
+ * coop_split, coop_overhead or wide_cost not > 0, coop_floor_rows < 0). */
+int damas_ctx_set_schedule(damas_ctx *ctx, const damas_tune_result *knobs);
+
 /* ---- graphs: one whole-path solve captured, replayed on any stream ------ */
 
 /* Capture the batched launches of damas_solve_dev with these arguments into

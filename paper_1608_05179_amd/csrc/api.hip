@@ -1043,13 +1043,17 @@ int prepare(damas_ctx *ctx, SolvePlan &P, double *b_map, int32_t *idx, int32_t *
 // Cooperative schedule of a batched solve, from the kept counts the host
 // knows.  The work of a bin is ld^2 (A elements per sweep).  With G
 // workgroups (the context's budget within the device's co-resident
-// capacity) and T = total work / G, a bin above 1.25 T gets ceil(work / T)
-// ranks (at most gs_max_ranks(), at least kCoopMinRows rows each, three
-// tiles), each the first job of its own workgroup; the other bins, largest
-// first, go after them on the least loaded workgroups.  The schedule is
+// capacity) and T = total work / G, a bin above 1.25 T (the split knob)
+// gets ceil(work / T) ranks (at most gs_max_ranks(), at least kCoopMinRows
+// rows each, three tiles), each the first job of its own workgroup; the
+// other bins, largest
+// first, form a queue the workgroups take from when their ranks are done
+// (the estimate places them on the least loaded workgroups).  The schedule is
 // used only if its estimated makespan (ranks cost kCoopOverhead more per
 // element than a bin alone) beats one workgroup per bin by 10 %.
-// tab = [first, end) job per workgroup, then (bin, rank, ranks) per job.
+// tab: header (queue length, offset of the ranges, offset of the jobs), the
+// queue of bins alone (longest first), [first, end) of the static jobs per
+// workgroup, then (bin, rank, ranks) per static job.
 int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int *gpw,
               const uint8_t *cls = nullptr)
 {
@@ -1117,53 +1121,52 @@ int plan_coop(damas_ctx *ctx, const SolvePlan &P, std::vector<int32_t> &tab, int
     }
     if (multi == 0 && nb <= G)
         return 0; // no bin would get a helper: one workgroup per bin
-    // Workgroups: ranked bins' ranks first, then the bins alone (longest
-    // processing time onto the least loaded workgroup).
-    std::vector<std::vector<int32_t>> wg_jobs(G);
+    // Workgroups: ranked bins' ranks first, each its own workgroup; the
+    // bins alone form a queue, longest first, that workgroups take from once
+    // their ranks are done.  The estimate of the makespan places them as
+    // the queue would under the cost model (longest processing time onto
+    // the least loaded workgroup).
     std::vector<double> load(G, 0.0);
-    int g = 0;
+    std::vector<int32_t> ranked; // (bin, rank, ranks) per ranked workgroup
     for (int f = 0; f < nb; ++f)
         if (ranks[f] > 1)
-            for (int h = 0; h < ranks[f]; ++h, ++g) {
-                wg_jobs[g] = {f, h, ranks[f]};
-                load[g] = kCoopOverhead *
-                          (kFloor > 0.0 ? cost(P.st_host[f],
-                                               (double)ld_of(P.st_host[f]) / ranks[f]) * scale(f)
-                                        : work[f] / ranks[f]);
+            for (int h = 0; h < ranks[f]; ++h) {
+                load[ranked.size() / 3] =
+                    kCoopOverhead *
+                    (kFloor > 0.0 ? cost(P.st_host[f], (double)ld_of(P.st_host[f]) / ranks[f]) *
+                                        scale(f)
+                                  : work[f] / ranks[f]);
+                ranked.insert(ranked.end(), {f, h, ranks[f]});
             }
     std::vector<int> solo;
     for (int f = 0; f < nb; ++f)
         if (ranks[f] == 1)
             solo.push_back(f);
-    std::sort(solo.begin(), solo.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::stable_sort(solo.begin(), solo.end(), [&](int a, int b) { return work[a] > work[b]; });
     for (int f : solo) {
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        wg_jobs[k].insert(wg_jobs[k].end(), {f, 0, 1});
         load[k] += work[f];
     }
     const double span = *std::max_element(load.begin(), load.end());
     if (!(span < 0.9 * plain_span) && nb <= G)
         return 0;
-    int n_wg = 0;
-    for (int k = 0; k < G; ++k)
-        if (!wg_jobs[k].empty())
-            ++n_wg;
-    tab.assign(2 * (size_t)n_wg, 0);
-    int pos = 0, w = 0, gmax = 0;
-    for (int k = 0; k < G; ++k) {
-        if (wg_jobs[k].empty())
-            continue;
-        tab[2 * w] = pos;
-        for (size_t j = 0; j < wg_jobs[k].size(); j += 3) {
-            const int f = wg_jobs[k][j], r = wg_jobs[k][j + 2];
-            tab.insert(tab.end(), {wg_jobs[k][j], wg_jobs[k][j + 1], r});
-            for (int prec : {P.p->precision, (int)DAMAS_PREC_FP32})
-                gmax = std::max(gmax, gs_groups_per_wave(prec, P.st_host[f], r));
-            ++pos;
-        }
-        tab[2 * w + 1] = pos;
-        ++w;
+    const int n_ranked = (int)(ranked.size() / 3);
+    const int n_wg = std::min(G, n_ranked + (int)solo.size());
+    const int n_q = (int)solo.size();
+    tab.assign(3, 0);
+    tab[0] = n_q;
+    tab.insert(tab.end(), solo.begin(), solo.end());
+    tab[1] = (int32_t)tab.size(); // ranges
+    for (int w = 0; w < n_wg; ++w) { // workgroup w < n_ranked: static job w; others: none
+        const int32_t first = std::min(w, n_ranked);
+        tab.insert(tab.end(), {first, w < n_ranked ? first + 1 : first});
     }
+    tab[2] = (int32_t)tab.size(); // jobs
+    tab.insert(tab.end(), ranked.begin(), ranked.end());
+    int gmax = 0;
+    for (int f = 0; f < nb; ++f)
+        for (int prec : {P.p->precision, (int)DAMAS_PREC_FP32})
+            gmax = std::max(gmax, gs_groups_per_wave(prec, P.st_host[f], ranks[f]));
     *gpw = gmax;
     return n_wg;
 }
@@ -2229,6 +2232,23 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
                         "written",
                         ctx->tune_cache.c_str());
     }
+    return DAMAS_OK;
+}
+
+extern "C" int damas_ctx_set_schedule(damas_ctx *ctx, const damas_tune_result *k)
+{
+    CtxScope scope(ctx);
+    if (!ctx || !k)
+        return fail(DAMAS_EINVAL, "ctx and knobs must be non-NULL");
+    if ((k->coop != 0 && k->coop != 1) || k->coop_min_rows < 64 || !(k->coop_split > 0.0) ||
+        !(k->coop_overhead > 0.0) || !(k->wide_cost > 0.0) || k->coop_floor_rows < 0)
+        return fail(DAMAS_EINVAL, "schedule knobs out of range");
+    ctx->tune.coop = k->coop == 1;
+    ctx->tune.min_rows = k->coop_min_rows;
+    ctx->tune.split = k->coop_split;
+    ctx->tune.overhead = k->coop_overhead;
+    ctx->tune.floor_rows = k->coop_floor_rows;
+    ctx->tune.wide_cost = k->wide_cost;
     return DAMAS_OK;
 }
 

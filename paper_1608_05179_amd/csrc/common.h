@@ -193,9 +193,12 @@ int gs_wide_capacity();
 int gs_max_kept(int precision);
 
 // Cooperative sweeps (several workgroups per bin, several bins per
-// workgroup).  tab (device int32): per workgroup its first job and one past
-// its last (2 n_wg), then per job the bin, its rank and the bin's rank
-// count; a job with ranks > 1 must be the first of its workgroup;
+// workgroup).  tab (device int32): a header (queue length Q, offset of the
+// ranges, offset of the jobs), a queue of Q bins that run alone (taken by
+// workgroups once their static jobs are done, in queue order), per
+// workgroup the [first, end) of its static jobs, then per job the bin, its
+// rank and the bin's rank count; a job with ranks > 1 must be the first of
+// its workgroup;
 // groups_per_wave: the most row groups any stream wave sums per strip;
 // ws: gs_coop_ws_bytes of device workspace.  Every bin needs >= 2 tiles.
 size_t gs_coop_ws_bytes(int n_bins, int max_kept);

@@ -684,11 +684,11 @@ constexpr int kGsAbort = kGsMaxRanks;
 constexpr long long kGsSpinMax = 1ll << 21; // polls (~0.2 s) before a wait gives up
 
 struct GsCoop {
-    const int32_t *wg;   // per workgroup: first job, one past its last job
-    const int32_t *jobs; // per job: bin, rank, ranks of the bin
+    const int32_t *tab;  // schedule table (header, queue, ranges, jobs)
     uint32_t *flags;
     double *part;
     double *xpub;
+    uint32_t *next;      // queue position (zeroed with the flags)
     int64_t xstride;
 };
 
@@ -1417,11 +1417,16 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
 }
 
 
-// The cooperative kernel: workgroup g runs jobs co.wg[2g] .. co.wg[2g+1]-1
-// of co.jobs (bin, rank, ranks) in order.  A bin with ranks > 1 is the first
-// job of each of its workgroups, so all its ranks run at once (the launch
-// keeps every workgroup resident); later jobs are bins alone, which wait on
-// nobody.
+// The cooperative kernel.  The schedule table holds a header (queue
+// length, offsets of the ranges and the jobs), a queue of bins that run
+// alone, longest first, the static jobs of each workgroup ([first, end)
+// per workgroup) and the jobs themselves (bin, rank, ranks).  Workgroup g
+// runs its static jobs -- ranks of the bins shared by several workgroups,
+// each the first job of its workgroup, so all ranks of a bin run at once
+// (the launch keeps every workgroup resident) -- and then takes bins from
+// the queue until it is empty: a workgroup that finishes early takes the
+// next longest bin, whatever the cost model predicted.  Bins alone wait on
+// nobody, and a bin's result does not depend on the workgroup that runs it.
 template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
 __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
     int N, const int32_t *__restrict__ s_tilde, int max_kept,
@@ -1431,11 +1436,35 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
     GsClasses gc)
 {
     extern __shared__ double xs[];
-    const int j0 = co.wg[2 * blockIdx.x], j1 = co.wg[2 * blockIdx.x + 1];
-    for (int j = j0; j < j1; ++j) {
-        coop_job<TA, TX, UNIT, NW, NH, NB>(co.jobs[3 * j], co.jobs[3 * j + 1],
-                                           co.jobs[3 * j + 2], N, s_tilde, max_kept, idx, off,
-                                           A_all, b, iters, x_init, x_map, fault, co, gc, xs);
+    __shared__ int taken;
+    const int32_t *tab = co.tab;
+    const int n_queue = tab[0];
+    const int32_t *queue = tab + 3, *wg = tab + tab[1], *jobs = tab + tab[2];
+    int j = wg[2 * blockIdx.x];
+    const int j1 = wg[2 * blockIdx.x + 1];
+    // One call site of the job body (it is inlined once).
+    for (;;) {
+        int f, rank, ranks;
+        if (j < j1) {
+            f = jobs[3 * j];
+            rank = jobs[3 * j + 1];
+            ranks = jobs[3 * j + 2];
+            ++j;
+        } else {
+            // `taken` is rewritten only after every thread passed the
+            // previous job's barriers, so all read the same position.
+            if (threadIdx.x == 0)
+                taken = (int)atomicAdd(co.next, 1u);
+            __syncthreads();
+            const int k = taken;
+            if (k >= n_queue)
+                break;
+            f = queue[k];
+            rank = 0;
+            ranks = 1;
+        }
+        coop_job<TA, TX, UNIT, NW, NH, NB>(f, rank, ranks, N, s_tilde, max_kept, idx, off, A_all,
+                                           b, iters, x_init, x_map, fault, co, gc, xs);
         __syncthreads(); // the next job reuses LDS
     }
 }
@@ -1558,9 +1587,10 @@ __global__ void zero_u32_kernel(uint32_t *p, int64_t n)
 }
 
 // Byte offsets of the exchange area within the workspace.
+// The flags of every bin, then the queue position.
 static size_t coop_flags_bytes(int n_bins)
 {
-    return ((size_t)n_bins * kGsFlagStride * sizeof(uint32_t) + 255) & ~(size_t)255;
+    return (((size_t)n_bins * kGsFlagStride + 1) * sizeof(uint32_t) + 255) & ~(size_t)255;
 }
 static size_t coop_part_bytes(int n_bins)
 {
@@ -1657,15 +1687,15 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
         return hipSuccess;
     char *base = (char *)ws;
     GsCoop co;
-    co.wg = tab;
-    co.jobs = tab + 2 * n_wg;
+    co.tab = tab;
     co.flags = (uint32_t *)base;
+    co.next = co.flags + (int64_t)n_bins * kGsFlagStride;
     co.part = (double *)(base + coop_flags_bytes(n_bins));
     co.xpub = (double *)(base + coop_flags_bytes(n_bins) + coop_part_bytes(n_bins));
     co.xstride = ld_of(max_kept);
-    // Flags start at zero (a kernel, so the launch sequence stays
-    // capturable in a graph).
-    const int64_t nflags = (int64_t)n_bins * kGsFlagStride;
+    // Flags and the queue position start at zero (a kernel, so the launch
+    // sequence stays capturable in a graph).
+    const int64_t nflags = (int64_t)n_bins * kGsFlagStride + 1;
     hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, s,
                        co.flags, nflags);
     hipError_t e = hipGetLastError();

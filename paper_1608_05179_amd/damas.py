@@ -147,6 +147,7 @@ class TuneResult(ctypes.Structure):
 
 _sig("damas_ctx_autotune", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
      c_i32, c_vp, ctypes.POINTER(TuneResult))
+_sig("damas_ctx_set_schedule", ctypes.c_int, c_vp, ctypes.POINTER(TuneResult))
 _sig("damas_graph_capture", ctypes.c_int, c_vp, _G, c_i32, c_vp, c_vp, ctypes.POINTER(Params),
      c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_vp))
 _sig("damas_graph_launch", ctypes.c_int, c_vp, c_vp)
@@ -565,6 +566,18 @@ class Context:
 
     def check(self, stream=None):
         check(self, stream)
+
+    def set_schedule(self, **knobs):
+        """Apply schedule knobs (keys of autotune()'s result: coop,
+        coop_min_rows, coop_split, coop_overhead, coop_floor_rows, wide_cost;
+        defaults for the others) without trial solves."""
+        r = TuneResult()
+        base = {"coop": 1, "coop_min_rows": 320, "coop_split": 1.25, "coop_overhead": 1.3,
+                "coop_floor_rows": 0, "wide_cost": 1.7}
+        base.update(knobs)
+        for k, v in base.items():
+            setattr(r, k, v)
+        _check(_lib.damas_ctx_set_schedule(self._h, ctypes.byref(r)))
 
     def autotune(self, g: Geometry, freq, csm, *, select_mode=SEL_KEEP_ALL, eps=0.0,
                  keep_count=None, precision=PREC_FP32, max_kept=0, trial_sweeps=30,

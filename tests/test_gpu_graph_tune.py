@@ -129,3 +129,33 @@ def test_autotune_keeps_a_valid_choice(orc, dm, dev):
         err = np.linalg.norm(x[f] - ref["x"]) / np.linalg.norm(ref["x"])
         assert err <= 1e-4, (f, err)
     ctx.close()
+
+
+def test_set_schedule_applies_knobs(dm, dev):
+    # Knobs applied without trials give the schedule they describe: the
+    # defaults reproduce an untuned context bitwise, and knobs that rank no
+    # bin give one workgroup per bin (plain sweeps), equal to coop = 0.
+    import torch
+    w = synth.compressed_fp32(n_bins=4, N=61, iterations=60)
+    Ks = [2400, 700, 3600, 150]
+    mic, g, freq, csm = _setup(dm, dev, w)
+    kw = dict(select_mode=dm.SEL_KEEP_COUNT, keep_count=Ks, iterations=w.iterations)
+    a = dm.Context(0)
+    xa = a.solve(g, freq, csm, **kw).clone()
+    b = dm.Context(0)
+    b.set_schedule()
+    xb = b.solve(g, freq, csm, **kw).clone()
+    assert torch.equal(xa, xb) and a.last_workgroups() == b.last_workgroups()
+    b.set_schedule(coop=0)
+    xc = b.solve(g, freq, csm, **kw)
+    assert b.last_workgroups() == w.n_bins
+    c = dm.Context(0)
+    c.set_coop(0)
+    xd = c.solve(g, freq, csm, **kw)
+    a.check(), b.check(), c.check()
+    assert torch.equal(xc, xd)
+    with pytest.raises(dm.DamasError) as ei:
+        b.set_schedule(coop_split=0.0)
+    assert ei.value.code == dm.EINVAL
+    for ctx in (a, b, c):
+        ctx.close()
