@@ -57,8 +57,8 @@ CSRC = os.path.join(ROOT, "paper_1608_05179_amd", "csrc")
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plain-bins", type=int, default=8,
                     help="bins of the band solved one launch per step (plain) for the "
                          "comparison; 0 skips it")
@@ -69,7 +69,7 @@ def _parse():
     ap.add_argument("--requests", type=int, default=40,
                     help="served workload: requests in the specified-rate trace")
     ap.add_argument("--workload", default=None,
-                    choices=["batched", "compressed", "plain", "precision", "served", "stream",
+                    choices=["batched", "compressed", "compressed10", "compressed30", "plain", "precision", "served", "stream",
                              "csm", "psf", "copy"])
     ap.add_argument("--refine", type=int, default=60,
                     help="FP32 refinement sweeps of the precision workload")
@@ -89,6 +89,16 @@ def _progress(msg):
     """One line per finished phase on stderr (stdout carries only the
     result line)."""
     print(f"bench.py: {msg} ({time.perf_counter() - _T0:.0f} s)", file=sys.stderr, flush=True)
+
+
+def _histogram(s_tilde):
+    """Kept counts per bin in 500-point classes: {"lo-hi": bins}."""
+    import numpy as np
+    top = int(np.ceil((int(s_tilde.max()) + 1) / 500.0)) * 500
+    edges = np.arange(0, top + 1, 500)
+    counts, _ = np.histogram(s_tilde, bins=edges)
+    return {f"{int(a)}-{int(b) - 1}": int(c) for a, b, c in zip(edges[:-1], edges[1:], counts)
+            if c}
 
 
 def _pct(v, q):
@@ -138,11 +148,14 @@ def _workload(name, refine):
 def _make_workload(name, refine):
     from paper_1608_05179_amd import damas as dm
     from paper_1608_05179_amd import synth
-    if name == "compressed":
-        w = synth.compressed_fp32(keep_frac=0.2)
-        return (w, dm.SEL_KEEP_COUNT, dm.PREC_FP32, 0,
-                "compressed-fp32: M=64 spiral, 41x41 grid, 64 bins 1-8 kHz, keep 20% "
-                "(S~=337), 1000 sweeps, A stored f32")
+    if name.startswith("compressed"):
+        # KEEP_FRAC p = 0.2 (the headline of this band), or 0.1 / 0.3
+        p = {"compressed": 0.2, "compressed10": 0.1, "compressed30": 0.3}[name]
+        w = synth.compressed_fp32(keep_frac=p)
+        w.keep_frac = p
+        return (w, dm.SEL_KEEP_FRAC, dm.PREC_FP32, 0,
+                f"compressed-fp32: M=64 spiral, 41x41 grid, 64 bins 1-8 kHz, KEEP_FRAC {p:g} "
+                f"(S~={w.keep_count}), 1000 sweeps, A stored f32")
     if name == "plain":
         w = synth.plain_fp64()
         return (w, dm.SEL_KEEP_ALL, dm.PREC_FP64, 0,
@@ -179,9 +192,13 @@ class _Problem:
         self.rho_wide = rho_wide
         dev = torch.device("cuda:0")
         self.K = None
+        self.frac = 0.0
         if mode == dm.SEL_KEEP_COUNT:
             self.K = ([int(v) for v in w.keep_counts] if w.keep_counts is not None
                       else int(w.keep_count))
+        elif mode == dm.SEL_KEEP_FRAC:
+            self.frac = float(w.keep_frac)
+            self.K = int(w.keep_count)  # ceil(p N^2), for the oracle
         self.mic = torch.tensor(w.mic, dtype=torch.float64, device=dev)
         self.g = dm.geometry(self.mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
         self.freq = torch.tensor(w.freqs, dtype=torch.float64, device=dev)
@@ -194,8 +211,14 @@ class _Problem:
         self.ctx = dm.Context(0)
         self.np = np
 
+    def _sel(self):
+        from paper_1608_05179_amd import damas as dm
+        if self.mode == dm.SEL_KEEP_FRAC:
+            return {"select_mode": self.mode, "keep_frac": self.frac}
+        return {"select_mode": self.mode, "keep_count": self.K}
+
     def solve(self, batched=True):
-        self.ctx.solve(self.g, self.freq, self.csm, select_mode=self.mode, keep_count=self.K,
+        self.ctx.solve(self.g, self.freq, self.csm, **self._sel(),
                        iterations=self.w.iterations, precision=self.prec, batched=batched,
                        refine_sweeps=self.R, x_map=self.x, s_tilde=self.st, idx=self.idx,
                        policy=self.policy, rho_wide=self.rho_wide)
@@ -203,15 +226,15 @@ class _Problem:
     def capture(self):
         """The same batched solve captured into a graph on this context (its
         cooperative schedule included); replays write self.x."""
-        return self.ctx.capture(self.g, self.freq, self.csm, select_mode=self.mode,
-                                keep_count=self.K, iterations=self.w.iterations,
+        return self.ctx.capture(self.g, self.freq, self.csm, **self._sel(),
+                                iterations=self.w.iterations,
                                 precision=self.prec, refine_sweeps=self.R, x_map=self.x,
                                 s_tilde=self.st, idx=self.idx, policy=self.policy,
                                 rho_wide=self.rho_wide)
 
     def tune(self, sweeps):
-        return self.ctx.autotune(self.g, self.freq, self.csm, select_mode=self.mode,
-                                 keep_count=self.K, precision=self.prec, trial_sweeps=sweeps,
+        return self.ctx.autotune(self.g, self.freq, self.csm, **self._sel(),
+                                 precision=self.prec, trial_sweeps=sweeps,
                                  policy=self.policy, rho_wide=self.rho_wide)
 
     def close(self):
@@ -319,6 +342,7 @@ def measure(name, steps, warmup, refine=60, tune_sweeps=0, fixed=False, rho_wide
         "workload": pb.label + (" [fixed precision]" if fixed else ""),
         "bins": w.n_bins, "iterations": w.iterations,
         "s_tilde_min": int(s_tilde.min()), "s_tilde_max": int(s_tilde.max()),
+        "s_tilde_histogram": _histogram(s_tilde),
         "updates_per_step": updates,
         "value": round(updates / (ms_step * 1e-3), 1), "unit": "grid-point updates/s",
         "ms_per_step": round(ms_step, 4),
@@ -424,10 +448,13 @@ def oracle_check(pb, bins, cores=None, extra_maps=()):
     cores = min(cores or _host_cores(), len(bins))
     xg = pb.x.double().cpu().numpy()
     jobs = []
+    from paper_1608_05179_amd import damas as dm
+    # KEEP_FRAC is KEEP_COUNT with K = ceil(p N^2) for the oracle
+    mode = oracle.SEL_KEEP_COUNT if pb.mode == dm.SEL_KEEP_FRAC else pb.mode
     for f in bins:
         K = pb.K[f] if isinstance(pb.K, list) else (pb.K or 0)
         jobs.append((w.mic, w.N, (w.x0, w.x1, w.y0, w.y1), w.z0, w.c, float(w.freqs[f]),
-                     w.csm[f], pb.mode, int(K), w.iterations))
+                     w.csm[f], mode, int(K), w.iterations))
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -688,7 +715,8 @@ def measure_psf(reps=5):
     return out
 
 
-def measure_precision(steps, warmup, refine, tune_sweeps, check_bins=(0, 31)):
+def measure_precision(steps, warmup, refine, tune_sweeps, check_bins=(0, 31),
+                      r_counts=(1, 10, 50)):
     """The precision band under the policy and with the bf16 setting fixed
     (the precision trade-off), each with its error against the oracle on
     sampled bins (the oracle needs about a minute per 6561-unknown bin)."""
@@ -696,22 +724,43 @@ def measure_precision(steps, warmup, refine, tune_sweeps, check_bins=(0, 31)):
                           tune_sweeps=tune_sweeps, fixed=True)
     x_fixed = pb_f.x.double().cpu().numpy()
     pb_f.close()
+    # the refinement count: bf16 bulk + R FP32 sweeps, every bin at bf16
+    import torch
+    r_sweep, r_maps = {}, []
+    for R in r_counts:
+        pr = _Problem("precision", R, fixed=True)
+        pr.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr.solve()
+        pr.ctx.check()
+        torch.cuda.synchronize()
+        r_sweep[R] = {"ms_per_step": round((time.perf_counter() - t0) * 1e3, 1)}
+        r_maps.append(pr.x.double().cpu().numpy())
+        pr.close()
+    _progress("precision: refinement-count solves")
     rec, pb = measure("precision", steps, warmup, refine=refine, tune_sweeps=tune_sweeps)
-    errs, _, wall, cores, (errs_f,) = oracle_check(pb, list(check_bins),
-                                                    extra_maps=(x_fixed,))
+    errs, _, wall, cores, extra = oracle_check(pb, list(check_bins),
+                                               extra_maps=(x_fixed, *r_maps))
     pb.close()
     note = f"bins {list(check_bins)}, {wall:.0f} s on {cores} cores"
-    for r, e in ((rec, errs), (rec_f, errs_f)):
+    for r, e in ((rec, errs), (rec_f, extra[0])):
         r["oracle_rel_l2"] = e
         r["oracle_max_rel_l2"] = max(e.values())
         r["oracle_check"] = note
-    return {"policy": rec, "bf16_fixed": rec_f}
+    for R, e in zip(r_counts, extra[1:]):
+        r_sweep[R]["oracle_rel_l2"] = e
+        r_sweep[R]["oracle_max_rel_l2"] = max(e.values())
+    return {"policy": rec, "bf16_fixed": rec_f,
+            "bf16_refine_sweeps": {"note": "every bin bf16 bulk + R FP32 sweeps of 1000, "
+                                           "one timed solve each; " + note,
+                                   "by_R": {str(k): v for k, v in r_sweep.items()}}}
 
 
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver path runs on one GPU; --gpus {args.gpus} is not supported "
               "(bins shard across GPUs with no exchange, but only the one-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
@@ -759,7 +808,11 @@ def main():
         print(json.dumps(measure_psf()), flush=True)
         torch.cuda.synchronize()
         return
-    if args.workload in ("compressed", "plain"):
+    if args.workload == "precision" and not args.fixed:
+        print(json.dumps(measure_precision(args.steps, args.warmup, args.refine,
+                                           args.tune_sweeps)), flush=True)
+        return
+    if args.workload in ("compressed", "compressed10", "compressed30", "plain"):
         print(json.dumps(measure_latency_bound(args.workload, args.steps, args.warmup,
                                                args.tune_sweeps)), flush=True)
         return
@@ -835,7 +888,11 @@ def main():
     if not args.no_variants:
         v = {}
         v["compressed"] = measure_latency_bound("compressed", 10, 2, args.tune_sweeps)
-        _progress("compressed variant")
+        for name in ("compressed10", "compressed30"):
+            r = measure_latency_bound(name, 10, 2, args.tune_sweeps)
+            v["compressed"][f"keep_frac_{name[-2:]}"] = {
+                k: r[k] for k in ("workload", "s_tilde_max", "ms_per_step", "value", "roofline")}
+        _progress("compressed variants")
         v["plain"] = measure_latency_bound("plain", 5, 1, 0)
         torch.cuda.empty_cache()
         _progress("plain variant")
