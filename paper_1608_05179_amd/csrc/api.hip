@@ -1309,11 +1309,22 @@ int enqueue_sweeps(damas_ctx *ctx, const SolvePlan &P, int32_t nb, int32_t max_k
         gate = std::unique_lock<std::mutex>(*ctx->sweep_gate_mu);
         HIP_TRY(hipStreamWaitEvent(s, *ctx->sweep_gate, 0), "hipStreamWaitEvent");
     }
+    // Elements of A over the launch's bins (the workspace's capacity where
+    // the host does not know the kept counts).
+    double a_elems = 0.0;
+    if (P.st_host.size() >= (size_t)nb)
+        for (int f = 0; f < nb; ++f)
+            a_elems += (double)ld_of(P.st_host[f]) * (double)ld_of(P.st_host[f]);
+    else
+        a_elems = (double)P.a_elems;
     auto sweeps = [&](int prec, const void *Ap, int iters, const void *xi,
                       const GsClassArgs &g) -> hipError_t {
+        const double es = prec == DAMAS_PREC_FP64 ? 8.0 : prec == DAMAS_PREC_BF16 ? 2.0 : 4.0;
+        const bool streamed = a_elems * es > kGsStreamBytes;
         if (n_wg > 0)
             return launch_gs_coop(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi,
-                                  x_map, P.fault, tab_dev, n_wg, gpw, ctx->coop_ws.p, g, s);
+                                  x_map, P.fault, tab_dev, n_wg, gpw, streamed, ctx->coop_ws.p,
+                                  g, s);
         return launch_gs(P.N, nb, st, max_kept, ix, P.off, prec, 1, Ap, bm, iters, xi, x_map,
                          P.fault, s, g);
     };

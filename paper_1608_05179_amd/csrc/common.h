@@ -211,8 +211,13 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
                           const int32_t *idx, const int64_t *off, int precision,
                           int unit_diagonal, const void *A, const double *b, int iterations,
                           const void *x_init, void *x_map, int *fault, const int32_t *tab,
-                          int n_wg, int groups_per_wave, void *ws, const GsClassArgs &gc,
-                          hipStream_t s);
+                          int n_wg, int groups_per_wave, bool streamed, void *ws,
+                          const GsClassArgs &gc, hipStream_t s);
+// Bytes of A (all bins of a launch) above which the cooperative sweeps
+// load it with the non-temporal hint: twice the 256 MB last-level cache,
+// so such a band is streamed from HBM every sweep and gains nothing from
+// being cached, while a smaller one stays (partly) in cache between sweeps.
+constexpr double kGsStreamBytes = 512.0 * 1024 * 1024;
 // Whether fn is one of the cooperative kernel's instances (graph capture
 // turns their cooperative launches into plain kernel nodes).
 bool gs_is_coop_kernel(const void *fn);

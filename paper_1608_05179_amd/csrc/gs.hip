@@ -201,7 +201,7 @@ static_assert(sizeof(double) * kGsTile * kGsTile % 16 == 0 &&
 // carry A's float part exactly), lo x_j in FP32 (a term 2^-24 of the first,
 // so its rounding is negligible), and the strip sums carry A to about
 // 2^-33.
-template <typename TA, int NW, int NH, int NB, bool DG = true, bool LO = false>
+template <typename TA, int NW, int NH, int NB, bool DG = true, bool LO = false, bool NT = false>
 struct StreamWave {
     static_assert(!LO || std::is_same<TA, float>::value, "wide bins store a float hi");
     typedef Vec16<TA> VA;
@@ -295,11 +295,16 @@ struct StreamWave {
         return (uint32_t)(((int64_t)jp * ld + T0 + cl) * (int64_t)sizeof(TA));
     }
 
+    // Cache policy of the strip loads: a band whose systems far exceed the
+    // caches streams them with the non-temporal hint (kept out of the way
+    // of data that is reused), a band that stays in cache without it.
+    static constexpr int kAux = NT ? 2 : 0;
+
     // Group g (wave-uniform) of the strip at per-lane offset vo.
     __device__ __forceinline__ VT load(int g, uint32_t vo) const
     {
         return __builtin_bit_cast(
-            VT, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)vo, (int)(g * gstride), 0));
+            VT, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)vo, (int)(g * gstride), kAux));
     }
 
     // The lo parts of group g (LO): half the byte offsets of the float hi.
@@ -307,7 +312,7 @@ struct StreamWave {
     {
         return __builtin_bit_cast(
             VL, __builtin_amdgcn_raw_buffer_load_b64(rlo, (int)(vo >> 1),
-                                                     (int)(g * (gstride >> 1)), 0));
+                                                     (int)(g * (gstride >> 1)), kAux));
     }
 
     // The head of strip T0 and, with `hand`, the rows of its hand-over
@@ -1031,7 +1036,8 @@ template <int NW, int WAVES> constexpr bool gs_spare_waves()
     return WAVES > 1 + NW;
 }
 
-template <typename TA, int NW, int WAVES, int NH, int NB, bool UNIT, bool LO = false>
+template <typename TA, int NW, int WAVES, int NH, int NB, bool UNIT, bool LO = false,
+          bool NT = false>
 __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xnew,
                                           TileBlocks<TA, LO> *blks, const TA *A, int64_t ld,
                                           int St, const int32_t *__restrict__ id,
@@ -1068,7 +1074,7 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
         // it (unit diagonal): fewer instructions for the stream waves, which
         // set the period once most tiles skip their zero rows.
         constexpr bool dg = !UNIT;
-        StreamWave<TA, NW, NH, NB, dg, LO> sw;
+        StreamWave<TA, NW, NH, NB, dg, LO, NT> sw;
         sw.init(A, ld, St, si, lane, si, nwt, Alo);
         const int t1 = nxt(0), t2 = nxt(t1);
         sw.prefetch(0, t1 * kGsTile);
@@ -1280,7 +1286,7 @@ __global__ __launch_bounds__(64 * WAVES) void gs_kernel(
 // bin.
 // One job of the cooperative kernel: rank `rank` of the `ranks` workgroups
 // of bin f (ranks == 1: the bin alone, nothing exchanged).
-template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB, bool LO>
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB, bool LO, bool NT>
 __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int64_t mb, int S, int St,
                                           int64_t ld_cap, const int32_t *__restrict__ idx,
                                           const TA *__restrict__ A, const bf16s *Alo,
@@ -1343,7 +1349,7 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int64_t mb
                 tc = nxt(tc);
             }
         } else {
-            StreamWave<TA, NW, NH, NB, true, LO> sw;
+            StreamWave<TA, NW, NH, NB, true, LO, NT> sw;
             sw.init(A, ld, St, w - 1, lane, rank * NW + w - 1, ranks * NW, Alo);
             sw.prefetch(0, 0, false);
             int tc = ntile - 1;
@@ -1361,7 +1367,7 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int64_t mb
 
     // Owner.
     if (total > 0)
-        sweep_bin<TA, NW, 1 + NW, NH, NB, UNIT, LO>(xs, parts, xnew, blks, A, ld, St, id, bf,
+        sweep_bin<TA, NW, 1 + NW, NH, NB, UNIT, LO, NT>(xs, parts, xnew, blks, A, ld, St, id, bf,
                                                     total, ntile, w, lane, ranks * NW,
                                                     OwnerLink{flags, part, xpub, ranks, fault},
                                                     Alo);
@@ -1372,7 +1378,7 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int64_t mb
 // One job: the bin's kept count (with the capacity checks), its class and
 // sweeps, then the body for a wide or an ordinary bin.  Every rank of a bin
 // reaches the same decisions.
-template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB, bool NT>
 __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
                                          const int32_t *__restrict__ s_tilde, int max_kept,
                                          const int32_t *__restrict__ idx,
@@ -1404,14 +1410,14 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
     bin_map(gc, f, N, &mb, &S);
     if constexpr (std::is_same<TA, float>::value) {
         if (wide) {
-            coop_body<TA, TX, UNIT, NW, kGsLoNH, kGsLoNB, true>(
+            coop_body<TA, TX, UNIT, NW, kGsLoNH, kGsLoNB, true, NT>(
                 f, rank, ranks, mb, S, St, ld_of(min(max_kept, gs_lo_cap<NW>())), idx, A_all + a0,
                 gc.lo + a0, b, iters_f, x_init, x_map, fault, co, xs,
                 gc.power ? gc.power + f : nullptr);
             return;
         }
     }
-    coop_body<TA, TX, UNIT, NW, NH, NB, false>(f, rank, ranks, mb, S, St, ld_of(max_kept), idx,
+    coop_body<TA, TX, UNIT, NW, NH, NB, false, NT>(f, rank, ranks, mb, S, St, ld_of(max_kept), idx,
                                                A_all + a0, nullptr, b, iters_f, x_init, x_map,
                                                fault, co, xs, gc.power ? gc.power + f : nullptr);
 }
@@ -1427,7 +1433,7 @@ __device__ __forceinline__ void coop_job(int f, int rank, int ranks, int N,
 // the queue until it is empty: a workgroup that finishes early takes the
 // next longest bin, whatever the cost model predicted.  Bins alone wait on
 // nobody, and a bin's result does not depend on the workgroup that runs it.
-template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB>
+template <typename TA, typename TX, bool UNIT, int NW, int NH, int NB, bool NT>
 __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
     int N, const int32_t *__restrict__ s_tilde, int max_kept,
     const int32_t *__restrict__ idx, const int64_t *__restrict__ off,
@@ -1463,7 +1469,7 @@ __global__ __launch_bounds__(64 * (1 + NW)) void gs_coop_kernel(
             rank = 0;
             ranks = 1;
         }
-        coop_job<TA, TX, UNIT, NW, NH, NB>(f, rank, ranks, N, s_tilde, max_kept, idx, off, A_all,
+        coop_job<TA, TX, UNIT, NW, NH, NB, NT>(f, rank, ranks, N, s_tilde, max_kept, idx, off, A_all,
                                            b, iters, x_init, x_map, fault, co, gc, xs);
         __syncthreads(); // the next job reuses LDS
     }
@@ -1621,24 +1627,26 @@ int gs_groups_per_wave(int precision, int s_tilde, int ranks)
 }
 
 template <typename TA, typename TX, bool UNIT, int NH, int NB>
-static const void *coop_fn()
+static const void *coop_fn(bool nt)
 {
-    return (const void *)gs_coop_kernel<TA, TX, UNIT, GsShapes<TA>::cnw, NH, NB>;
+    return nt ? (const void *)gs_coop_kernel<TA, TX, UNIT, GsShapes<TA>::cnw, NH, NB, true>
+              : (const void *)gs_coop_kernel<TA, TX, UNIT, GsShapes<TA>::cnw, NH, NB, false>;
 }
 
-// The kernel instance for a precision and the most groups any stream
-// wave sums per strip (short shape when they fit its head).
-static const void *coop_pick(int precision, int unit, int groups_per_wave)
+// The kernel instance for a precision, the most groups any stream wave
+// sums per strip (short shape when they fit its head) and the cache policy
+// of the strip loads (nt: non-temporal).
+static const void *coop_pick(int precision, int unit, int groups_per_wave, bool nt = false)
 {
 #define DAMAS_COOP_PICK(TA, TX)                                                                \
     {                                                                                          \
         typedef GsShapes<TA> SH;                                                               \
         const bool shrt = groups_per_wave <= SH::c_short_nh;                                  \
         if (unit)                                                                              \
-            return shrt ? coop_fn<TA, TX, true, SH::c_short_nh, SH::c_short_nb>()             \
-                        : coop_fn<TA, TX, true, SH::c_long_nh, SH::c_long_nb>();              \
-        return shrt ? coop_fn<TA, TX, false, SH::c_short_nh, SH::c_short_nb>()                \
-                    : coop_fn<TA, TX, false, SH::c_long_nh, SH::c_long_nb>();                 \
+            return shrt ? coop_fn<TA, TX, true, SH::c_short_nh, SH::c_short_nb>(nt)           \
+                        : coop_fn<TA, TX, true, SH::c_long_nh, SH::c_long_nb>(nt);            \
+        return shrt ? coop_fn<TA, TX, false, SH::c_short_nh, SH::c_short_nb>(nt)              \
+                    : coop_fn<TA, TX, false, SH::c_long_nh, SH::c_long_nb>(nt);               \
     }
     if (precision == DAMAS_PREC_FP64)
         DAMAS_COOP_PICK(double, double)
@@ -1653,8 +1661,9 @@ bool gs_is_coop_kernel(const void *fn)
     for (int prec : {DAMAS_PREC_FP64, DAMAS_PREC_FP32, DAMAS_PREC_BF16})
         for (int unit : {0, 1})
             for (int gpw : {1, 1 << 30}) // the short and the long shape
-                if (fn == coop_pick(prec, unit, gpw))
-                    return true;
+                for (bool nt : {false, true})
+                    if (fn == coop_pick(prec, unit, gpw, nt))
+                        return true;
     return false;
 }
 
@@ -1680,8 +1689,8 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
                           const int32_t *idx, const int64_t *off, int precision,
                           int unit_diagonal, const void *A, const double *b, int iterations,
                           const void *x_init, void *x_map, int *fault, const int32_t *tab,
-                          int n_wg, int groups_per_wave, void *ws, const GsClassArgs &gca,
-                          hipStream_t s)
+                          int n_wg, int groups_per_wave, bool streamed, void *ws,
+                          const GsClassArgs &gca, hipStream_t s)
 {
     if (n_bins == 0 || n_wg == 0)
         return hipSuccess;
@@ -1701,7 +1710,7 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const void *fn = coop_pick(precision, unit_diagonal, groups_per_wave);
+    const void *fn = coop_pick(precision, unit_diagonal, groups_per_wave, streamed);
     (void)allow_big_lds(fn);
     const int nw = coop_stream_waves(precision);
     size_t lds = gs_coop_lds_bytes(precision, max_kept, gca.lo != nullptr);
