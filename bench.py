@@ -68,6 +68,8 @@ def _parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--requests", type=int, default=40,
                     help="served workload: requests in the specified-rate trace")
+    ap.add_argument("--sus-requests", type=int, default=16,
+                    help="served workload: requests per sustainable-rate trial")
     ap.add_argument("--workload", default=None,
                     choices=["batched", "compressed", "compressed10", "compressed30", "plain", "precision", "served", "stream",
                              "csm", "psf", "copy"])
@@ -798,7 +800,7 @@ def main():
         return
     if args.workload == "served":
         # the one-request-per-launch comparison only on short traces
-        print(json.dumps(measure_served(n_trace=args.requests,
+        print(json.dumps(measure_served(n_trace=args.requests, n_sus=args.sus_requests,
                                         compare_unbatched=args.requests <= 100)), flush=True)
         return
     if args.workload == "csm":
