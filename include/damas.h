@@ -690,7 +690,9 @@ typedef struct {
 int damas_server_create(const damas_server_opts *o, damas_server **out);
 
 /* Stops the workers after the running requests; waiting requests finish
- * with status DAMAS_EBUSY.  Frees every device buffer of the server. */
+ * with status DAMAS_EBUSY.  Frees every device buffer of the server and
+ * every ticket not yet collected by damas_wait: no other call on the
+ * server may run during or after it (collect the tickets first). */
 void damas_server_destroy(damas_server *srv);
 
 /* Queue a request.  DAMAS_EINVAL: invalid request (validated as for

@@ -209,6 +209,11 @@ void damas_server::work(int k)
         lk.unlock();
         const int rc = batch.size() == 1 ? run(me, batch[0]) : run_batch(me, batch);
         const std::string err = rc ? std::string(damas_last_error()) : std::string();
+        // A failed request may leave copies from its inputs or into its
+        // x_map in flight; they end before it is reported done (its caller
+        // may then free x_map, and damas_wait frees the inputs).
+        if (rc)
+            (void)hipStreamSynchronize(me.stream);
         lk.lock();
         const auto t_end = Clock::now();
         for (Req *r : batch) {
