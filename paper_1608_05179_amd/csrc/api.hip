@@ -590,7 +590,18 @@ int pop_events(damas_ctx *ctx, std::pair<hipEvent_t, hipEvent_t> *ev)
 
 namespace {
 
-// Autotune cache lines: key, then the knobs and the timed ms per sweep.
+// Schedule knobs the cooperative planner accepts (it divides by min_rows
+// and weighs work by split, overhead and wide_cost).
+bool knobs_valid(int coop, int min_rows, double split, double overhead, int floor_rows,
+                 double wide_cost)
+{
+    return (coop == 0 || coop == 1) && min_rows >= 64 && split > 0.0 && overhead > 0.0 &&
+           wide_cost > 0.0 && floor_rows >= 0 && std::isfinite(split) &&
+           std::isfinite(overhead) && std::isfinite(wide_cost);
+}
+
+// Autotune cache lines: key, then the knobs and the timed ms per sweep;
+// a line that does not parse or holds knobs out of range is skipped.
 void load_tune_cache(damas_ctx *c)
 {
     FILE *fh = fopen(c->tune_cache.c_str(), "r");
@@ -602,7 +613,8 @@ void load_tune_cache(damas_ctx *c)
         int coop = 0, mr = 0, fl = 0;
         double sp = 0, ov = 0, wc = 0, ms = 0;
         if (sscanf(line, "%511s %d %d %lf %lf %d %lf %lf", key, &coop, &mr, &sp, &ov, &fl, &wc,
-                   &ms) == 8) {
+                   &ms) == 8 &&
+            knobs_valid(coop, mr, sp, ov, fl, wc)) {
             TuneKnobs k;
             k.coop = coop != 0;
             k.min_rows = mr;
@@ -2251,8 +2263,8 @@ extern "C" int damas_ctx_set_schedule(damas_ctx *ctx, const damas_tune_result *k
     CtxScope scope(ctx);
     if (!ctx || !k)
         return fail(DAMAS_EINVAL, "ctx and knobs must be non-NULL");
-    if ((k->coop != 0 && k->coop != 1) || k->coop_min_rows < 64 || !(k->coop_split > 0.0) ||
-        !(k->coop_overhead > 0.0) || !(k->wide_cost > 0.0) || k->coop_floor_rows < 0)
+    if (!knobs_valid(k->coop, k->coop_min_rows, k->coop_split, k->coop_overhead,
+                     k->coop_floor_rows, k->wide_cost))
         return fail(DAMAS_EINVAL, "schedule knobs out of range");
     ctx->tune.coop = k->coop == 1;
     ctx->tune.min_rows = k->coop_min_rows;

@@ -121,3 +121,25 @@ def test_tune_cache_is_reused(dm, dev, tmp_path):
     assert len(path.read_text().splitlines()) == 2
     c1.close()
     c2.close()
+
+
+def test_tune_cache_skips_knobs_out_of_range(dm, dev, tmp_path):
+    # a cache line whose knobs the planner cannot take (rows per rank 0,
+    # a negative split) is ignored: the problem is tuned again, and the
+    # solve runs on valid knobs
+    path = tmp_path / "tune.txt"
+    w = synth.compressed_fp32(n_bins=4, N=61, iterations=100)
+    mic, g, freq, csm = _setup(dm, dev, w)
+    kw = dict(select_mode=dm.SEL_KEEP_COUNT, keep_count=KS)
+    c1 = dm.Context(0, tune_cache=path)
+    c1.autotune(g, freq, csm, trial_sweeps=5, **kw)
+    c1.close()
+    key = path.read_text().split()[0]
+    path.write_text(f"{key} 1 0 -1 1.3 0 1.7 0.5\n")
+    c2 = dm.Context(0, tune_cache=path)
+    r2 = c2.autotune(g, freq, csm, trial_sweeps=5, **kw)
+    assert r2["candidates_timed"] >= 2
+    assert r2["coop_min_rows"] >= 64 and r2["coop_split"] > 0
+    c2.solve(g, freq, csm, iterations=w.iterations, **kw)
+    c2.check()
+    c2.close()
