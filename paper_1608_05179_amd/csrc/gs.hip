@@ -38,11 +38,11 @@
 // which each r_i's terms are summed (and, for a diagonal other than 1, the
 // scaling by 1 / A_ii) differ.
 //
-// Rows at or beyond S~ contribute exact zeros: A's padding rows are zero
-// (loads past a bin's system return 0), and the stream waves mask columns
-// past S~ out of the partial sums.  The serial wave's lanes past S~ may carry
-// other values (hand-over columns past S~ are not masked), but whatever they
-// broadcast multiplies zero rows, and their values are never stored.
+// Rows at or beyond S~ contribute exact zeros: A's padding rows are zero,
+// columns past ld read as 0 (their lanes' offsets lie outside the buffer),
+// and the stream waves mask columns past S~ out of the partial sums.  The
+// serial wave's lanes past S~ carry zeros or padding values, and whatever
+// they broadcast multiplies zero rows; their values are never stored.
 #include "common.h"
 
 #include <type_traits>
@@ -289,9 +289,17 @@ struct StreamWave {
         }
     }
 
-    // Per-lane byte offset of row jp, columns from T0 + cl.
+    // Per-lane byte offset of row jp, columns from T0 + cl.  The lanes of
+    // columns past ld (the last strip of a bin whose ld is an odd multiple
+    // of 32) get an offset outside the buffer's range: they read 0 and move
+    // no bytes, where the row's next elements would otherwise be fetched
+    // and masked (for the bin's last row, elements past its system).  The
+    // bound holds for the lo arena's halved offsets too (systems < 1 GiB).
+    static constexpr uint32_t kOutside = 0x80000000u;
     __device__ __forceinline__ uint32_t voff(int T0) const
     {
+        if (T0 + cl >= ld)
+            return kOutside;
         return (uint32_t)(((int64_t)jp * ld + T0 + cl) * (int64_t)sizeof(TA));
     }
 
