@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -2200,10 +2201,12 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
     };
     double best = 1e300, dflt = 0.0;
     size_t bi = 0;
+    std::vector<std::pair<double, size_t>> scan; // (time, candidate) of the grid
     for (size_t c = 0; c < cands.size() && rc == DAMAS_OK; ++c) {
         double ms = 0.0;
         if ((rc = time_cand(cands[c], &ms)))
             break;
+        scan.push_back({ms, c});
         if (c == 1)
             dflt = ms; // the untuned knobs
         if (ms < best) {
@@ -2212,20 +2215,40 @@ extern "C" int damas_ctx_autotune(damas_ctx *ctx, const damas_geometry *g, int32
         }
     }
     // With wide bins, the cost of their elements in the schedule, around
-    // the best knobs.
-    if (rc == DAMAS_OK && any_wide && cands[bi].coop) {
-        const Cand base = cands[bi];
-        for (double wcost : {1.0, 1.35, 2.1, 2.6}) {
-            Cand c = base;
-            c.wide_cost = wcost;
-            double ms = 0.0;
-            if ((rc = time_cand(c, &ms)))
-                break;
-            cands.push_back(c);
-            if (ms < best) {
-                best = ms;
-                bi = cands.size() - 1;
+    // the three fastest cooperative grid points (the best wide cost depends
+    // on the other knobs: around the single best point the search missed
+    // schedules 4 % faster).
+    if (rc == DAMAS_OK && any_wide) {
+        std::stable_sort(scan.begin(), scan.end());
+        std::vector<size_t> bases;
+        std::set<std::vector<int32_t>> distinct;
+        for (const auto &e : scan) {
+            if (!cands[e.second].coop || bases.size() >= 3)
+                continue;
+            apply(cands[e.second]);
+            std::vector<int32_t> tab;
+            int gpw = 0;
+            if (plan_coop(ctx, P, tab, &gpw, cls.empty() ? nullptr : cls.data()) == 0)
+                tab.clear();
+            if (distinct.insert(tab).second)
+                bases.push_back(e.second);
+        }
+        for (size_t b : bases) {
+            const Cand base = cands[b];
+            for (double wcost : {1.0, 1.35, 2.1, 2.6}) {
+                Cand c = base;
+                c.wide_cost = wcost;
+                double ms = 0.0;
+                if ((rc = time_cand(c, &ms)))
+                    break;
+                cands.push_back(c);
+                if (ms < best) {
+                    best = ms;
+                    bi = cands.size() - 1;
+                }
             }
+            if (rc)
+                break;
         }
     }
     // The schedules within 5 % of the best are timed twice more, in turn,
