@@ -295,12 +295,13 @@ struct StreamWave {
     // no bytes, where the row's next elements would otherwise be fetched
     // and masked (for the bin's last row, elements past its system).  The
     // bound holds for the lo arena's halved offsets too (systems < 1 GiB).
+    // (The bit is or-ed in rather than selected by a branch: the double
+    // kernel's 32-group head leaves no register for the branch's form.)
     static constexpr uint32_t kOutside = 0x80000000u;
     __device__ __forceinline__ uint32_t voff(int T0) const
     {
-        if (T0 + cl >= ld)
-            return kOutside;
-        return (uint32_t)(((int64_t)jp * ld + T0 + cl) * (int64_t)sizeof(TA));
+        const uint32_t o = (uint32_t)(((int64_t)jp * ld + T0 + cl) * (int64_t)sizeof(TA));
+        return o | (T0 + cl >= (int)ld ? kOutside : 0u);
     }
 
     // Cache policy of the strip loads: a band whose systems far exceed the
