@@ -292,9 +292,11 @@ struct StreamWave {
     // Per-lane byte offset of row jp, columns from T0 + cl.  The lanes of
     // columns past ld (the last strip of a bin whose ld is an odd multiple
     // of 32) get an offset outside the buffer's range: they read 0 and move
-    // no bytes, where the row's next elements would otherwise be fetched
-    // and masked (for the bin's last row, elements past its system).  The
-    // bound holds for the lo arena's halved offsets too (systems < 1 GiB).
+    // no bytes, where the next row's first elements would otherwise be
+    // fetched only to be masked.  (The range check covers the lane and the
+    // group offset together, so groups past the bin's rows read 0 as well.)
+    // The bound holds for the lo arena's halved offsets too (systems
+    // < 1 GiB).
     // (The bit is or-ed in rather than selected by a branch: the double
     // kernel's 32-group head leaves no register for the branch's form.)
     static constexpr uint32_t kOutside = 0x80000000u;
