@@ -373,7 +373,9 @@ typedef struct {
                                 problem up there (and applies the stored
                                 choice without trial solves), else tunes
                                 and appends the choice; the file is read
-                                at creation                                */
+                                at creation, and lines that do not parse
+                                or hold knobs damas_ctx_set_schedule would
+                                refuse are skipped                         */
     int32_t deterministic;   /* 1: sweeps run one workgroup per bin (no
                                 cooperative schedule), so results depend
                                 only on the inputs, not on tuning or on
