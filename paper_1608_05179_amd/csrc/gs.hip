@@ -792,9 +792,22 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
     auto wd = [](TA h, bf16s l) { return LO ? widen(h) + widen(l) : widen(h); };
     int t = 0;
     const int t1 = nxt(0), t2 = nxt(t1);
-    double bt = lane < St ? bf[id[lane]] : 0.0;               // tile t
-    double bq1 = t1 * kGsTile + lane < St ? bf[id[t1 * kGsTile + lane]] : 0.0; // tile t+1
-    int iq2 = t2 * kGsTile + lane < St ? id[t2 * kGsTile + lane] : 0;         // tile t+2
+    // b~ of tile t, of tile t+1, and the grid index of tile t+2's rows.  The
+    // loads are unconditional, on indices clamped to the bin's kept points:
+    // a lane past S~ has rho = 0 whatever its b~ (see `mine`), and a load
+    // under a per-lane condition made the wave wait for it at the end of
+    // every period, a cache round trip on the row chain's critical path.
+    // (An empty bin, whose index array holds nothing, loads nothing: its
+    // loop below does not run.)
+    const int last = St - 1;
+    auto kept = [&](int row) { return id[min(row, last)]; };
+    double bt = 0.0, bq1 = 0.0;
+    int iq2 = 0;
+    if (St > 0) {
+        bt = bf[kept(lane)];                  // tile t
+        bq1 = bf[kept(t1 * kGsTile + lane)];  // tile t+1
+        iq2 = kept(t2 * kGsTile + lane);      // tile t+2
+    }
     double rn = 0.0;    // change of the next tile's residuals from this tile
     double xkeep = 0.0; // the tile's new values (read back when it is the only tile)
     for (long long q = 0; q < total; ++q) {
@@ -1017,8 +1030,8 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
         // period ago), grid index of tile t+3 (tn = t+1).
         const int ta = nxt(tn), tb = nxt(ta);
         bt = bq1;
-        bq1 = ta * kGsTile + lane < St ? bf[iq2] : 0.0;
-        iq2 = tb * kGsTile + lane < St ? id[tb * kGsTile + lane] : 0;
+        bq1 = bf[iq2];
+        iq2 = kept(tb * kGsTile + lane);
         t = tn;
         __syncthreads();
     }
