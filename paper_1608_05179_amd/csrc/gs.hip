@@ -27,6 +27,10 @@
 //     64-column strip, 16 bytes per lane.  While summing they hand wave 0,
 //     through double-buffered LDS, the next tile's diagonal block and its
 //     coupling to the tile after it (both are rows of the same strip).
+//     Those blocks are the only reads of their rows: a strip's loads leave
+//     out the rows of its own tile and of tile q, whose terms come from the
+//     hand-over registers and tile q's coupling block in LDS, so each byte
+//     of A is read once per sweep.
 // A is constant, so each stream wave issues the loads of the first part of
 // its next strip a whole tile ahead (the "head", held in registers); only
 // the rest of a long strip (the "tail") is fetched within the tile, two
@@ -326,16 +330,59 @@ struct StreamWave {
                                                      (int)(g * (gstride >> 1)), kAux));
     }
 
-    // The head of strip T0 and, with `hand`, the rows of its hand-over
-    // blocks (columns of tile T0 for U, of tile TN0 for C).
-    __device__ __forceinline__ void prefetch_head(int T0)
+    // Strip loads leave out the rows of two tiles, which reach the sums from
+    // on chip instead (add_own, add_prev): the strip's own tile (its rows
+    // are the U block, in the hand-over registers since the period before)
+    // and the tile before it, which the serial wave updates while the strip
+    // is summed (its rows are that tile's C block, in LDS).  Reading them
+    // again from memory would move each of those bytes twice.  The two are
+    // adjacent, one range of groups [s, s + len); a left-out group gets a
+    // group offset past every system (< 1 GiB) and reads 0 without a fetch.
+    // The own tile is left out only in bins of more than two tiles: with
+    // one or two, it is the tile whose new values the waves copy into x~ in
+    // the same period, each its own rows with no barrier between (commit),
+    // so only the rows a wave copied itself may be read from x~.  The tile
+    // before strip 0 (the last tile, in the first period of each sweep) is
+    // read from memory: it is not adjacent.
+    static constexpr uint32_t kFar = 0x40000000u;
+    __device__ __forceinline__ bool own() const { return St > 2 * kGsTile; }
+    // A tile P0 is left out (and added from its C block) for strip T0.
+    __device__ __forceinline__ static bool has_prev(int T0, int P0) { return T0 > 0 && P0 != T0; }
+    __device__ __forceinline__ void skip_range(int T0, int P0, int &s, int &len) const
+    {
+        const bool p = has_prev(T0, P0), o = own();
+        s = (p ? P0 : T0) / CPL;
+        len = (p ? GT : 0) + (o ? GT : 0);
+    }
+    __device__ __forceinline__ uint32_t soff(int g, int s, int len, uint32_t stride) const
+    {
+        return (uint32_t)(g - s) < (uint32_t)len ? kFar : (uint32_t)g * stride;
+    }
+    __device__ __forceinline__ VT load_s(int g, uint32_t vo, int s, int len) const
+    {
+        return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(
+                                          rsrc, (int)vo, (int)soff(g, s, len, gstride), kAux));
+    }
+    __device__ __forceinline__ VL load_lo_s(int g, uint32_t vo, int s, int len) const
+    {
+        return __builtin_bit_cast(
+            VL, __builtin_amdgcn_raw_buffer_load_b64(rlo, (int)(vo >> 1),
+                                                     (int)soff(g, s, len, gstride >> 1), kAux));
+    }
+
+    // The head of strip T0, whose sums run while the serial wave updates
+    // tile P0 (P0 = T0: no such tile), and, with `hand`, the rows of its
+    // hand-over blocks (columns of tile T0 for U, of tile TN0 for C).
+    __device__ __forceinline__ void prefetch_head(int T0, int P0)
     {
         const uint32_t vo = voff(T0);
+        int s0, len;
+        skip_range(T0, P0, s0, len);
 #pragma unroll
         for (int n = 0; n < NH; ++n) {
-            head[n] = load(gsw + nwt * n, vo);
+            head[n] = load_s(gsw + nwt * n, vo, s0, len);
             if constexpr (LO)
-                hlo[n] = load_lo(gsw + nwt * n, vo);
+                hlo[n] = load_lo_s(gsw + nwt * n, vo, s0, len);
         }
     }
     __device__ __forceinline__ void prefetch_hand(int T0, int TN0)
@@ -351,9 +398,9 @@ struct StreamWave {
             }
         }
     }
-    __device__ __forceinline__ void prefetch(int T0, int TN0, bool hand = true)
+    __device__ __forceinline__ void prefetch(int T0, int P0, int TN0, bool hand = true)
     {
-        prefetch_head(T0);
+        prefetch_head(T0, P0);
         if (hand)
             prefetch_hand(T0, TN0);
     }
@@ -443,6 +490,68 @@ struct StreamWave {
         }
     }
 
+    // acc += group g's piece v (and its lo parts vl) times x~ of the
+    // group's row.
+    __device__ __forceinline__ void add_group(const VT &v, const VL &vl, int g, AT (&acc)[CPL],
+                                              const double *xs) const
+    {
+        if constexpr (LO) {
+            const double xj = xrow(g, xs)[jp];
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+                acc[s] = fma((double)VA::raw(v, s) + (double)lo_elem(vl, s), xj, acc[s]);
+        } else {
+            const AT xj = (AT)xrow(g, xs)[jp];
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+                acc[s] += VA::toacc(VA::raw(v, s)) * xj;
+        }
+    }
+
+    // The terms of the rows the strip loads leave out, from on chip; each
+    // group once, by the owner's wave that hands it over.  The strip's own
+    // tile T0: its rows at columns T0 are the U rows in hu (loaded with
+    // this strip's head; x~ holds the tile at its old values, copied in an
+    // earlier period).  The tile P0 before it, which the serial wave is
+    // updating (has_prev): its rows at columns T0 are the C block that wave
+    // reads this period, C[i][l] = A_{P0+i, T0+l}; x~ holds P0 at its old
+    // values until the next period's commit, and the serial wave adds the
+    // change, as for the rows the loads bring.  (A wide bin's terms are
+    // formed from hi + lo, exact in double.)
+    __device__ __forceinline__ void add_own(int T0, AT (&acc)[CPL], const double *xs) const
+    {
+#pragma unroll
+        for (int m = 0; m < NU; ++m) {
+            if (sw + NW * m >= GT) // wave-uniform
+                break;
+            if constexpr (LO)
+                add_group(hu[m], hulo[m], T0 / CPL + sw + NW * m, acc, xs);
+            else
+                add_group(hu[m], VL{}, T0 / CPL + sw + NW * m, acc, xs);
+        }
+    }
+    __device__ __forceinline__ void add_prev(int P0, const TileBlocks<TA, LO> *pb,
+                                             AT (&acc)[CPL], const double *xs) const
+    {
+#pragma unroll
+        for (int m = 0; m < NU; ++m) {
+            if (sw + NW * m >= GT)
+                break;
+            const int i = (sw + NW * m) * CPL + jp; // row within tile P0
+            const VT c = *reinterpret_cast<const VT *>(&pb->C[i * kGsTile + cl]);
+            VL c_lo{};
+            if constexpr (LO) {
+                uint32_t e[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    e[s] = pb->Clo[lo_at(i, cl + s)].u;
+                c_lo.x = e[0] | (e[1] << 16);
+                c_lo.y = e[2] | (e[3] << 16);
+            }
+            add_group(c, c_lo, P0 / CPL + sw + NW * m, acc, xs);
+        }
+    }
+
     // Blocks of tile T for the serial wave: U and dg from hu (zero outside
     // S~), C from hc.
     __device__ __forceinline__ void handover(int T0, const bool (&colok)[CPL],
@@ -497,15 +606,18 @@ struct StreamWave {
         }
     }
 
-    // The period that sums strip T and, with `hand`, hands over the blocks
-    // of T (coupled to the tile after it); it also issues the head of strip
-    // NT0 (and, with `hand`, its hand-over rows, coupled to tile NTN0) for
-    // the following period (after the last period those loads go unused:
-    // issuing them unconditionally keeps the head in the same registers
-    // from one period to the next).
-    __device__ __forceinline__ void period(const double *xs, int T0, int NT0, int NTN0,
+    // The period that sums strip T while the serial wave updates tile P0
+    // (P0 = T0 in the first period, which has no such tile, and in a bin of
+    // one tile) and, with `hand`, hands over the blocks of T (coupled to the
+    // tile after it) into blk and adds the rows the loads leave out (pblk:
+    // the blocks of P0); it also issues the head of strip NT0 (and, with
+    // `hand`, its hand-over rows, coupled to tile NTN0) for the following
+    // period, whose serial tile is T (after the last period those loads go
+    // unused: issuing them unconditionally keeps the head in the same
+    // registers from one period to the next).
+    __device__ __forceinline__ void period(const double *xs, int T0, int P0, int NT0, int NTN0,
                                            double *part, TileBlocks<TA, LO> *blk,
-                                           bool hand = true)
+                                           const TileBlocks<TA, LO> *pblk, bool hand = true)
     {
         AT acc[CPL];
         float acl[CPL]; // LO: the lo terms
@@ -533,17 +645,24 @@ struct StreamWave {
             sum(head, gsw, acc, xs);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (kEarlyHead)
-            prefetch_head(NT0);
+            prefetch_head(NT0, T0);
         __builtin_amdgcn_sched_barrier(0);
-        if (hand)
+        // The left-out rows' terms come after every loaded group, the own
+        // tile's first, so the sum has the same order whatever the head's
+        // length (a bin gives the same bits in every launch shape).  hu
+        // holds the own tile's rows until they are added; the next strip's
+        // hand-over rows are issued right after (with no tail: here).
+        if (hand) {
             handover(T0, colok, blk);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (kEarlyHead) {
-            if (hand)
+            if constexpr (NB == 0) {
+                if (own())
+                    add_own(T0, acc, xs);
                 prefetch_hand(NT0, NTN0);
-        } else {
-            prefetch(NT0, NTN0, hand);
+            }
         }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!kEarlyHead)
+            prefetch_head(NT0, T0);
         __builtin_amdgcn_sched_barrier(0);
 
         // Tail: groups NH .. nk-1 in batches of NB, two batches in flight
@@ -557,14 +676,16 @@ struct StreamWave {
         if constexpr (NB > 0) {
             if (nk > NH) {
                 const uint32_t vo = voff(T0);
+                int s0, len;
+                skip_range(T0, P0, s0, len);
                 VT b0[NB], b1[NB];
                 VL l0[LO ? NB : 1], l1[LO ? NB : 1];
                 auto fill = [&](VT(&dst)[NB], VL(&dlo)[LO ? NB : 1], int k0) {
 #pragma unroll
                     for (int n = 0; n < NB; ++n) {
-                        dst[n] = load(gsw + nwt * (k0 + n), vo);
+                        dst[n] = load_s(gsw + nwt * (k0 + n), vo, s0, len);
                         if constexpr (LO)
-                            dlo[n] = load_lo(gsw + nwt * (k0 + n), vo);
+                            dlo[n] = load_lo_s(gsw + nwt * (k0 + n), vo, s0, len);
                     }
                 };
                 auto add = [&](const VT(&v)[NB], const VL(&vl)[LO ? NB : 1], int g0) {
@@ -595,6 +716,15 @@ struct StreamWave {
                     add(b0, l0, gsw + nwt * k0);
                 }
             }
+        }
+        if (hand) {
+            if constexpr (NB > 0)
+                if (own())
+                    add_own(T0, acc, xs);
+            if (has_prev(T0, P0))
+                add_prev(P0, pblk, acc, xs);
+            if constexpr (NB > 0)
+                prefetch_hand(NT0, NTN0);
         }
 
         if constexpr (LO) {
@@ -813,7 +943,6 @@ __device__ __forceinline__ void serial_role(double *xs, const double *parts, dou
     for (long long q = 0; q < total; ++q) {
         const int t0 = t * kGsTile;
         const int tn = nxt(t);
-        const int tn0 = tn * kGsTile;
         const int rows = min(kGsTile, St - t0);
         const int steps = (rows + 7) & ~7;
         const bool mine = lane < rows;
@@ -1101,16 +1230,16 @@ __device__ __forceinline__ void sweep_bin(double *xs, double *parts, double *xne
         StreamWave<TA, NW, NH, NB, dg, LO, NT> sw;
         sw.init(A, ld, St, si, lane, si, nwt, Alo);
         const int t1 = nxt(0), t2 = nxt(t1);
-        sw.prefetch(0, t1 * kGsTile);
-        sw.period(xs, 0, t1 * kGsTile, t2 * kGsTile, parts, &blks[0]);
+        sw.prefetch(0, 0, t1 * kGsTile);
+        sw.period(xs, 0, 0, t1 * kGsTile, t2 * kGsTile, parts, &blks[0], nullptr);
         __syncthreads();
         int tp = 0, t = 0;
         for (long long q = 0; q + 1 < total; ++q) {
             const int tn = nxt(t), tnn = nxt(tn), tn3 = nxt(tnn);
             if (q > 0)
                 sw.commit(xnew + ((q - 1) & 1) * kGsTile, xs, tp * kGsTile);
-            sw.period(xs, tn * kGsTile, tnn * kGsTile, tn3 * kGsTile,
-                      parts + ((q + 1) & 1) * NW * kGsTile, &blks[(q + 1) & 1]);
+            sw.period(xs, tn * kGsTile, t * kGsTile, tnn * kGsTile, tn3 * kGsTile,
+                      parts + ((q + 1) & 1) * NW * kGsTile, &blks[(q + 1) & 1], &blks[q & 1]);
             __syncthreads();
             tp = t;
             t = tn;
@@ -1375,13 +1504,14 @@ __device__ __forceinline__ void coop_body(int f, int rank, int ranks, int64_t mb
         } else {
             StreamWave<TA, NW, NH, NB, true, LO, NT> sw;
             sw.init(A, ld, St, w - 1, lane, rank * NW + w - 1, ranks * NW, Alo);
-            sw.prefetch(0, 0, false);
+            sw.prefetch(0, 0, 0, false);
             int tc = ntile - 1;
             for (long long p = -1; p + 1 < total; ++p) {
                 const int tn = nxt(tc), tnn = nxt(tn);
                 __syncthreads();
-                sw.period(xs, tn * kGsTile, tnn * kGsTile, tnn * kGsTile, parts,
-                          (TileBlocks<TA, LO> *)nullptr, false);
+                // the owner's serial tile of period p: tc (none in period -1)
+                sw.period(xs, tn * kGsTile, (p < 0 ? tn : tc) * kGsTile, tnn * kGsTile,
+                          tnn * kGsTile, parts, (TileBlocks<TA, LO> *)nullptr, nullptr, false);
                 __syncthreads();
                 tc = tn;
             }
