@@ -344,10 +344,17 @@ struct StreamWave {
     // so only the rows a wave copied itself may be read from x~.  The tile
     // before strip 0 (the last tile, in the first period of each sweep) is
     // read from memory: it is not adjacent.
+    // Only streamed launches (NT: A far larger than the caches) do this:
+    // in a cache-resident launch the second read hits in L2 and the sums
+    // from on chip would only lengthen the stream waves' period.
+    static constexpr bool kOnce = NT;
     static constexpr uint32_t kFar = 0x40000000u;
-    __device__ __forceinline__ bool own() const { return St > 2 * kGsTile; }
+    __device__ __forceinline__ bool own() const { return kOnce && St > 2 * kGsTile; }
     // A tile P0 is left out (and added from its C block) for strip T0.
-    __device__ __forceinline__ static bool has_prev(int T0, int P0) { return T0 > 0 && P0 != T0; }
+    __device__ __forceinline__ static bool has_prev(int T0, int P0)
+    {
+        return kOnce && T0 > 0 && P0 != T0;
+    }
     __device__ __forceinline__ void skip_range(int T0, int P0, int &s, int &len) const
     {
         const bool p = has_prev(T0, P0), o = own();
@@ -654,7 +661,7 @@ struct StreamWave {
         // hand-over rows are issued right after (with no tail: here).
         if (hand) {
             handover(T0, colok, blk);
-            if constexpr (NB == 0) {
+            if constexpr (NB == 0 && kOnce) {
                 if (own())
                     add_own(T0, acc, xs);
                 prefetch_hand(NT0, NTN0);
@@ -663,6 +670,9 @@ struct StreamWave {
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (!kEarlyHead)
             prefetch_head(NT0, T0);
+        if constexpr (!kOnce)
+            if (hand)
+                prefetch_hand(NT0, NTN0);
         __builtin_amdgcn_sched_barrier(0);
 
         // Tail: groups NH .. nk-1 in batches of NB, two batches in flight
@@ -717,14 +727,16 @@ struct StreamWave {
                 }
             }
         }
-        if (hand) {
-            if constexpr (NB > 0)
-                if (own())
-                    add_own(T0, acc, xs);
-            if (has_prev(T0, P0))
-                add_prev(P0, pblk, acc, xs);
-            if constexpr (NB > 0)
-                prefetch_hand(NT0, NTN0);
+        if constexpr (kOnce) {
+            if (hand) {
+                if constexpr (NB > 0)
+                    if (own())
+                        add_own(T0, acc, xs);
+                if (has_prev(T0, P0))
+                    add_prev(P0, pblk, acc, xs);
+                if constexpr (NB > 0)
+                    prefetch_hand(NT0, NTN0);
+            }
         }
 
         if constexpr (LO) {
