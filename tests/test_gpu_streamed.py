@@ -14,9 +14,17 @@ from paper_1608_05179_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-BIG, N_BIG = 2000, 36
 SMALL = [1, 2, 64, 65, 128, 129, 130, 257]
 ITERS = 30
+BIG, N_BIG = 2000, 36  # the FP32 band
+# storage type: (precision, kept points of the long bins, their count, bins
+# per cache-resident launch, tolerance of the summation order)
+CASES = {
+    "fp32": ("PREC_FP32", 2000, 36, 30, 1e-5),
+    "bf16": ("PREC_BF16", 2000, 68, 34, 1e-5),
+    "fp64": ("PREC_FP64", 1800, 21, 20, 1e-11),
+}
+ELEM = {"fp32": 4, "bf16": 2, "fp64": 8}
 
 
 def _t(a, dtype, dev):
@@ -28,28 +36,38 @@ def _ld(k):
     return (k + 31) // 32 * 32
 
 
-@pytest.fixture(scope="module")
-def band():
-    w = synth.batched_fp32(n_bins=N_BIG + len(SMALL), N=61, iterations=ITERS)
-    K = np.array([BIG] * N_BIG + SMALL, dtype=np.int32)
+def _band(case):
+    _, big, n_big, chunk, _ = CASES[case]
+    w = synth.batched_fp32(n_bins=n_big + len(SMALL), N=61, iterations=ITERS)
+    K = np.array([big] * n_big + SMALL, dtype=np.int32)
+    es = ELEM[case]
     # A of the whole band: beyond the 512 MiB above which sweeps stream it
-    assert sum(_ld(int(k)) ** 2 for k in K) * 4 > 512 * 1024 * 1024
+    assert sum(_ld(int(k)) ** 2 for k in K) * es > 512 * 1024 * 1024
     # each reference launch: below it
-    assert 30 * _ld(BIG) ** 2 * 4 < 512 * 1024 * 1024
+    assert (chunk * _ld(big) ** 2 + sum(_ld(k) ** 2 for k in SMALL)) * es < 512 * 1024 * 1024
     return w, K
 
 
-def _solve(dm, dev, w, K, bins):
+@pytest.fixture(scope="module")
+def band():
+    return _band("fp32")
+
+
+def _solve(dm, dev, w, K, bins, case="fp32"):
     import torch
+    prec = getattr(dm, CASES[case][0])
     mic = _t(w.mic, torch.float64, dev)
     g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
     ctx = dm.Context(0)
+    # bf16: every sweep on the bf16 system (no per-bin classes, no refinement)
+    extra = ({"policy": dm.POLICY_FIXED, "refine_sweeps": 0} if case == "bf16" else {})
     x = ctx.solve(g, _t(w.freqs[bins], torch.float64, dev),
                   _t(w.csm[bins], torch.complex128, dev), select_mode=dm.SEL_KEEP_COUNT,
                   keep_count=[int(K[b]) for b in bins], iterations=ITERS,
-                  precision=dm.PREC_FP32, batched=True)
+                  precision=prec, batched=True, **extra)
     ctx.check()
-    out = x.double().cpu().numpy(), ctx.last_workgroups(), ctx.classes(len(bins))
+    cls = ctx.classes(len(bins)) if case == "fp32" else None  # per-bin classes: FP32 policy
+    out = x.double().cpu().numpy(), ctx.last_workgroups(), cls
     ctx.close()
     return out
 
@@ -58,21 +76,25 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def test_streamed_band_equals_cache_resident_launches(dm, dev, band):
-    w, K = band
+@pytest.mark.parametrize("case", list(CASES))
+def test_streamed_band_equals_cache_resident_launches(dm, dev, case):
+    w, K = _band(case)
+    _, _, n_big, chunk, tol = CASES[case]
     allb = list(range(len(K)))
-    xs, wg, cls = _solve(dm, dev, w, K, allb)
+    xs, wg, cls = _solve(dm, dev, w, K, allb, case)
     assert wg > len(K)                      # cooperative job lists
-    assert (cls == 2).any() and (cls == 0).any(), cls  # wide and narrow bins
-    refs = [list(range(0, 30)), list(range(30, N_BIG)), list(range(N_BIG, len(K)))]
+    if case == "fp32":
+        assert (cls == 2).any() and (cls == 0).any(), cls  # wide and narrow bins
+    refs = [list(range(i, min(i + chunk, n_big))) for i in range(0, n_big, chunk)]
+    refs.append(list(range(n_big, len(K))))
     worst = 0.0
     for bins in refs:
-        xr, _, _ = _solve(dm, dev, w, K, bins)
+        xr, _, _ = _solve(dm, dev, w, K, bins, case)
         for i, b in enumerate(bins):
             e = _rel(xs[b], xr[i])
             worst = max(worst, e)
-            assert e <= 1e-5, (b, int(K[b]), e)
-    print(f"streamed vs cache-resident launches: worst rel L2 {worst:.2e}")
+            assert e <= tol, (case, b, int(K[b]), e)
+    print(f"{case}: streamed vs cache-resident launches: worst rel L2 {worst:.2e}")
 
 
 def test_streamed_small_bins_match_oracle(dm, dev, orc, band):
