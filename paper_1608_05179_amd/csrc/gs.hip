@@ -27,10 +27,12 @@
 //     64-column strip, 16 bytes per lane.  While summing they hand wave 0,
 //     through double-buffered LDS, the next tile's diagonal block and its
 //     coupling to the tile after it (both are rows of the same strip).
-//     Those blocks are the only reads of their rows: a strip's loads leave
-//     out the rows of its own tile and of tile q, whose terms come from the
-//     hand-over registers and tile q's coupling block in LDS, so each byte
-//     of A is read once per sweep.
+//     In a launch that streams A from memory those blocks are the only
+//     reads of their rows: a strip's loads leave out the rows of its own
+//     tile and of tile q, whose terms come from the hand-over registers and
+//     tile q's coupling block in LDS, so each byte of A is read once per
+//     sweep (a launch whose A stays in cache reads those rows again, from
+//     L2).
 // A is constant, so each stream wave issues the loads of the first part of
 // its next strip a whole tile ahead (the "head", held in registers); only
 // the rest of a long strip (the "tail") is fetched within the tile, two
