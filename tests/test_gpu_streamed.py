@@ -105,3 +105,34 @@ def test_streamed_small_bins_match_oracle(dm, dev, orc, band):
         ref = orc.solve_bin(og, w.freqs[b], w.csm[b], orc.SEL_KEEP_COUNT,
                             keep_count=int(K[b]), iters=ITERS)["x"]
         assert _rel(xs[b], ref) <= 1e-4, (b, int(K[b]))
+
+
+def test_streamed_graph_replays_match_eager(dm, dev, band):
+    # The streamed band captured into a graph (cooperative, non-temporal
+    # strip loads, hand-over rows left out of the strips): every replay
+    # equals the eager solve bitwise, with eager work between replays.
+    import torch
+    w, K = band
+    mic = _t(w.mic, torch.float64, dev)
+    g = dm.geometry(mic, w.N, w.x0, w.x1, w.y0, w.y1, w.z0, w.c)
+    freq = _t(w.freqs, torch.float64, dev)
+    csm = torch.view_as_real(_t(w.csm, torch.complex128, dev)).contiguous()
+    kw = dict(select_mode=dm.SEL_KEEP_COUNT, keep_count=[int(k) for k in K],
+              iterations=ITERS, precision=dm.PREC_FP32)
+    eager = dm.Context(0)
+    ref = eager.solve(g, freq, csm, **kw).clone()
+    eager.check()
+    ctx = dm.Context(0)
+    graph = ctx.capture(g, freq, csm, **kw)
+    assert graph.workgroups() == eager.last_workgroups() > len(K)
+    for _ in range(2):
+        graph.x_map.fill_(-1.0)
+        out = graph.launch()
+        torch.cuda.synchronize()
+        ctx.check()
+        assert torch.equal(out, ref)
+        eager.solve(g, freq, csm, **dict(kw, iterations=5))
+        torch.cuda.synchronize()
+    graph.close()
+    ctx.close()
+    eager.close()
