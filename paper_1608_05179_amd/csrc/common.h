@@ -200,6 +200,7 @@ int gs_max_kept(int precision);
 // rank and the bin's rank count; a job with ranks > 1 must be the first of
 // its workgroup;
 // groups_per_wave: the most row groups any stream wave sums per strip;
+// streamed: A exceeds kGsStreamBytes (see there);
 // ws: gs_coop_ws_bytes of device workspace.  Every bin needs >= 2 tiles.
 size_t gs_coop_ws_bytes(int n_bins, int max_kept);
 int gs_max_ranks();
@@ -214,9 +215,11 @@ hipError_t launch_gs_coop(int N, int n_bins, const int32_t *s_tilde, int max_kep
                           int n_wg, int groups_per_wave, bool streamed, void *ws,
                           const GsClassArgs &gc, hipStream_t s);
 // Bytes of A (all bins of a launch) above which the cooperative sweeps
-// load it with the non-temporal hint: twice the 256 MB last-level cache,
-// so such a band is streamed from HBM every sweep and gains nothing from
-// being cached, while a smaller one stays (partly) in cache between sweeps.
+// load it with the non-temporal hint and read each row once per sweep (the
+// hand-over rows left out of the strip loads): twice the 256 MB last-level
+// cache, so such a band is streamed from HBM every sweep and gains nothing
+// from being cached, while a smaller one stays (partly) in cache between
+// sweeps, where a second read of the hand-over rows hits in L2.
 constexpr double kGsStreamBytes = 512.0 * 1024 * 1024;
 // Whether fn is one of the cooperative kernel's instances (graph capture
 // turns their cooperative launches into plain kernel nodes).
